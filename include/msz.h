@@ -1,0 +1,191 @@
+/*
+ * msz.h -- C ABI of the MI355X (gfx950) MSz correction library, libmsz.so.
+ *
+ * The library corrects an error-bounded decompression fhat of a piecewise
+ * linear scalar field f so that the ascending and descending Morse-Smale
+ * segmentations of the edited field g = fhat + delta equal those of f, while
+ * |f - g| <= xi holds at every vertex (MSz, arXiv 2406.09423, Problem
+ * Statement).  Every step runs in HIP kernels on the GPU.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grids: row-major with x fastest, vertex id i = x + nx*(y + ny*z).
+ *    ndim == 2 (nz must be 1): every quad is split along its (0,0)-(1,1)
+ *    diagonal, so interior vertices have 6 neighbours.  ndim == 3: Freudenthal
+ *    split of every cube along (0,0,0)-(1,1,1), 14 neighbours (Sec. 3, the PL
+ *    setting).  No periodic wrap.  nx, ny, nz >= 1 and nx*ny*nz < 2^31.
+ *  - Order (Sec. 4, simulation of simplicity): vertex a is above b iff
+ *    h_a > h_b, or h_a == h_b and a > b.  -0 and +0 compare equal.
+ *  - Arrays: float32 / int32, DEVICE pointers, owned by the caller, at least
+ *    n = nx*ny*nz elements.  Host structs (stats, counts) are filled before
+ *    the call returns.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  All work is enqueued on it; each call synchronises on it
+ *    before returning (the loop makes host decisions between rounds).
+ *  - Errors: the return code is the only error channel; no global state.
+ *    msz_strerror() names a code.  Inputs must be finite with magnitude at
+ *    most 2^100 (so that no edit can overflow float32).
+ *  - Concurrency: calls on different streams with separate workspaces are
+ *    independent.  Calls sharing a workspace must not overlap.
+ */
+#ifndef MSZ_H
+#define MSZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MSZ_OK = 0,
+    MSZ_EINVAL = -1,     /* bad dims, NULL pointer, bad option or workspace too small */
+    MSZ_ENONFINITE = -2, /* NaN / Inf (or |v| > 2^100) in f, fhat, warm start or xi */
+    MSZ_EBOUND = -3,     /* |f - fhat| > xi somewhere, or warm start outside [L, fhat] */
+    MSZ_ESTALL = -4,     /* a round had targets but every target sat at its floor L */
+    MSZ_ENOCONV = -5,    /* max_rounds productive rounds were not enough */
+    MSZ_EDEVICE = -6,    /* a HIP runtime call failed */
+    MSZ_ENOMEM = -7      /* the library could not allocate scratch memory */
+};
+
+/* Kernels timed under MSZ_FLAG_TIMING (indices of msz_stats.phase_ms). */
+enum {
+    MSZ_PHASE_VALIDATE = 0,     /* input contract, floors L, start field */
+    MSZ_PHASE_DIRS = 1,         /* steepest directions of f */
+    MSZ_PHASE_DIRS_DETECT = 2,  /* directions of g fused with C-loop detection */
+    MSZ_PHASE_DETECT = 3,       /* C-loop detection from stored directions */
+    MSZ_PHASE_APPLY = 4,        /* halving of the round's targets */
+    MSZ_PHASE_LABEL_TILE = 5,   /* in-LDS pointer jumping per tile */
+    MSZ_PHASE_LABEL_JUMP = 6,   /* pointer compression of tile-face vertices */
+    MSZ_PHASE_LABEL_FINAL = 7,  /* labels of f */
+    MSZ_PHASE_DETECT_R = 8,     /* troublemaker detection */
+    MSZ_PHASE_DELTA = 9,        /* output deltas */
+    MSZ_N_PHASES = 10
+};
+
+/* msz_options.flags bits. */
+#define MSZ_FLAG_TIMING 1 /* record hipEvents around every launch (adds a little overhead) */
+
+typedef struct {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t nx, ny, nz;  /* nz == 1 when ndim == 2 */
+} msz_dims;
+
+/* Statistics of one correction (the per-type round counts mirror the paper's
+ * per-iteration breakdown, Sec. 8 / Fig. 12). */
+typedef struct {
+    int64_t rounds[4];     /* productive rounds of the FPmax, FPmin, FNmax, FNmin sub-loops */
+    int64_t rounds_r;      /* productive R-loop rounds */
+    int64_t outer_iters;   /* times the C phase was entered */
+    int64_t n_edited;      /* vertices whose final g differs from fhat */
+    int64_t false_init[4]; /* false critical points of each type in the start field */
+    int64_t n_inexact;     /* vertices where no float32 delta gives fl(fhat + delta) == g */
+    int32_t status;        /* the return code of the call */
+    int32_t pad;
+    /* Filled only with MSZ_FLAG_TIMING: summed GPU time (ms, hipEvents around each
+     * launch) and launch count of each kernel, indexed by MSZ_PHASE_*. */
+    float phase_ms[MSZ_N_PHASES];
+    int32_t phase_launches[MSZ_N_PHASES];
+} msz_stats;
+
+/* Counts returned by msz_count_false (Defs. 1-3; Appendix B right-labelled ratio). */
+typedef struct {
+    int64_t fp_max, fp_min, fn_max, fn_min; /* false critical points of g w.r.t. f */
+    int64_t wrong_max, wrong_min;           /* vertices whose max / min label differs */
+    int64_t wrong_any;                      /* vertices with either label wrong (N_f) */
+} msz_false_counts;
+
+/* Options; pass NULL for all defaults. */
+typedef struct {
+    int64_t max_rounds;       /* cap on productive rounds; <= 0 means 2^30 */
+    const float* warm_start;  /* DEVICE start field g0 with L <= g0 <= fhat, or NULL for fhat */
+    float* g_out;             /* DEVICE array receiving the edited field g, or NULL */
+    void* workspace;          /* DEVICE scratch of >= msz_workspace_bytes(dims), or NULL */
+    size_t workspace_bytes;   /* size of `workspace` */
+    int32_t tile_override;    /* 0: autotuned/default tile; k > 0: tile variant k (see msz_tile_variants) */
+    int32_t flags;            /* 0 or MSZ_FLAG_TIMING */
+} msz_options;
+
+/*
+ * msz_fix -- the correction loop (Sec. 5: C-loops and R-loops alternated
+ * until no false critical point and no mislabelled vertex remains).
+ *
+ *  f, fhat    DEVICE float32[n]: original field and its decompression; the
+ *             input contract is |f_i - fhat_i| <= xi (checked exactly).
+ *  d          grid description.
+ *  xi         absolute error bound, finite, >= 0.
+ *  edits_out  DEVICE float32[n]: receives delta with fl32(fhat + delta) == g
+ *             wherever a float achieves it (stats->n_inexact counts the rest).
+ *  opt        options or NULL.
+ *  stats      HOST struct, required.
+ *
+ * Edits only ever lower values: g_i lies in [L_i, fhat_i], where L_i is the
+ * smallest float32 >= f_i - xi (Eq. 1).  Each round works on a snapshot of g
+ * and halves every proposed target once: g <- fl(fl(g + L)/2), snapped to L
+ * when rounding makes no progress (Eqs. 2-6).  Sub-loop order FPmax, FPmin,
+ * FNmax, FNmin (Sec. 5.1); an FPmin lowers the vertex's descent neighbour in
+ * f; an FNmax lowers the vertex's ascent neighbour in g; the R-loop lowers
+ * dn_f(u) for a wrong-minimum troublemaker u and up_g(u) for a wrong-maximum
+ * one (Sec. 5.2, Eq. 6).  The result is bit-identical to the serial oracle's.
+ * On MSZ_ESTALL / MSZ_ENOCONV, edits_out still holds a valid, bounded delta.
+ */
+int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edits_out,
+            const msz_options* opt, msz_stats* stats, void* stream);
+
+/*
+ * msz_labels -- ascending / descending segmentation labels of one field
+ * (Sec. 3): max_label[i] (min_label[i]) is the id of the maximum (minimum)
+ * that the steepest ascending (descending) integral line from i reaches.
+ * field: DEVICE float32[n]; max_label, min_label: DEVICE int32[n].
+ */
+int msz_labels(const float* field, msz_dims d, int32_t* max_label, int32_t* min_label,
+               void* stream);
+
+/*
+ * msz_count_false -- false critical points of g with respect to f (Defs. 1-3)
+ * and mislabelled vertices (Problem Statement; wrong_any is N_f of the
+ * right-labelled ratio 1 - N_f/N, Appendix B).  f, g: DEVICE float32[n];
+ * out: HOST struct.
+ */
+int msz_count_false(const float* f, const float* g, msz_dims d, msz_false_counts* out,
+                    void* stream);
+
+/* One field of a batch. */
+typedef struct {
+    const float* f;      /* DEVICE float32[n] */
+    const float* fhat;   /* DEVICE float32[n] */
+    msz_dims d;
+    float xi;
+    float* edits_out;    /* DEVICE float32[n] */
+    float* g_out;        /* DEVICE float32[n] or NULL */
+    msz_stats* stats;    /* HOST, required */
+} msz_job;
+
+/*
+ * msz_fix_batch -- corrects n_jobs independent fields of uneven sizes
+ * together: every round advances all unconverged fields at once, each by the
+ * same schedule msz_fix follows, so each field's result is bit-identical to
+ * its own msz_fix.  opt->workspace (if given) must hold
+ * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start and
+ * opt->g_out must be NULL (use msz_job.g_out).  Returns MSZ_OK when every
+ * field converged, else the first failing field's code (see each stats).
+ */
+int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, void* stream);
+
+/* Scratch bytes msz_fix needs for dims d (0 for invalid dims). */
+size_t msz_workspace_bytes(msz_dims d);
+
+/* Scratch bytes msz_fix_batch needs for these jobs (0 if any dims are invalid). */
+size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs);
+
+/* Number of tile variants selectable through msz_options.tile_override for ndim. */
+int msz_tile_variants(int32_t ndim);
+
+/* Human-readable name of a return code (static string). */
+const char* msz_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSZ_H */

@@ -1,0 +1,245 @@
+"""MSz correction loop on AMD Instinct MI355X (gfx950).
+
+A thin ctypes binding over ``libmsz.so`` (the C ABI in ``include/msz.h``).
+Every step of the correction runs in the library's HIP kernels; this module
+only passes device pointers, sizes and the current stream.  PyTorch provides
+device memory and streams.  There is no CPU fallback: if ``libmsz.so`` has
+not been built, the first call raises.
+
+Fields are contiguous float32 CUDA tensors shaped ``(ny, nx)`` (2D, 6
+neighbours) or ``(nz, ny, nx)`` (3D, Freudenthal 14 neighbours), so that the
+vertex id is ``x + nx*(y + ny*z)``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsz.so")
+
+OK, EINVAL, ENONFINITE, EBOUND, ESTALL, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+CASE_NAMES = ("fp_max", "fp_min", "fn_max", "fn_min")
+PHASES = ("validate", "dirs", "dirs_detect", "detect", "apply", "label_tile", "label_jump",
+          "label_final", "detect_r", "delta")
+N_PHASES = len(PHASES)
+FLAG_TIMING = 1
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64 * 4), ("rounds_r", ctypes.c_int64),
+                ("outer_iters", ctypes.c_int64), ("n_edited", ctypes.c_int64),
+                ("false_init", ctypes.c_int64 * 4), ("n_inexact", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("phase_ms", ctypes.c_float * N_PHASES), ("phase_launches", ctypes.c_int32 * N_PHASES)]
+
+    def timing(self) -> dict:
+        """Per-kernel GPU time (ms) and launches, filled when the call ran with timing on."""
+        return {name: {"ms": float(self.phase_ms[k]), "launches": int(self.phase_launches[k])}
+                for k, name in enumerate(PHASES)}
+
+    def as_dict(self) -> dict:
+        return {
+            "rounds": [int(x) for x in self.rounds],
+            "rounds_r": int(self.rounds_r),
+            "outer_iters": int(self.outer_iters),
+            "n_edited": int(self.n_edited),
+            "false_init": [int(x) for x in self.false_init],
+            "n_inexact": int(self.n_inexact),
+            "status": int(self.status),
+        }
+
+
+class FalseCounts(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in
+                ("fp_max", "fp_min", "fn_max", "fn_min", "wrong_max", "wrong_min", "wrong_any")]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("max_rounds", ctypes.c_int64), ("warm_start", ctypes.c_void_p),
+                ("g_out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("tile_override", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_void_p), ("fhat", ctypes.c_void_p), ("d", Dims),
+                ("xi", ctypes.c_float), ("edits_out", ctypes.c_void_p), ("g_out", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(Stats))]
+
+
+class MszError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmsz.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2406_09423_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, F, I32 = ctypes.c_void_p, ctypes.c_float, ctypes.c_int32
+        L.msz_fix.argtypes = [P, P, Dims, F, P, ctypes.POINTER(Options), ctypes.POINTER(Stats), P]
+        L.msz_labels.argtypes = [P, Dims, P, P, P]
+        L.msz_count_false.argtypes = [P, P, Dims, ctypes.POINTER(FalseCounts), P]
+        L.msz_fix_batch.argtypes = [ctypes.POINTER(Job), I32, ctypes.POINTER(Options), P]
+        L.msz_workspace_bytes.argtypes = [Dims]
+        L.msz_workspace_bytes.restype = ctypes.c_size_t
+        L.msz_batch_workspace_bytes.argtypes = [ctypes.POINTER(Job), I32]
+        L.msz_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.msz_tile_variants.argtypes = [I32]
+        L.msz_strerror.argtypes = [ctypes.c_int]
+        L.msz_strerror.restype = ctypes.c_char_p
+        for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants):
+            fn.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().msz_strerror(int(code)).decode()
+    except ImportError:
+        return str(code)
+
+
+def dims_of(shape) -> Dims:
+    if len(shape) == 2:
+        return Dims(2, int(shape[1]), int(shape[0]), 1)
+    if len(shape) == 3:
+        return Dims(3, int(shape[2]), int(shape[1]), int(shape[0]))
+    raise ValueError(f"fields are 2D (ny, nx) or 3D (nz, ny, nx), got shape {tuple(shape)}")
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check_field(t, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 tensor")
+
+
+def workspace_bytes(shape) -> int:
+    return int(lib().msz_workspace_bytes(dims_of(shape)))
+
+
+def tile_variants(ndim: int) -> int:
+    return int(lib().msz_tile_variants(int(ndim)))
+
+
+def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: bool = True,
+        workspace=None, tile: int = 0, edits_out=None, g_out=None, timing: bool = False,
+        stream=None):
+    """Runs the correction loop on the GPU.
+
+    Returns ``(status, delta, g, stats)``: ``delta`` with fl(fhat + delta) == g,
+    ``g`` the edited field (None unless ``want_g``), ``stats`` a dict (with a
+    per-kernel ``"timing"`` entry when ``timing`` is set).
+    """
+    import torch
+    _check_field(f, "f")
+    _check_field(fhat, "fhat")
+    if f.shape != fhat.shape:
+        raise ValueError("f and fhat differ in shape")
+    d = dims_of(f.shape)
+    edits = edits_out if edits_out is not None else torch.empty_like(f)
+    g = g_out if g_out is not None else (torch.empty_like(f) if want_g else None)
+    opt = Options()
+    opt.max_rounds = int(max_rounds)
+    if warm_start is not None:
+        _check_field(warm_start, "warm_start")
+        opt.warm_start = warm_start.data_ptr()
+    opt.g_out = g.data_ptr() if g is not None else None
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    opt.tile_override = int(tile)
+    opt.flags = FLAG_TIMING if timing else 0
+    st = Stats()
+    rc = lib().msz_fix(f.data_ptr(), fhat.data_ptr(), d, float(xi), edits.data_ptr(),
+                       ctypes.byref(opt), ctypes.byref(st), _stream(stream))
+    out = st.as_dict()
+    if timing:
+        out["timing"] = st.timing()
+    return int(rc), edits, g, out
+
+
+def labels(field, stream=None):
+    """(max_label, min_label) int32 tensors of extremum vertex ids."""
+    import torch
+    _check_field(field, "field")
+    M = torch.empty(field.shape, dtype=torch.int32, device=field.device)
+    m = torch.empty_like(M)
+    rc = lib().msz_labels(field.data_ptr(), dims_of(field.shape), M.data_ptr(), m.data_ptr(),
+                          _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_labels")
+    return M, m
+
+
+def count_false(f, g, stream=None) -> dict:
+    _check_field(f, "f")
+    _check_field(g, "g")
+    c = FalseCounts()
+    rc = lib().msz_count_false(f.data_ptr(), g.data_ptr(), dims_of(f.shape), ctypes.byref(c),
+                               _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_count_false")
+    return {k: int(getattr(c, k)) for k, _ in FalseCounts._fields_}
+
+
+def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, stream=None):
+    """Corrects a list of (f, fhat, xi) together.
+
+    Returns ``(status, [(status_j, delta_j, g_j, stats_j), ...])``.
+    """
+    import torch
+    n = len(fields)
+    jobs = (Job * n)()
+    stats = [Stats() for _ in range(n)]
+    outs = []
+    for j, (f, fh, xi) in enumerate(fields):
+        _check_field(f, f"f[{j}]")
+        _check_field(fh, f"fhat[{j}]")
+        e = torch.empty_like(f)
+        g = torch.empty_like(f) if want_g else None
+        jobs[j].f, jobs[j].fhat = f.data_ptr(), fh.data_ptr()
+        jobs[j].d = dims_of(f.shape)
+        jobs[j].xi = float(xi)
+        jobs[j].edits_out = e.data_ptr()
+        jobs[j].g_out = g.data_ptr() if g is not None else None
+        jobs[j].stats = ctypes.pointer(stats[j])
+        outs.append((e, g))
+    opt = Options()
+    opt.max_rounds = int(max_rounds)
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    rc = lib().msz_fix_batch(jobs, n, ctypes.byref(opt), _stream(stream))
+    res = [(stats[j].status, outs[j][0], outs[j][1], stats[j].as_dict()) for j in range(n)]
+    return int(rc), res
+
+
+def batch_workspace_bytes(shapes) -> int:
+    n = len(shapes)
+    jobs = (Job * n)()
+    for j, s in enumerate(shapes):
+        jobs[j].d = dims_of(s)
+    return int(lib().msz_batch_workspace_bytes(jobs, n))

