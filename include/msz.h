@@ -17,8 +17,11 @@
  *  - Order (Sec. 4, simulation of simplicity): vertex a is above b iff
  *    h_a > h_b, or h_a == h_b and a > b.  -0 and +0 compare equal.
  *  - Arrays: float32 / int32, DEVICE pointers, owned by the caller, at least
- *    n = nx*ny*nz elements.  Host structs (stats, counts) are filled before
- *    the call returns.
+ *    n = nx*ny*nz elements.  The arrays of msz_fix / msz_fix_batch (f, fhat,
+ *    edits_out, warm_start, g_out, workspace) and the label arrays of
+ *    msz_labels must be 16-byte aligned (every hipMalloc / torch allocation
+ *    is); MSZ_EINVAL otherwise.  Host structs (stats, counts) are filled
+ *    before the call returns.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  *    stream).  All work is enqueued on it; each call synchronises on it
  *    before returning (the loop makes host decisions between rounds).

@@ -46,9 +46,12 @@ bool make_grid(const msz_dims& d, Grid& gr) {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// The kernels move four vertices per dwordx4 access.
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, Mf, mf, qu, qd, list, cnt, total;
+    size_t L, g, dirs_f, dirs_g, marks, Mf, mf, qu, qd, cnt, total;
 };
 
 Layout layout_for(int64_t n) {
@@ -59,17 +62,16 @@ Layout layout_for(int64_t n) {
         o += align256(bytes);
         return r;
     };
-    l.cnt = take(kCntSlots * sizeof(unsigned));
+    l.cnt = take(kCntBlockWords * sizeof(unsigned));
     l.L = take(n * 4);
     l.g = take(n * 4);
     l.dirs_f = take(n);
     l.dirs_g = take(n);
-    l.marks = take((n + 3) & ~int64_t(3));
+    l.marks = take((n + 15) & ~int64_t(15));
     l.Mf = take(n * 4);
     l.mf = take(n * 4);
     l.qu = take(n * 4);
     l.qd = take(n * 4);
-    l.list = take(n * 4);
     l.total = o;
     return l;
 }
@@ -145,7 +147,7 @@ struct Field {
     float *edits, *g_out;
     float *L, *g;
     uint8_t *dirs_f, *dirs_g, *marks;
-    int *Mf, *mf, *qu, *qd, *list;
+    int *Mf, *mf, *qu, *qd;
     unsigned* cnt;
 };
 
@@ -160,30 +162,39 @@ void bind(Field& F, char* ws, const Layout& l) {
     F.mf = reinterpret_cast<int*>(ws + l.mf);
     F.qu = reinterpret_cast<int*>(ws + l.qu);
     F.qd = reinterpret_cast<int*>(ws + l.qd);
-    F.list = reinterpret_cast<int*>(ws + l.list);
 }
 
-// Pinned host copy of the counter block, one per host thread.
+// Pinned host copy of the counter block (all slots, then the summed counters
+// in the last kCntSlots words), one per host thread.
 unsigned* host_counters() {
     thread_local unsigned* p = nullptr;
     if (!p) {
         void* q = nullptr;
-        if (hipHostMalloc(&q, kCntSlots * sizeof(unsigned), hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc(&q, (kCntBlockWords + kCntSlots) * sizeof(unsigned), hipHostMallocDefault) !=
+            hipSuccess)
+            return nullptr;
         p = static_cast<unsigned*>(q);
     }
-    return p;
+    return p + kCntBlockWords;  // the summed view; the raw slots precede it
 }
 
+// Copies the counter slots back, waits, and sums them into host[0..kCntSlots).
 int read_counters(const unsigned* dev, unsigned* host, hipStream_t s, Timing* tm = nullptr) {
+    unsigned* raw = host - kCntBlockWords;
     MSZ_HIP(hipGetLastError());
-    MSZ_HIP(hipMemcpyAsync(host, dev, kCntSlots * sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    MSZ_HIP(hipMemcpyAsync(raw, dev, kCntBlockWords * sizeof(unsigned), hipMemcpyDeviceToHost, s));
     MSZ_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < kCntSlots; ++k) host[k] = 0;
+    for (int b = 0; b < kSlots; ++b) {
+        const unsigned* slot = raw + b * kSlotStride;
+        for (int k = 0; k < kCntSlots; ++k) host[k] = k == kCntErr ? (host[k] | slot[k]) : host[k] + slot[k];
+    }
     if (tm) tm->collect();
     return MSZ_OK;
 }
 
 int clear_counters(unsigned* dev, hipStream_t s) {
-    MSZ_HIP(hipMemsetAsync(dev, 0, kCntSlots * sizeof(unsigned), s));
+    MSZ_HIP(hipMemsetAsync(dev, 0, kCntBlockWords * sizeof(unsigned), s));
     return MSZ_OK;
 }
 
@@ -215,7 +226,7 @@ struct Scratch {
 int precompute(Field& F, unsigned* hc, hipStream_t s) {
     const int n = F.gr.n;
     if (clear_counters(F.cnt, s)) return MSZ_EDEVICE;
-    MSZ_HIP(hipMemsetAsync(F.marks, 0, (n + 3) & ~3, s));
+    MSZ_HIP(hipMemsetAsync(F.marks, 0, (n + 15) & ~15, s));
     TIMED(F, MSZ_PHASE_VALIDATE, s, launch_validate_init(F.f, F.fhat, F.warm, F.xi, n, F.L, F.g, F.cnt, s));
     TIMED(F, MSZ_PHASE_DIRS, s, launch_dirs(F.f, F.gr, F.variant, F.dirs_f, s));
     TIMED(F, MSZ_PHASE_LABEL_TILE, s, launch_label_tile(F.dirs_f, F.gr, F.qu, F.qd, s));
@@ -247,7 +258,7 @@ int run_loop(Field& F, int64_t cap, msz_stats* st, unsigned* hc, hipStream_t s) 
     int type = 0;
     if (begin()) return MSZ_EDEVICE;
     TIMED(F, MSZ_PHASE_DIRS_DETECT, s,
-          launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.list, F.cnt, s));
+          launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.cnt, s));
     if (int rc = step_read()) return rc;
     for (int t = 0; t < 4; ++t) st->false_init[t] = c[kCntCase + t];
 
@@ -260,9 +271,9 @@ int run_loop(Field& F, int64_t cap, msz_stats* st, unsigned* hc, hipStream_t s) 
                 if (rounds >= cap) return MSZ_ENOCONV;
                 if (begin()) return MSZ_EDEVICE;
                 TIMED(F, MSZ_PHASE_APPLY, s,
-                      launch_apply(F.list, static_cast<int>(c[kCntList]), F.g, F.L, F.marks, F.cnt, s));
+                      launch_apply(F.g, F.L, F.marks, gr.n, F.cnt, s));
                 TIMED(F, MSZ_PHASE_DIRS_DETECT, s,
-                      launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.list, F.cnt, s));
+                      launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.cnt, s));
                 if (int rc = step_read()) return rc;
                 if (c[kCntChanged] == 0) return MSZ_ESTALL;
                 ++rounds;
@@ -279,7 +290,7 @@ int run_loop(Field& F, int64_t cap, msz_stats* st, unsigned* hc, hipStream_t s) 
             if (in_c) {
                 if (begin()) return MSZ_EDEVICE;
                 TIMED(F, MSZ_PHASE_DETECT, s,
-                      launch_detect_only(F.dirs_f, F.dirs_g, gr, type, F.marks, F.list, F.cnt, s));
+                      launch_detect_only(F.dirs_f, F.dirs_g, gr, type, F.marks, F.cnt, s));
                 if (int rc = step_read()) return rc;
                 continue;
             }
@@ -289,17 +300,17 @@ int run_loop(Field& F, int64_t cap, msz_stats* st, unsigned* hc, hipStream_t s) 
         TIMED(F, MSZ_PHASE_LABEL_TILE, s, launch_label_tile(F.dirs_g, gr, F.qu, F.qd, s));
         TIMED(F, MSZ_PHASE_LABEL_JUMP, s, launch_label_compress(gr, F.qu, F.qd, F.cnt, s));
         TIMED(F, MSZ_PHASE_DETECT_R, s,
-              launch_detect_r(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, F.marks, F.list, F.cnt, s));
+              launch_detect_r(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, F.marks, F.cnt, s));
         if (int rc = step_read()) return rc;
         if (c[kCntErr] & kErrWalk) return MSZ_EDEVICE;
         if (c[kCntWrong] == 0) return MSZ_OK;
         if (rounds >= cap) return MSZ_ENOCONV;
         if (begin()) return MSZ_EDEVICE;
         TIMED(F, MSZ_PHASE_APPLY, s,
-              launch_apply(F.list, static_cast<int>(c[kCntList]), F.g, F.L, F.marks, F.cnt, s));
+              launch_apply(F.g, F.L, F.marks, gr.n, F.cnt, s));
         type = 0;
         TIMED(F, MSZ_PHASE_DIRS_DETECT, s,
-              launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.list, F.cnt, s));
+              launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.cnt, s));
         if (int rc = step_read()) return rc;
         if (c[kCntChanged] == 0) return MSZ_ESTALL;
         ++rounds;
@@ -384,6 +395,9 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     if (!make_grid(d, gr) || !f || !fhat || !edits_out) return done(MSZ_EINVAL);
     msz_options o{};
     if (opt) o = *opt;
+    if (!aligned16(f) || !aligned16(fhat) || !aligned16(edits_out) || !aligned16(o.warm_start) ||
+        !aligned16(o.g_out) || !aligned16(o.workspace))
+        return done(MSZ_EINVAL);
     if ((o.flags & ~MSZ_FLAG_TIMING) != 0 || o.tile_override < 0 ||
         o.tile_override > tile_variant_count(d.ndim))
         return done(MSZ_EINVAL);
@@ -454,14 +468,15 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
 int msz_labels(const float* field, msz_dims d, int32_t* max_label, int32_t* min_label, void* stream) {
     Grid gr;
     if (!make_grid(d, gr) || !field || !max_label || !min_label) return MSZ_EINVAL;
+    if (!aligned16(max_label) || !aligned16(min_label)) return MSZ_EINVAL;
     unsigned* hc = host_counters();
     if (!hc) return MSZ_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t need = align256(kCntSlots * sizeof(unsigned)) + align256(gr.n);
+    const size_t need = align256(kCntBlockWords * sizeof(unsigned)) + align256(gr.n);
     Scratch ws;
     if (int rc = ws.get(nullptr, 0, need, s)) return rc;
     unsigned* cnt = static_cast<unsigned*>(ws.p);
-    uint8_t* dirs = static_cast<uint8_t*>(ws.p) + align256(kCntSlots * sizeof(unsigned));
+    uint8_t* dirs = static_cast<uint8_t*>(ws.p) + align256(kCntBlockWords * sizeof(unsigned));
     if (clear_counters(cnt, s)) return MSZ_EDEVICE;
     launch_check_finite(field, gr.n, cnt, s);
     launch_dirs(field, gr, 0, dirs, s);
@@ -479,7 +494,7 @@ int msz_count_false(const float* f, const float* g, msz_dims d, msz_false_counts
     unsigned* hc = host_counters();
     if (!hc) return MSZ_EDEVICE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const size_t c0 = align256(kCntSlots * sizeof(unsigned));
+    const size_t c0 = align256(kCntBlockWords * sizeof(unsigned));
     const size_t nb = align256(gr.n), ni = align256(size_t(gr.n) * 4);
     Scratch ws;
     if (int rc = ws.get(nullptr, 0, c0 + 2 * nb + 4 * ni, s)) return rc;

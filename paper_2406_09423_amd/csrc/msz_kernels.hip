@@ -3,10 +3,11 @@
 // Data layout in HBM (one field of n vertices, x fastest):
 //   h / g / L      float32[n]
 //   dirs           uint8[n]   high nibble = ascent slot, low nibble = descent slot, 0xF = self
-//   marks          uint8[n]   1 = "halve this vertex in the pending round" (padded to 4 B)
+//   marks          uint8[n]   1 = "halve this vertex in the pending round" (padded to 16 B)
 //   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests
-//   list           int32[n]   compacted, duplicate-free edit targets of one round
-//   cnt            uint32[64] round counters read back by the host
+//   cnt            uint32[kSlots][kSlotStride] round counters, read back and summed by
+//                  the host; block b adds into slot b % kSlots so that no cache line
+//                  takes more than a few hundred atomics per launch
 //
 // Neighbour slots (Sec. 3 PL mesh; 2D uses slots 0..5, 3D all 14):
 //   0 (+1,0,0)  1 (-1,0,0)  2 (0,+1,0)  3 (0,-1,0)  4 (+1,+1,0)  5 (-1,-1,0)
@@ -41,31 +42,13 @@ __device__ __forceinline__ void block_add(unsigned (&v)[K], unsigned* dst, const
     if (threadIdx.x < K) {
         unsigned s = 0;
         for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
-        if (s) atomicAdd(dst + idx[threadIdx.x], s);
+        if (s) atomicAdd(dst + (blockIdx.x & (kSlots - 1)) * kSlotStride + idx[threadIdx.x], s);
     }
 }
 
-// Claims vertex t for the pending round; true for exactly one caller per round.
-__device__ __forceinline__ bool claim_mark(uint8_t* marks, int t) {
-    unsigned* w = reinterpret_cast<unsigned*>(marks + (t & ~3));
-    const unsigned bit = 1u << ((t & 3) * 8);
-    return (atomicOr(w, bit) & bit) == 0;
-}
-
-// Appends the claimed targets of a wave to the round's list with one atomic per wave.
-__device__ __forceinline__ void push_targets(bool claimed, int t, int* list, unsigned* len) {
-    const unsigned long long m = __ballot(claimed);
-    if (m == 0ull) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll(static_cast<long long>(m)) - 1;
-    unsigned base = 0;
-    if (lane == leader) base = atomicAdd(len, static_cast<unsigned>(__popcll(m)));
-    base = __shfl(base, leader);
-    if (claimed) {
-        const unsigned rank = __popcll(m & ((1ull << lane) - 1ull));
-        list[base + rank] = t;
-    }
-}
+// Proposals of one round form a set: every proposer of target t stores the
+// same byte, so plain (idempotent) byte stores need no atomics.
+__device__ __forceinline__ void mark(uint8_t* marks, int t) { marks[t] = 1; }
 
 // One decreasing edit (Eqs. 2-6): halfway to the floor, snapped to it when
 // float32 rounding would leave the value unchanged.
@@ -127,6 +110,25 @@ __device__ __forceinline__ bool value_ok(float v) {
 // ------------------------------------------------------ validate and init ---
 
 // Checks the input contract, computes the floor L and the start field g.
+// Four vertices per thread with dwordx4 accesses (arrays are 16-byte aligned);
+// the last n % 4 vertices are handled one by one.
+__device__ __forceinline__ void validate_one(float fi, float hi, const float* warm, int i, float xi,
+                                             float& li, float& gi, unsigned& bad) {
+    li = 0.0f;
+    gi = hi;
+    if (!value_ok(fi) || !value_ok(hi)) {
+        bad |= kErrNonFinite;
+        return;
+    }
+    if (!diff_at_most(fi, hi, xi) || !diff_at_least(fi, hi, -xi)) bad |= kErrBound;
+    li = floor_bound(fi, xi);
+    if (warm) {
+        gi = warm[i];
+        if (!value_ok(gi)) bad |= kErrWarmNonFinite;
+        else if (!(gi >= li && gi <= hi)) bad |= kErrWarmBound;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_validate_init(const float* __restrict__ f,
                                                        const float* __restrict__ fhat,
                                                        const float* __restrict__ warm, float xi,
@@ -134,21 +136,21 @@ __global__ void __launch_bounds__(256) k_validate_init(const float* __restrict__
                                                        float* __restrict__ g,
                                                        unsigned* __restrict__ cnt) {
     unsigned bad = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float fi = f[i], hi = fhat[i];
-        if (!value_ok(fi) || !value_ok(hi)) {
-            bad |= kErrNonFinite;
-            continue;
-        }
-        if (!diff_at_most(fi, hi, xi) || !diff_at_least(fi, hi, -xi)) bad |= kErrBound;
-        const float li = floor_bound(fi, xi);
+    const int ng = n >> 2;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
+        const float4 f4 = reinterpret_cast<const float4*>(f)[w];
+        const float4 h4 = reinterpret_cast<const float4*>(fhat)[w];
+        const float fv[4] = {f4.x, f4.y, f4.z, f4.w}, hv[4] = {h4.x, h4.y, h4.z, h4.w};
+        float lv[4], gv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) validate_one(fv[j], hv[j], warm, 4 * w + j, xi, lv[j], gv[j], bad);
+        reinterpret_cast<float4*>(L)[w] = make_float4(lv[0], lv[1], lv[2], lv[3]);
+        reinterpret_cast<float4*>(g)[w] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+    }
+    for (int i = 4 * ng + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float li, gi;
+        validate_one(f[i], fhat[i], warm, i, xi, li, gi, bad);
         L[i] = li;
-        float gi = hi;
-        if (warm) {
-            gi = warm[i];
-            if (!value_ok(gi)) bad |= kErrWarmNonFinite;
-            else if (!(gi >= li && gi <= hi)) bad |= kErrWarmBound;
-        }
         g[i] = gi;
     }
     if (bad) atomicOr(cnt + kCntErr, bad);
@@ -184,19 +186,16 @@ __device__ __forceinline__ unsigned c_cases(unsigned df, unsigned dg, int i, int
     return c0 | (c1 << 1) | (c2 << 2) | (c3 << 3);
 }
 
-// Counts every C type, marks and lists the targets of `type`.
+// Counts every C type and marks the targets of `type`.
 __device__ __forceinline__ void detect_vertex(bool valid, unsigned df, unsigned dg, int i, int type,
-                                              const Grid& gr, uint8_t* marks, int* list,
-                                              unsigned* cnt, unsigned (&c)[4]) {
+                                              const Grid& gr, uint8_t* marks, unsigned (&c)[4]) {
     int t = 0;
     const unsigned bits = valid ? c_cases(df, dg, i, type, gr, t) : 0u;
     c[0] += bits & 1u;
     c[1] += (bits >> 1) & 1u;
     c[2] += (bits >> 2) & 1u;
     c[3] += (bits >> 3) & 1u;
-    const bool hit = (bits >> type) & 1u;
-    const bool claimed = hit && claim_mark(marks, t);
-    push_targets(claimed, t, list, cnt + kCntList);
+    if ((bits >> type) & 1u) mark(marks, t);
 }
 
 // --------------------------------------------------- steepest directions ---
@@ -258,7 +257,7 @@ template <int NDIM, int TY, int ZC, int MODE>
 __global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, Grid gr,
                                                   uint8_t* __restrict__ dirs_out,
                                                   const uint8_t* __restrict__ dirs_f, int type,
-                                                  uint8_t* __restrict__ marks, int* __restrict__ list,
+                                                  uint8_t* __restrict__ marks,
                                                   unsigned* __restrict__ cnt) {
     constexpr int W = kTileX + 2, H = TY + 2, P = W * H;
     constexpr int NP = NDIM == 3 ? 3 : 1;
@@ -275,6 +274,8 @@ __global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, G
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int y = y0 + ty;
     const int z0 = NDIM == 3 ? bz * ZC : 0;
+    // rows start at multiples of 4 vertices: packed direction bytes move as dwords
+    const bool vec4 = (gr.nx & 3) == 0;
 
     unsigned c[4] = {0u, 0u, 0u, 0u};
 
@@ -299,13 +300,28 @@ __global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, G
         const float* A = sm + above * P;
         const float* B = sm + below * P;
         const int r = ty + 1;
+        // the thread's four vertices: one dword of directions when rows are 4-aligned
+        const int xa = x0 + tx * 4;
+        const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
+        const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
+        unsigned df4 = 0xFFFFFFFFu;
+        if constexpr (MODE == 1) {
+            if (full) {
+                df4 = *reinterpret_cast<const unsigned*>(dirs_f + i0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (xa + k < gr.nx && y < gr.ny)
+                        df4 = (df4 & ~(0xFFu << (8 * k))) | (static_cast<unsigned>(dirs_f[i0 + k]) << (8 * k));
+            }
+        }
+        unsigned out4 = 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int x = x0 + tx * 4 + k;
+            const int x = xa + k;
             const int cc = tx * 4 + k + 1;
             const bool valid = x < gr.nx && y < gr.ny;
-            const long ii = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + x;
-            const int i = static_cast<int>(ii);
+            const int i = static_cast<int>(i0) + k;
             unsigned packed = 0xFFu;
             if (valid) {
                 const float v = C[r * W + cc];
@@ -327,13 +343,12 @@ __global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, G
                     consider(b, B[(r - 1) * W + cc - 1], gr.off[13], 13);
                 }
                 packed = (b.us << 4) | b.ds;
-                dirs_out[ii] = static_cast<uint8_t>(packed);
+                out4 = (out4 & ~(0xFFu << (8 * k))) | (packed << (8 * k));
+                if (!full) dirs_out[i0 + k] = static_cast<uint8_t>(packed);
             }
-            if constexpr (MODE == 1) {
-                const unsigned df = valid ? dirs_f[ii] : 0xFFu;
-                detect_vertex(valid, df, packed, i, type, gr, marks, list, cnt, c);
-            }
+            if constexpr (MODE == 1) detect_vertex(valid, (df4 >> (8 * k)) & 0xFFu, packed, i, type, gr, marks, c);
         }
+        if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
         __syncthreads();  // the oldest plane is overwritten next
         if constexpr (NDIM == 3) {
             const int t = below;
@@ -349,22 +364,25 @@ __global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, G
 }
 
 // Detection from stored directions (g unchanged since they were computed).
+// Four vertices per thread: one dword of each direction array.
 __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__ dirs_f,
                                                      const uint8_t* __restrict__ dirs_g, Grid gr,
                                                      int type, uint8_t* __restrict__ marks,
-                                                     int* __restrict__ list,
                                                      unsigned* __restrict__ cnt) {
     unsigned c[4] = {0u, 0u, 0u, 0u};
     const int n = gr.n;
-    const int stride = gridDim.x * blockDim.x;
-    // loop bound is uniform across each wave so the ballots stay convergent
-    const int iters = (n + stride - 1) / stride;
-    for (int it = 0; it < iters; ++it) {
-        const int i = it * stride + blockIdx.x * blockDim.x + threadIdx.x;
-        const bool valid = i < n;
-        const unsigned df = valid ? dirs_f[i] : 0xFFu;
-        const unsigned dg = valid ? dirs_g[i] : 0xFFu;
-        detect_vertex(valid, df, dg, i, type, gr, marks, list, cnt, c);
+    const int ng = (n + 3) >> 2;
+    // the direction arrays live in 256-byte padded workspace segments, so the
+    // last partial dword can be read whole; lanes past n are masked
+    const unsigned* wf = reinterpret_cast<const unsigned*>(dirs_f);
+    const unsigned* wg = reinterpret_cast<const unsigned*>(dirs_g);
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
+        const unsigned df4 = wf[w], dg4 = wg[w];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * w + j;
+            detect_vertex(i < n, (df4 >> (8 * j)) & 0xFFu, (dg4 >> (8 * j)) & 0xFFu, i, type, gr, marks, c);
+        }
     }
     const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
     block_add<4>(c, cnt, idx);
@@ -372,19 +390,33 @@ __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__
 
 // ---------------------------------------------------------------- apply ---
 
-// Halves every listed target once (the round's union of proposals) and clears its mark.
-__global__ void __launch_bounds__(256) k_apply(const int* __restrict__ list, int len,
-                                               float* __restrict__ g, const float* __restrict__ L,
-                                               uint8_t* __restrict__ marks,
+// Halves every marked vertex once (the round's union of proposals) and clears
+// its mark.  Marks are scanned 16 at a time; the padding bytes are never set.
+__global__ void __launch_bounds__(256) k_apply(float* __restrict__ g, const float* __restrict__ L,
+                                               uint8_t* __restrict__ marks, int n,
                                                unsigned* __restrict__ cnt) {
     unsigned changed = 0;
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < len; k += gridDim.x * blockDim.x) {
-        const int t = list[k];
-        const float old = g[t];
-        const float nv = halve(old, L[t]);
-        g[t] = nv;
-        marks[t] = 0;
-        changed += nv != old;
+    const int nw = (n + 15) >> 4;
+    uint4* mw = reinterpret_cast<uint4*>(marks);
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
+        const uint4 m = mw[w];
+        if ((m.x | m.y | m.z | m.w) == 0u) continue;
+        const unsigned part[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!part[q]) continue;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                if ((part[q] >> (8 * b)) & 0xFFu) {
+                    const int t = w * 16 + q * 4 + b;
+                    const float old = g[t];
+                    const float nv = halve(old, L[t]);
+                    g[t] = nv;
+                    changed += nv != old;
+                }
+            }
+        }
+        mw[w] = make_uint4(0u, 0u, 0u, 0u);
     }
     unsigned v[1] = {changed};
     const int idx[1] = {kCntChanged};
@@ -440,63 +472,100 @@ __global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ 
     const int bx = lb % tx_n, by = (lb / tx_n) % ty_n, bz = lb / (tx_n * ty_n);
     const int X0 = bx * T::X, Y0 = by * T::Y, Z0 = bz * T::Z;
 
-    // terminal pointers are stored as -(global id) - 1
+    // Thread t owns the 4-vertex row groups starting at l = 4 t + 1024 k.
+    // Terminal pointers are stored as -(global id) - 1.
+    const bool vec4 = (gr.nx & 3) == 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int l = threadIdx.x + k * 256;
-        const int lx = l % T::X, ly = (l / T::X) % T::Y, lz = l / (T::X * T::Y);
-        const int x = X0 + lx, y = Y0 + ly, z = Z0 + lz;
-        int pu = -1, pd = -1;
-        if (x < gr.nx && y < gr.ny && z < gr.nz) {
-            const int i = x + gr.nx * y + gr.nxy * z;
-            const unsigned d = dirs[i];
-            const unsigned s2[2] = {d >> 4, d & 15u};
-            int p[2];
+    for (int k = 0; k < PER / 4; ++k) {
+        const int l0 = 4 * threadIdx.x + 1024 * k;
+        const int lx0 = l0 % T::X, ly = (l0 / T::X) % T::Y, lz = l0 / (T::X * T::Y);
+        const int xa = X0 + lx0, y = Y0 + ly, z = Z0 + lz;
+        const bool row_in = y < gr.ny && z < gr.nz;
+        const int i0 = xa + gr.nx * y + gr.nxy * z;
+        unsigned d4 = 0xFFFFFFFFu;
+        if (row_in && vec4 && xa + 3 < gr.nx) {
+            d4 = *reinterpret_cast<const unsigned*>(dirs + i0);
+        } else if (row_in) {
 #pragma unroll
-            for (int w = 0; w < 2; ++w) {
-                const unsigned s = s2[w];
-                if (s == kSelf) {
-                    p[w] = -i - 1;
-                } else {
-                    int dx, dy, dz;
-                    slot_delta(s, dx, dy, dz);
-                    const int ax = lx + dx, ay = ly + dy, az = lz + dz;
-                    if (ax >= 0 && ax < T::X && ay >= 0 && ay < T::Y && az >= 0 && az < T::Z)
-                        p[w] = ax + T::X * (ay + T::Y * az);
-                    else
-                        p[w] = -(i + gr.off[s]) - 1;
-                }
-            }
-            pu = p[0];
-            pd = p[1];
+            for (int j = 0; j < 4; ++j)
+                if (xa + j < gr.nx) d4 = (d4 & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs[i0 + j]) << (8 * j));
         }
-        su[l] = pu;
-        sd[l] = pd;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int l = l0 + j, lx = lx0 + j;
+            int pu = -1, pd = -1;
+            if (row_in && xa + j < gr.nx) {
+                const int i = i0 + j;
+                const unsigned d = (d4 >> (8 * j)) & 0xFFu;
+                const unsigned s2[2] = {d >> 4, d & 15u};
+                int p[2];
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const unsigned s = s2[w];
+                    if (s == kSelf) {
+                        p[w] = -i - 1;
+                    } else {
+                        int dx, dy, dz;
+                        slot_delta(s, dx, dy, dz);
+                        const int ax = lx + dx, ay = ly + dy, az = lz + dz;
+                        if (ax >= 0 && ax < T::X && ay >= 0 && ay < T::Y && az >= 0 && az < T::Z)
+                            p[w] = ax + T::X * (ay + T::Y * az);
+                        else
+                            p[w] = -(i + gr.off[s]) - 1;
+                    }
+                }
+                pu = p[0];
+                pd = p[1];
+            }
+            su[l] = pu;
+            sd[l] = pd;
+        }
     }
     __syncthreads();
+    // doubling passes; stop early once every pointer of the tile is terminal
     for (int pass = 0; pass < PASSES; ++pass) {
+        int pending = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int l = threadIdx.x + k * 256;
+            const int l = 4 * threadIdx.x + 1024 * (k >> 2) + (k & 3);
             const int a = su[l];
-            if (a >= 0) su[l] = su[a];
+            if (a >= 0) {
+                const int a2 = su[a];
+                su[l] = a2;
+                pending |= a2 >= 0;
+            }
             const int b = sd[l];
-            if (b >= 0) sd[l] = sd[b];
+            if (b >= 0) {
+                const int b2 = sd[b];
+                sd[l] = b2;
+                pending |= b2 >= 0;
+            }
         }
-        __syncthreads();
+        if (!__syncthreads_or(pending)) break;
     }
+    // Every in-tile path is shorter than the tile, so all pointers are terminal
+    // here; a non-terminal one would still name an in-grid ancestor.
+    auto global_of = [&](int a) {
+        return a < 0 ? -a - 1
+                     : X0 + a % T::X + gr.nx * (Y0 + (a / T::X) % T::Y) + gr.nxy * (Z0 + a / (T::X * T::Y));
+    };
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int l = threadIdx.x + k * 256;
-        const int lx = l % T::X, ly = (l / T::X) % T::Y, lz = l / (T::X * T::Y);
-        const int x = X0 + lx, y = Y0 + ly, z = Z0 + lz;
-        if (x < gr.nx && y < gr.ny && z < gr.nz) {
-            const int i = x + gr.nx * y + gr.nxy * z;
-            // every in-tile path is shorter than the tile, so all pointers are terminal
-            // here; a non-terminal one would still name an in-grid ancestor
-            const int a = su[l], b = sd[l];
-            q_up[i] = a < 0 ? -a - 1 : X0 + a % T::X + gr.nx * (Y0 + (a / T::X) % T::Y) + gr.nxy * (Z0 + a / (T::X * T::Y));
-            q_dn[i] = b < 0 ? -b - 1 : X0 + b % T::X + gr.nx * (Y0 + (b / T::X) % T::Y) + gr.nxy * (Z0 + b / (T::X * T::Y));
+    for (int k = 0; k < PER / 4; ++k) {
+        const int l0 = 4 * threadIdx.x + 1024 * k;
+        const int lx0 = l0 % T::X, ly = (l0 / T::X) % T::Y, lz = l0 / (T::X * T::Y);
+        const int xa = X0 + lx0, y = Y0 + ly, z = Z0 + lz;
+        if (y >= gr.ny || z >= gr.nz) continue;
+        const int i0 = xa + gr.nx * y + gr.nxy * z;
+        if (vec4 && xa + 3 < gr.nx) {
+            *reinterpret_cast<int4*>(q_up + i0) =
+                make_int4(global_of(su[l0]), global_of(su[l0 + 1]), global_of(su[l0 + 2]), global_of(su[l0 + 3]));
+            *reinterpret_cast<int4*>(q_dn + i0) =
+                make_int4(global_of(sd[l0]), global_of(sd[l0 + 1]), global_of(sd[l0 + 2]), global_of(sd[l0 + 3]));
+        } else {
+            for (int j = 0; j < 4 && xa + j < gr.nx; ++j) {
+                q_up[i0 + j] = global_of(su[l0 + j]);
+                q_dn[i0 + j] = global_of(sd[l0 + j]);
+            }
         }
     }
 }
@@ -593,11 +662,20 @@ __global__ void __launch_bounds__(256) k_label_compress(Grid gr, int* __restrict
     }
 }
 
-// Writes the final labels label(i) = q[q[i]].
-// May run in place (M == q_up, m == q_dn): the values it reads are fixed points.
+// Writes the final labels label(i) = q[q[i]].  May run in place (M == q_up,
+// m == q_dn): the values it reads are fixed points.  Arrays are 16-byte aligned.
 __global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int* q_dn, int n, int* M,
                                                      int* m) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int ng = n >> 2;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
+        const int4 a = reinterpret_cast<const int4*>(q_up)[w];
+        const int4 b = reinterpret_cast<const int4*>(q_dn)[w];
+        const int4 ra = make_int4(q_up[a.x], q_up[a.y], q_up[a.z], q_up[a.w]);
+        const int4 rb = make_int4(q_dn[b.x], q_dn[b.y], q_dn[b.z], q_dn[b.w]);
+        reinterpret_cast<int4*>(M)[w] = ra;
+        reinterpret_cast<int4*>(m)[w] = rb;
+    }
+    for (int i = 4 * ng + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         M[i] = q_up[q_up[i]];
         m[i] = q_dn[q_dn[i]];
     }
@@ -605,11 +683,7 @@ __global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int*
 
 // ------------------------------------------------------- R-loop detection ---
 //
-// A vertex u is a troublemaker when its steepest step in g leaves the one in
-// f while its label is wrong (Sec. 5.2); the first divergence on the integral
-// line of any mislabelled vertex is such a vertex, and every such vertex is
-// its own first divergence.  Wrong minimum: lower dn_f(u); wrong maximum:
-// lower up_g(u) (Eq. 6 under value-lowering edits).
+// Four vertices per thread (dword / dwordx4 accesses of the padded workspace arrays).
 __global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ dirs_f,
                                                   const uint8_t* __restrict__ dirs_g,
                                                   const int* __restrict__ q_up,
@@ -617,31 +691,33 @@ __global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ di
                                                   const int* __restrict__ Mf,
                                                   const int* __restrict__ mf, Grid gr,
                                                   uint8_t* __restrict__ marks,
-                                                  int* __restrict__ list,
                                                   unsigned* __restrict__ cnt) {
     unsigned wrong = 0, cases = 0;
     const int n = gr.n;
-    const int stride = gridDim.x * blockDim.x;
-    const int iters = (n + stride - 1) / stride;
-    for (int it = 0; it < iters; ++it) {
-        const int i = it * stride + blockIdx.x * blockDim.x + threadIdx.x;
-        bool rmin = false, rmax = false;
-        int tmin = 0, tmax = 0;
-        if (i < n) {
-            const unsigned df = dirs_f[i], dg = dirs_g[i];
-            const bool wM = q_up[q_up[i]] != Mf[i];
-            const bool wm = q_dn[q_dn[i]] != mf[i];
+    const int ng = (n + 3) >> 2;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
+        const unsigned df4 = reinterpret_cast<const unsigned*>(dirs_f)[w];
+        const unsigned dg4 = reinterpret_cast<const unsigned*>(dirs_g)[w];
+        const int4 qu4 = reinterpret_cast<const int4*>(q_up)[w];
+        const int4 qd4 = reinterpret_cast<const int4*>(q_dn)[w];
+        const int4 Mf4 = reinterpret_cast<const int4*>(Mf)[w];
+        const int4 mf4 = reinterpret_cast<const int4*>(mf)[w];
+        const int qu[4] = {qu4.x, qu4.y, qu4.z, qu4.w}, qd[4] = {qd4.x, qd4.y, qd4.z, qd4.w};
+        const int Mv[4] = {Mf4.x, Mf4.y, Mf4.z, Mf4.w}, mv[4] = {mf4.x, mf4.y, mf4.z, mf4.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * w + j;
+            if (i >= n) break;
+            const unsigned df = (df4 >> (8 * j)) & 0xFFu, dg = (dg4 >> (8 * j)) & 0xFFu;
+            const bool wM = q_up[qu[j]] != Mv[j];
+            const bool wm = q_dn[qd[j]] != mv[j];
             wrong += wM || wm;
-            rmin = wm && ((dg & 15u) != (df & 15u));
-            rmax = wM && ((dg >> 4) != (df >> 4));
-            tmin = i + gr.off[df & 15u];
-            tmax = i + gr.off[dg >> 4];
+            const bool rmin = wm && ((dg & 15u) != (df & 15u));
+            const bool rmax = wM && ((dg >> 4) != (df >> 4));
             cases += rmin + rmax;
+            if (rmin) mark(marks, i + gr.off[df & 15u]);
+            if (rmax) mark(marks, i + gr.off[dg >> 4]);
         }
-        const bool c1 = rmin && claim_mark(marks, tmin);
-        push_targets(c1, tmin, list, cnt + kCntList);
-        const bool c2 = rmax && claim_mark(marks, tmax);
-        push_targets(c2, tmax, list, cnt + kCntList);
     }
     unsigned v[2] = {wrong, cases};
     const int idx[2] = {kCntWrong, kCntRCases};
@@ -680,32 +756,47 @@ __global__ void __launch_bounds__(256) k_compare(const uint8_t* __restrict__ dir
 //
 // delta = fl(g - fhat); when fl(fhat + delta) misses g, the floats up to two
 // ulps either side are tried in the order +1, -1, +2, -2.
+__device__ __forceinline__ float delta_one(float gi, float hi, unsigned& edited, unsigned& inexact) {
+    const float d0 = __fsub_rn(gi, hi);
+    float d = d0;
+    bool ok = __fadd_rn(hi, d0) == gi;
+    if (!ok) {
+        const float up1 = f32_next_up(d0), dn1 = f32_next_down(d0);
+        const float cand[4] = {up1, dn1, f32_next_up(up1), f32_next_down(dn1)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!ok && __fadd_rn(hi, cand[k]) == gi) {
+                d = cand[k];
+                ok = true;
+            }
+        }
+    }
+    edited += gi != hi;
+    inexact += !ok;
+    return ok ? d : d0;
+}
+
 __global__ void __launch_bounds__(256) k_delta(const float* __restrict__ g,
                                                const float* __restrict__ fhat, int n,
                                                float* __restrict__ delta,
                                                float* __restrict__ g_out,
                                                unsigned* __restrict__ cnt) {
     unsigned edited = 0, inexact = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float gi = g[i], hi = fhat[i];
-        const float d0 = __fsub_rn(gi, hi);
-        float d = d0;
-        bool ok = __fadd_rn(hi, d0) == gi;
-        if (!ok) {
-            const float up1 = f32_next_up(d0), dn1 = f32_next_down(d0);
-            const float cand[4] = {up1, dn1, f32_next_up(up1), f32_next_down(dn1)};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (!ok && __fadd_rn(hi, cand[k]) == gi) {
-                    d = cand[k];
-                    ok = true;
-                }
-            }
-        }
-        delta[i] = ok ? d : d0;
+    const int ng = n >> 2;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
+        const float4 g4 = reinterpret_cast<const float4*>(g)[w];
+        const float4 h4 = reinterpret_cast<const float4*>(fhat)[w];
+        const float4 d4 = make_float4(delta_one(g4.x, h4.x, edited, inexact),
+                                      delta_one(g4.y, h4.y, edited, inexact),
+                                      delta_one(g4.z, h4.z, edited, inexact),
+                                      delta_one(g4.w, h4.w, edited, inexact));
+        reinterpret_cast<float4*>(delta)[w] = d4;
+        if (g_out) reinterpret_cast<float4*>(g_out)[w] = g4;
+    }
+    for (int i = 4 * ng + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        delta[i] = delta_one(gi, fhat[i], edited, inexact);
         if (g_out) g_out[i] = gi;
-        edited += gi != hi;
-        inexact += !ok;
     }
     unsigned v[2] = {edited, inexact};
     const int idx[2] = {kCntEdited, kCntInexact};
@@ -735,55 +826,53 @@ int tile_variant_count(int ndim) {
 
 template <int NDIM, int TY, int ZC, int MODE>
 static void launch_dirs_t(const float* h, const Grid& gr, uint8_t* dirs_out, const uint8_t* dirs_f,
-                          int type, uint8_t* marks, int* list, unsigned* cnt, hipStream_t s) {
+                          int type, uint8_t* marks, unsigned* cnt, hipStream_t s) {
     const int tx = (gr.nx + kTileX - 1) / kTileX;
     const int ty = (gr.ny + TY - 1) / TY;
     const int tz = NDIM == 3 ? (gr.nz + ZC - 1) / ZC : 1;
     const int nb = tx * ty * tz;
     hipLaunchKernelGGL((k_dirs<NDIM, TY, ZC, MODE>), dim3(nb), dim3(16 * TY), 0, s, h, gr, dirs_out,
-                       dirs_f, type, marks, list, cnt);
+                       dirs_f, type, marks, cnt);
 }
 
 template <int MODE>
 static void launch_dirs_mode(const float* h, const Grid& gr, int variant, uint8_t* dirs_out,
-                             const uint8_t* dirs_f, int type, uint8_t* marks, int* list,
+                             const uint8_t* dirs_f, int type, uint8_t* marks,
                              unsigned* cnt, hipStream_t s) {
     if (gr.ndim == 2) {
         const int ty = kVariants2D[variant].ty;
-        if (ty == 16) launch_dirs_t<2, 16, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
-        else if (ty == 8) launch_dirs_t<2, 8, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
-        else launch_dirs_t<2, 4, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
+        if (ty == 16) launch_dirs_t<2, 16, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else if (ty == 8) launch_dirs_t<2, 8, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else launch_dirs_t<2, 4, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
     } else {
         const DirsVariant v = kVariants3D[variant];
-        if (v.ty == 16 && v.zc == 16) launch_dirs_t<3, 16, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
-        else if (v.ty == 8 && v.zc == 16) launch_dirs_t<3, 8, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
-        else if (v.ty == 4 && v.zc == 32) launch_dirs_t<3, 4, 32, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
-        else if (v.ty == 16 && v.zc == 8) launch_dirs_t<3, 16, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
-        else launch_dirs_t<3, 8, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, list, cnt, s);
+        if (v.ty == 16 && v.zc == 16) launch_dirs_t<3, 16, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else if (v.ty == 8 && v.zc == 16) launch_dirs_t<3, 8, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else if (v.ty == 4 && v.zc == 32) launch_dirs_t<3, 4, 32, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else if (v.ty == 16 && v.zc == 8) launch_dirs_t<3, 16, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else launch_dirs_t<3, 8, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
     }
 }
 
 void launch_dirs(const float* h, const Grid& gr, int variant, uint8_t* dirs_out, hipStream_t s) {
-    launch_dirs_mode<0>(h, gr, variant, dirs_out, nullptr, 0, nullptr, nullptr, nullptr, s);
+    launch_dirs_mode<0>(h, gr, variant, dirs_out, nullptr, 0, nullptr, nullptr, s);
 }
 
 void launch_dirs_detect(const float* g, const Grid& gr, int variant, uint8_t* dirs_g,
-                        const uint8_t* dirs_f, int type, uint8_t* marks, int* list, unsigned* cnt,
+                        const uint8_t* dirs_f, int type, uint8_t* marks, unsigned* cnt,
                         hipStream_t s) {
-    launch_dirs_mode<1>(g, gr, variant, dirs_g, dirs_f, type, marks, list, cnt, s);
+    launch_dirs_mode<1>(g, gr, variant, dirs_g, dirs_f, type, marks, cnt, s);
 }
 
 void launch_detect_only(const uint8_t* dirs_f, const uint8_t* dirs_g, const Grid& gr, int type,
-                        uint8_t* marks, int* list, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_detect_only, dim3(blocks_for(gr.n, 256 * 4, 8192)), dim3(256), 0, s, dirs_f,
-                       dirs_g, gr, type, marks, list, cnt);
+                        uint8_t* marks, unsigned* cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_detect_only, dim3(blocks_for((gr.n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, dirs_f,
+                       dirs_g, gr, type, marks, cnt);
 }
 
-void launch_apply(const int* list, int len, float* g, const float* L, uint8_t* marks, unsigned* cnt,
-                  hipStream_t s) {
-    if (len <= 0) return;
-    hipLaunchKernelGGL(k_apply, dim3(blocks_for(len, 256, 4096)), dim3(256), 0, s, list, len, g, L,
-                       marks, cnt);
+void launch_apply(float* g, const float* L, uint8_t* marks, int n, unsigned* cnt, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply, dim3(blocks_for((n + 15) / 16, 256, kGridCap)), dim3(256), 0, s, g, L,
+                       marks, n, cnt);
 }
 
 static int label_tiles(const Grid& gr) {
@@ -814,36 +903,36 @@ void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q
 }
 
 void launch_label_final(const int* q_up, const int* q_dn, int n, int* M, int* m, hipStream_t s) {
-    hipLaunchKernelGGL(k_label_final, dim3(blocks_for(n, 256 * 4, 8192)), dim3(256), 0, s, q_up, q_dn,
+    hipLaunchKernelGGL(k_label_final, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, q_up, q_dn,
                        n, M, m);
 }
 
 void launch_detect_r(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* q_up, const int* q_dn,
-                     const int* Mf, const int* mf, const Grid& gr, uint8_t* marks, int* list,
+                     const int* Mf, const int* mf, const Grid& gr, uint8_t* marks,
                      unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_detect_r, dim3(blocks_for(gr.n, 256 * 4, 8192)), dim3(256), 0, s, dirs_f,
-                       dirs_g, q_up, q_dn, Mf, mf, gr, marks, list, cnt);
+    hipLaunchKernelGGL(k_detect_r, dim3(blocks_for((gr.n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, dirs_f,
+                       dirs_g, q_up, q_dn, Mf, mf, gr, marks, cnt);
 }
 
 void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu, const int* qfd,
                     const int* qgu, const int* qgd, int n, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_compare, dim3(blocks_for(n, 256 * 4, 8192)), dim3(256), 0, s, dirs_f, dirs_g,
+    hipLaunchKernelGGL(k_compare, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, dirs_f, dirs_g,
                        qfu, qfd, qgu, qgd, n, cnt);
 }
 
 void launch_validate_init(const float* f, const float* fhat, const float* warm, float xi, int n,
                           float* L, float* g, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_init, dim3(blocks_for(n, 256 * 4, 8192)), dim3(256), 0, s, f, fhat,
+    hipLaunchKernelGGL(k_validate_init, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, f, fhat,
                        warm, xi, n, L, g, cnt);
 }
 
 void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n, 256 * 4, 8192)), dim3(256), 0, s, h, n, cnt);
+    hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, h, n, cnt);
 }
 
 void launch_delta(const float* g, const float* fhat, int n, float* delta, float* g_out, unsigned* cnt,
                   hipStream_t s) {
-    hipLaunchKernelGGL(k_delta, dim3(blocks_for(n, 256 * 4, 8192)), dim3(256), 0, s, g, fhat, n, delta,
+    hipLaunchKernelGGL(k_delta, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, g, fhat, n, delta,
                        g_out, cnt);
 }
 

@@ -58,7 +58,8 @@ def assert_fix_parity(msz, f, fh, xi, **kw):
 # ------------------------------------------------------------ labels ---
 
 LABEL_SHAPES = [(1, 1), (1, 7), (9, 1), (64, 64), (70, 130), (129, 65), (200, 333),
-                (1, 1, 1), (2, 3, 4), (16, 16, 16), (17, 33, 19), (40, 50, 61), (5, 80, 3)]
+                (1, 1, 1), (2, 3, 4), (16, 16, 16), (17, 33, 19), (40, 50, 61), (5, 80, 3),
+                (17, 33, 20), (3, 70, 132)]
 
 
 @pytest.mark.parametrize("shape", LABEL_SHAPES)
@@ -117,7 +118,8 @@ def test_fix_bumps128(msz):
     assert rc == msz.OK and st["n_edited"] > 0
 
 
-@pytest.mark.parametrize("shape", [(3, 3), (4, 7), (13, 11), (64, 65), (3, 3, 3), (5, 6, 7), (20, 17, 9)])
+@pytest.mark.parametrize("shape", [(3, 3), (4, 7), (13, 11), (64, 65), (33, 68), (3, 3, 3), (5, 6, 7),
+                                   (20, 17, 9), (20, 17, 12)])
 def test_fix_random_small(msz, shape):
     rng = np.random.default_rng(15)
     for k in range(6):
@@ -185,6 +187,9 @@ def test_error_paths(msz):
     assert_fix_parity(msz, f, fh, xi, max_rounds=7)
     small_ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     assert msz.fix(dev(f), dev(fh), xi, workspace=small_ws)[0] == msz.EINVAL
+    # arrays must be 16-byte aligned: a view starting one float in is rejected
+    big_f = dev(np.concatenate([f.ravel(), f.ravel()[:1]]))[1:].reshape(f.shape)
+    assert msz.fix(big_f, dev(fh), xi)[0] == msz.EINVAL
     with pytest.raises(msz.MszError):
         msz.labels(dev(nan))
 
