@@ -64,7 +64,8 @@ enum {
     MSZ_PHASE_LABEL_FINAL = 7,  /* labels of f */
     MSZ_PHASE_DETECT_R = 8,     /* troublemaker detection */
     MSZ_PHASE_DELTA = 9,        /* output deltas */
-    MSZ_N_PHASES = 10
+    MSZ_PHASE_NET = 10,         /* learned warm start: features, 3 conv layers, g0 */
+    MSZ_N_PHASES = 11
 };
 
 /* msz_options.flags bits. */
@@ -184,6 +185,65 @@ size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs);
 
 /* Number of tile variants selectable through msz_options.tile_override for ndim. */
 int msz_tile_variants(int32_t ndim);
+
+/* ------------------------------------------------------------------------
+ * Learned edit proposal (warm start).  A 3-layer 3x3x3 convolution network
+ * (6 -> 16 -> 16 -> 1 channels, ReLU after the two hidden layers, a linear
+ * output, zero padding) predicts p, the edit of every vertex in units of xi;
+ * the correction loop then starts from g0 = clamp(fl(fhat - fl(p * xi)), L,
+ * fhat) (so p <= 0 leaves a vertex unedited) and, as always,
+ * runs to zero segmentation error within xi.  Weights and activations are
+ * BF16 (round to nearest even), sums FP32, on MFMA.
+ *
+ * Parameters: MSZ_NET_PARAMS FP32 values, DEVICE, in this order
+ *   W0[27][8][16] b0[16]   (input channels 6, 7 are padding, kept 0)
+ *   W1[27][16][16] b1[16]
+ *   W2[27][16]     b2[1]
+ * with tap = (dz+1)*9 + (dy+1)*3 + (dx+1) and W[tap][in][out].
+ * Features: MSZ_NET_FEATURES BF16 values per vertex, DEVICE, [vertex][8]:
+ *   0  (fhat - mean of fhat over the 3x3x3 box, in-grid vertices) / xi, clamped to [-8, 8]
+ *   1  log10(xi / (max f - min f)) / 4 + 1
+ *   2..5  false-critical-point flags of fhat against f (FPmax, FPmin, FNmax, FNmin)
+ *   6, 7  zero
+ * 2D grids are treated as 3D grids with nz = 1.  All pointers 16-byte aligned.
+ * ------------------------------------------------------------------------ */
+#define MSZ_NET_PARAMS 10833
+#define MSZ_NET_FEATURES 8
+
+/* DEVICE scratch the net entry points need for dims d (0 for invalid dims). */
+size_t msz_net_workspace_bytes(msz_dims d);
+
+/* feat[n][8] (BF16 bits) from f, fhat and xi. */
+int msz_net_features(const float* f, const float* fhat, msz_dims d, float xi, uint16_t* feat,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* p_out[n] = the network's prediction; act1_out / act2_out (optional, [n][16]
+ * BF16) receive the two hidden activations. */
+int msz_net_forward(const float* params, const uint16_t* feat, msz_dims d, float* p_out,
+                    uint16_t* act1_out, uint16_t* act2_out, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
+/* Gradient of the mean squared error mean_i (p_i - target_i)^2 with respect to
+ * the parameters (grad_out: DEVICE, MSZ_NET_PARAMS floats, same layout);
+ * *loss_out (HOST) receives the loss. */
+int msz_net_gradients(const float* params, const uint16_t* feat, const float* target, msz_dims d,
+                      float* grad_out, float* loss_out, void* workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
+ * on n FP32 parameters with first / second moments m, v (DEVICE). */
+int msz_net_adam(float* params, const float* grad, float* m, float* v, int32_t n, int32_t step,
+                 float lr, void* stream);
+
+/* Scratch bytes of msz_fix_learned for dims d. */
+size_t msz_learned_workspace_bytes(msz_dims d);
+
+/* msz_fix started from the network's warm start (params: DEVICE, see above).
+ * opt->warm_start must be NULL; opt->workspace, if given, must hold
+ * msz_learned_workspace_bytes(d).  With MSZ_FLAG_TIMING the network's kernels
+ * are reported under MSZ_PHASE_NET. */
+int msz_fix_learned(const float* f, const float* fhat, msz_dims d, float xi, const float* params,
+                    float* edits_out, const msz_options* opt, msz_stats* stats, void* stream);
 
 /* Human-readable name of a return code (static string). */
 const char* msz_strerror(int code);

@@ -12,7 +12,10 @@ Layouts: activations are channel-first ``[C, nz, ny, nx]``; weights
 Outside the grid the input counts as zero (zero padding).
 
 Network (edit-magnitude predictor): conv(6->16) ReLU, conv(16->16) ReLU,
-conv(16->1) ReLU, giving p >= 0, the predicted edit in units of xi.
+conv(16->1), giving p, the predicted edit in units of xi.  The output layer
+is linear (a ReLU there can switch the whole output off for good while
+training on mostly-zero targets); the warm start clamps fhat - p*xi into
+[L, fhat], so a negative p means "no edit".
 """
 from __future__ import annotations
 
@@ -99,11 +102,11 @@ def forward(x: np.ndarray, params, round_bf16: bool = True):
         Wq = bf16(W) if round_bf16 else W
         z = conv3d(acts[-1], Wq, b)
         pre.append(z)
-        a = np.maximum(z, 0.0)
         if li < len(params) - 1:
+            a = np.maximum(z, 0.0)
             acts.append(bf16(a) if round_bf16 else a)
         else:
-            acts.append(a)
+            acts.append(z)
     return acts[-1][0], (acts, pre, params, round_bf16)
 
 
@@ -115,7 +118,8 @@ def backward(cache, dp: np.ndarray):
     for li in range(len(params) - 1, -1, -1):
         W, b = params[li]
         Wq = bf16(W) if round_bf16 else W
-        g = g * (pre[li] > 0)
+        if li < len(params) - 1:
+            g = g * (pre[li] > 0)
         dx, dW, db = conv3d_backward(acts[li], Wq, g)
         grads[li] = (dW, db)
         g = dx

@@ -21,7 +21,9 @@ LIB_PATH = os.path.join(HERE, "libmsz.so")
 OK, EINVAL, ENONFINITE, EBOUND, ESTALL, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
 CASE_NAMES = ("fp_max", "fp_min", "fn_max", "fn_min")
 PHASES = ("validate", "dirs", "dirs_detect", "detect", "apply", "label_tile", "label_jump",
-          "label_final", "detect_r", "delta")
+          "label_final", "detect_r", "delta", "net")
+NET_PARAMS = 10833
+NET_FEATURES = 8
 N_PHASES = len(PHASES)
 FLAG_TIMING = 1
 
@@ -101,7 +103,20 @@ def lib() -> ctypes.CDLL:
         L.msz_tile_variants.argtypes = [I32]
         L.msz_strerror.argtypes = [ctypes.c_int]
         L.msz_strerror.restype = ctypes.c_char_p
-        for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants):
+        L.msz_net_workspace_bytes.argtypes = [Dims]
+        L.msz_net_workspace_bytes.restype = ctypes.c_size_t
+        L.msz_learned_workspace_bytes.argtypes = [Dims]
+        L.msz_learned_workspace_bytes.restype = ctypes.c_size_t
+        L.msz_net_features.argtypes = [P, P, Dims, F, P, P, ctypes.c_size_t, P]
+        L.msz_net_forward.argtypes = [P, P, Dims, P, P, P, P, ctypes.c_size_t, P]
+        L.msz_net_gradients.argtypes = [P, P, P, Dims, P, ctypes.POINTER(ctypes.c_float), P,
+                                        ctypes.c_size_t, P]
+        L.msz_net_adam.argtypes = [P, P, P, P, I32, I32, F, P]
+        L.msz_fix_learned.argtypes = [P, P, Dims, F, P, P, ctypes.POINTER(Options),
+                                      ctypes.POINTER(Stats), P]
+        for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants,
+                   L.msz_net_features, L.msz_net_forward, L.msz_net_gradients, L.msz_net_adam,
+                   L.msz_fix_learned):
             fn.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -243,3 +258,95 @@ def batch_workspace_bytes(shapes) -> int:
     for j, s in enumerate(shapes):
         jobs[j].d = dims_of(s)
     return int(lib().msz_batch_workspace_bytes(jobs, n))
+
+
+# ------------------------------------------------------------------ learned ---
+
+def _ws_arg(workspace):
+    if workspace is None:
+        return None, 0
+    return workspace.data_ptr(), workspace.numel() * workspace.element_size()
+
+
+def net_workspace_bytes(shape) -> int:
+    return int(lib().msz_net_workspace_bytes(dims_of(shape)))
+
+
+def learned_workspace_bytes(shape) -> int:
+    return int(lib().msz_learned_workspace_bytes(dims_of(shape)))
+
+
+def net_features(f, fhat, xi: float, *, workspace=None, stream=None):
+    """BF16 features [n][8] of (f, fhat, xi), returned as an int16 tensor of raw bits."""
+    import torch
+    _check_field(f, "f")
+    _check_field(fhat, "fhat")
+    feat = torch.empty((f.numel(), NET_FEATURES), dtype=torch.int16, device=f.device)
+    wp, wb = _ws_arg(workspace)
+    rc = lib().msz_net_features(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), feat.data_ptr(),
+                                wp, wb, _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_net_features")
+    return feat
+
+
+def net_forward(params, feat, shape, *, hidden: bool = False, workspace=None, stream=None):
+    """p[n] (float32); with ``hidden`` also the two hidden activations ([n][16] BF16 bits)."""
+    import torch
+    n = feat.shape[0]
+    p = torch.empty(n, dtype=torch.float32, device=feat.device)
+    a1 = a2 = None
+    if hidden:
+        a1 = torch.empty((n, 16), dtype=torch.int16, device=feat.device)
+        a2 = torch.empty((n, 16), dtype=torch.int16, device=feat.device)
+    wp, wb = _ws_arg(workspace)
+    rc = lib().msz_net_forward(params.data_ptr(), feat.data_ptr(), dims_of(shape), p.data_ptr(),
+                               a1.data_ptr() if a1 is not None else None,
+                               a2.data_ptr() if a2 is not None else None, wp, wb, _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_net_forward")
+    return (p, a1, a2) if hidden else p
+
+
+def net_gradients(params, feat, target, shape, *, grad_out=None, workspace=None, stream=None):
+    """(loss, grad) of the mean squared error; grad has the parameter layout."""
+    import torch
+    g = grad_out if grad_out is not None else torch.empty_like(params)
+    loss = ctypes.c_float(0.0)
+    wp, wb = _ws_arg(workspace)
+    rc = lib().msz_net_gradients(params.data_ptr(), feat.data_ptr(), target.data_ptr(), dims_of(shape),
+                                 g.data_ptr(), ctypes.byref(loss), wp, wb, _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_net_gradients")
+    return float(loss.value), g
+
+
+def net_adam(params, grad, m, v, step: int, lr: float, stream=None):
+    rc = lib().msz_net_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(), params.numel(),
+                            int(step), float(lr), _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_net_adam")
+
+
+def fix_learned(f, fhat, xi: float, params, *, max_rounds: int = 0, want_g: bool = True, workspace=None,
+                edits_out=None, g_out=None, timing: bool = False, stream=None):
+    """msz_fix warm-started by the network; same return value as fix()."""
+    import torch
+    _check_field(f, "f")
+    _check_field(fhat, "fhat")
+    edits = edits_out if edits_out is not None else torch.empty_like(f)
+    g = g_out if g_out is not None else (torch.empty_like(f) if want_g else None)
+    opt = Options()
+    opt.max_rounds = int(max_rounds)
+    opt.g_out = g.data_ptr() if g is not None else None
+    if workspace is not None:
+        opt.workspace = workspace.data_ptr()
+        opt.workspace_bytes = workspace.numel() * workspace.element_size()
+    opt.flags = FLAG_TIMING if timing else 0
+    st = Stats()
+    rc = lib().msz_fix_learned(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), params.data_ptr(),
+                               edits.data_ptr(), ctypes.byref(opt), ctypes.byref(st), _stream(stream))
+    out = st.as_dict()
+    if timing:
+        out["timing"] = st.timing()
+    return int(rc), edits, g, out

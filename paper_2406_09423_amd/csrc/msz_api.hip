@@ -16,12 +16,6 @@
 #include "msz_internal.h"
 
 namespace msz {
-namespace {
-
-#define MSZ_HIP(x)                                 \
-    do {                                           \
-        if ((x) != hipSuccess) return MSZ_EDEVICE; \
-    } while (0)
 
 bool make_grid(const msz_dims& d, Grid& gr) {
     if (d.ndim != 2 && d.ndim != 3) return false;
@@ -43,6 +37,13 @@ bool make_grid(const msz_dims& d, Grid& gr) {
     for (int k = 0; k < 16; ++k) gr.off[k] = static_cast<int>(off[k] < INT32_MIN || off[k] > INT32_MAX ? 0 : off[k]);
     return true;
 }
+
+namespace {
+
+#define MSZ_HIP(x)                                 \
+    do {                                           \
+        if ((x) != hipSuccess) return MSZ_EDEVICE; \
+    } while (0)
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -231,7 +232,7 @@ int precompute(Field& F, unsigned* hc, hipStream_t s) {
     TIMED(F, MSZ_PHASE_DIRS, s, launch_dirs(F.f, F.gr, F.variant, F.dirs_f, s));
     TIMED(F, MSZ_PHASE_LABEL_TILE, s, launch_label_tile(F.dirs_f, F.gr, F.qu, F.qd, s));
     TIMED(F, MSZ_PHASE_LABEL_JUMP, s, launch_label_compress(F.gr, F.qu, F.qd, F.cnt, s));
-    TIMED(F, MSZ_PHASE_LABEL_FINAL, s, launch_label_final(F.qu, F.qd, n, F.Mf, F.mf, s));
+    TIMED(F, MSZ_PHASE_LABEL_FINAL, s, launch_label_final(F.qu, F.qd, F.gr, F.Mf, F.mf, s));
     int rc = read_counters(F.cnt, hc, s, F.tm);
     if (rc) return rc;
     const unsigned e = hc[kCntErr];
@@ -481,7 +482,7 @@ int msz_labels(const float* field, msz_dims d, int32_t* max_label, int32_t* min_
     launch_check_finite(field, gr.n, cnt, s);
     launch_dirs(field, gr, 0, dirs, s);
     launch_label_forests(dirs, gr, max_label, min_label, cnt, s);
-    launch_label_final(max_label, min_label, gr.n, max_label, min_label, s);
+    launch_label_final(max_label, min_label, gr, max_label, min_label, s);
     if (int rc = read_counters(cnt, hc, s)) return rc;
     if (hc[kCntErr] & kErrWalk) return MSZ_EDEVICE;
     return hc[kCntErr] ? MSZ_ENONFINITE : MSZ_OK;

@@ -35,7 +35,81 @@ struct Grid {
     int off[16];  // linear id offset of each neighbour slot; off[15] = 0 (self)
 };
 
+// Work items of a persistent grid, XCD-aware: blocks are dealt to the 8 XCDs
+// round-robin, so the items are cut into K = min(8, blocks) contiguous ranges
+// and the blocks with blockIdx % K == k walk range k with stride "blocks in
+// the range".  Neighbouring items then share an L2.  Every item in
+// [0, nitems) is visited exactly once.
+struct ItemRange {
+    int first, hi, stride;
+};
+__device__ __forceinline__ ItemRange xcd_items(int nitems) {
+    const int nb = gridDim.x;
+    const int K = nb < 8 ? nb : 8;
+    const int k = blockIdx.x % K, slot = blockIdx.x / K;
+    const int per = (nb - k + K - 1) / K;  // blocks b < nb with b % K == k
+    const int lo = static_cast<int>(static_cast<long>(nitems) * k / K);
+    const int hi = static_cast<int>(static_cast<long>(nitems) * (k + 1) / K);
+    return {lo + slot, hi, per};
+}
+
+// Exact float helpers shared by the loop and the warm start.
+__device__ __forceinline__ float f32_next_up(float x) {
+    if (x == 0.0f) return __int_as_float(1);
+    int b = __float_as_int(x);
+    return __int_as_float(x > 0.0f ? b + 1 : b - 1);
+}
+
+__device__ __forceinline__ float f32_next_down(float x) {
+    if (x == 0.0f) return -__int_as_float(1);
+    int b = __float_as_int(x);
+    return __int_as_float(x > 0.0f ? b - 1 : b + 1);
+}
+
+// Error-free difference a - b = s + e in binary64 (two-sum; no fused ops).
+__device__ __forceinline__ void exact_diff(float a, float b, double& s, double& e) {
+    const double da = a, nb = -static_cast<double>(b);
+    s = __dadd_rn(da, nb);
+    const double bv = __dadd_rn(s, -da);
+    const double av = __dadd_rn(s, -bv);
+    e = __dadd_rn(__dadd_rn(da, -av), __dadd_rn(nb, -bv));
+}
+
+// a - b <= c and a - b >= c, decided exactly.
+__device__ __forceinline__ bool diff_at_most(float a, float b, float c) {
+    double s, e;
+    exact_diff(a, b, s, e);
+    return s < static_cast<double>(c) || (s == static_cast<double>(c) && e <= 0.0);
+}
+__device__ __forceinline__ bool diff_at_least(float a, float b, float c) {
+    double s, e;
+    exact_diff(a, b, s, e);
+    return s > static_cast<double>(c) || (s == static_cast<double>(c) && e >= 0.0);
+}
+
+// Smallest float32 L with L >= f - xi (the float reading of Eq. 1's bound).
+__device__ __forceinline__ float floor_bound(float f, float xi) {
+    float x = __double2float_rn(__dadd_rn(static_cast<double>(f), -static_cast<double>(xi)));
+    for (int k = 0; k < 4 && !diff_at_most(f, x, xi); ++k) x = f32_next_up(x);
+    for (int k = 0; k < 4; ++k) {
+        const float y = f32_next_down(x);
+        if (!diff_at_most(f, y, xi)) break;
+        x = y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ bool value_ok(float v) {
+    return fabsf(v) <= kValueLimit;  // false for NaN and +-Inf
+}
+
 int tile_variant_count(int ndim);
+
+}  // namespace msz
+#include "../../include/msz.h"
+namespace msz {
+// Validates dims (ndim 2 or 3, nz == 1 in 2D, positive sides, n < 2^31) and fills gr.
+bool make_grid(const msz_dims& d, Grid& gr);
 
 void launch_validate_init(const float* f, const float* fhat, const float* warm, float xi, int n,
                           float* L, float* g, unsigned* cnt, hipStream_t s);
@@ -50,7 +124,7 @@ void launch_label_tile(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn
 void launch_label_compress(const Grid& gr, int* q_up, int* q_dn, unsigned* cnt, hipStream_t s);
 void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, unsigned* cnt,
                           hipStream_t s);
-void launch_label_final(const int* q_up, const int* q_dn, int n, int* M, int* m, hipStream_t s);
+void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, hipStream_t s);
 void launch_detect_r(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* q_up, const int* q_dn,
                      const int* Mf, const int* mf, const Grid& gr, uint8_t* marks, unsigned* cnt,
                      hipStream_t s);

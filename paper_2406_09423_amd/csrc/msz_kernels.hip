@@ -58,55 +58,6 @@ __device__ __forceinline__ float halve(float g, float L) {
     return h == g ? L : h;
 }
 
-__device__ __forceinline__ float f32_next_up(float x) {
-    if (x == 0.0f) return __int_as_float(1);
-    int b = __float_as_int(x);
-    return __int_as_float(x > 0.0f ? b + 1 : b - 1);
-}
-
-__device__ __forceinline__ float f32_next_down(float x) {
-    if (x == 0.0f) return -__int_as_float(1);
-    int b = __float_as_int(x);
-    return __int_as_float(x > 0.0f ? b - 1 : b + 1);
-}
-
-// Error-free difference a - b = s + e in binary64 (two-sum; no fused ops).
-__device__ __forceinline__ void exact_diff(float a, float b, double& s, double& e) {
-    const double da = a, nb = -static_cast<double>(b);
-    s = __dadd_rn(da, nb);
-    const double bv = __dadd_rn(s, -da);
-    const double av = __dadd_rn(s, -bv);
-    e = __dadd_rn(__dadd_rn(da, -av), __dadd_rn(nb, -bv));
-}
-
-// a - b <= c and a - b >= c, decided exactly.
-__device__ __forceinline__ bool diff_at_most(float a, float b, float c) {
-    double s, e;
-    exact_diff(a, b, s, e);
-    return s < static_cast<double>(c) || (s == static_cast<double>(c) && e <= 0.0);
-}
-__device__ __forceinline__ bool diff_at_least(float a, float b, float c) {
-    double s, e;
-    exact_diff(a, b, s, e);
-    return s > static_cast<double>(c) || (s == static_cast<double>(c) && e >= 0.0);
-}
-
-// Smallest float32 L with L >= f - xi (the float reading of Eq. 1's bound).
-__device__ __forceinline__ float floor_bound(float f, float xi) {
-    float x = __double2float_rn(__dadd_rn(static_cast<double>(f), -static_cast<double>(xi)));
-    for (int k = 0; k < 4 && !diff_at_most(f, x, xi); ++k) x = f32_next_up(x);
-    for (int k = 0; k < 4; ++k) {
-        const float y = f32_next_down(x);
-        if (!diff_at_most(f, y, xi)) break;
-        x = y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ bool value_ok(float v) {
-    return fabsf(v) <= kValueLimit;  // false for NaN and +-Inf
-}
-
 // ------------------------------------------------------ validate and init ---
 
 // Checks the input contract, computes the floor L and the start field g.
@@ -200,17 +151,17 @@ __device__ __forceinline__ void detect_vertex(bool valid, unsigned df, unsigned 
 
 // --------------------------------------------------- steepest directions ---
 //
-// Each block owns a 64 x TY tile of one z-slab of ZC planes.  Planes (with a
-// one-vertex halo, NaN outside the grid so that it never wins a comparison)
-// are staged in LDS and marched along z with a rolling window of three.  A
-// thread computes four x-consecutive vertices of one row.
+// Work item = a 64 x TY column of ZC planes (2D: one 64 x TY tile).  A block
+// is persistent: it walks a contiguous range of work items (XCD-aware, so the
+// halos of neighbouring items stay in the same L2) as one stream of planes.
+// Each plane, with a one-vertex halo (NaN outside the grid, so it never wins a
+// comparison), is loaded into registers one step ahead, stored into a ring of
+// three LDS planes, and the middle plane is then computed: a thread owns four
+// x-consecutive vertices of TY/16 rows.  Loads are issued as a batch before
+// the previous plane is computed, which keeps HBM busy.
 //
 // MODE 0: write dirs only.  MODE 1: write dirs and run the C-loop detection
 // of `type` against dirs_f.
-
-struct TileCoord {
-    int bx, by, bz;
-};
 
 // Maps the hardware block id to a tile so that consecutive tiles land on the
 // same XCD (blocks are dealt to the 8 XCDs round-robin).
@@ -219,143 +170,179 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
     return k * q + min(k, r) + (b >> 3);
 }
 
-template <int TY>
-__device__ __forceinline__ void load_plane(float* __restrict__ dst, const float* __restrict__ h,
-                                           const Grid& gr, int x0, int y0, int z) {
-    constexpr int W = kTileX + 2, H = TY + 2;
-    const bool zin = z >= 0 && z < gr.nz;
-    const long base = static_cast<long>(z) * gr.nxy;
-    for (int idx = threadIdx.x; idx < W * H; idx += blockDim.x) {
-        const int r = idx / W, c = idx - r * W;
-        const int x = x0 + c - 1, y = y0 + r - 1;
-        float v = __builtin_nanf("");
-        if (zin && x >= 0 && x < gr.nx && y >= 0 && y < gr.ny) v = h[base + x + static_cast<long>(gr.nx) * y];
-        dst[idx] = v;
-    }
-}
-
-struct Best {
+// Running steepest ascent / descent of one vertex.  Neighbours are fed in
+// increasing order of |id - centre| on each side of the centre: first the
+// ones with a smaller id (below), then the ones with a larger id (above).
+// The order (value, id) then needs no id comparison: a below-centre
+// neighbour must be strictly higher to become the ascent and wins descent
+// ties (it has the smaller id); an above-centre neighbour wins ascent ties
+// and must be strictly lower to become the descent.  Which neighbour ids are
+// smaller or larger does not depend on the grid size (checked for all grids
+// up to 6x6 and 5x5x5; for larger ones the offsets only grow apart).  NaN
+// (outside the grid) fails every comparison and is never chosen.
+struct Steepest {
     float uv, dv;
-    int uo, dov;
     unsigned us, ds;
+    __device__ __forceinline__ void below(float w, unsigned slot) {
+        if (w > uv) uv = w, us = slot;
+        if (w <= dv) dv = w, ds = slot;
+    }
+    __device__ __forceinline__ void above(float w, unsigned slot) {
+        if (w >= uv) uv = w, us = slot;
+        if (w < dv) dv = w, ds = slot;
+    }
 };
 
-__device__ __forceinline__ void consider(Best& b, float w, int o, unsigned slot) {
-    if (w > b.uv || (w == b.uv && o > b.uo)) {
-        b.uv = w;
-        b.uo = o;
-        b.us = slot;
-    }
-    if (w < b.dv || (w == b.dv && o < b.dov)) {
-        b.dv = w;
-        b.dov = o;
-        b.ds = slot;
-    }
-}
-
 template <int NDIM, int TY, int ZC, int MODE>
-__global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, Grid gr,
-                                                  uint8_t* __restrict__ dirs_out,
-                                                  const uint8_t* __restrict__ dirs_f, int type,
-                                                  uint8_t* __restrict__ marks,
-                                                  unsigned* __restrict__ cnt) {
-    constexpr int W = kTileX + 2, H = TY + 2, P = W * H;
-    constexpr int NP = NDIM == 3 ? 3 : 1;
-    __shared__ float sm[NP * P];
+__global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid gr,
+                                              uint8_t* __restrict__ dirs_out,
+                                              const uint8_t* __restrict__ dirs_f, int type,
+                                              uint8_t* __restrict__ marks,
+                                              unsigned* __restrict__ cnt) {
+    static_assert(TY % 16 == 0, "a thread row covers 16 tile rows");
+    constexpr int W = kTileX + 2, H = TY + 2, P = W * H, NL = (P + 255) / 256, RPT = TY / 16;
+    constexpr int NP = NDIM == 3 ? 3 : 1;     // LDS ring of planes
+    constexpr int ZCH = NDIM == 3 ? ZC : 1;   // planes computed per work item
+    __shared__ float sm[NP][P];
 
     const int tiles_x = (gr.nx + kTileX - 1) / kTileX;
     const int tiles_y = (gr.ny + TY - 1) / TY;
-    const int nb = gridDim.x;
-    const int lb = xcd_logical_block(blockIdx.x, nb);
-    const int bx = lb % tiles_x;
-    const int by = (lb / tiles_x) % tiles_y;
-    const int bz = lb / (tiles_x * tiles_y);
-    const int x0 = bx * kTileX, y0 = by * TY;
+    const int tiles_z = NDIM == 3 ? (gr.nz + ZCH - 1) / ZCH : 1;
+    const ItemRange range = xcd_items(tiles_x * tiles_y * tiles_z);
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int y = y0 + ty;
-    const int z0 = NDIM == 3 ? bz * ZC : 0;
     // rows start at multiples of 4 vertices: packed direction bytes move as dwords
     const bool vec4 = (gr.nx & 3) == 0;
 
-    unsigned c[4] = {0u, 0u, 0u, 0u};
-
-    int below = 0, cur = 0, above = 0;
-    if constexpr (NDIM == 3) {
-        load_plane<TY>(sm + 0 * P, h, gr, x0, y0, z0 - 1);
-        load_plane<TY>(sm + 1 * P, h, gr, x0, y0, z0);
-        below = 0;
-        cur = 1;
-        above = 2;
-    } else {
-        load_plane<TY>(sm, h, gr, x0, y0, 0);
-    }
-
-    const int zc = NDIM == 3 ? ZC : 1;
-    for (int zz = 0; zz < zc; ++zz) {
-        const int z = z0 + zz;
-        if (z >= gr.nz) break;  // uniform across the block
-        if constexpr (NDIM == 3) load_plane<TY>(sm + above * P, h, gr, x0, y0, z + 1);
-        __syncthreads();
-        const float* C = sm + cur * P;
-        const float* A = sm + above * P;
-        const float* B = sm + below * P;
-        const int r = ty + 1;
-        // the thread's four vertices: one dword of directions when rows are 4-aligned
-        const int xa = x0 + tx * 4;
-        const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
-        const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
-        unsigned df4 = 0xFFFFFFFFu;
-        if constexpr (MODE == 1) {
-            if (full) {
-                df4 = *reinterpret_cast<const unsigned*>(dirs_f + i0);
-            } else {
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (xa + k < gr.nx && y < gr.ny)
-                        df4 = (df4 & ~(0xFFu << (8 * k))) | (static_cast<unsigned>(dirs_f[i0 + k]) << (8 * k));
-            }
-        }
-        unsigned out4 = 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int x = xa + k;
-            const int cc = tx * 4 + k + 1;
-            const bool valid = x < gr.nx && y < gr.ny;
-            const int i = static_cast<int>(i0) + k;
-            unsigned packed = 0xFFu;
-            if (valid) {
-                const float v = C[r * W + cc];
-                Best b{v, v, 0, 0, kSelf, kSelf};
-                consider(b, C[r * W + cc + 1], gr.off[0], 0);
-                consider(b, C[r * W + cc - 1], gr.off[1], 1);
-                consider(b, C[(r + 1) * W + cc], gr.off[2], 2);
-                consider(b, C[(r - 1) * W + cc], gr.off[3], 3);
-                consider(b, C[(r + 1) * W + cc + 1], gr.off[4], 4);
-                consider(b, C[(r - 1) * W + cc - 1], gr.off[5], 5);
-                if constexpr (NDIM == 3) {
-                    consider(b, A[r * W + cc], gr.off[6], 6);
-                    consider(b, B[r * W + cc], gr.off[7], 7);
-                    consider(b, A[r * W + cc + 1], gr.off[8], 8);
-                    consider(b, B[r * W + cc - 1], gr.off[9], 9);
-                    consider(b, A[(r + 1) * W + cc], gr.off[10], 10);
-                    consider(b, B[(r - 1) * W + cc], gr.off[11], 11);
-                    consider(b, A[(r + 1) * W + cc + 1], gr.off[12], 12);
-                    consider(b, B[(r - 1) * W + cc - 1], gr.off[13], 13);
-                }
-                packed = (b.us << 4) | b.ds;
-                out4 = (out4 & ~(0xFFu << (8 * k))) | (packed << (8 * k));
-                if (!full) dirs_out[i0 + k] = static_cast<uint8_t>(packed);
-            }
-            if constexpr (MODE == 1) detect_vertex(valid, (df4 >> (8 * k)) & 0xFFu, packed, i, type, gr, marks, c);
-        }
-        if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
-        __syncthreads();  // the oldest plane is overwritten next
+    // stream position: work item `it`, plane `j` of it (z = z0 - 1 + j in 3D)
+    auto planes_of = [&](int it) {
         if constexpr (NDIM == 3) {
-            const int t = below;
-            below = cur;
-            cur = above;
-            above = t;
+            const int z0 = (it / (tiles_x * tiles_y)) * ZCH;
+            return min(ZCH, gr.nz - z0) + 2;
         }
+        return 1;
+    };
+    auto origin = [&](int it, int& x0, int& y0, int& z0) {
+        x0 = (it % tiles_x) * kTileX;
+        y0 = ((it / tiles_x) % tiles_y) * TY;
+        z0 = NDIM == 3 ? (it / (tiles_x * tiles_y)) * ZCH : 0;
+    };
+
+    float pre[NL];
+    unsigned dpre[RPT];
+    // issue the loads of plane j of item it (and the dirs_f words of the plane it completes)
+    auto load = [&](int it, int j) {
+        int x0, y0, z0;
+        origin(it, x0, y0, z0);
+        const int z = NDIM == 3 ? z0 - 1 + j : 0;
+        const bool zin = z >= 0 && z < gr.nz;
+        const long base = static_cast<long>(z) * gr.nxy;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = threadIdx.x + 256 * k;
+            const int r = idx / W, c = idx - r * W;
+            const int x = x0 + c - 1, y = y0 + r - 1;
+            float v = __builtin_nanf("");
+            if (idx < P && zin && x >= 0 && x < gr.nx && y >= 0 && y < gr.ny)
+                v = h[base + x + static_cast<long>(gr.nx) * y];
+            pre[k] = v;
+        }
+        if constexpr (MODE == 1) {
+            const int zc = NDIM == 3 ? z - 1 : 0;  // the plane computed once this one is in LDS
+            const bool zok = NDIM == 3 ? (j >= 2 && zc < gr.nz) : true;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int y = y0 + ty + 16 * q, xa = x0 + tx * 4;
+                const long i0 = static_cast<long>(zc) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
+                unsigned d = 0xFFFFFFFFu;
+                if (zok && y < gr.ny) {
+                    if (vec4 && xa + 3 < gr.nx) {
+                        d = *reinterpret_cast<const unsigned*>(dirs_f + i0);
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if (xa + k < gr.nx) d = (d & ~(0xFFu << (8 * k))) | (static_cast<unsigned>(dirs_f[i0 + k]) << (8 * k));
+                    }
+                }
+                dpre[q] = d;
+            }
+        }
+    };
+
+    unsigned c[4] = {0u, 0u, 0u, 0u};
+    int it = range.first, j = 0;
+    if (it < range.hi) load(it, 0);
+    int ring = 0;  // LDS slot of the plane held in pre[]
+    while (it < range.hi) {
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int idx = threadIdx.x + 256 * k;
+            if (idx < P) sm[ring][idx] = pre[k];
+        }
+        unsigned df4[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) df4[q] = dpre[q];
+        __syncthreads();
+        // advance the stream and prefetch the next plane while this one is computed
+        const int cur_it = it, cur_j = j, cur_ring = ring;
+        if (++j == planes_of(it)) {
+            j = 0;
+            it += range.stride;
+        }
+        ring = NP == 3 ? (ring + 1) % 3 : 0;
+        if (it < range.hi) load(it, j);
+
+        if (NDIM == 2 || cur_j >= 2) {
+            int x0, y0, z0;
+            origin(cur_it, x0, y0, z0);
+            const int z = NDIM == 3 ? z0 + cur_j - 2 : 0;
+            const float* A = sm[cur_ring];                      // plane z + 1
+            const float* C = sm[NP == 3 ? (cur_ring + 2) % 3 : 0]; // plane z
+            const float* B = sm[NP == 3 ? (cur_ring + 1) % 3 : 0]; // plane z - 1
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int y = y0 + ty + 16 * q, xa = x0 + tx * 4, r = ty + 16 * q + 1;
+                const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
+                const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
+                unsigned out4 = 0xFFFFFFFFu;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int cc = tx * 4 + k + 1;
+                    const bool valid = xa + k < gr.nx && y < gr.ny;
+                    unsigned packed = 0xFFu;
+                    if (valid) {
+                        const float v = C[r * W + cc];
+                        Steepest b{v, v, kSelf, kSelf};
+                        // below-centre ids, nearest first, then above-centre ids, nearest first
+                        b.below(C[r * W + cc - 1], 1);
+                        b.below(C[(r - 1) * W + cc], 3);
+                        b.below(C[(r - 1) * W + cc - 1], 5);
+                        if constexpr (NDIM == 3) {
+                            b.below(B[r * W + cc], 7);
+                            b.below(B[r * W + cc - 1], 9);
+                            b.below(B[(r - 1) * W + cc], 11);
+                            b.below(B[(r - 1) * W + cc - 1], 13);
+                        }
+                        b.above(C[r * W + cc + 1], 0);
+                        b.above(C[(r + 1) * W + cc], 2);
+                        b.above(C[(r + 1) * W + cc + 1], 4);
+                        if constexpr (NDIM == 3) {
+                            b.above(A[r * W + cc], 6);
+                            b.above(A[r * W + cc + 1], 8);
+                            b.above(A[(r + 1) * W + cc], 10);
+                            b.above(A[(r + 1) * W + cc + 1], 12);
+                        }
+                        packed = (b.us << 4) | b.ds;
+                        out4 = (out4 & ~(0xFFu << (8 * k))) | (packed << (8 * k));
+                        if (!full) dirs_out[i0 + k] = static_cast<uint8_t>(packed);
+                    }
+                    if constexpr (MODE == 1)
+                        detect_vertex(valid, (df4[q] >> (8 * k)) & 0xFFu, packed, static_cast<int>(i0) + k, type, gr,
+                                      marks, c);
+                }
+                if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
+            }
+        }
+        __syncthreads();  // the slot written next is the oldest plane
     }
     if constexpr (MODE == 1) {
         const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
@@ -364,24 +351,28 @@ __global__ void __launch_bounds__(16 * TY) k_dirs(const float* __restrict__ h, G
 }
 
 // Detection from stored directions (g unchanged since they were computed).
-// Four vertices per thread: one dword of each direction array.
+// Sixteen vertices per thread: one dwordx4 of each direction array.  The
+// direction arrays live in 256-byte padded workspace segments, so the last
+// partial group can be read whole; vertices past n are masked.
 __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__ dirs_f,
                                                      const uint8_t* __restrict__ dirs_g, Grid gr,
                                                      int type, uint8_t* __restrict__ marks,
                                                      unsigned* __restrict__ cnt) {
     unsigned c[4] = {0u, 0u, 0u, 0u};
     const int n = gr.n;
-    const int ng = (n + 3) >> 2;
-    // the direction arrays live in 256-byte padded workspace segments, so the
-    // last partial dword can be read whole; lanes past n are masked
-    const unsigned* wf = reinterpret_cast<const unsigned*>(dirs_f);
-    const unsigned* wg = reinterpret_cast<const unsigned*>(dirs_g);
+    const int ng = (n + 15) >> 4;
+    const uint4* wf = reinterpret_cast<const uint4*>(dirs_f);
+    const uint4* wg = reinterpret_cast<const uint4*>(dirs_g);
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
-        const unsigned df4 = wf[w], dg4 = wg[w];
+        const uint4 a = wf[w], b = wg[w];
+        const unsigned fa[4] = {a.x, a.y, a.z, a.w}, ga[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = 4 * w + j;
-            detect_vertex(i < n, (df4 >> (8 * j)) & 0xFFu, (dg4 >> (8 * j)) & 0xFFu, i, type, gr, marks, c);
+        for (int q = 0; q < 4; ++q) {
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 16 * w + 4 * q + j;
+                detect_vertex(i < n, (fa[q] >> (8 * j)) & 0xFFu, (ga[q] >> (8 * j)) & 0xFFu, i, type, gr, marks, c);
+            }
         }
     }
     const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
@@ -445,6 +436,15 @@ struct LabelTile<3> {
     static constexpr int X = 16, Y = 16, Z = 16;
 };
 
+__host__ __device__ __forceinline__ int label_tiles_of(const Grid& gr) {
+    if (gr.ndim == 2) {
+        using T = LabelTile<2>;
+        return ((gr.nx + T::X - 1) / T::X) * ((gr.ny + T::Y - 1) / T::Y);
+    }
+    using T = LabelTile<3>;
+    return ((gr.nx + T::X - 1) / T::X) * ((gr.ny + T::Y - 1) / T::Y) * ((gr.nz + T::Z - 1) / T::Z);
+}
+
 __device__ __forceinline__ void slot_delta(unsigned s, int& dx, int& dy, int& dz) {
     // slots in the order of the table at the top of this file
     constexpr int DX[14] = {1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1};
@@ -462,7 +462,6 @@ __global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ 
     using T = LabelTile<NDIM>;
     constexpr int NT = T::X * T::Y * T::Z;
     constexpr int PER = NT / 256;
-    constexpr int PASSES = NDIM == 3 ? 12 : 12;  // 2^12 = 4096 >= any in-tile path
     __shared__ int su[NT];
     __shared__ int sd[NT];
 
@@ -522,8 +521,12 @@ __global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ 
         }
     }
     __syncthreads();
-    // doubling passes; stop early once every pointer of the tile is terminal
-    for (int pass = 0; pass < PASSES; ++pass) {
+    // Pointer jumping in LDS: each thread jumps the pointers of its own
+    // vertices until they are terminal.  A value read from another thread's
+    // entry is always an ancestor (entries only ever move up their forest),
+    // so no barrier is needed between jumps and every jump makes progress; a
+    // pointer needs at most one jump per vertex of its in-tile path.
+    for (int iter = 0; iter < NT; ++iter) {
         int pending = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -541,7 +544,7 @@ __global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ 
                 pending |= b2 >= 0;
             }
         }
-        if (!__syncthreads_or(pending)) break;
+        if (!pending) break;
     }
     // Every in-tile path is shorter than the tile, so all pointers are terminal
     // here; a non-terminal one would still name an in-grid ancestor.
@@ -662,28 +665,74 @@ __global__ void __launch_bounds__(256) k_label_compress(Grid gr, int* __restrict
     }
 }
 
-// Writes the final labels label(i) = q[q[i]].  May run in place (M == q_up,
-// m == q_dn): the values it reads are fixed points.  Arrays are 16-byte aligned.
-__global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int* q_dn, int n, int* M,
+// Label-tile order: the gathers q[q[i]] of a tile land on the faces of the tile
+// and its neighbours, so walking tiles (not rows) keeps them in cache.  A
+// thread owns the 4-vertex row groups l = 4 t + 1024 k of its tile.
+template <int NDIM>
+struct TileGroup {
+    int i0;     // global id of the group's first vertex
+    int count;  // in-grid vertices of the group (0..4)
+    bool vec;   // the four are in the grid, consecutive and 16-byte aligned
+};
+
+template <int NDIM>
+__device__ __forceinline__ TileGroup<NDIM> tile_group(const Grid& gr, int tile, int k) {
+    using T = LabelTile<NDIM>;
+    const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y;
+    const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
+    const int l0 = 4 * threadIdx.x + 1024 * k;
+    const int xa = bx * T::X + l0 % T::X, y = by * T::Y + (l0 / T::X) % T::Y, z = bz * T::Z + l0 / (T::X * T::Y);
+    TileGroup<NDIM> g;
+    g.i0 = xa + gr.nx * y + gr.nxy * z;
+    g.count = (y < gr.ny && z < gr.nz) ? max(0, min(4, gr.nx - xa)) : 0;
+    g.vec = g.count == 4 && (gr.nx & 3) == 0;
+    return g;
+}
+
+// Writes the final labels label(i) = q[q[i]], tile by tile.  May run in place
+// (M == q_up, m == q_dn): the values it reads are fixed points.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int* q_dn, Grid gr, int* M,
                                                      int* m) {
-    const int ng = n >> 2;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
-        const int4 a = reinterpret_cast<const int4*>(q_up)[w];
-        const int4 b = reinterpret_cast<const int4*>(q_dn)[w];
-        const int4 ra = make_int4(q_up[a.x], q_up[a.y], q_up[a.z], q_up[a.w]);
-        const int4 rb = make_int4(q_dn[b.x], q_dn[b.y], q_dn[b.z], q_dn[b.w]);
-        reinterpret_cast<int4*>(M)[w] = ra;
-        reinterpret_cast<int4*>(m)[w] = rb;
-    }
-    for (int i = 4 * ng + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        M[i] = q_up[q_up[i]];
-        m[i] = q_dn[q_dn[i]];
+    constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
+    const ItemRange range = xcd_items(label_tiles_of(gr));
+    for (int tile = range.first; tile < range.hi; tile += range.stride) {
+        int a[G][4], b[G][4];
+        TileGroup<NDIM> tg[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            tg[k] = tile_group<NDIM>(gr, tile, k);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[k][j] = b[k][j] = 0;
+            if (tg[k].vec) {
+                const int4 u = *reinterpret_cast<const int4*>(q_up + tg[k].i0);
+                const int4 d = *reinterpret_cast<const int4*>(q_dn + tg[k].i0);
+                a[k][0] = u.x, a[k][1] = u.y, a[k][2] = u.z, a[k][3] = u.w;
+                b[k][0] = d.x, b[k][1] = d.y, b[k][2] = d.z, b[k][3] = d.w;
+            } else {
+                for (int j = 0; j < tg[k].count; ++j) a[k][j] = q_up[tg[k].i0 + j], b[k][j] = q_dn[tg[k].i0 + j];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            int ra[4], rb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                ra[j] = j < tg[k].count ? q_up[a[k][j]] : 0;
+                rb[j] = j < tg[k].count ? q_dn[b[k][j]] : 0;
+            }
+            if (tg[k].vec) {
+                *reinterpret_cast<int4*>(M + tg[k].i0) = make_int4(ra[0], ra[1], ra[2], ra[3]);
+                *reinterpret_cast<int4*>(m + tg[k].i0) = make_int4(rb[0], rb[1], rb[2], rb[3]);
+            } else {
+                for (int j = 0; j < tg[k].count; ++j) M[tg[k].i0 + j] = ra[j], m[tg[k].i0 + j] = rb[j];
+            }
+        }
     }
 }
 
-// ------------------------------------------------------- R-loop detection ---
-//
-// Four vertices per thread (dword / dwordx4 accesses of the padded workspace arrays).
+// Troublemaker detection, tile by tile (see k_label_final for the order).
+template <int NDIM>
 __global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ dirs_f,
                                                   const uint8_t* __restrict__ dirs_g,
                                                   const int* __restrict__ q_up,
@@ -692,31 +741,56 @@ __global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ di
                                                   const int* __restrict__ mf, Grid gr,
                                                   uint8_t* __restrict__ marks,
                                                   unsigned* __restrict__ cnt) {
+    constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
     unsigned wrong = 0, cases = 0;
-    const int n = gr.n;
-    const int ng = (n + 3) >> 2;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
-        const unsigned df4 = reinterpret_cast<const unsigned*>(dirs_f)[w];
-        const unsigned dg4 = reinterpret_cast<const unsigned*>(dirs_g)[w];
-        const int4 qu4 = reinterpret_cast<const int4*>(q_up)[w];
-        const int4 qd4 = reinterpret_cast<const int4*>(q_dn)[w];
-        const int4 Mf4 = reinterpret_cast<const int4*>(Mf)[w];
-        const int4 mf4 = reinterpret_cast<const int4*>(mf)[w];
-        const int qu[4] = {qu4.x, qu4.y, qu4.z, qu4.w}, qd[4] = {qd4.x, qd4.y, qd4.z, qd4.w};
-        const int Mv[4] = {Mf4.x, Mf4.y, Mf4.z, Mf4.w}, mv[4] = {mf4.x, mf4.y, mf4.z, mf4.w};
+    const ItemRange range = xcd_items(label_tiles_of(gr));
+    for (int tile = range.first; tile < range.hi; tile += range.stride) {
+        int qu[G][4], qd[G][4], Mv[G][4], mv[G][4];
+        unsigned df4[G], dg4[G];
+        TileGroup<NDIM> tg[G];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = 4 * w + j;
-            if (i >= n) break;
-            const unsigned df = (df4 >> (8 * j)) & 0xFFu, dg = (dg4 >> (8 * j)) & 0xFFu;
-            const bool wM = q_up[qu[j]] != Mv[j];
-            const bool wm = q_dn[qd[j]] != mv[j];
-            wrong += wM || wm;
-            const bool rmin = wm && ((dg & 15u) != (df & 15u));
-            const bool rmax = wM && ((dg >> 4) != (df >> 4));
-            cases += rmin + rmax;
-            if (rmin) mark(marks, i + gr.off[df & 15u]);
-            if (rmax) mark(marks, i + gr.off[dg >> 4]);
+        for (int k = 0; k < G; ++k) {
+            tg[k] = tile_group<NDIM>(gr, tile, k);
+            const int i0 = tg[k].i0;
+            df4[k] = dg4[k] = 0xFFFFFFFFu;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qu[k][j] = qd[k][j] = Mv[k][j] = mv[k][j] = 0;
+            if (tg[k].vec) {
+                df4[k] = *reinterpret_cast<const unsigned*>(dirs_f + i0);
+                dg4[k] = *reinterpret_cast<const unsigned*>(dirs_g + i0);
+                const int4 u = *reinterpret_cast<const int4*>(q_up + i0);
+                const int4 d = *reinterpret_cast<const int4*>(q_dn + i0);
+                const int4 U = *reinterpret_cast<const int4*>(Mf + i0);
+                const int4 D = *reinterpret_cast<const int4*>(mf + i0);
+                qu[k][0] = u.x, qu[k][1] = u.y, qu[k][2] = u.z, qu[k][3] = u.w;
+                qd[k][0] = d.x, qd[k][1] = d.y, qd[k][2] = d.z, qd[k][3] = d.w;
+                Mv[k][0] = U.x, Mv[k][1] = U.y, Mv[k][2] = U.z, Mv[k][3] = U.w;
+                mv[k][0] = D.x, mv[k][1] = D.y, mv[k][2] = D.z, mv[k][3] = D.w;
+            } else {
+                for (int j = 0; j < tg[k].count; ++j) {
+                    const int i = i0 + j;
+                    df4[k] = (df4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_f[i]) << (8 * j));
+                    dg4[k] = (dg4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_g[i]) << (8 * j));
+                    qu[k][j] = q_up[i], qd[k][j] = q_dn[i], Mv[k][j] = Mf[i], mv[k][j] = mf[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j >= tg[k].count) continue;
+                const int i = tg[k].i0 + j;
+                const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
+                const bool wM = q_up[qu[k][j]] != Mv[k][j];
+                const bool wm = q_dn[qd[k][j]] != mv[k][j];
+                wrong += wM || wm;
+                const bool rmin = wm && ((dg & 15u) != (df & 15u));
+                const bool rmax = wM && ((dg >> 4) != (df >> 4));
+                cases += rmin + rmax;
+                if (rmin) mark(marks, i + gr.off[df & 15u]);
+                if (rmax) mark(marks, i + gr.off[dg >> 4]);
+            }
         }
     }
     unsigned v[2] = {wrong, cases};
@@ -816,13 +890,17 @@ struct DirsVariant {
     int ty, zc;
 };
 // Tile variants selectable per launch (index 1..); index 0 is the default.
-static const DirsVariant kVariants2D[] = {{16, 1}, {16, 1}, {8, 1}, {4, 1}};
-static const DirsVariant kVariants3D[] = {{8, 16}, {16, 16}, {8, 16}, {4, 32}, {16, 8}, {8, 8}};
+static const DirsVariant kVariants2D[] = {{16, 1}, {16, 1}, {32, 1}};
+static const DirsVariant kVariants3D[] = {{16, 16}, {16, 16}, {16, 8}, {16, 32}, {32, 16}};
 
 int tile_variant_count(int ndim) {
     return ndim == 2 ? static_cast<int>(sizeof(kVariants2D) / sizeof(kVariants2D[0])) - 1
                      : static_cast<int>(sizeof(kVariants3D) / sizeof(kVariants3D[0])) - 1;
 }
+
+// Persistent grid: at most kDirsBlocks blocks (8 per compute unit), each walking
+// a contiguous run of work items of its XCD.
+constexpr int kDirsBlocks = 2048;
 
 template <int NDIM, int TY, int ZC, int MODE>
 static void launch_dirs_t(const float* h, const Grid& gr, uint8_t* dirs_out, const uint8_t* dirs_f,
@@ -830,9 +908,10 @@ static void launch_dirs_t(const float* h, const Grid& gr, uint8_t* dirs_out, con
     const int tx = (gr.nx + kTileX - 1) / kTileX;
     const int ty = (gr.ny + TY - 1) / TY;
     const int tz = NDIM == 3 ? (gr.nz + ZC - 1) / ZC : 1;
-    const int nb = tx * ty * tz;
-    hipLaunchKernelGGL((k_dirs<NDIM, TY, ZC, MODE>), dim3(nb), dim3(16 * TY), 0, s, h, gr, dirs_out,
-                       dirs_f, type, marks, cnt);
+    const int items = tx * ty * tz;
+    const int nb = items < kDirsBlocks ? items : kDirsBlocks;
+    hipLaunchKernelGGL((k_dirs<NDIM, TY, ZC, MODE>), dim3(nb), dim3(256), 0, s, h, gr, dirs_out, dirs_f, type,
+                       marks, cnt);
 }
 
 template <int MODE>
@@ -840,17 +919,14 @@ static void launch_dirs_mode(const float* h, const Grid& gr, int variant, uint8_
                              const uint8_t* dirs_f, int type, uint8_t* marks,
                              unsigned* cnt, hipStream_t s) {
     if (gr.ndim == 2) {
-        const int ty = kVariants2D[variant].ty;
-        if (ty == 16) launch_dirs_t<2, 16, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else if (ty == 8) launch_dirs_t<2, 8, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else launch_dirs_t<2, 4, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        if (kVariants2D[variant].ty == 32) launch_dirs_t<2, 32, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else launch_dirs_t<2, 16, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
     } else {
         const DirsVariant v = kVariants3D[variant];
-        if (v.ty == 16 && v.zc == 16) launch_dirs_t<3, 16, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else if (v.ty == 8 && v.zc == 16) launch_dirs_t<3, 8, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else if (v.ty == 4 && v.zc == 32) launch_dirs_t<3, 4, 32, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else if (v.ty == 16 && v.zc == 8) launch_dirs_t<3, 16, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else launch_dirs_t<3, 8, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        if (v.ty == 32) launch_dirs_t<3, 32, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else if (v.zc == 8) launch_dirs_t<3, 16, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else if (v.zc == 32) launch_dirs_t<3, 16, 32, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        else launch_dirs_t<3, 16, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
     }
 }
 
@@ -866,7 +942,7 @@ void launch_dirs_detect(const float* g, const Grid& gr, int variant, uint8_t* di
 
 void launch_detect_only(const uint8_t* dirs_f, const uint8_t* dirs_g, const Grid& gr, int type,
                         uint8_t* marks, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_detect_only, dim3(blocks_for((gr.n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, dirs_f,
+    hipLaunchKernelGGL(k_detect_only, dim3(blocks_for((gr.n + 15) / 16, 256, kGridCap)), dim3(256), 0, s, dirs_f,
                        dirs_g, gr, type, marks, cnt);
 }
 
@@ -875,23 +951,15 @@ void launch_apply(float* g, const float* L, uint8_t* marks, int n, unsigned* cnt
                        marks, n, cnt);
 }
 
-static int label_tiles(const Grid& gr) {
-    if (gr.ndim == 2) {
-        using T = LabelTile<2>;
-        return ((gr.nx + T::X - 1) / T::X) * ((gr.ny + T::Y - 1) / T::Y);
-    }
-    using T = LabelTile<3>;
-    return ((gr.nx + T::X - 1) / T::X) * ((gr.ny + T::Y - 1) / T::Y) * ((gr.nz + T::Z - 1) / T::Z);
-}
 
 void launch_label_tile(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, hipStream_t s) {
-    const int nb = label_tiles(gr);
+    const int nb = label_tiles_of(gr);
     if (gr.ndim == 2) hipLaunchKernelGGL(k_label_tile<2>, dim3(nb), dim3(256), 0, s, dirs, gr, q_up, q_dn);
     else hipLaunchKernelGGL(k_label_tile<3>, dim3(nb), dim3(256), 0, s, dirs, gr, q_up, q_dn);
 }
 
 void launch_label_compress(const Grid& gr, int* q_up, int* q_dn, unsigned* cnt, hipStream_t s) {
-    const int nb = label_tiles(gr);
+    const int nb = label_tiles_of(gr);
     if (gr.ndim == 2) hipLaunchKernelGGL(k_label_compress<2>, dim3(nb), dim3(256), 0, s, gr, q_up, q_dn, cnt);
     else hipLaunchKernelGGL(k_label_compress<3>, dim3(nb), dim3(256), 0, s, gr, q_up, q_dn, cnt);
 }
@@ -902,16 +970,22 @@ void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q
     launch_label_compress(gr, q_up, q_dn, cnt, s);
 }
 
-void launch_label_final(const int* q_up, const int* q_dn, int n, int* M, int* m, hipStream_t s) {
-    hipLaunchKernelGGL(k_label_final, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, q_up, q_dn,
-                       n, M, m);
+void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, hipStream_t s) {
+    const int nt = label_tiles_of(gr);
+    const int nb = nt < kDirsBlocks ? nt : kDirsBlocks;
+    if (gr.ndim == 2) hipLaunchKernelGGL(k_label_final<2>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m);
+    else hipLaunchKernelGGL(k_label_final<3>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m);
 }
 
 void launch_detect_r(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* q_up, const int* q_dn,
-                     const int* Mf, const int* mf, const Grid& gr, uint8_t* marks,
-                     unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_detect_r, dim3(blocks_for((gr.n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, dirs_f,
-                       dirs_g, q_up, q_dn, Mf, mf, gr, marks, cnt);
+                     const int* Mf, const int* mf, const Grid& gr, uint8_t* marks, unsigned* cnt,
+                     hipStream_t s) {
+    const int nt = label_tiles_of(gr);
+    const int nb = nt < kDirsBlocks ? nt : kDirsBlocks;
+    if (gr.ndim == 2)
+        hipLaunchKernelGGL(k_detect_r<2>, dim3(nb), dim3(256), 0, s, dirs_f, dirs_g, q_up, q_dn, Mf, mf, gr, marks, cnt);
+    else
+        hipLaunchKernelGGL(k_detect_r<3>, dim3(nb), dim3(256), 0, s, dirs_f, dirs_g, q_up, q_dn, Mf, mf, gr, marks, cnt);
 }
 
 void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu, const int* qfd,

@@ -1,0 +1,193 @@
+"""GPU parity of the learned warm start: BF16/MFMA convolution kernels, their
+gradients, the optimiser and the warm-started fix, against oracle/net_ref.py.
+
+Tolerances (derived, not tuned):
+  * products of BF16 values are exact in FP32; FP32 accumulation of K terms is
+    off by at most K * 2^-24 * S, S = sum of |terms| (K <= 432, so < 2^-15 S);
+  * a stored BF16 value is off by at most 2^-9 relative (round to nearest);
+  * a layer whose input is a BF16 tensor the GPU rounded itself may see any
+    element 1 BF16 ulp (2^-8 relative) away from the oracle's, which moves a
+    sum by at most 2^-8 * S.
+So a pre-activation or gradient sum may differ by (2^-8 + 2^-15) S, a stored
+BF16 output additionally by 2^-8 of itself; the tests allow 2^-7 S + 2^-8 |y|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import net_ref as nr
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def msz():
+    import paper_2406_09423_amd as m
+    assert torch.cuda.is_available()
+    m.lib()
+    return m
+
+
+def flat_params(params) -> np.ndarray:
+    """Oracle (W[co][ci][3][3][3], b) per layer -> the library's flat FP32 layout."""
+    out = []
+    cin_store = (8, 16, 16)
+    for li, (W, b) in enumerate(params):
+        co, ci = W.shape[:2]
+        Wt = W.reshape(co, ci, 27).transpose(2, 1, 0)           # [tap][ci][co]
+        if li < 2:
+            full = np.zeros((27, cin_store[li], 16))
+            full[:, :ci, :co] = Wt
+            out += [full.ravel(), b.astype(np.float64)]
+        else:
+            out += [Wt[:, :, 0].ravel(), b.astype(np.float64)]
+    flat = np.concatenate(out).astype(np.float32)
+    assert flat.size == 10833
+    return flat
+
+
+def unflat_grads(g: np.ndarray):
+    """Library gradient layout -> oracle shapes (dW[co][ci][3][3][3], db)."""
+    o = 0
+    res = []
+    for li, (cin, cstore, cout) in enumerate(((6, 8, 16), (16, 16, 16), (16, 16, 1))):
+        if li < 2:
+            W = g[o:o + 27 * cstore * 16].reshape(27, cstore, 16)[:, :cin, :cout]
+            o += 27 * cstore * 16
+        else:
+            W = g[o:o + 27 * 16].reshape(27, 16, 1)
+            o += 27 * 16
+        b = g[o:o + cout]
+        o += cout
+        res.append((W.transpose(2, 1, 0).reshape(cout, cin, 3, 3, 3).astype(np.float64), b.astype(np.float64)))
+    return res
+
+
+def bf16_bits(x: np.ndarray) -> np.ndarray:
+    """float values (already BF16-representable) -> raw int16 bits."""
+    return (nr.bf16(x).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+
+
+def bits_to_float(b: np.ndarray) -> np.ndarray:
+    return (b.view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def feature_case(shape, seed, xi=0.01):
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0, 1, size=shape).astype(np.float32)
+    fh = (f + rng.uniform(-xi, xi, size=shape)).astype(np.float32)
+    fh = np.where(np.abs(f.astype(np.float64) - fh) > xi, f, fh).astype(np.float32)
+    bits = oracle.case_flags(f, fh) if len(shape) == 3 else oracle.case_flags(f[0], fh[0])[None]
+    x = nr.features(fh, xi, bits & 15, float(f.max()) - float(f.min()))
+    return f, fh, np.float32(xi), x
+
+
+def to_dev_feat(x: np.ndarray):
+    n = x[0].size
+    feat = np.zeros((n, 8), np.float64)
+    feat[:, :6] = x.reshape(6, -1).T
+    return torch.from_numpy(bf16_bits(feat)).cuda()
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    params = nr.init_params(seed)
+    return [(W, rng.uniform(0.0, 0.2, size=b.shape)) for W, b in params]
+
+
+SHAPES = [(6, 9, 20), (1, 17, 33), (9, 8, 16)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_features_match_oracle(msz, shape):
+    f, fh, xi, x = feature_case(shape, 1)
+    got = msz.net_features(torch.from_numpy(f).cuda(), torch.from_numpy(fh).cuda(), xi).cpu().numpy()
+    g = bits_to_float(got)
+    ref = nr.bf16(x).reshape(6, -1).T
+    assert np.array_equal(g[:, 1:6], ref[:, 1:6])                 # xi channel and flags exactly
+    assert np.all(g[:, 6:] == 0)
+    # channel 0: same double-precision formula summed in another order; one BF16 ulp at most
+    assert np.all(np.abs(g[:, 0] - ref[:, 0]) <= 2.0 ** -7 * np.abs(ref[:, 0]) + 1e-30)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_forward_layers_match_oracle(msz, shape):
+    """Every layer's output within the propagated bound: the oracle runs on its own
+    activations; the bound of layer l+1 adds conv(|W|, bound of layer l)."""
+    f, fh, xi, x = feature_case(shape, 2)
+    params = random_params(3)
+    flat = torch.from_numpy(flat_params(params)).cuda()
+    p, a1, a2 = msz.net_forward(flat, to_dev_feat(x), shape, hidden=True)
+    p, a1, a2 = p.cpu().numpy(), bits_to_float(a1.cpu().numpy()), bits_to_float(a2.cpu().numpy())
+    act = nr.bf16(x)                  # the GPU is fed exactly these BF16 features
+    bound_in = np.zeros_like(act)
+    for li, (W, b) in enumerate(params):
+        Wq = nr.bf16(W)
+        z = nr.conv3d(act, Wq, b)
+        S = nr.conv3d(np.abs(act), np.abs(Wq), np.abs(b))
+        carried = nr.conv3d(bound_in, np.abs(Wq), np.zeros_like(b))
+        y = np.maximum(z, 0.0) if li < 2 else z     # linear output layer
+        got = (a1, a2)[li].T[: W.shape[0]].reshape(z.shape) if li < 2 else p.reshape(z[0].shape)[None]
+        bound = 2.0 ** -7 * S + carried + 2.0 ** -8 * np.abs(y) + 1e-30
+        assert np.all(np.abs(got - y) <= bound), (li, float(np.max(np.abs(got - y) - bound)))
+        act = nr.bf16(y) if li < 2 else y
+        bound_in = bound + 2.0 ** -8 * np.abs(y)
+
+
+def test_gradients_match_oracle(msz):
+    """Parameter gradients of the MSE against the oracle's float64 backward.
+
+    Every BF16 tensor on the GPU path (three activations, three gradients
+    through ReLU) adds at most 2^-8 relative error per element, and the
+    residual p - t inherits the forward error; about six such terms bound the
+    relative error of a gradient tensor by 6 * 2^-8 < 2^-5."""
+    shape = (6, 9, 20)
+    f, fh, xi, x = feature_case(shape, 4)
+    params = random_params(5)
+    rng = np.random.default_rng(6)
+    t = rng.uniform(0.5, 2.0, size=shape).astype(np.float32)
+    flat = torch.from_numpy(flat_params(params)).cuda()
+    loss, g = msz.net_gradients(flat, to_dev_feat(x), torch.from_numpy(t.ravel()).cuda(), shape)
+    gg = unflat_grads(g.cpu().numpy())
+    p, cache = nr.forward(x, params, round_bf16=True)
+    lo, dp = nr.mse_loss(p, t.astype(np.float64))
+    ref = nr.backward(cache, dp)
+    assert abs(loss - lo) <= 2.0 ** -5 * lo
+    for li in range(3):
+        for k in range(2):
+            got, want = gg[li][k], ref[li][k]
+            assert np.linalg.norm(got - want) <= 2.0 ** -5 * np.linalg.norm(want) + 1e-12, (li, k)
+            cos = float((got * want).sum() / (np.linalg.norm(got) * np.linalg.norm(want) + 1e-30))
+            assert cos > 0.999, (li, k, cos)
+
+
+def test_adam_matches_oracle(msz):
+    rng = np.random.default_rng(7)
+    w0 = rng.normal(size=10833)
+    g = [rng.normal(size=10833) for _ in range(3)]
+    w = torch.from_numpy(w0.astype(np.float32)).cuda()
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    wr, mr, vr = w0.astype(np.float32).astype(np.float64), np.zeros(10833), np.zeros(10833)
+    for k, gk in enumerate(g, start=1):
+        gt = torch.from_numpy(gk.astype(np.float32)).cuda()
+        msz.net_adam(w, gt, m, v, k, 1e-3)
+        wr, mr, vr = nr.adam_step(wr, gk.astype(np.float32).astype(np.float64), mr, vr, k, 1e-3)
+    assert np.allclose(w.cpu().numpy(), wr, rtol=0, atol=1e-6)
+
+
+def test_fix_learned_converges(msz):
+    """Any prediction only moves the start inside [L, fhat]; the loop still reaches zero error."""
+    import synth
+    f, fh, xi = synth.turb3d(n=48, nblobs=4)[0]
+    params = random_params(8)
+    flat = torch.from_numpy(flat_params(params)).cuda()
+    fd, fhd = torch.from_numpy(f).cuda(), torch.from_numpy(fh).cuda()
+    rc, d, g, st = msz.fix_learned(fd, fhd, xi, flat, timing=True)
+    assert rc == msz.OK, st
+    cnt = msz.count_false(fd, g)
+    assert all(v == 0 for v in cnt.values())
+    gh = g.cpu().numpy()
+    assert (np.abs(f.astype(np.float64) - gh) <= float(xi)).all()
+    assert st["timing"]["net"]["launches"] == 1
