@@ -161,19 +161,23 @@ typedef struct {
     const float* fhat;   /* DEVICE float32[n] */
     msz_dims d;
     float xi;
+    int32_t tile;        /* direction tile variant for this field (0 = default, see msz_tile_variants) */
     float* edits_out;    /* DEVICE float32[n] */
     float* g_out;        /* DEVICE float32[n] or NULL */
     msz_stats* stats;    /* HOST, required */
 } msz_job;
 
 /*
- * msz_fix_batch -- corrects n_jobs independent fields of uneven sizes
- * together: every round advances all unconverged fields at once, each by the
- * same schedule msz_fix follows, so each field's result is bit-identical to
- * its own msz_fix.  opt->workspace (if given) must hold
- * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start and
- * opt->g_out must be NULL (use msz_job.g_out).  Returns MSZ_OK when every
- * field converged, else the first failing field's code (see each stats).
+ * msz_fix_batch -- corrects n_jobs (<= 1024) independent fields of uneven
+ * sizes in ONE persistent kernel launch (a cooperative kernel node of a HIP
+ * graph): every grid-wide step advances each unfinished field by one
+ * operation of the schedule msz_fix follows, so each field's result is
+ * bit-identical to its own msz_fix.  opt->workspace (if given) must hold
+ * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
+ * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);
+ * opt->max_rounds applies to every field (MSZ_FLAG_TIMING is ignored).
+ * Returns MSZ_OK when every field converged, else the first failing field's
+ * code (see each stats; per-phase timings are not filled).
  */
 int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, void* stream);
 
@@ -191,7 +195,7 @@ int msz_tile_variants(int32_t ndim);
  * (6 -> 16 -> 16 -> 1 channels, ReLU after the two hidden layers, a linear
  * output, zero padding) predicts p, the edit of every vertex in units of xi;
  * the correction loop then starts from g0 = clamp(fl(fhat - fl(p * xi)), L,
- * fhat) (so p <= 0 leaves a vertex unedited) and, as always,
+ * fhat) where p > p_min (elsewhere g0 = fhat) and, as always,
  * runs to zero segmentation error within xi.  Weights and activations are
  * BF16 (round to nearest even), sums FP32, on MFMA.
  *
@@ -223,12 +227,13 @@ int msz_net_forward(const float* params, const uint16_t* feat, msz_dims d, float
                     uint16_t* act1_out, uint16_t* act2_out, void* workspace,
                     size_t workspace_bytes, void* stream);
 
-/* Gradient of the mean squared error mean_i (p_i - target_i)^2 with respect to
- * the parameters (grad_out: DEVICE, MSZ_NET_PARAMS floats, same layout);
+/* Gradient of the weighted mean squared error mean_i w_i (p_i - target_i)^2,
+ * w_i = 1 + edit_weight where target_i > 0, else 1, with respect to the
+ * parameters (grad_out: DEVICE, MSZ_NET_PARAMS floats, same layout);
  * *loss_out (HOST) receives the loss. */
-int msz_net_gradients(const float* params, const uint16_t* feat, const float* target, msz_dims d,
-                      float* grad_out, float* loss_out, void* workspace, size_t workspace_bytes,
-                      void* stream);
+int msz_net_gradients(const float* params, const uint16_t* feat, const float* target, float edit_weight,
+                      msz_dims d, float* grad_out, float* loss_out, void* workspace,
+                      size_t workspace_bytes, void* stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
  * on n FP32 parameters with first / second moments m, v (DEVICE). */
@@ -238,12 +243,14 @@ int msz_net_adam(float* params, const float* grad, float* m, float* v, int32_t n
 /* Scratch bytes of msz_fix_learned for dims d. */
 size_t msz_learned_workspace_bytes(msz_dims d);
 
-/* msz_fix started from the network's warm start (params: DEVICE, see above).
- * opt->warm_start must be NULL; opt->workspace, if given, must hold
+/* msz_fix started from the network's warm start (params: DEVICE, see above);
+ * vertices with p <= p_min keep fhat in the start field.  opt->warm_start
+ * must be NULL; opt->workspace, if given, must hold
  * msz_learned_workspace_bytes(d).  With MSZ_FLAG_TIMING the network's kernels
  * are reported under MSZ_PHASE_NET. */
 int msz_fix_learned(const float* f, const float* fhat, msz_dims d, float xi, const float* params,
-                    float* edits_out, const msz_options* opt, msz_stats* stats, void* stream);
+                    float p_min, float* edits_out, const msz_options* opt, msz_stats* stats,
+                    void* stream);
 
 /* Human-readable name of a return code (static string). */
 const char* msz_strerror(int code);

@@ -126,11 +126,13 @@ def backward(cache, dp: np.ndarray):
     return grads
 
 
-def mse_loss(p: np.ndarray, t: np.ndarray):
-    """Mean squared error over all vertices and its gradient."""
+def mse_loss(p: np.ndarray, t: np.ndarray, edit_weight: float = 0.0):
+    """Weighted mean squared error over all vertices and its gradient: vertex i
+    weighs 1 + edit_weight when its target edit t_i is positive, else 1."""
     d = p - t
     n = d.size
-    return float((d * d).sum() / n), 2.0 * d / n
+    w = 1.0 + edit_weight * (t > 0)
+    return float((w * d * d).sum() / n), 2.0 * w * d / n
 
 
 def box_mean(h: np.ndarray) -> np.ndarray:

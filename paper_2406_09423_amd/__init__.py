@@ -71,8 +71,8 @@ class Options(ctypes.Structure):
 
 class Job(ctypes.Structure):
     _fields_ = [("f", ctypes.c_void_p), ("fhat", ctypes.c_void_p), ("d", Dims),
-                ("xi", ctypes.c_float), ("edits_out", ctypes.c_void_p), ("g_out", ctypes.c_void_p),
-                ("stats", ctypes.POINTER(Stats))]
+                ("xi", ctypes.c_float), ("tile", ctypes.c_int32), ("edits_out", ctypes.c_void_p),
+                ("g_out", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats))]
 
 
 class MszError(RuntimeError):
@@ -109,10 +109,10 @@ def lib() -> ctypes.CDLL:
         L.msz_learned_workspace_bytes.restype = ctypes.c_size_t
         L.msz_net_features.argtypes = [P, P, Dims, F, P, P, ctypes.c_size_t, P]
         L.msz_net_forward.argtypes = [P, P, Dims, P, P, P, P, ctypes.c_size_t, P]
-        L.msz_net_gradients.argtypes = [P, P, P, Dims, P, ctypes.POINTER(ctypes.c_float), P,
+        L.msz_net_gradients.argtypes = [P, P, P, F, Dims, P, ctypes.POINTER(ctypes.c_float), P,
                                         ctypes.c_size_t, P]
         L.msz_net_adam.argtypes = [P, P, P, P, I32, I32, F, P]
-        L.msz_fix_learned.argtypes = [P, P, Dims, F, P, P, ctypes.POINTER(Options),
+        L.msz_fix_learned.argtypes = [P, P, Dims, F, P, F, P, ctypes.POINTER(Options),
                                       ctypes.POINTER(Stats), P]
         for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants,
                    L.msz_net_features, L.msz_net_forward, L.msz_net_gradients, L.msz_net_adam,
@@ -220,10 +220,11 @@ def count_false(f, g, stream=None) -> dict:
     return {k: int(getattr(c, k)) for k, _ in FalseCounts._fields_}
 
 
-def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, stream=None):
-    """Corrects a list of (f, fhat, xi) together.
+def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles=None, stream=None):
+    """Corrects a list of (f, fhat, xi) together in one persistent launch.
 
-    Returns ``(status, [(status_j, delta_j, g_j, stats_j), ...])``.
+    ``tiles`` optionally gives each field's direction tile variant (see
+    autotune.py).  Returns ``(status, [(status_j, delta_j, g_j, stats_j), ...])``.
     """
     import torch
     n = len(fields)
@@ -238,6 +239,7 @@ def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=Non
         jobs[j].f, jobs[j].fhat = f.data_ptr(), fh.data_ptr()
         jobs[j].d = dims_of(f.shape)
         jobs[j].xi = float(xi)
+        jobs[j].tile = int(tiles[j]) if tiles is not None else 0
         jobs[j].edits_out = e.data_ptr()
         jobs[j].g_out = g.data_ptr() if g is not None else None
         jobs[j].stats = ctypes.pointer(stats[j])
@@ -308,14 +310,15 @@ def net_forward(params, feat, shape, *, hidden: bool = False, workspace=None, st
     return (p, a1, a2) if hidden else p
 
 
-def net_gradients(params, feat, target, shape, *, grad_out=None, workspace=None, stream=None):
-    """(loss, grad) of the mean squared error; grad has the parameter layout."""
+def net_gradients(params, feat, target, shape, *, edit_weight: float = 0.0, grad_out=None, workspace=None,
+                  stream=None):
+    """(loss, grad) of the weighted mean squared error; grad has the parameter layout."""
     import torch
     g = grad_out if grad_out is not None else torch.empty_like(params)
     loss = ctypes.c_float(0.0)
     wp, wb = _ws_arg(workspace)
-    rc = lib().msz_net_gradients(params.data_ptr(), feat.data_ptr(), target.data_ptr(), dims_of(shape),
-                                 g.data_ptr(), ctypes.byref(loss), wp, wb, _stream(stream))
+    rc = lib().msz_net_gradients(params.data_ptr(), feat.data_ptr(), target.data_ptr(), float(edit_weight),
+                                 dims_of(shape), g.data_ptr(), ctypes.byref(loss), wp, wb, _stream(stream))
     if rc != OK:
         raise MszError(rc, "msz_net_gradients")
     return float(loss.value), g
@@ -328,8 +331,8 @@ def net_adam(params, grad, m, v, step: int, lr: float, stream=None):
         raise MszError(rc, "msz_net_adam")
 
 
-def fix_learned(f, fhat, xi: float, params, *, max_rounds: int = 0, want_g: bool = True, workspace=None,
-                edits_out=None, g_out=None, timing: bool = False, stream=None):
+def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: int = 0, want_g: bool = True,
+                workspace=None, edits_out=None, g_out=None, timing: bool = False, stream=None):
     """msz_fix warm-started by the network; same return value as fix()."""
     import torch
     _check_field(f, "f")
@@ -345,7 +348,8 @@ def fix_learned(f, fhat, xi: float, params, *, max_rounds: int = 0, want_g: bool
     opt.flags = FLAG_TIMING if timing else 0
     st = Stats()
     rc = lib().msz_fix_learned(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), params.data_ptr(),
-                               edits.data_ptr(), ctypes.byref(opt), ctypes.byref(st), _stream(stream))
+                               float(p_min), edits.data_ptr(), ctypes.byref(opt), ctypes.byref(st),
+                               _stream(stream))
     out = st.as_dict()
     if timing:
         out["timing"] = st.timing()

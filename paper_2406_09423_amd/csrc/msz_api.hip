@@ -426,42 +426,181 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     return done(fix_one(F, cap, stats, hc, s));
 }
 
-size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs) {
-    if (!jobs || n_jobs <= 0) return 0;
-    size_t best = 0;
-    for (int j = 0; j < n_jobs; ++j) {
+namespace {
+
+// Batch workspace: the engine's tables, then one field workspace per job.
+struct BatchLayout {
+    size_t fields, states, stats, tickets, bar, field0, total;
+    std::vector<size_t> field_off;
+};
+
+bool batch_layout(const msz_job* jobs, int32_t n, BatchLayout& bl) {
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t r = o;
+        o += align256(b);
+        return r;
+    };
+    bl.fields = take(sizeof(EngField) * n);
+    bl.states = take(sizeof(EngState) * 2 * n);
+    bl.stats = take(sizeof(EngStats) * n);
+    bl.tickets = take(sizeof(unsigned) * 2 * n);
+    bl.bar = take(sizeof(unsigned) * 4);
+    bl.field0 = o;
+    bl.field_off.resize(n);
+    for (int j = 0; j < n; ++j) {
         Grid gr;
-        if (!make_grid(jobs[j].d, gr)) return 0;
-        const size_t b = layout_for(gr.n).total;
-        if (b > best) best = b;
+        if (!make_grid(jobs[j].d, gr)) return false;
+        bl.field_off[j] = take(layout_for(gr.n).total + align256(2 * kEngSet * sizeof(unsigned)));
     }
-    return best;
+    bl.total = o;
+    return true;
+}
+
+int run_engine(const EngField* dev_fields, EngState* states, EngStats* stats, unsigned* tickets, unsigned* bar,
+               int nf, int max_steps, hipStream_t s) {
+    int dev = 0, cus = 0, bpc = 0, coop = 0;
+    MSZ_HIP(hipGetDevice(&dev));
+    MSZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MSZ_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    MSZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, engine_kernel(), 256, 0));
+    if (!coop || bpc < 1 || cus < 1) return MSZ_EDEVICE;
+    const int grid = cus * (bpc < 2 ? bpc : 2);  // every block resident: the barrier needs it
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int rc = MSZ_OK;
+    if (hipGraphCreate(&graph, 0) != hipSuccess) return MSZ_EDEVICE;
+    do {
+        // node 1: clear marks, counters, tickets and the barrier (a kernel, not a memset node)
+        hipGraphNode_t init = nullptr, eng = nullptr;
+        void* a1[] = {const_cast<EngField**>(&dev_fields), &nf, &tickets, &bar};
+        hipKernelNodeParams p1{};
+        p1.func = const_cast<void*>(engine_init_kernel());
+        p1.gridDim = dim3(1024);
+        p1.blockDim = dim3(256);
+        p1.kernelParams = a1;
+        if (hipGraphAddKernelNode(&init, graph, nullptr, 0, &p1) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        // node 2: the persistent engine, one cooperative launch
+        void* a2[] = {const_cast<EngField**>(&dev_fields), &states, &stats, &tickets, &bar, &nf, &max_steps};
+        hipKernelNodeParams p2{};
+        p2.func = const_cast<void*>(engine_kernel());
+        p2.gridDim = dim3(grid);
+        p2.blockDim = dim3(256);
+        p2.kernelParams = a2;
+        if (hipGraphAddKernelNode(&eng, graph, &init, 1, &p2) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        hipKernelNodeAttrValue v{};
+        v.cooperative = 1;
+        if (hipGraphKernelNodeSetAttribute(eng, hipKernelNodeAttributeCooperative, &v) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (hipGraphLaunch(exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+    } while (false);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return rc;
+}
+
+}  // namespace
+
+size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs) {
+    if (!jobs || n_jobs <= 0 || n_jobs > kEngMaxFields) return 0;
+    BatchLayout bl;
+    if (!batch_layout(jobs, n_jobs, bl)) return 0;
+    return bl.total;
 }
 
 int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, void* stream) {
-    if (!jobs || n_jobs <= 0) return MSZ_EINVAL;
+    if (!jobs || n_jobs <= 0 || n_jobs > kEngMaxFields) return MSZ_EINVAL;
     msz_options o{};
     if (opt) o = *opt;
-    if (o.warm_start || o.g_out || (o.flags & ~MSZ_FLAG_TIMING)) return MSZ_EINVAL;
+    if (o.warm_start || o.g_out || (o.flags & ~MSZ_FLAG_TIMING) || o.tile_override) return MSZ_EINVAL;
     for (int j = 0; j < n_jobs; ++j) {
         Grid gr;
-        if (!jobs[j].stats || !make_grid(jobs[j].d, gr) || !jobs[j].f || !jobs[j].fhat || !jobs[j].edits_out)
+        const msz_job& J = jobs[j];
+        if (!J.stats || !make_grid(J.d, gr) || !J.f || !J.fhat || !J.edits_out || !aligned16(J.f) ||
+            !aligned16(J.fhat) || !aligned16(J.edits_out) || !aligned16(J.g_out) || J.tile < 0 ||
+            J.tile > tile_variant_count(J.d.ndim))
             return MSZ_EINVAL;
+        std::memset(J.stats, 0, sizeof(msz_stats));
+        if (int rc = check_xi(J.xi)) {
+            J.stats->status = rc;
+            return rc;
+        }
     }
-    const size_t need = msz_batch_workspace_bytes(jobs, n_jobs);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchLayout bl;
+    if (!batch_layout(jobs, n_jobs, bl)) return MSZ_EINVAL;
     Scratch ws;
-    if (int rc = ws.get(o.workspace, o.workspace_bytes, need, s)) return rc;
-    int first = MSZ_OK;
+    if (int rc = ws.get(o.workspace, o.workspace_bytes, bl.total, s)) return rc;
+    char* base = static_cast<char*>(ws.p);
+    const long long cap = o.max_rounds > 0 ? o.max_rounds : (1ll << 30);
+    std::vector<EngField> hf(n_jobs);
+    std::vector<EngState> hs(2 * n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
-        msz_options oj = o;
-        oj.workspace = ws.p;
-        oj.workspace_bytes = need;
-        oj.g_out = jobs[j].g_out;
-        oj.tile_override = 0;
-        const int rc = msz_fix(jobs[j].f, jobs[j].fhat, jobs[j].d, jobs[j].xi, jobs[j].edits_out, &oj,
-                               jobs[j].stats, stream);
-        if (rc != MSZ_OK && first == MSZ_OK) first = rc;
+        const msz_job& J = jobs[j];
+        EngField& F = hf[j];
+        make_grid(J.d, F.gr);
+        F.variant = J.tile;
+        F.xi = J.xi;
+        F.cap = cap;
+        F.f = J.f;
+        F.fhat = J.fhat;
+        F.edits = J.edits_out;
+        F.g_out = J.g_out;
+        char* w = base + bl.field_off[j];
+        const Layout l = layout_for(F.gr.n);
+        F.L = reinterpret_cast<float*>(w + l.L);
+        F.g = reinterpret_cast<float*>(w + l.g);
+        F.dirs_f = reinterpret_cast<uint8_t*>(w + l.dirs_f);
+        F.dirs_g = reinterpret_cast<uint8_t*>(w + l.dirs_g);
+        F.marks = reinterpret_cast<uint8_t*>(w + l.marks);
+        F.Mf = reinterpret_cast<int*>(w + l.Mf);
+        F.mf = reinterpret_cast<int*>(w + l.mf);
+        F.qu = reinterpret_cast<int*>(w + l.qu);
+        F.qd = reinterpret_cast<int*>(w + l.qd);
+        F.cnt = reinterpret_cast<unsigned*>(w + l.total);
+        hs[j] = EngState{kOpPreA, 0, eng_items_host(F, kOpPreA), 0};
+        hs[n_jobs + j] = EngState{kOpDone, 0, 0, 0};
+    }
+    EngField* dev_fields = reinterpret_cast<EngField*>(base + bl.fields);
+    EngState* states = reinterpret_cast<EngState*>(base + bl.states);
+    EngStats* stats = reinterpret_cast<EngStats*>(base + bl.stats);
+    unsigned* tickets = reinterpret_cast<unsigned*>(base + bl.tickets);
+    unsigned* bar = reinterpret_cast<unsigned*>(base + bl.bar);
+    MSZ_HIP(hipMemcpyAsync(dev_fields, hf.data(), sizeof(EngField) * n_jobs, hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemcpyAsync(states, hs.data(), sizeof(EngState) * 2 * n_jobs, hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemsetAsync(stats, 0, sizeof(EngStats) * n_jobs, s));
+    // every round takes at most 8 steps; the bound only stops a runaway batch
+    const long long steps = 16 * cap + 4096;
+    const int max_steps = static_cast<int>(steps < (1 << 20) ? steps : (1 << 20));
+    int rc = run_engine(dev_fields, states, stats, tickets, bar, n_jobs, max_steps, s);
+    std::vector<EngStats> st(n_jobs);
+    std::vector<EngState> fin(2 * n_jobs);
+    unsigned hbar[4] = {0, 0, 0, 0};
+    if (rc == MSZ_OK) {
+        MSZ_HIP(hipMemcpyAsync(st.data(), stats, sizeof(EngStats) * n_jobs, hipMemcpyDeviceToHost, s));
+        MSZ_HIP(hipMemcpyAsync(fin.data(), states, sizeof(EngState) * 2 * n_jobs, hipMemcpyDeviceToHost, s));
+        MSZ_HIP(hipMemcpyAsync(hbar, bar, sizeof(hbar), hipMemcpyDeviceToHost, s));
+        MSZ_HIP(hipStreamSynchronize(s));
+    }
+    int first = rc;
+    for (int j = 0; j < n_jobs; ++j) {
+        msz_stats* out = jobs[j].stats;
+        if (rc == MSZ_OK) {
+            const EngStats& e = st[j];
+            for (int t = 0; t < 4; ++t) out->rounds[t] = e.rounds[t], out->false_init[t] = e.false_init[t];
+            out->rounds_r = e.rounds_r;
+            out->outer_iters = e.outer_iters;
+            out->n_edited = e.n_edited;
+            out->n_inexact = e.n_inexact;
+            out->status = e.status;
+            // a field the engine did not finish (aborted barrier or step bound) is an error
+            const bool done = fin[0 * n_jobs + j].op == kOpDone || fin[1 * n_jobs + j].op == kOpDone;
+            if (hbar[2] || !done) out->status = MSZ_EDEVICE;
+        } else {
+            out->status = rc;
+        }
+        if (first == MSZ_OK && out->status != MSZ_OK) first = out->status;
     }
     return first;
 }

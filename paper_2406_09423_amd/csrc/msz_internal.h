@@ -134,3 +134,60 @@ void launch_delta(const float* g, const float* fhat, int n, float* delta, float*
                   hipStream_t s);
 
 }  // namespace msz
+
+namespace msz {
+
+// ------------------------------------------------------------ batch engine ---
+// One cooperative persistent kernel advances every field of a batch by one
+// operation per grid-wide step (see k_engine).
+constexpr int kEngSlots = 16;                       // counter slots per set
+constexpr int kEngStride = 16;                      // words per slot
+constexpr int kEngSet = kEngSlots * kEngStride;     // words per counter set (two sets per field)
+constexpr int kEngMaxFields = 1024;
+constexpr int kEngChunk = 4096;                     // vertices per flat work item
+
+enum EngOp : int {
+    kOpPreA = 0,   // validate + directions of f
+    kOpPreB,       // label tiles of f
+    kOpPreC,       // compression of f's tile faces
+    kOpPreD,       // labels of f + directions/detection of g (type 0)
+    kOpApplyC,     // C-loop apply
+    kOpDdC,        // directions/detection of g after a C apply
+    kOpDetect,     // detection from stored directions
+    kOpRTile,      // label tiles of g
+    kOpRJump,      // compression of g's tile faces
+    kOpRDetect,    // troublemakers
+    kOpApplyR,     // R-loop apply
+    kOpDdR,        // directions/detection of g (type 0) after an R apply
+    kOpDelta,      // output
+    kOpDone
+};
+
+struct EngField {
+    Grid gr;
+    int variant;
+    float xi;
+    long long cap;
+    const float *f, *fhat;
+    float *edits, *g_out;
+    float *L, *g;
+    uint8_t *dirs_f, *dirs_g, *marks;
+    int *Mf, *mf, *qu, *qd;
+    unsigned* cnt;  // 2 * kEngSet words
+};
+
+struct EngState {
+    int op, type, items, pad;
+};
+
+struct EngStats {
+    long long rounds[4], rounds_r, outer_iters, n_edited, false_init[4], n_inexact, rounds_total;
+    int status, pad;
+};
+
+// Number of work items of operation op for one field (device and host).
+int eng_items_host(const EngField& F, int op);
+const void* engine_kernel();       // k_engine(fields, states, stats, tickets, bar, nf, max_steps)
+const void* engine_init_kernel();  // k_engine_init(fields, nf, tickets, bar)
+
+}  // namespace msz

@@ -28,7 +28,8 @@ __device__ __forceinline__ unsigned wave_sum(unsigned v) {
 
 // Block-wide reduction of K counters followed by one atomic per non-zero total.
 template <int K>
-__device__ __forceinline__ void block_add(unsigned (&v)[K], unsigned* dst, const int* idx) {
+__device__ __forceinline__ void block_add(unsigned (&v)[K], unsigned* dst, const int* idx, int nslots = kSlots,
+                                          int stride = kSlotStride) {
     __shared__ unsigned red[K][16];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -42,7 +43,7 @@ __device__ __forceinline__ void block_add(unsigned (&v)[K], unsigned* dst, const
     if (threadIdx.x < K) {
         unsigned s = 0;
         for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
-        if (s) atomicAdd(dst + (blockIdx.x & (kSlots - 1)) * kSlotStride + idx[threadIdx.x], s);
+        if (s) atomicAdd(dst + (blockIdx.x % nslots) * stride + idx[threadIdx.x], s);
     }
 }
 
@@ -80,15 +81,11 @@ __device__ __forceinline__ void validate_one(float fi, float hi, const float* wa
     }
 }
 
-__global__ void __launch_bounds__(256) k_validate_init(const float* __restrict__ f,
-                                                       const float* __restrict__ fhat,
-                                                       const float* __restrict__ warm, float xi,
-                                                       int n, float* __restrict__ L,
-                                                       float* __restrict__ g,
-                                                       unsigned* __restrict__ cnt) {
-    unsigned bad = 0;
-    const int ng = n >> 2;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
+// Validation of the 4-vertex group w (vector path when the group is whole).
+__device__ __forceinline__ void validate_group(const float* __restrict__ f, const float* __restrict__ fhat,
+                                               const float* __restrict__ warm, float xi, int n, float* __restrict__ L,
+                                               float* __restrict__ g, int w, unsigned& bad) {
+    if (4 * w + 3 < n) {
         const float4 f4 = reinterpret_cast<const float4*>(f)[w];
         const float4 h4 = reinterpret_cast<const float4*>(fhat)[w];
         const float fv[4] = {f4.x, f4.y, f4.z, f4.w}, hv[4] = {h4.x, h4.y, h4.z, h4.w};
@@ -97,13 +94,26 @@ __global__ void __launch_bounds__(256) k_validate_init(const float* __restrict__
         for (int j = 0; j < 4; ++j) validate_one(fv[j], hv[j], warm, 4 * w + j, xi, lv[j], gv[j], bad);
         reinterpret_cast<float4*>(L)[w] = make_float4(lv[0], lv[1], lv[2], lv[3]);
         reinterpret_cast<float4*>(g)[w] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+    } else {
+        for (int i = 4 * w; i < n; ++i) {
+            float li, gi;
+            validate_one(f[i], fhat[i], warm, i, xi, li, gi, bad);
+            L[i] = li;
+            g[i] = gi;
+        }
     }
-    for (int i = 4 * ng + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float li, gi;
-        validate_one(f[i], fhat[i], warm, i, xi, li, gi, bad);
-        L[i] = li;
-        g[i] = gi;
-    }
+}
+
+__global__ void __launch_bounds__(256) k_validate_init(const float* __restrict__ f,
+                                                       const float* __restrict__ fhat,
+                                                       const float* __restrict__ warm, float xi,
+                                                       int n, float* __restrict__ L,
+                                                       float* __restrict__ g,
+                                                       unsigned* __restrict__ cnt) {
+    unsigned bad = 0;
+    const int ng = (n + 3) >> 2;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x)
+        validate_group(f, fhat, warm, xi, n, L, g, w, bad);
     if (bad) atomicOr(cnt + kCntErr, bad);
 }
 
@@ -193,157 +203,193 @@ struct Steepest {
     }
 };
 
+template <int NDIM, int TY, int ZC>
+struct DirsGeom {
+    static constexpr int W = kTileX + 2, H = TY + 2, P = W * H, NL = (P + 255) / 256, RPT = TY / 16;
+    static constexpr int NP = NDIM == 3 ? 3 : 1;     // LDS ring of planes
+    static constexpr int ZCH = NDIM == 3 ? ZC : 1;   // planes computed per work item
+    int tiles_x, tiles_y, tiles_z;
+    __device__ __forceinline__ explicit DirsGeom(const Grid& gr)
+        : tiles_x((gr.nx + kTileX - 1) / kTileX),
+          tiles_y((gr.ny + TY - 1) / TY),
+          tiles_z(NDIM == 3 ? (gr.nz + ZCH - 1) / ZCH : 1) {}
+    __device__ __forceinline__ int items() const { return tiles_x * tiles_y * tiles_z; }
+    __device__ __forceinline__ void origin(int it, int& x0, int& y0, int& z0) const {
+        x0 = (it % tiles_x) * kTileX;
+        y0 = ((it / tiles_x) % tiles_y) * TY;
+        z0 = NDIM == 3 ? (it / (tiles_x * tiles_y)) * ZCH : 0;
+    }
+    // planes streamed for item it: z0 - 1 .. z0 + zc in 3D, the single plane in 2D
+    __device__ __forceinline__ int planes(const Grid& gr, int it) const {
+        if constexpr (NDIM == 3) {
+            const int z0 = (it / (tiles_x * tiles_y)) * ZCH;
+            return min(ZCH, gr.nz - z0) + 2;
+        }
+        return 1;
+    }
+};
+
+// Issues the loads of plane j of item it into registers (and, in MODE 1, the
+// dirs_f words of the plane that is computed once this one is in LDS).
+template <int NDIM, int TY, int ZC, int MODE>
+__device__ __forceinline__ void dirs_load(const float* __restrict__ h, const uint8_t* __restrict__ dirs_f,
+                                          const Grid& gr, const DirsGeom<NDIM, TY, ZC>& geo, int it, int j,
+                                          float (&pre)[DirsGeom<NDIM, TY, ZC>::NL],
+                                          unsigned (&dpre)[DirsGeom<NDIM, TY, ZC>::RPT]) {
+    using G = DirsGeom<NDIM, TY, ZC>;
+    int x0, y0, z0;
+    geo.origin(it, x0, y0, z0);
+    const int z = NDIM == 3 ? z0 - 1 + j : 0;
+    const bool zin = z >= 0 && z < gr.nz;
+    const long base = static_cast<long>(z) * gr.nxy;
+#pragma unroll
+    for (int k = 0; k < G::NL; ++k) {
+        const int idx = threadIdx.x + 256 * k;
+        const int r = idx / G::W, c = idx - r * G::W;
+        const int x = x0 + c - 1, y = y0 + r - 1;
+        float v = __builtin_nanf("");
+        if (idx < G::P && zin && x >= 0 && x < gr.nx && y >= 0 && y < gr.ny)
+            v = h[base + x + static_cast<long>(gr.nx) * y];
+        pre[k] = v;
+    }
+    if constexpr (MODE == 1) {
+        const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+        const bool vec4 = (gr.nx & 3) == 0;
+        const int zc = NDIM == 3 ? z - 1 : 0;
+        const bool zok = NDIM == 3 ? (j >= 2 && zc < gr.nz) : true;
+#pragma unroll
+        for (int q = 0; q < G::RPT; ++q) {
+            const int y = y0 + ty + 16 * q, xa = x0 + tx * 4;
+            const long i0 = static_cast<long>(zc) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
+            unsigned d = 0xFFFFFFFFu;
+            if (zok && y < gr.ny) {
+                if (vec4 && xa + 3 < gr.nx) {
+                    d = *reinterpret_cast<const unsigned*>(dirs_f + i0);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (xa + k < gr.nx) d = (d & ~(0xFFu << (8 * k))) | (static_cast<unsigned>(dirs_f[i0 + k]) << (8 * k));
+                }
+            }
+            dpre[q] = d;
+        }
+    }
+}
+
+// Directions (and, in MODE 1, detection) of plane z of item it, from the LDS
+// planes C (z), A (z + 1) and B (z - 1).
+template <int NDIM, int TY, int ZC, int MODE>
+__device__ __forceinline__ void dirs_compute(const float* C, const float* A, const float* B, const Grid& gr,
+                                             const DirsGeom<NDIM, TY, ZC>& geo, int it, int z,
+                                             const unsigned (&df4)[DirsGeom<NDIM, TY, ZC>::RPT],
+                                             uint8_t* __restrict__ dirs_out, int type, uint8_t* __restrict__ marks,
+                                             unsigned (&c)[4]) {
+    using G = DirsGeom<NDIM, TY, ZC>;
+    constexpr int W = G::W;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const bool vec4 = (gr.nx & 3) == 0;
+    int x0, y0, z0;
+    geo.origin(it, x0, y0, z0);
+#pragma unroll
+    for (int q = 0; q < G::RPT; ++q) {
+        const int y = y0 + ty + 16 * q, xa = x0 + tx * 4, r = ty + 16 * q + 1;
+        const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
+        const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
+        unsigned out4 = 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int cc = tx * 4 + k + 1;
+            const bool valid = xa + k < gr.nx && y < gr.ny;
+            unsigned packed = 0xFFu;
+            if (valid) {
+                const float v = C[r * W + cc];
+                Steepest b{v, v, kSelf, kSelf};
+                // below-centre ids, nearest first, then above-centre ids, nearest first
+                b.below(C[r * W + cc - 1], 1);
+                b.below(C[(r - 1) * W + cc], 3);
+                b.below(C[(r - 1) * W + cc - 1], 5);
+                if constexpr (NDIM == 3) {
+                    b.below(B[r * W + cc], 7);
+                    b.below(B[r * W + cc - 1], 9);
+                    b.below(B[(r - 1) * W + cc], 11);
+                    b.below(B[(r - 1) * W + cc - 1], 13);
+                }
+                b.above(C[r * W + cc + 1], 0);
+                b.above(C[(r + 1) * W + cc], 2);
+                b.above(C[(r + 1) * W + cc + 1], 4);
+                if constexpr (NDIM == 3) {
+                    b.above(A[r * W + cc], 6);
+                    b.above(A[r * W + cc + 1], 8);
+                    b.above(A[(r + 1) * W + cc], 10);
+                    b.above(A[(r + 1) * W + cc + 1], 12);
+                }
+                packed = (b.us << 4) | b.ds;
+                out4 = (out4 & ~(0xFFu << (8 * k))) | (packed << (8 * k));
+                if (!full) dirs_out[i0 + k] = static_cast<uint8_t>(packed);
+            }
+            if constexpr (MODE == 1)
+                detect_vertex(valid, (df4[q] >> (8 * k)) & 0xFFu, packed, static_cast<int>(i0) + k, type, gr, marks, c);
+        }
+        if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
+    }
+}
+
+// Stream of planes over the work items `range` (one item, or a persistent
+// block's whole range), each plane prefetched in registers one step ahead.
+// sm: LDS of NP * P floats.
+template <int NDIM, int TY, int ZC, int MODE>
+__device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const Grid& gr, ItemRange range,
+                                            uint8_t* __restrict__ dirs_out, const uint8_t* __restrict__ dirs_f,
+                                            int type, uint8_t* __restrict__ marks, float* sm, unsigned (&c)[4]) {
+    using G = DirsGeom<NDIM, TY, ZC>;
+    const G geo(gr);
+    float pre[G::NL];
+    unsigned dpre[G::RPT];
+    int it = range.first, j = 0;
+    if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, it, 0, pre, dpre);
+    int ring = 0;  // LDS slot of the plane held in pre[]
+    while (it < range.hi) {
+#pragma unroll
+        for (int k = 0; k < G::NL; ++k) {
+            const int idx = threadIdx.x + 256 * k;
+            if (idx < G::P) sm[ring * G::P + idx] = pre[k];
+        }
+        unsigned df4[G::RPT];
+#pragma unroll
+        for (int q = 0; q < G::RPT; ++q) df4[q] = dpre[q];
+        __syncthreads();
+        // advance the stream and prefetch the next plane while this one is computed
+        const int cur_it = it, cur_j = j, cur_ring = ring;
+        if (++j == geo.planes(gr, it)) {
+            j = 0;
+            it += range.stride;
+        }
+        ring = G::NP == 3 ? (ring + 1) % 3 : 0;
+        if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, it, j, pre, dpre);
+        if (NDIM == 2 || cur_j >= 2) {
+            int x0, y0, z0;
+            geo.origin(cur_it, x0, y0, z0);
+            const int z = NDIM == 3 ? z0 + cur_j - 2 : 0;
+            const float* A = sm + cur_ring * G::P;                             // plane z + 1
+            const float* C = sm + (G::NP == 3 ? (cur_ring + 2) % 3 : 0) * G::P; // plane z
+            const float* B = sm + (G::NP == 3 ? (cur_ring + 1) % 3 : 0) * G::P; // plane z - 1
+            dirs_compute<NDIM, TY, ZC, MODE>(C, A, B, gr, geo, cur_it, z, df4, dirs_out, type, marks, c);
+        }
+        __syncthreads();  // the slot written next is the oldest plane
+    }
+}
+
 template <int NDIM, int TY, int ZC, int MODE>
 __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid gr,
                                               uint8_t* __restrict__ dirs_out,
                                               const uint8_t* __restrict__ dirs_f, int type,
                                               uint8_t* __restrict__ marks,
                                               unsigned* __restrict__ cnt) {
+    using G = DirsGeom<NDIM, TY, ZC>;
     static_assert(TY % 16 == 0, "a thread row covers 16 tile rows");
-    constexpr int W = kTileX + 2, H = TY + 2, P = W * H, NL = (P + 255) / 256, RPT = TY / 16;
-    constexpr int NP = NDIM == 3 ? 3 : 1;     // LDS ring of planes
-    constexpr int ZCH = NDIM == 3 ? ZC : 1;   // planes computed per work item
-    __shared__ float sm[NP][P];
-
-    const int tiles_x = (gr.nx + kTileX - 1) / kTileX;
-    const int tiles_y = (gr.ny + TY - 1) / TY;
-    const int tiles_z = NDIM == 3 ? (gr.nz + ZCH - 1) / ZCH : 1;
-    const ItemRange range = xcd_items(tiles_x * tiles_y * tiles_z);
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    // rows start at multiples of 4 vertices: packed direction bytes move as dwords
-    const bool vec4 = (gr.nx & 3) == 0;
-
-    // stream position: work item `it`, plane `j` of it (z = z0 - 1 + j in 3D)
-    auto planes_of = [&](int it) {
-        if constexpr (NDIM == 3) {
-            const int z0 = (it / (tiles_x * tiles_y)) * ZCH;
-            return min(ZCH, gr.nz - z0) + 2;
-        }
-        return 1;
-    };
-    auto origin = [&](int it, int& x0, int& y0, int& z0) {
-        x0 = (it % tiles_x) * kTileX;
-        y0 = ((it / tiles_x) % tiles_y) * TY;
-        z0 = NDIM == 3 ? (it / (tiles_x * tiles_y)) * ZCH : 0;
-    };
-
-    float pre[NL];
-    unsigned dpre[RPT];
-    // issue the loads of plane j of item it (and the dirs_f words of the plane it completes)
-    auto load = [&](int it, int j) {
-        int x0, y0, z0;
-        origin(it, x0, y0, z0);
-        const int z = NDIM == 3 ? z0 - 1 + j : 0;
-        const bool zin = z >= 0 && z < gr.nz;
-        const long base = static_cast<long>(z) * gr.nxy;
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int idx = threadIdx.x + 256 * k;
-            const int r = idx / W, c = idx - r * W;
-            const int x = x0 + c - 1, y = y0 + r - 1;
-            float v = __builtin_nanf("");
-            if (idx < P && zin && x >= 0 && x < gr.nx && y >= 0 && y < gr.ny)
-                v = h[base + x + static_cast<long>(gr.nx) * y];
-            pre[k] = v;
-        }
-        if constexpr (MODE == 1) {
-            const int zc = NDIM == 3 ? z - 1 : 0;  // the plane computed once this one is in LDS
-            const bool zok = NDIM == 3 ? (j >= 2 && zc < gr.nz) : true;
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int y = y0 + ty + 16 * q, xa = x0 + tx * 4;
-                const long i0 = static_cast<long>(zc) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
-                unsigned d = 0xFFFFFFFFu;
-                if (zok && y < gr.ny) {
-                    if (vec4 && xa + 3 < gr.nx) {
-                        d = *reinterpret_cast<const unsigned*>(dirs_f + i0);
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            if (xa + k < gr.nx) d = (d & ~(0xFFu << (8 * k))) | (static_cast<unsigned>(dirs_f[i0 + k]) << (8 * k));
-                    }
-                }
-                dpre[q] = d;
-            }
-        }
-    };
-
+    __shared__ float sm[G::NP * G::P];
     unsigned c[4] = {0u, 0u, 0u, 0u};
-    int it = range.first, j = 0;
-    if (it < range.hi) load(it, 0);
-    int ring = 0;  // LDS slot of the plane held in pre[]
-    while (it < range.hi) {
-#pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int idx = threadIdx.x + 256 * k;
-            if (idx < P) sm[ring][idx] = pre[k];
-        }
-        unsigned df4[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) df4[q] = dpre[q];
-        __syncthreads();
-        // advance the stream and prefetch the next plane while this one is computed
-        const int cur_it = it, cur_j = j, cur_ring = ring;
-        if (++j == planes_of(it)) {
-            j = 0;
-            it += range.stride;
-        }
-        ring = NP == 3 ? (ring + 1) % 3 : 0;
-        if (it < range.hi) load(it, j);
-
-        if (NDIM == 2 || cur_j >= 2) {
-            int x0, y0, z0;
-            origin(cur_it, x0, y0, z0);
-            const int z = NDIM == 3 ? z0 + cur_j - 2 : 0;
-            const float* A = sm[cur_ring];                      // plane z + 1
-            const float* C = sm[NP == 3 ? (cur_ring + 2) % 3 : 0]; // plane z
-            const float* B = sm[NP == 3 ? (cur_ring + 1) % 3 : 0]; // plane z - 1
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int y = y0 + ty + 16 * q, xa = x0 + tx * 4, r = ty + 16 * q + 1;
-                const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
-                const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
-                unsigned out4 = 0xFFFFFFFFu;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int cc = tx * 4 + k + 1;
-                    const bool valid = xa + k < gr.nx && y < gr.ny;
-                    unsigned packed = 0xFFu;
-                    if (valid) {
-                        const float v = C[r * W + cc];
-                        Steepest b{v, v, kSelf, kSelf};
-                        // below-centre ids, nearest first, then above-centre ids, nearest first
-                        b.below(C[r * W + cc - 1], 1);
-                        b.below(C[(r - 1) * W + cc], 3);
-                        b.below(C[(r - 1) * W + cc - 1], 5);
-                        if constexpr (NDIM == 3) {
-                            b.below(B[r * W + cc], 7);
-                            b.below(B[r * W + cc - 1], 9);
-                            b.below(B[(r - 1) * W + cc], 11);
-                            b.below(B[(r - 1) * W + cc - 1], 13);
-                        }
-                        b.above(C[r * W + cc + 1], 0);
-                        b.above(C[(r + 1) * W + cc], 2);
-                        b.above(C[(r + 1) * W + cc + 1], 4);
-                        if constexpr (NDIM == 3) {
-                            b.above(A[r * W + cc], 6);
-                            b.above(A[r * W + cc + 1], 8);
-                            b.above(A[(r + 1) * W + cc], 10);
-                            b.above(A[(r + 1) * W + cc + 1], 12);
-                        }
-                        packed = (b.us << 4) | b.ds;
-                        out4 = (out4 & ~(0xFFu << (8 * k))) | (packed << (8 * k));
-                        if (!full) dirs_out[i0 + k] = static_cast<uint8_t>(packed);
-                    }
-                    if constexpr (MODE == 1)
-                        detect_vertex(valid, (df4[q] >> (8 * k)) & 0xFFu, packed, static_cast<int>(i0) + k, type, gr,
-                                      marks, c);
-                }
-                if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
-            }
-        }
-        __syncthreads();  // the slot written next is the oldest plane
-    }
+    dirs_stream<NDIM, TY, ZC, MODE>(h, gr, xcd_items(G(gr).items()), dirs_out, dirs_f, type, marks, sm, c);
     if constexpr (MODE == 1) {
         const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
         block_add<4>(c, cnt, idx);
@@ -354,27 +400,31 @@ __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid 
 // Sixteen vertices per thread: one dwordx4 of each direction array.  The
 // direction arrays live in 256-byte padded workspace segments, so the last
 // partial group can be read whole; vertices past n are masked.
+// C-loop detection of the 16-vertex group w from stored directions.  The
+// direction arrays live in 256-byte padded workspace segments, so the last
+// partial group can be read whole; vertices past n are masked.
+__device__ __forceinline__ void detect_group(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
+                                             const Grid& gr, int type, uint8_t* __restrict__ marks, int w,
+                                             unsigned (&c)[4]) {
+    const uint4 a = reinterpret_cast<const uint4*>(dirs_f)[w], b = reinterpret_cast<const uint4*>(dirs_g)[w];
+    const unsigned fa[4] = {a.x, a.y, a.z, a.w}, ga[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 16 * w + 4 * q + j;
+            detect_vertex(i < gr.n, (fa[q] >> (8 * j)) & 0xFFu, (ga[q] >> (8 * j)) & 0xFFu, i, type, gr, marks, c);
+        }
+}
+
 __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__ dirs_f,
                                                      const uint8_t* __restrict__ dirs_g, Grid gr,
                                                      int type, uint8_t* __restrict__ marks,
                                                      unsigned* __restrict__ cnt) {
     unsigned c[4] = {0u, 0u, 0u, 0u};
-    const int n = gr.n;
-    const int ng = (n + 15) >> 4;
-    const uint4* wf = reinterpret_cast<const uint4*>(dirs_f);
-    const uint4* wg = reinterpret_cast<const uint4*>(dirs_g);
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
-        const uint4 a = wf[w], b = wg[w];
-        const unsigned fa[4] = {a.x, a.y, a.z, a.w}, ga[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int i = 16 * w + 4 * q + j;
-                detect_vertex(i < n, (fa[q] >> (8 * j)) & 0xFFu, (ga[q] >> (8 * j)) & 0xFFu, i, type, gr, marks, c);
-            }
-        }
-    }
+    const int ng = (gr.n + 15) >> 4;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x)
+        detect_group(dirs_f, dirs_g, gr, type, marks, w, c);
     const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
     block_add<4>(c, cnt, idx);
 }
@@ -383,32 +433,38 @@ __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__
 
 // Halves every marked vertex once (the round's union of proposals) and clears
 // its mark.  Marks are scanned 16 at a time; the padding bytes are never set.
+// Halves every marked vertex of the 16-vertex group w once and clears the
+// marks (padding bytes past n are never set).
+__device__ __forceinline__ void apply_group(float* __restrict__ g, const float* __restrict__ L,
+                                            uint8_t* __restrict__ marks, int w, unsigned& changed) {
+    uint4* mw = reinterpret_cast<uint4*>(marks);
+    const uint4 m = mw[w];
+    if ((m.x | m.y | m.z | m.w) == 0u) return;
+    const unsigned part[4] = {m.x, m.y, m.z, m.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (!part[q]) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if ((part[q] >> (8 * b)) & 0xFFu) {
+                const int t = w * 16 + q * 4 + b;
+                const float old = g[t];
+                const float nv = halve(old, L[t]);
+                g[t] = nv;
+                changed += nv != old;
+            }
+        }
+    }
+    mw[w] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 __global__ void __launch_bounds__(256) k_apply(float* __restrict__ g, const float* __restrict__ L,
                                                uint8_t* __restrict__ marks, int n,
                                                unsigned* __restrict__ cnt) {
     unsigned changed = 0;
     const int nw = (n + 15) >> 4;
-    uint4* mw = reinterpret_cast<uint4*>(marks);
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x) {
-        const uint4 m = mw[w];
-        if ((m.x | m.y | m.z | m.w) == 0u) continue;
-        const unsigned part[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (!part[q]) continue;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                if ((part[q] >> (8 * b)) & 0xFFu) {
-                    const int t = w * 16 + q * 4 + b;
-                    const float old = g[t];
-                    const float nv = halve(old, L[t]);
-                    g[t] = nv;
-                    changed += nv != old;
-                }
-            }
-        }
-        mw[w] = make_uint4(0u, 0u, 0u, 0u);
-    }
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x)
+        apply_group(g, L, marks, w, changed);
     unsigned v[1] = {changed};
     const int idx[1] = {kCntChanged};
     block_add<1>(v, cnt, idx);
@@ -455,20 +511,18 @@ __device__ __forceinline__ void slot_delta(unsigned s, int& dx, int& dy, int& dz
     dz = DZ[s];
 }
 
+// One label tile; su, sd: LDS arrays of the tile's vertex count.  The caller
+// separates consecutive tiles of one block with a barrier.
 template <int NDIM>
-__global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ dirs, Grid gr,
-                                                    int* __restrict__ q_up,
-                                                    int* __restrict__ q_dn) {
+__device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs, const Grid& gr, int tile,
+                                                int* __restrict__ q_up, int* __restrict__ q_dn, int* su, int* sd) {
     using T = LabelTile<NDIM>;
     constexpr int NT = T::X * T::Y * T::Z;
     constexpr int PER = NT / 256;
-    __shared__ int su[NT];
-    __shared__ int sd[NT];
 
     const int tx_n = (gr.nx + T::X - 1) / T::X;
     const int ty_n = (gr.ny + T::Y - 1) / T::Y;
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int bx = lb % tx_n, by = (lb / tx_n) % ty_n, bz = lb / (tx_n * ty_n);
+    const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
     const int X0 = bx * T::X, Y0 = by * T::Y, Z0 = bz * T::Z;
 
     // Thread t owns the 4-vertex row groups starting at l = 4 t + 1024 k.
@@ -573,6 +627,16 @@ __global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ 
     }
 }
 
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ dirs, Grid gr,
+                                                    int* __restrict__ q_up,
+                                                    int* __restrict__ q_dn) {
+    constexpr int NT = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z;
+    __shared__ int su[NT];
+    __shared__ int sd[NT];
+    label_tile_body<NDIM>(dirs, gr, xcd_logical_block(blockIdx.x, gridDim.x), q_up, q_dn, su, sd);
+}
+
 // Number of face-layer vertices of a full label tile.
 template <int NDIM>
 __host__ __device__ constexpr int face_count() {
@@ -642,16 +706,16 @@ __device__ __forceinline__ bool compress_one(int* q, int x) {
     return false;
 }
 
+// Compresses the pointers of one tile's face-layer vertices; false if a walk hit its cap.
 template <int NDIM>
-__global__ void __launch_bounds__(256) k_label_compress(Grid gr, int* __restrict__ q_up,
-                                                        int* __restrict__ q_dn,
-                                                        unsigned* __restrict__ cnt) {
+__device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __restrict__ q_up,
+                                              int* __restrict__ q_dn) {
     using T = LabelTile<NDIM>;
     constexpr int FC = face_count<NDIM>();
     const int tx_n = (gr.nx + T::X - 1) / T::X;
     const int ty_n = (gr.ny + T::Y - 1) / T::Y;
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int bx = lb % tx_n, by = (lb / tx_n) % ty_n, bz = lb / (tx_n * ty_n);
+    const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
+    bool ok = true;
     for (int b = threadIdx.x; b < FC; b += blockDim.x) {
         int lx, ly, lz;
         face_vertex<NDIM>(b, lx, ly, lz);
@@ -660,9 +724,17 @@ __global__ void __launch_bounds__(256) k_label_compress(Grid gr, int* __restrict
         const int i = x + gr.nx * y + gr.nxy * z;
         const bool ok_up = compress_one(q_up, i);
         const bool ok_dn = compress_one(q_dn, i);
-        const bool ok = ok_up && ok_dn;
-        if (!ok) atomicOr(cnt + kCntErr, kErrWalk);
+        ok = ok && ok_up && ok_dn;
     }
+    return ok;
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_label_compress(Grid gr, int* __restrict__ q_up,
+                                                        int* __restrict__ q_dn,
+                                                        unsigned* __restrict__ cnt) {
+    if (!compress_tile<NDIM>(gr, xcd_logical_block(blockIdx.x, gridDim.x), q_up, q_dn))
+        atomicOr(cnt + kCntErr, kErrWalk);
 }
 
 // Label-tile order: the gathers q[q[i]] of a tile land on the faces of the tile
@@ -692,46 +764,105 @@ __device__ __forceinline__ TileGroup<NDIM> tile_group(const Grid& gr, int tile, 
 // Writes the final labels label(i) = q[q[i]], tile by tile.  May run in place
 // (M == q_up, m == q_dn): the values it reads are fixed points.
 template <int NDIM>
-__global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int* q_dn, Grid gr, int* M,
-                                                     int* m) {
+__device__ __forceinline__ void label_final_tile(const int* q_up, const int* q_dn, const Grid& gr, int tile, int* M,
+                                                 int* m) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
-    const ItemRange range = xcd_items(label_tiles_of(gr));
-    for (int tile = range.first; tile < range.hi; tile += range.stride) {
-        int a[G][4], b[G][4];
-        TileGroup<NDIM> tg[G];
+    int a[G][4], b[G][4];
+    TileGroup<NDIM> tg[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
-            tg[k] = tile_group<NDIM>(gr, tile, k);
+    for (int k = 0; k < G; ++k) {
+        tg[k] = tile_group<NDIM>(gr, tile, k);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) a[k][j] = b[k][j] = 0;
-            if (tg[k].vec) {
-                const int4 u = *reinterpret_cast<const int4*>(q_up + tg[k].i0);
-                const int4 d = *reinterpret_cast<const int4*>(q_dn + tg[k].i0);
-                a[k][0] = u.x, a[k][1] = u.y, a[k][2] = u.z, a[k][3] = u.w;
-                b[k][0] = d.x, b[k][1] = d.y, b[k][2] = d.z, b[k][3] = d.w;
-            } else {
-                for (int j = 0; j < tg[k].count; ++j) a[k][j] = q_up[tg[k].i0 + j], b[k][j] = q_dn[tg[k].i0 + j];
-            }
+        for (int j = 0; j < 4; ++j) a[k][j] = b[k][j] = 0;
+        if (tg[k].vec) {
+            const int4 u = *reinterpret_cast<const int4*>(q_up + tg[k].i0);
+            const int4 d = *reinterpret_cast<const int4*>(q_dn + tg[k].i0);
+            a[k][0] = u.x, a[k][1] = u.y, a[k][2] = u.z, a[k][3] = u.w;
+            b[k][0] = d.x, b[k][1] = d.y, b[k][2] = d.z, b[k][3] = d.w;
+        } else {
+            for (int j = 0; j < tg[k].count; ++j) a[k][j] = q_up[tg[k].i0 + j], b[k][j] = q_dn[tg[k].i0 + j];
         }
+    }
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
-            int ra[4], rb[4];
+    for (int k = 0; k < G; ++k) {
+        int ra[4], rb[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                ra[j] = j < tg[k].count ? q_up[a[k][j]] : 0;
-                rb[j] = j < tg[k].count ? q_dn[b[k][j]] : 0;
-            }
-            if (tg[k].vec) {
-                *reinterpret_cast<int4*>(M + tg[k].i0) = make_int4(ra[0], ra[1], ra[2], ra[3]);
-                *reinterpret_cast<int4*>(m + tg[k].i0) = make_int4(rb[0], rb[1], rb[2], rb[3]);
-            } else {
-                for (int j = 0; j < tg[k].count; ++j) M[tg[k].i0 + j] = ra[j], m[tg[k].i0 + j] = rb[j];
-            }
+        for (int j = 0; j < 4; ++j) {
+            ra[j] = j < tg[k].count ? q_up[a[k][j]] : 0;
+            rb[j] = j < tg[k].count ? q_dn[b[k][j]] : 0;
+        }
+        if (tg[k].vec) {
+            *reinterpret_cast<int4*>(M + tg[k].i0) = make_int4(ra[0], ra[1], ra[2], ra[3]);
+            *reinterpret_cast<int4*>(m + tg[k].i0) = make_int4(rb[0], rb[1], rb[2], rb[3]);
+        } else {
+            for (int j = 0; j < tg[k].count; ++j) M[tg[k].i0 + j] = ra[j], m[tg[k].i0 + j] = rb[j];
         }
     }
 }
 
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int* q_dn, Grid gr, int* M,
+                                                     int* m) {
+    const ItemRange range = xcd_items(label_tiles_of(gr));
+    for (int tile = range.first; tile < range.hi; tile += range.stride) label_final_tile<NDIM>(q_up, q_dn, gr, tile, M, m);
+}
+
 // Troublemaker detection, tile by tile (see k_label_final for the order).
+template <int NDIM>
+__device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
+                                              const int* __restrict__ q_up, const int* __restrict__ q_dn,
+                                              const int* __restrict__ Mf, const int* __restrict__ mf, const Grid& gr,
+                                              int tile, uint8_t* __restrict__ marks, unsigned& wrong, unsigned& cases) {
+    constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
+    int qu[G][4], qd[G][4], Mv[G][4], mv[G][4];
+    unsigned df4[G], dg4[G];
+    TileGroup<NDIM> tg[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        tg[k] = tile_group<NDIM>(gr, tile, k);
+        const int i0 = tg[k].i0;
+        df4[k] = dg4[k] = 0xFFFFFFFFu;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) qu[k][j] = qd[k][j] = Mv[k][j] = mv[k][j] = 0;
+        if (tg[k].vec) {
+            df4[k] = *reinterpret_cast<const unsigned*>(dirs_f + i0);
+            dg4[k] = *reinterpret_cast<const unsigned*>(dirs_g + i0);
+            const int4 u = *reinterpret_cast<const int4*>(q_up + i0);
+            const int4 d = *reinterpret_cast<const int4*>(q_dn + i0);
+            const int4 U = *reinterpret_cast<const int4*>(Mf + i0);
+            const int4 D = *reinterpret_cast<const int4*>(mf + i0);
+            qu[k][0] = u.x, qu[k][1] = u.y, qu[k][2] = u.z, qu[k][3] = u.w;
+            qd[k][0] = d.x, qd[k][1] = d.y, qd[k][2] = d.z, qd[k][3] = d.w;
+            Mv[k][0] = U.x, Mv[k][1] = U.y, Mv[k][2] = U.z, Mv[k][3] = U.w;
+            mv[k][0] = D.x, mv[k][1] = D.y, mv[k][2] = D.z, mv[k][3] = D.w;
+        } else {
+            for (int j = 0; j < tg[k].count; ++j) {
+                const int i = i0 + j;
+                df4[k] = (df4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_f[i]) << (8 * j));
+                dg4[k] = (dg4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_g[i]) << (8 * j));
+                qu[k][j] = q_up[i], qd[k][j] = q_dn[i], Mv[k][j] = Mf[i], mv[k][j] = mf[i];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j >= tg[k].count) continue;
+            const int i = tg[k].i0 + j;
+            const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
+            const bool wM = q_up[qu[k][j]] != Mv[k][j];
+            const bool wm = q_dn[qd[k][j]] != mv[k][j];
+            wrong += wM || wm;
+            const bool rmin = wm && ((dg & 15u) != (df & 15u));
+            const bool rmax = wM && ((dg >> 4) != (df >> 4));
+            cases += rmin + rmax;
+            if (rmin) mark(marks, i + gr.off[df & 15u]);
+            if (rmax) mark(marks, i + gr.off[dg >> 4]);
+        }
+    }
+}
+
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ dirs_f,
                                                   const uint8_t* __restrict__ dirs_g,
@@ -741,58 +872,10 @@ __global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ di
                                                   const int* __restrict__ mf, Grid gr,
                                                   uint8_t* __restrict__ marks,
                                                   unsigned* __restrict__ cnt) {
-    constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
     unsigned wrong = 0, cases = 0;
     const ItemRange range = xcd_items(label_tiles_of(gr));
-    for (int tile = range.first; tile < range.hi; tile += range.stride) {
-        int qu[G][4], qd[G][4], Mv[G][4], mv[G][4];
-        unsigned df4[G], dg4[G];
-        TileGroup<NDIM> tg[G];
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-            tg[k] = tile_group<NDIM>(gr, tile, k);
-            const int i0 = tg[k].i0;
-            df4[k] = dg4[k] = 0xFFFFFFFFu;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) qu[k][j] = qd[k][j] = Mv[k][j] = mv[k][j] = 0;
-            if (tg[k].vec) {
-                df4[k] = *reinterpret_cast<const unsigned*>(dirs_f + i0);
-                dg4[k] = *reinterpret_cast<const unsigned*>(dirs_g + i0);
-                const int4 u = *reinterpret_cast<const int4*>(q_up + i0);
-                const int4 d = *reinterpret_cast<const int4*>(q_dn + i0);
-                const int4 U = *reinterpret_cast<const int4*>(Mf + i0);
-                const int4 D = *reinterpret_cast<const int4*>(mf + i0);
-                qu[k][0] = u.x, qu[k][1] = u.y, qu[k][2] = u.z, qu[k][3] = u.w;
-                qd[k][0] = d.x, qd[k][1] = d.y, qd[k][2] = d.z, qd[k][3] = d.w;
-                Mv[k][0] = U.x, Mv[k][1] = U.y, Mv[k][2] = U.z, Mv[k][3] = U.w;
-                mv[k][0] = D.x, mv[k][1] = D.y, mv[k][2] = D.z, mv[k][3] = D.w;
-            } else {
-                for (int j = 0; j < tg[k].count; ++j) {
-                    const int i = i0 + j;
-                    df4[k] = (df4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_f[i]) << (8 * j));
-                    dg4[k] = (dg4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_g[i]) << (8 * j));
-                    qu[k][j] = q_up[i], qd[k][j] = q_dn[i], Mv[k][j] = Mf[i], mv[k][j] = mf[i];
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < G; ++k) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (j >= tg[k].count) continue;
-                const int i = tg[k].i0 + j;
-                const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
-                const bool wM = q_up[qu[k][j]] != Mv[k][j];
-                const bool wm = q_dn[qd[k][j]] != mv[k][j];
-                wrong += wM || wm;
-                const bool rmin = wm && ((dg & 15u) != (df & 15u));
-                const bool rmax = wM && ((dg >> 4) != (df >> 4));
-                cases += rmin + rmax;
-                if (rmin) mark(marks, i + gr.off[df & 15u]);
-                if (rmax) mark(marks, i + gr.off[dg >> 4]);
-            }
-        }
-    }
+    for (int tile = range.first; tile < range.hi; tile += range.stride)
+        detect_r_tile<NDIM>(dirs_f, dirs_g, q_up, q_dn, Mf, mf, gr, tile, marks, wrong, cases);
     unsigned v[2] = {wrong, cases};
     const int idx[2] = {kCntWrong, kCntRCases};
     block_add<2>(v, cnt, idx);
@@ -850,28 +933,35 @@ __device__ __forceinline__ float delta_one(float gi, float hi, unsigned& edited,
     return ok ? d : d0;
 }
 
+// Deltas of the 4-vertex group w (vector path when the group is whole).
+__device__ __forceinline__ void delta_group(const float* __restrict__ g, const float* __restrict__ fhat, int n,
+                                            float* __restrict__ delta, float* __restrict__ g_out, int w,
+                                            unsigned& edited, unsigned& inexact) {
+    if (4 * w + 3 < n) {
+        const float4 g4 = reinterpret_cast<const float4*>(g)[w];
+        const float4 h4 = reinterpret_cast<const float4*>(fhat)[w];
+        const float4 d4 = make_float4(delta_one(g4.x, h4.x, edited, inexact), delta_one(g4.y, h4.y, edited, inexact),
+                                      delta_one(g4.z, h4.z, edited, inexact), delta_one(g4.w, h4.w, edited, inexact));
+        reinterpret_cast<float4*>(delta)[w] = d4;
+        if (g_out) reinterpret_cast<float4*>(g_out)[w] = g4;
+    } else {
+        for (int i = 4 * w; i < n; ++i) {
+            const float gi = g[i];
+            delta[i] = delta_one(gi, fhat[i], edited, inexact);
+            if (g_out) g_out[i] = gi;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_delta(const float* __restrict__ g,
                                                const float* __restrict__ fhat, int n,
                                                float* __restrict__ delta,
                                                float* __restrict__ g_out,
                                                unsigned* __restrict__ cnt) {
     unsigned edited = 0, inexact = 0;
-    const int ng = n >> 2;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x) {
-        const float4 g4 = reinterpret_cast<const float4*>(g)[w];
-        const float4 h4 = reinterpret_cast<const float4*>(fhat)[w];
-        const float4 d4 = make_float4(delta_one(g4.x, h4.x, edited, inexact),
-                                      delta_one(g4.y, h4.y, edited, inexact),
-                                      delta_one(g4.z, h4.z, edited, inexact),
-                                      delta_one(g4.w, h4.w, edited, inexact));
-        reinterpret_cast<float4*>(delta)[w] = d4;
-        if (g_out) reinterpret_cast<float4*>(g_out)[w] = g4;
-    }
-    for (int i = 4 * ng + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float gi = g[i];
-        delta[i] = delta_one(gi, fhat[i], edited, inexact);
-        if (g_out) g_out[i] = gi;
-    }
+    const int ng = (n + 3) >> 2;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x)
+        delta_group(g, fhat, n, delta, g_out, w, edited, inexact);
     unsigned v[2] = {edited, inexact};
     const int idx[2] = {kCntEdited, kCntInexact};
     block_add<2>(v, cnt, idx);
@@ -889,14 +979,19 @@ static int blocks_for(long work, int per_block, int cap = 1 << 20) {
 struct DirsVariant {
     int ty, zc;
 };
-// Tile variants selectable per launch (index 1..); index 0 is the default.
-static const DirsVariant kVariants2D[] = {{16, 1}, {16, 1}, {32, 1}};
-static const DirsVariant kVariants3D[] = {{16, 16}, {16, 16}, {16, 8}, {16, 32}, {32, 16}};
-
-int tile_variant_count(int ndim) {
-    return ndim == 2 ? static_cast<int>(sizeof(kVariants2D) / sizeof(kVariants2D[0])) - 1
-                     : static_cast<int>(sizeof(kVariants3D) / sizeof(kVariants3D[0])) - 1;
+// Tile variants of the direction kernel selectable per call (index 1..);
+// index 0 is the default (2D: 64 x 16 tiles; 3D: 64 x 16 x 16 columns).
+__host__ __device__ inline DirsVariant variant_of(int ndim, int v) {
+    if (ndim == 2) return v == 2 ? DirsVariant{32, 1} : DirsVariant{16, 1};
+    switch (v) {
+        case 2: return {16, 8};
+        case 3: return {16, 32};
+        case 4: return {32, 16};
+        default: return {16, 16};
+    }
 }
+
+int tile_variant_count(int ndim) { return ndim == 2 ? 2 : 4; }
 
 // Persistent grid: at most kDirsBlocks blocks (8 per compute unit), each walking
 // a contiguous run of work items of its XCD.
@@ -919,10 +1014,10 @@ static void launch_dirs_mode(const float* h, const Grid& gr, int variant, uint8_
                              const uint8_t* dirs_f, int type, uint8_t* marks,
                              unsigned* cnt, hipStream_t s) {
     if (gr.ndim == 2) {
-        if (kVariants2D[variant].ty == 32) launch_dirs_t<2, 32, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
+        if (variant_of(2, variant).ty == 32) launch_dirs_t<2, 32, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
         else launch_dirs_t<2, 16, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
     } else {
-        const DirsVariant v = kVariants3D[variant];
+        const DirsVariant v = variant_of(3, variant);
         if (v.ty == 32) launch_dirs_t<3, 32, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
         else if (v.zc == 8) launch_dirs_t<3, 16, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
         else if (v.zc == 32) launch_dirs_t<3, 16, 32, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
@@ -996,7 +1091,7 @@ void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu
 
 void launch_validate_init(const float* f, const float* fhat, const float* warm, float xi, int n,
                           float* L, float* g, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_init, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, f, fhat,
+    hipLaunchKernelGGL(k_validate_init, dim3(blocks_for((n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, f, fhat,
                        warm, xi, n, L, g, cnt);
 }
 
@@ -1006,8 +1101,348 @@ void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s) {
 
 void launch_delta(const float* g, const float* fhat, int n, float* delta, float* g_out, unsigned* cnt,
                   hipStream_t s) {
-    hipLaunchKernelGGL(k_delta, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, g, fhat, n, delta,
+    hipLaunchKernelGGL(k_delta, dim3(blocks_for((n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, g, fhat, n, delta,
                        g_out, cnt);
 }
+
+// ============================================================ batch engine ==
+//
+// k_engine corrects a batch of fields in one persistent launch.  Every step,
+// each unfinished field performs one operation of its schedule (the same
+// sequence of operations msz_fix runs, so each field's result is
+// bit-identical to its own msz_fix); the operations' work items of all fields
+// form one index space that the blocks walk.  The block that completes a
+// field's last item of the step (completion ticket) reads that field's
+// counters and writes its next operation; a grid-wide barrier then separates
+// the steps.  Counters and states are double-buffered by step parity.
+
+__host__ __device__ inline int dirs_items_of(const Grid& gr, int variant) {
+    const DirsVariant v = variant_of(gr.ndim, variant);
+    const int tx = (gr.nx + kTileX - 1) / kTileX, ty = (gr.ny + v.ty - 1) / v.ty;
+    const int tz = gr.ndim == 3 ? (gr.nz + v.zc - 1) / v.zc : 1;
+    return tx * ty * tz;
+}
+
+__host__ __device__ inline int eng_items(const EngField& F, int op) {
+    const int chunks = (F.gr.n + kEngChunk - 1) / kEngChunk;
+    const int tiles = label_tiles_of(F.gr);
+    const int dirs = dirs_items_of(F.gr, F.variant);
+    switch (op) {
+        case kOpPreA: return chunks + dirs;
+        case kOpPreB: case kOpPreC: case kOpRTile: case kOpRJump: case kOpRDetect: return tiles;
+        case kOpPreD: return tiles + dirs;
+        case kOpApplyC: case kOpApplyR: case kOpDetect: case kOpDelta: return chunks;
+        case kOpDdC: case kOpDdR: return dirs;
+        default: return 0;
+    }
+}
+
+int eng_items_host(const EngField& F, int op) { return eng_items(F, op); }
+
+// One direction work item of field F with its variant's tile shape.
+template <int MODE>
+__device__ __forceinline__ void eng_dirs_item(const EngField& F, const float* h, uint8_t* out, int type, int item,
+                                              float* sm, unsigned (&c)[4]) {
+    const ItemRange r{item, item + 1, 1};
+    const Grid& gr = F.gr;
+    if (gr.ndim == 2) {
+        if (variant_of(2, F.variant).ty == 32) dirs_stream<2, 32, 1, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+        else dirs_stream<2, 16, 1, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+    } else {
+        const DirsVariant v = variant_of(3, F.variant);
+        if (v.ty == 32) dirs_stream<3, 32, 16, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+        else if (v.zc == 8) dirs_stream<3, 16, 8, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+        else if (v.zc == 32) dirs_stream<3, 16, 32, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+        else dirs_stream<3, 16, 16, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+    }
+}
+
+// Runs work item `local` of the field's current operation (block-wide).
+__device__ void eng_run(const EngField& F, const EngState& st, int local, char* smem, unsigned* cset) {
+    const Grid& gr = F.gr;
+    const int chunks = (gr.n + kEngChunk - 1) / kEngChunk;
+    const int tiles = label_tiles_of(gr);
+    int* su = reinterpret_cast<int*>(smem);
+    int* sd = su + 4096;
+    float* sm = reinterpret_cast<float*>(smem);
+    const int cidx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
+    switch (st.op) {
+        case kOpPreA:
+            if (local < chunks) {
+                unsigned bad = 0;
+                const int ng = (gr.n + 3) >> 2;
+                for (int k = 0; k < kEngChunk / 1024; ++k) {
+                    const int w = local * (kEngChunk / 4) + threadIdx.x + 256 * k;
+                    if (w < ng) validate_group(F.f, F.fhat, nullptr, F.xi, gr.n, F.L, F.g, w, bad);
+                }
+                if (bad) atomicOr(cset + kCntErr, bad);
+            } else {
+                unsigned c[4] = {0u, 0u, 0u, 0u};
+                eng_dirs_item<0>(F, F.f, F.dirs_f, 0, local - chunks, sm, c);
+            }
+            break;
+        case kOpPreB:
+        case kOpRTile: {
+            const uint8_t* d = st.op == kOpPreB ? F.dirs_f : F.dirs_g;
+            if (gr.ndim == 2) label_tile_body<2>(d, gr, local, F.qu, F.qd, su, sd);
+            else label_tile_body<3>(d, gr, local, F.qu, F.qd, su, sd);
+            break;
+        }
+        case kOpPreC:
+        case kOpRJump: {
+            const bool ok = gr.ndim == 2 ? compress_tile<2>(gr, local, F.qu, F.qd) : compress_tile<3>(gr, local, F.qu, F.qd);
+            if (!ok) atomicOr(cset + kCntErr, kErrWalk);
+            break;
+        }
+        case kOpPreD:
+            if (local < tiles) {
+                if (gr.ndim == 2) label_final_tile<2>(F.qu, F.qd, gr, local, F.Mf, F.mf);
+                else label_final_tile<3>(F.qu, F.qd, gr, local, F.Mf, F.mf);
+            } else {
+                unsigned c[4] = {0u, 0u, 0u, 0u};
+                eng_dirs_item<1>(F, F.g, F.dirs_g, 0, local - tiles, sm, c);
+                block_add<4>(c, cset, cidx, kEngSlots, kEngStride);
+            }
+            break;
+        case kOpApplyC:
+        case kOpApplyR: {
+            unsigned changed = 0;
+            const int w = local * (kEngChunk / 16) + threadIdx.x;
+            if (w < (gr.n + 15) >> 4) apply_group(F.g, F.L, F.marks, w, changed);
+            unsigned v[1] = {changed};
+            const int idx[1] = {kCntChanged};
+            block_add<1>(v, cset, idx, kEngSlots, kEngStride);
+            break;
+        }
+        case kOpDdC:
+        case kOpDdR: {
+            unsigned c[4] = {0u, 0u, 0u, 0u};
+            eng_dirs_item<1>(F, F.g, F.dirs_g, st.type, local, sm, c);
+            block_add<4>(c, cset, cidx, kEngSlots, kEngStride);
+            break;
+        }
+        case kOpDetect: {
+            unsigned c[4] = {0u, 0u, 0u, 0u};
+            const int w = local * (kEngChunk / 16) + threadIdx.x;
+            if (w < (gr.n + 15) >> 4) detect_group(F.dirs_f, F.dirs_g, gr, st.type, F.marks, w, c);
+            block_add<4>(c, cset, cidx, kEngSlots, kEngStride);
+            break;
+        }
+        case kOpRDetect: {
+            unsigned wrong = 0, cases = 0;
+            if (gr.ndim == 2) detect_r_tile<2>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, local, F.marks, wrong, cases);
+            else detect_r_tile<3>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, local, F.marks, wrong, cases);
+            unsigned v[2] = {wrong, cases};
+            const int idx[2] = {kCntWrong, kCntRCases};
+            block_add<2>(v, cset, idx, kEngSlots, kEngStride);
+            break;
+        }
+        case kOpDelta: {
+            unsigned edited = 0, inexact = 0;
+            const int ng = (gr.n + 3) >> 2;
+            for (int k = 0; k < kEngChunk / 1024; ++k) {
+                const int w = local * (kEngChunk / 4) + threadIdx.x + 256 * k;
+                if (w < ng) delta_group(F.g, F.fhat, gr.n, F.edits, F.g_out, w, edited, inexact);
+            }
+            unsigned v[2] = {edited, inexact};
+            const int idx[2] = {kCntEdited, kCntInexact};
+            block_add<2>(v, cset, idx, kEngSlots, kEngStride);
+            break;
+        }
+        default:
+            break;
+    }
+    // Every wave's stores and counter atomics complete and become visible
+    // device-wide before thread 0 takes the item's completion ticket.
+    __threadfence();
+    __syncthreads();  // the next item reuses the LDS
+}
+
+// The schedule (the host loop of msz_fix, step by step): reads the finished
+// step's counters of one field, clears them, and returns its next state.
+__device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, unsigned* cset) {
+    unsigned c[kCntSlots];
+    for (int k = 0; k < kCntSlots; ++k) c[k] = 0;
+    for (int b = 0; b < kEngSlots; ++b)
+        for (int k = 0; k < kCntSlots; ++k) {
+            const unsigned v = __hip_atomic_load(cset + b * kEngStride + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            c[k] = k == kCntErr ? (c[k] | v) : c[k] + v;
+        }
+    for (int w = 0; w < kEngSet; ++w) cset[w] = 0u;
+    auto go = [&](int op) {
+        st.op = op;
+        st.items = eng_items(F, op);
+        return st;
+    };
+    auto finish = [&](int status) {  // output the deltas, then stop
+        S->status = status;
+        return go(kOpDelta);
+    };
+    auto stop = [&](int status) {    // stop without output (invalid input, device error)
+        S->status = status;
+        return go(kOpDone);
+    };
+    auto c_decide = [&]() {
+        if (c[kCntCase + st.type] > 0) return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
+        if (st.type < 3) {
+            st.type += 1;
+            return go(kOpDetect);
+        }
+        if (c[kCntCase + 0] + c[kCntCase + 1] + c[kCntCase + 2] > 0) {
+            st.type = 0;
+            return go(kOpDetect);
+        }
+        return go(kOpRTile);
+    };
+    switch (st.op) {
+        case kOpPreA:
+            if (c[kCntErr] & kErrNonFinite) return stop(MSZ_ENONFINITE);
+            if (c[kCntErr] & kErrBound) return stop(MSZ_EBOUND);
+            return go(kOpPreB);
+        case kOpPreB:
+            return go(kOpPreC);
+        case kOpPreC:
+            if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
+            return go(kOpPreD);
+        case kOpPreD:
+            for (int t = 0; t < 4; ++t) S->false_init[t] = c[kCntCase + t];
+            S->outer_iters = 1;
+            st.type = 0;
+            return c_decide();
+        case kOpDdC:
+        case kOpDetect:
+            return c_decide();
+        case kOpApplyC:
+            if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
+            S->rounds_total += 1;
+            S->rounds[st.type] += 1;
+            return go(kOpDdC);
+        case kOpRTile:
+            return go(kOpRJump);
+        case kOpRJump:
+            if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
+            return go(kOpRDetect);
+        case kOpRDetect:
+            if (c[kCntWrong] == 0) return finish(MSZ_OK);
+            if (S->rounds_total >= F.cap) return finish(MSZ_ENOCONV);
+            return go(kOpApplyR);
+        case kOpApplyR:
+            if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
+            S->rounds_total += 1;
+            S->rounds_r += 1;
+            st.type = 0;
+            return go(kOpDdR);
+        case kOpDdR:
+            if (c[kCntCase + 0] + c[kCntCase + 1] + c[kCntCase + 2] + c[kCntCase + 3] > 0) {
+                S->outer_iters += 1;
+                return c_decide();
+            }
+            return go(kOpRTile);
+        case kOpDelta:
+            S->n_edited = c[kCntEdited];
+            S->n_inexact = c[kCntInexact];
+            return go(kOpDone);
+        default:
+            return go(kOpDone);
+    }
+}
+
+// Grid-wide barrier: arrive on a counter, the last block bumps the generation.
+// All blocks are resident (the grid is sized to the occupancy limit and
+// launched cooperatively); a block that waits longer than ~4 s raises the
+// abort flag instead of hanging, and every block leaves at the next barrier.
+__device__ __forceinline__ bool eng_barrier(unsigned* bar, unsigned& gen) {
+    __shared__ int s_abort;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned arrived = atomicAdd(&bar[0], 1u) + 1u;
+        if (arrived == gridDim.x) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();
+            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const unsigned long long t0 = wall_clock64();
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+                if (wall_clock64() - t0 > 400000000ull) {  // 4 s at the 100 MHz constant clock
+                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        __threadfence();
+        gen += 1u;
+        s_abort = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    }
+    __syncthreads();
+    return s_abort == 0;
+}
+
+__global__ void __launch_bounds__(256) k_engine(const EngField* __restrict__ fields, EngState* states,
+                                                EngStats* stats, unsigned* tickets, unsigned* bar, int nf,
+                                                int max_steps) {
+    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    __shared__ int pre[kEngMaxFields + 1];
+    unsigned gen = 0;
+    for (int step = 0; step < max_steps; ++step) {
+        const int par = step & 1;
+        const EngState* cur = states + par * nf;
+        EngState* nxt = states + (par ^ 1) * nf;
+        for (int f = threadIdx.x; f < nf; f += blockDim.x) pre[f + 1] = cur[f].items;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            pre[0] = 0;
+            for (int f = 0; f < nf; ++f) pre[f + 1] += pre[f];
+        }
+        __syncthreads();
+        const int total = pre[nf];
+        if (total == 0) break;  // every field is done (the same for all blocks)
+        if (blockIdx.x == 0)
+            for (int f = threadIdx.x; f < nf; f += blockDim.x)
+                if (cur[f].items == 0) nxt[f] = cur[f];  // finished fields keep their state
+        for (int item = blockIdx.x; item < total; item += gridDim.x) {
+            int lo = 0, hi = nf - 1;  // the field whose items contain `item`
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= item) lo = mid;
+                else hi = mid - 1;
+            }
+            const EngField& F = fields[lo];
+            const EngState st = cur[lo];
+            unsigned* cset = F.cnt + par * kEngSet;
+            eng_run(F, st, item - pre[lo], smem, cset);
+            if (threadIdx.x == 0) {
+                __threadfence();
+                const unsigned done = atomicAdd(&tickets[2 * lo + par], 1u);
+                if (done + 1u == static_cast<unsigned>(st.items)) {
+                    __threadfence();
+                    tickets[2 * lo + par] = 0u;
+                    nxt[lo] = eng_decide(F, st, stats + lo, cset);
+                }
+            }
+        }
+        if (!eng_barrier(bar, gen)) return;
+    }
+}
+
+// Zeroes the per-field marks and counters and the engine's control words.
+__global__ void __launch_bounds__(256) k_engine_init(const EngField* __restrict__ fields, int nf, unsigned* tickets,
+                                                     unsigned* bar) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
+    for (int f = 0; f < nf; ++f) {
+        const EngField& F = fields[f];
+        uint4* m = reinterpret_cast<uint4*>(F.marks);
+        const int nw = (F.gr.n + 15) >> 4;
+        for (int w = tid; w < nw; w += nthr) m[w] = make_uint4(0u, 0u, 0u, 0u);
+        for (int w = tid; w < 2 * kEngSet; w += nthr) F.cnt[w] = 0u;
+    }
+    for (int w = tid; w < 2 * nf; w += nthr) tickets[w] = 0u;
+    if (tid < 4) bar[tid] = 0u;
+}
+
+const void* engine_kernel() { return reinterpret_cast<const void*>(&k_engine); }
+const void* engine_init_kernel() { return reinterpret_cast<const void*>(&k_engine_init); }
 
 }  // namespace msz

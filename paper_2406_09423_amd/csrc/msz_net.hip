@@ -307,15 +307,19 @@ __global__ void __launch_bounds__(256) k_features(const float* __restrict__ fhat
 
 // Mean squared error: loss partial sums and dL/dp (the output layer is
 // linear), stored as a 16-channel gradient tensor with channel 0 in use.
+// Vertex i weighs 1 + edit_weight when its target is positive.
 __global__ void __launch_bounds__(256) k_mse(const float* __restrict__ p, const float* __restrict__ target, int n,
-                                             uint16_t* __restrict__ dz, float* __restrict__ loss_part) {
+                                             float edit_weight, uint16_t* __restrict__ dz,
+                                             float* __restrict__ loss_part) {
     __shared__ float red[4];
     float acc = 0.0f;
     const float scale = 2.0f / static_cast<float>(n);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float d = p[i] - target[i];
-        acc += d * d;
-        const float gz = scale * d;
+        const float t = target[i];
+        const float d = p[i] - t;
+        const float w = t > 0.0f ? 1.0f + edit_weight : 1.0f;
+        acc += w * d * d;
+        const float gz = scale * w * d;
         uint4* row = reinterpret_cast<uint4*>(dz) + 2 * static_cast<long>(i);
         row[0] = make_uint4(bf16_bits(gz), 0u, 0u, 0u);
         row[1] = make_uint4(0u, 0u, 0u, 0u);
@@ -340,14 +344,15 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, const float
     }
 }
 
-// Warm start: g0 = clamp(fl(fhat - fl(p * xi)), L, fhat).
+// Warm start: g0 = clamp(fl(fhat - fl(p * xi)), L, fhat) where p > p_min, else fhat.
 __global__ void __launch_bounds__(256) k_warm_start(const float* __restrict__ p, const float* __restrict__ L,
-                                                    const float* __restrict__ fhat, float xi, int n,
+                                                    const float* __restrict__ fhat, float xi, float p_min, int n,
                                                     float* __restrict__ g0) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const float h = fhat[i];
-        const float v = __fsub_rn(h, __fmul_rn(p[i], xi));
-        g0[i] = fminf(fmaxf(v, L[i]), h);
+        const float pi = p[i];
+        const float v = __fsub_rn(h, __fmul_rn(pi, xi));
+        g0[i] = pi > p_min ? fminf(fmaxf(v, L[i]), h) : h;
     }
 }
 
@@ -571,8 +576,8 @@ int msz_net_forward(const float* params, const uint16_t* feat, msz_dims d, float
     return hipStreamSynchronize(s) == hipSuccess ? MSZ_OK : MSZ_EDEVICE;
 }
 
-int msz_net_gradients(const float* params, const uint16_t* feat, const float* target, msz_dims d, float* grad_out,
-                      float* loss_out, void* workspace, size_t workspace_bytes, void* stream) {
+int msz_net_gradients(const float* params, const uint16_t* feat, const float* target, float edit_weight, msz_dims d,
+                      float* grad_out, float* loss_out, void* workspace, size_t workspace_bytes, void* stream) {
     Grid gr;
     if (!make_grid(d, gr) || !params || !feat || !target || !grad_out || !loss_out || !al16(feat)) return MSZ_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -591,7 +596,7 @@ int msz_net_gradients(const float* params, const uint16_t* feat, const float* ta
     const int nt = conv_tile_count(gr);
     net_forward(params, feat, gr, a1, a2, p, s);
     const int nb = blocks_n(gr.n);
-    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, p, target, gr.n, dza, lp);
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, p, target, gr.n, edit_weight, dza, lp);
     const int rb = (27 * 256 + 16 + 255) / 256;
     // layer 2
     launch_dw_t<16>(a2, dza, gr, part, part_b, s);
@@ -629,8 +634,8 @@ int msz_net_adam(float* params, const float* grad, float* m, float* v, int32_t n
     return hipStreamSynchronize(s) == hipSuccess ? MSZ_OK : MSZ_EDEVICE;
 }
 
-int msz_fix_learned(const float* f, const float* fhat, msz_dims d, float xi, const float* params, float* edits_out,
-                    const msz_options* opt, msz_stats* stats, void* stream) {
+int msz_fix_learned(const float* f, const float* fhat, msz_dims d, float xi, const float* params, float p_min,
+                    float* edits_out, const msz_options* opt, msz_stats* stats, void* stream) {
     if (!stats) return MSZ_EINVAL;
     std::memset(stats, 0, sizeof(*stats));
     Grid gr;
@@ -661,7 +666,7 @@ int msz_fix_learned(const float* f, const float* fhat, msz_dims d, float xi, con
     if (rc == MSZ_OK) {
         net_forward(params, feat, gr, reinterpret_cast<uint16_t*>(w + l.a1), reinterpret_cast<uint16_t*>(w + l.a2), p, s);
         hipLaunchKernelGGL(k_floor, dim3(blocks_n(gr.n)), dim3(256), 0, s, f, xi, gr.n, L);
-        hipLaunchKernelGGL(k_warm_start, dim3(blocks_n(gr.n)), dim3(256), 0, s, p, L, fhat, xi, gr.n, g0);
+        hipLaunchKernelGGL(k_warm_start, dim3(blocks_n(gr.n)), dim3(256), 0, s, p, L, fhat, xi, p_min, gr.n, g0);
         if (hipGetLastError() != hipSuccess) rc = MSZ_EDEVICE;
     }
     if (timing) (void)hipEventRecord(e1, s);

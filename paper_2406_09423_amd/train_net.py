@@ -3,8 +3,12 @@
 Training pairs come from the plain correction loop: for each seeded 128^3
 field, the target of vertex i is its final edit in units of xi,
 t_i = (fhat_i - g_i) / xi >= 0, and the inputs are the library's features of
-(f, fhat, xi).  Loss: mean squared error; optimiser: Adam on FP32 master
-weights; forward and backward run in BF16 on MFMA (msz_net_gradients).
+(f, fhat, xi).  Loss: mean squared error in which vertices with a non-zero
+target weigh 1 + edit_weight (edited vertices are a few percent of a field,
+so an unweighted loss settles on a small positive edit everywhere);
+optimiser: Adam on FP32 master weights; forward and backward run in BF16 on
+MFMA (msz_net_gradients).  The warm start applies a prediction only where it
+exceeds p_min, so that vertices the network is unsure about keep fhat.
 
   python -m paper_2406_09423_amd.train_net --fields 200 --epochs 6 --out weights.npy
 """
@@ -65,7 +69,7 @@ def make_pair(f, fh, xi, ws):
 
 
 def train(n_fields: int = 200, side: int = 128, epochs: int = 6, lr: float = 2e-3, seed: int = 0,
-          log_every: int = 50):
+          edit_weight: float = 8.0, log_every: int = 50):
     import torch
 
     import synth
@@ -93,7 +97,8 @@ def train(n_fields: int = 200, side: int = 128, epochs: int = 6, lr: float = 2e-
         losses = []
         for k in order:
             feat, t = data[k]
-            loss, _ = msz.net_gradients(params, feat, t, shape, grad_out=grad, workspace=nws)
+            loss, _ = msz.net_gradients(params, feat, t, shape, edit_weight=edit_weight, grad_out=grad,
+                                        workspace=nws)
             step += 1
             msz.net_adam(params, grad, m, v, step, lr)
             losses.append(loss)
@@ -101,10 +106,11 @@ def train(n_fields: int = 200, side: int = 128, epochs: int = 6, lr: float = 2e-
         log(f"epoch {ep + 1}/{epochs}: mean loss {history[-1]:.5f} ({time.perf_counter() - t1:.1f} s)")
     torch.cuda.synchronize()
     return params, {"loss_per_epoch": history, "fields": n_fields, "side": side, "epochs": epochs, "lr": lr,
-                    "train_seconds": time.perf_counter() - t1, "data_seconds": t1 - t0}
+                    "edit_weight": edit_weight, "train_seconds": time.perf_counter() - t1,
+                    "data_seconds": t1 - t0}
 
 
-def evaluate(params, fields, reps: int = 3):
+def evaluate(params, fields, reps: int = 3, p_mins=(0.5,)):
     """Rounds and time of the plain loop against the warm-started loop on each field."""
     import torch
     out = []
@@ -112,8 +118,11 @@ def evaluate(params, fields, reps: int = 3):
         fd, fhd = torch.from_numpy(f).cuda(), torch.from_numpy(fh).cuda()
         ws = torch.empty(msz.learned_workspace_bytes(f.shape), dtype=torch.uint8, device="cuda")
         res = {}
-        for name, fn in (("plain", lambda: msz.fix(fd, fhd, xi, workspace=ws)),
-                         ("learned", lambda: msz.fix_learned(fd, fhd, xi, params, workspace=ws))):
+        runs = [("plain", lambda: msz.fix(fd, fhd, xi, workspace=ws))]
+        for pm in p_mins:
+            runs.append((f"learned@{pm:g}",
+                         lambda pm=pm: msz.fix_learned(fd, fhd, xi, params, p_min=pm, workspace=ws)))
+        for name, fn in runs:
             fn()
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -135,14 +144,16 @@ def main():
     ap.add_argument("--side", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--edit-weight", type=float, default=8.0)
+    ap.add_argument("--p-min", type=float, nargs="+", default=[0.5])
     ap.add_argument("--out", default=WEIGHTS_PATH)
     ap.add_argument("--eval", type=int, default=4, help="held-out 128^3 fields to evaluate")
     args = ap.parse_args()
     import synth
-    params, info = train(args.fields, args.side, args.epochs, args.lr)
+    params, info = train(args.fields, args.side, args.epochs, args.lr, edit_weight=args.edit_weight)
     np.save(args.out, params.cpu().numpy())
     held = [synth.heldout_field(k, n=args.side) for k in range(args.eval)]
-    info["heldout"] = evaluate(params, held)
+    info["heldout"] = evaluate(params, held, p_mins=args.p_min)
     print(json.dumps(info), flush=True)
 
 

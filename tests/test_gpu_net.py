@@ -148,10 +148,11 @@ def test_gradients_match_oracle(msz):
     rng = np.random.default_rng(6)
     t = rng.uniform(0.5, 2.0, size=shape).astype(np.float32)
     flat = torch.from_numpy(flat_params(params)).cuda()
-    loss, g = msz.net_gradients(flat, to_dev_feat(x), torch.from_numpy(t.ravel()).cuda(), shape)
+    t[rng.uniform(size=shape) < 0.6] = 0.0      # sparse targets, as in training
+    loss, g = msz.net_gradients(flat, to_dev_feat(x), torch.from_numpy(t.ravel()).cuda(), shape, edit_weight=4.0)
     gg = unflat_grads(g.cpu().numpy())
     p, cache = nr.forward(x, params, round_bf16=True)
-    lo, dp = nr.mse_loss(p, t.astype(np.float64))
+    lo, dp = nr.mse_loss(p, t.astype(np.float64), edit_weight=4.0)
     ref = nr.backward(cache, dp)
     assert abs(loss - lo) <= 2.0 ** -5 * lo
     for li in range(3):

@@ -258,3 +258,51 @@ def test_full_turb256_properties(msz):
     assert (Mg == Mf).all() and (mg == mf).all()
     # the oracle's own run (about 2.5 min of CPU) took the same rounds: sampled here by its stats
     assert sum(st["rounds"]) + st["rounds_r"] > 0
+
+
+# ------------------------------------------------------------ batched ---
+
+def _batch_case(seed):
+    rng = np.random.default_rng(seed)
+    shapes = [(37, 70), (128, 96), (1, 5), (20, 33, 17), (48, 48, 48), (3, 200), (16, 16, 16), (250, 301)]
+    fields = []
+    for k, shape in enumerate(shapes):
+        f = synth.gaussian_random_field(shape, 3.0, rng).astype(np.float32)
+        rel = (1e-4, 1e-3, 1e-2)[k % 3]
+        xi = synth.xi_for(f, rel) if f.max() > f.min() else np.float32(0.01)
+        fields.append((f, synth.quantize(f, xi), xi))
+    return fields
+
+
+@pytest.mark.parametrize("seed,tiles", [(21, None), (22, "mixed")])
+def test_batch_bit_exact_with_single_fix(msz, seed, tiles):
+    fields = _batch_case(seed)
+    tl = None
+    if tiles == "mixed":
+        tl = [(j % (msz.tile_variants(f.ndim) + 1)) for j, (f, _, _) in enumerate(fields)]
+    _say("batch of", len(fields), "tiles", tl)
+    rc, res = msz.fix_batch([(dev(f), dev(fh), xi) for f, fh, xi in fields], tiles=tl)
+    torch.cuda.synchronize()
+    for j, (f, fh, xi) in enumerate(fields):
+        st_b, d_b, g_b, s_b = res[j]
+        rc_s, d_s, g_s, s_s = msz.fix(dev(f), dev(fh), xi)
+        assert st_b == rc_s == s_b["status"], (j, st_b, rc_s)
+        assert (_bits(host(g_b)) == _bits(host(g_s))).all(), j
+        assert (_bits(host(d_b)) == _bits(host(d_s))).all(), j
+        assert s_b == s_s, (j, s_b, s_s)
+    assert rc == msz.OK
+
+
+def test_batch_error_and_cap(msz):
+    fields = _batch_case(23)[:4]
+    f, fh, xi = fields[1]
+    bad = fh.copy()
+    bad.ravel()[7] = f.ravel()[7] + np.float32(3) * xi
+    jobs = [(dev(a), dev(b), x) for a, b, x in fields] + [(dev(f), dev(bad), xi)]
+    rc, res = msz.fix_batch(jobs, max_rounds=2)
+    assert res[-1][0] == msz.EBOUND
+    for j, (a, b, x) in enumerate(fields):
+        rc_s, d_s, g_s, s_s = msz.fix(dev(a), dev(b), x, max_rounds=2)
+        assert res[j][0] == rc_s
+        assert (_bits(host(res[j][2])) == _bits(host(g_s))).all()
+    assert rc != msz.OK
