@@ -2,13 +2,22 @@
 
 A step corrects the 3600x2400 k^-3 Gaussian-random-field pair (xi = 1e-4 and
 1e-3 of the value range) to zero segmentation error with the plain loop; the
-fields are resident in HBM before the clock starts.  Prints one JSON line.
+fields are resident in HBM before the clock starts.  The same run also times
+the two other forms on their own workloads (reported under "forms"):
+  batched  96 uneven k^-3 fields (64 2D with sides 64..2048, 32 3D cubes
+           32^3..192^3, xi in {1e-4, 1e-3, 1e-2} x range) in one launch
+  learned  a 512^3 k^-11/3 field at xi = 1e-3 x range: the warm-started loop
+           (features + network + loop) against the plain loop on that field.
+Every result is checked for zero segmentation error outside the clock.
+Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,batched,learned]
+                  [--no-cpu-baseline] [--calib-copy]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,13 +29,18 @@ if ROOT not in sys.path:
 
 METRIC = "Gvertices/s corrected to zero MS-label error @xi; plain vs batched vs learned"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2406_09423_amd/csrc/msz_kernels.hip", "paper_2406_09423_amd/csrc/msz_internal.h")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ocean2d.json")
+CALIB_BYTES = 1 << 30   # bytes read (and written) by the calibration copy
 
 # Algorithmic (compulsory) HBM bytes per vertex of each kernel kind, per launch.
 BYTES_PER_VERTEX = {
     "dirs_detect": 4 + 1 + 1,   # read g, read dirs_f, write dirs_g (targets are sparse)
     "dirs": 4 + 1,              # read the field, write dirs
     "detect": 1 + 1,            # read dirs_f and dirs_g
+    "apply": 1,                 # read the marks (edited vertices are sparse)
     "label_tile": 1 + 8,        # read dirs, write both pointer arrays
+    "label_jump": 0,            # touches only the tiles' face layers
     "detect_r": 2 + 8 + 8 + 8,  # dirs x2, pointers x2, pointer-of-pointer x2, labels of f x2
     "delta": 4 + 4 + 4 + 4,     # read g, fhat; write delta, g
     "validate": 4 + 4 + 4 + 4,  # read f, fhat; write L, g
@@ -38,32 +52,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the correction loop of one field runs on one GPU; see DESIGN.md for sharding)",
-              file=sys.stderr)
-        sys.exit(2)
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
-    import numpy as np
-    import torch
 
-    import paper_2406_09423_amd as msz
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    with open(TRAFFIC_SUMMARY) as fh:
+        s = json.load(fh)
+    if s.get("source_hash") != kernel_source_hash():
+        return None
+    k = s.get("kernels", {}).get(kernel)
+    return int(k["bytes_per_launch"]) if k else None
+
+
+def checked(msz, f, g, xi):
+    cnt = msz.count_false(f, g)
+    if any(v != 0 for v in cnt.values()):
+        raise RuntimeError(f"segmentation error left: {cnt}")
+    err = (f.double() - g.double()).abs().max().item()
+    if err > xi:
+        raise RuntimeError(f"bound broken: {err} > {xi}")
+
+
+def bench_plain(msz, torch, dev, args):
     import synth
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     log("bench: generating the 3600x2400 pair")
     pairs = synth.ocean2d()
-    fields = []
-    for f, fh, xi in pairs:
-        fields.append((torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)))
+    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)) for f, fh, xi in pairs]
     n_per = fields[0][0].numel()
     ws = torch.empty(msz.workspace_bytes(fields[0][0].shape), dtype=torch.uint8, device=dev)
     outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
@@ -82,10 +105,9 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
-    phase_ms = {}
-    phase_n = {}
+    phase_ms, phase_n = {}, {}
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for _ in range(args.steps):
         sts = step(timing=True)
         for st in sts:
             for name, v in st["timing"].items():
@@ -95,20 +117,15 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     verts = n_per * len(fields)
-    value = verts / (ms_per_step * 1e-3) / 1e9
-    log(f"bench: {ms_per_step:.3f} ms/step, {value:.3f} Gvertices/s")
-
-    # outside the clock: every result must have zero segmentation error within xi
-    for (f, fh, xi), (e, g), st in zip(fields, outs, sts):
-        cnt = msz.count_false(f, g)
-        assert all(v == 0 for v in cnt.values()), cnt
-        err = (f.double() - g.double()).abs().max().item()
-        assert err <= xi, (err, xi)
+    log(f"bench: plain {ms_per_step:.3f} ms/step, {verts / ms_per_step / 1e6:.3f} Gvertices/s")
+    for (f, fh, xi), (e, g) in zip(fields, outs):
+        checked(msz, f, g, xi)
 
     dominant = max((k for k in phase_ms if phase_n.get(k)), key=lambda k: phase_ms[k])
     avg_ms = phase_ms[dominant] / phase_n[dominant]
     bpl = BYTES_PER_VERTEX.get(dominant, 0) * n_per
     achieved = bpl / (avg_ms * 1e-3) / 1e9 if bpl else None
+    traffic = stored_traffic(dominant)
     roofline = {
         "kernel": dominant,
         "bound": "hbm",
@@ -116,28 +133,171 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": None,
+        "traffic": traffic,
         "avg_launch_us": round(avg_ms * 1e3, 2),
         "bytes_per_launch": bpl,
         "launches_per_step": phase_n[dominant] / args.steps,
     }
-    phases = {k: {"ms_per_step": round(phase_ms[k] / args.steps, 4),
-                  "launches_per_step": phase_n[k] / args.steps,
-                  "avg_us": round(phase_ms[k] / phase_n[k] * 1e3, 2) if phase_n[k] else None}
-              for k in phase_ms}
+    phases = {}
+    for k in phase_ms:
+        if not phase_n[k]:
+            continue
+        us = phase_ms[k] / phase_n[k] * 1e3
+        b = BYTES_PER_VERTEX.get(k)
+        phases[k] = {"ms_per_step": round(phase_ms[k] / args.steps, 4),
+                     "launches_per_step": phase_n[k] / args.steps, "avg_us": round(us, 2),
+                     "algorithmic_GBps": round(b * n_per / (us * 1e-6) / 1e9, 1) if b else None}
+    rounds = [{"xi": xi, "rounds": st["rounds"], "rounds_r": st["rounds_r"], "outer_iters": st["outer_iters"],
+               "n_edited": st["n_edited"]} for (_, _, xi), st in zip(fields, sts)]
+    return pairs, verts, ms_per_step, roofline, phases, rounds
+
+
+def bench_batched(msz, torch, dev, steps):
+    import synth
+    from paper_2406_09423_amd import autotune
+    log("bench: generating the 96-field batch")
+    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi))
+              for f, fh, xi in synth.batch_fields(0)]
+    shapes = [f.shape for f, _, _ in fields]
+    tiles = autotune.tiles_for(shapes)
+    verts = sum(f.numel() for f, _, _ in fields)
+    outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
+    ws = torch.empty(msz.batch_workspace_bytes(shapes), dtype=torch.uint8, device=dev)
+
+    def run():
+        rc, res = msz.fix_batch(fields, workspace=ws, tiles=tiles, outs=outs)
+        if rc != msz.OK:
+            raise RuntimeError(f"msz_fix_batch failed: {msz.strerror(rc)}")
+        return res
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    for (f, fh, xi), (_, _, g, _) in zip(fields, res):
+        checked(msz, f, g, xi)
+    # the same fields one msz_fix call after another, for comparison
+    ws1 = torch.empty(max(msz.workspace_bytes(s) for s in shapes), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (f, fh, xi), (e, g), tl in zip(fields, outs, tiles):
+        rc, _, _, _ = msz.fix(f, fh, xi, workspace=ws1, edits_out=e, g_out=g, tile=tl)
+        if rc != msz.OK:
+            raise RuntimeError(f"msz_fix failed: {msz.strerror(rc)}")
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3
+    log(f"bench: batched {ms:.2f} ms ({verts / ms / 1e6:.3f} Gv/s), one by one {ms_seq:.2f} ms")
+    rounds = [sum(st["rounds"]) + st["rounds_r"] for _, _, _, st in res]
+    return {"workload": "96 uneven k^-3 fields: 64 2D (sides U{64..2048}), 32 3D (U{32..192}^3), "
+                        "xi in {1e-4,1e-3,1e-2} x range; one persistent launch",
+            "vertices": verts, "ms": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
+            "steps": steps, "sequential_ms": round(ms_seq, 3),
+            "speedup_vs_sequential": round(ms_seq / ms, 3), "max_rounds": max(rounds),
+            "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}}
+
+
+def bench_learned(msz, torch, dev, steps):
+    import numpy as np
+
+    import synth
+    from paper_2406_09423_amd import train_net
+    if not os.path.exists(train_net.WEIGHTS_PATH):
+        return {"skipped": "no trained weights stored"}
+    params = train_net.load_weights()
+    p_min = train_net.stored_p_min()
+    log("bench: generating the 512^3 field")
+    f, fh, xi = synth.turb512()[0]
+    fd, fhd = torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev)
+    del f, fh
+    xi = float(xi)
+    ws = torch.empty(msz.learned_workspace_bytes(fd.shape), dtype=torch.uint8, device=dev)
+    e, g = torch.empty_like(fd), torch.empty_like(fd)
+    out = {"workload": "512^3 k^-11/3 Gaussian random field, xi = 1e-3 x range", "vertices": fd.numel(),
+           "p_min": p_min, "steps": steps}
+    for name, fn in (("plain", lambda t: msz.fix(fd, fhd, xi, workspace=ws, edits_out=e, g_out=g, timing=t)),
+                     ("learned", lambda t: msz.fix_learned(fd, fhd, xi, params, p_min=p_min, workspace=ws,
+                                                           edits_out=e, g_out=g, timing=t))):
+        fn(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rc, _, _, st = fn(False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if rc != msz.OK:
+            raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
+        checked(msz, fd, g, xi)
+        _, _, _, stt = fn(True)
+        out[name] = {"ms": round(ms, 3), "value": round(fd.numel() / ms / 1e6, 4),
+                     "rounds": sum(st["rounds"]) + st["rounds_r"], "outer_iters": st["outer_iters"],
+                     "n_edited": st["n_edited"], "net_ms": round(stt["timing"]["net"]["ms"], 3)}
+        log(f"bench: {name} 512^3 {ms:.2f} ms, rounds {out[name]['rounds']}")
+    out["speedup"] = round(out["plain"]["ms"] / out["learned"]["ms"], 4)
+    out["unit"] = "Gvertices/s"
+    return out
+
+
+def calibration_copy(torch, dev):
+    """A plain device copy of CALIB_BYTES, so that a counter run sees a kernel of known traffic."""
+    a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--forms", default="plain,batched,learned")
+    ap.add_argument("--form-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: one field's "
+              "correction loop runs on one GPU (DESIGN.md describes how the work would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    forms = [x for x in args.forms.split(",") if x]
+
+    import torch
+
+    import paper_2406_09423_amd as msz
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    msz.lib()
+    if args.calib_copy:
+        calibration_copy(torch, dev)
+    pairs, verts, ms_per_step, roofline, phases, rounds = bench_plain(msz, torch, dev, args)
+    value = verts / (ms_per_step * 1e-3) / 1e9
+
+    extra = {}
+    if "batched" in forms:
+        extra["batched"] = bench_batched(msz, torch, dev, args.form_steps)
+    if "learned" in forms:
+        extra["learned"] = bench_learned(msz, torch, dev, args.form_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
+        oracle.build()
         f, fh, xi = pairs[0]
-        log("bench: oracle on the xi=1e-4 field (one core)")
+        log("bench: oracle on the xi = 1e-4 field (serial C, one core)")
         tc = time.perf_counter()
         rc, _, _, _ = oracle.fix(f, fh, xi)
         dt = time.perf_counter() - tc
         assert rc == 0
         cpu = {"value": round(f.size / dt / 1e9, 6), "unit": "Gvertices/s", "cores": 1, "kind": "oracle",
-               "sample": "the xi=1e-4 field of the 3600x2400 pair (half a step), serial C oracle",
-               "seconds": round(dt, 2)}
+               "sample": "half a step: the xi = 1e-4 field of the 3600x2400 pair (8.64 M vertices), "
+                         "serial C oracle on one core", "seconds": round(dt, 2)}
 
     out = {
         "metric": METRIC,
@@ -158,9 +318,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,
-        "rounds": [{"xi": xi, "rounds": st["rounds"], "rounds_r": st["rounds_r"],
-                    "outer_iters": st["outer_iters"], "n_edited": st["n_edited"]}
-                   for (_, _, xi), st in zip(fields, sts)],
+        "rounds": rounds,
+        "forms": extra,
+        "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
 

@@ -191,33 +191,43 @@ size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs);
 int msz_tile_variants(int32_t ndim);
 
 /* ------------------------------------------------------------------------
- * Learned edit proposal (warm start).  A 3-layer 3x3x3 convolution network
- * (6 -> 16 -> 16 -> 1 channels, ReLU after the two hidden layers, a linear
- * output, zero padding) predicts p, the edit of every vertex in units of xi;
- * the correction loop then starts from g0 = clamp(fl(fhat - fl(p * xi)), L,
- * fhat) where p > p_min (elsewhere g0 = fhat) and, as always,
- * runs to zero segmentation error within xi.  Weights and activations are
- * BF16 (round to nearest even), sums FP32, on MFMA.
+ * Learned edit proposal (warm start).  Every edit of the correction loop
+ * moves g_i one step down the chain fhat_i, halve(fhat_i), ... towards L_i
+ * (Eqs. 2-6), so an edit is a count of halvings.  A 3-layer 3x3x3
+ * convolution network (16 -> 16 -> 16 -> 1 channels, ReLU after the two
+ * hidden layers, a linear output, zero padding) predicts p, the count of
+ * every vertex; the correction loop then starts from g0_i = fhat_i halved
+ * k_i times, k_i = floor(fl(p_i - p_min)) + 1 clamped to [0, 64] (0 for a
+ * NaN p), and, as always, runs to zero segmentation error within xi.
+ * Weights and activations are BF16 (round to nearest even), sums FP32, on
+ * MFMA.
  *
  * Parameters: MSZ_NET_PARAMS FP32 values, DEVICE, in this order
- *   W0[27][8][16] b0[16]   (input channels 6, 7 are padding, kept 0)
+ *   W0[27][16][16] b0[16]
  *   W1[27][16][16] b1[16]
  *   W2[27][16]     b2[1]
  * with tap = (dz+1)*9 + (dy+1)*3 + (dx+1) and W[tap][in][out].
- * Features: MSZ_NET_FEATURES BF16 values per vertex, DEVICE, [vertex][8]:
- *   0  (fhat - mean of fhat over the 3x3x3 box, in-grid vertices) / xi, clamped to [-8, 8]
+ * Features: MSZ_NET_FEATURES BF16 values per vertex, DEVICE, [vertex][16]
+ * (box = the 3x3x3 block around the vertex clipped to the grid; every
+ * clamp is to [-8, 8]; u ranges over the neighbours of the vertex i):
+ *   0  (fhat - mean of fhat over the box) / xi
  *   1  log10(xi / (max f - min f)) / 4 + 1
  *   2..5  false-critical-point flags of fhat against f (FPmax, FPmin, FNmax, FNmin)
- *   6, 7  zero
+ *   6  (fhat - f) / xi
+ *   7  (f - mean of f over the box) / xi
+ *   8  i = dn_f(u) for an FPmin vertex u      9  i = up_fhat(u) for an FNmax vertex u
+ *   10 i = dn_f(u) for a u with dn_fhat(u) != dn_f(u)
+ *   11 i = up_fhat(u) for a u with up_fhat(u) != up_f(u)
+ *   12..15 zero
  * 2D grids are treated as 3D grids with nz = 1.  All pointers 16-byte aligned.
  * ------------------------------------------------------------------------ */
-#define MSZ_NET_PARAMS 10833
-#define MSZ_NET_FEATURES 8
+#define MSZ_NET_PARAMS 14289
+#define MSZ_NET_FEATURES 16
 
 /* DEVICE scratch the net entry points need for dims d (0 for invalid dims). */
 size_t msz_net_workspace_bytes(msz_dims d);
 
-/* feat[n][8] (BF16 bits) from f, fhat and xi. */
+/* feat[n][16] (BF16 bits) from f, fhat and xi. */
 int msz_net_features(const float* f, const float* fhat, msz_dims d, float xi, uint16_t* feat,
                      void* workspace, size_t workspace_bytes, void* stream);
 
@@ -235,6 +245,12 @@ int msz_net_gradients(const float* params, const uint16_t* feat, const float* ta
                       msz_dims d, float* grad_out, float* loss_out, void* workspace,
                       size_t workspace_bytes, void* stream);
 
+/* Training target: k_out[i] = the number of halvings that take fhat_i to g_i
+ * (L from f and xi as in msz_fix), or -1 where g_i is not on that chain
+ * within 256 steps.  All arrays DEVICE, n floats; scratch: n floats. */
+int msz_net_halvings(const float* f, const float* fhat, const float* g, msz_dims d, float xi,
+                     float* k_out, void* workspace, size_t workspace_bytes, void* stream);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; step >= 1)
  * on n FP32 parameters with first / second moments m, v (DEVICE). */
 int msz_net_adam(float* params, const float* grad, float* m, float* v, int32_t n, int32_t step,
@@ -243,8 +259,8 @@ int msz_net_adam(float* params, const float* grad, float* m, float* v, int32_t n
 /* Scratch bytes of msz_fix_learned for dims d. */
 size_t msz_learned_workspace_bytes(msz_dims d);
 
-/* msz_fix started from the network's warm start (params: DEVICE, see above);
- * vertices with p <= p_min keep fhat in the start field.  opt->warm_start
+/* msz_fix started from the network's warm start (params: DEVICE; p_min: the
+ * count threshold, see above, 0.5 rounds p to the nearest count).  opt->warm_start
  * must be NULL; opt->workspace, if given, must hold
  * msz_learned_workspace_bytes(d).  With MSZ_FLAG_TIMING the network's kernels
  * are reported under MSZ_PHASE_NET. */

@@ -11,19 +11,23 @@ Layouts: activations are channel-first ``[C, nz, ny, nx]``; weights
 ``[C_out, C_in, 3, 3, 3]`` indexed by (dz+1, dy+1, dx+1); biases ``[C_out]``.
 Outside the grid the input counts as zero (zero padding).
 
-Network (edit-magnitude predictor): conv(6->16) ReLU, conv(16->16) ReLU,
-conv(16->1), giving p, the predicted edit in units of xi.  The output layer
-is linear (a ReLU there can switch the whole output off for good while
-training on mostly-zero targets); the warm start clamps fhat - p*xi into
-[L, fhat], so a negative p means "no edit".
+Network (edit predictor): conv(12->16) ReLU, conv(16->16) ReLU, conv(16->1),
+giving p, the predicted number of halvings (Eqs. 2-6) the correction loop
+applies to the vertex.  Every edit of the loop moves g_i one step down the
+chain fhat_i, halve(fhat_i), halve(halve(fhat_i)), ... towards L_i, so a
+count reproduces an edit bit-exactly.  The output layer is linear (a ReLU
+there can switch the whole output off for good while training on
+mostly-zero targets).  The warm start applies k_i = floor(p_i - p_min) + 1
+halvings, clamped to [0, 64] (p_min = 1/2 rounds p to the nearest count).
 """
 from __future__ import annotations
 
 import numpy as np
 
 TAPS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-CHANNELS = (6, 16, 16, 1)
-N_FEATURES = 6
+CHANNELS = (12, 16, 16, 1)
+N_FEATURES = 12
+MAX_WARM_HALVINGS = 64
 
 
 def bf16(a) -> np.ndarray:
@@ -146,19 +150,82 @@ def box_mean(h: np.ndarray) -> np.ndarray:
     return s / c
 
 
-def features(fhat: np.ndarray, xi: float, case_bits: np.ndarray, value_range: float) -> np.ndarray:
-    """The six input channels of a field shaped (nz, ny, nx):
+def features(f: np.ndarray, fhat: np.ndarray, xi: float, case_bits: np.ndarray, value_range: float,
+             dirs_f, dirs_h) -> np.ndarray:
+    """The twelve input channels of a field shaped (nz, ny, nx).  dirs_f and
+    dirs_h are the (up, dn) steepest-neighbour ids of f and fhat.
       0  (fhat - 3x3x3 box mean of fhat) / xi, clamped to [-8, 8]
       1  log10(xi / value_range) / 4 + 1      (constant over the field)
       2..5  the four false-critical-point flags of fhat against f
-            (FPmax, FPmin, FNmax, FNmin; bits 0..3 of case_bits)."""
+            (FPmax, FPmin, FNmax, FNmin; bits 0..3 of case_bits)
+      6  (fhat - f) / xi, clamped to [-8, 8]  (room above the floor f - xi)
+      7  (f - 3x3x3 box mean of f) / xi, clamped to [-8, 8]
+      8  the vertex is dn_f(u) of an FPmin vertex u (that case's edit target)
+      9  the vertex is up_fhat(u) of an FNmax vertex u (that case's edit target)
+      10 the vertex is dn_f(u) of a neighbour u whose descent differs (dn_fhat(u) != dn_f(u))
+      11 the vertex is up_fhat(u) of a neighbour u whose ascent differs (up_fhat(u) != up_f(u))."""
     x = np.zeros((N_FEATURES,) + fhat.shape, dtype=np.float64)
-    local = (fhat.astype(np.float64) - box_mean(fhat)) / float(xi)
-    x[0] = np.clip(local, -8.0, 8.0)
+    f64, h64 = f.astype(np.float64), fhat.astype(np.float64)
+    x[0] = np.clip((h64 - box_mean(fhat)) / float(xi), -8.0, 8.0)
     x[1] = np.log10(float(xi) / float(value_range)) / 4.0 + 1.0
     for t in range(4):
         x[2 + t] = (case_bits >> t) & 1
+    x[6] = np.clip((h64 - f64) / float(xi), -8.0, 8.0)
+    x[7] = np.clip((f64 - box_mean(f)) / float(xi), -8.0, 8.0)
+    uf, df = (np.asarray(a).ravel() for a in dirs_f)
+    uh, dh = (np.asarray(a).ravel() for a in dirs_h)
+    ids = np.arange(uf.size)
+    sources = [
+        ((case_bits.ravel() >> 1) & 1).astype(bool), df,       # FPmin u -> dn_f(u)
+        ((case_bits.ravel() >> 2) & 1).astype(bool), uh,       # FNmax u -> up_fhat(u)
+        (dh != df) & (df != ids), df,                          # descent differs -> dn_f(u)
+        (uh != uf) & (uh != ids), uh,                          # ascent differs -> up_fhat(u)
+    ]
+    for c in range(4):
+        sel, tgt = sources[2 * c], sources[2 * c + 1]
+        flat = np.zeros(uf.size)
+        flat[tgt[sel]] = 1.0
+        x[8 + c] = flat.reshape(fhat.shape)
     return x
+
+
+def halve32(g: np.ndarray, L: np.ndarray) -> np.ndarray:
+    """One decreasing edit in float32 (Eqs. 2-6 read with the float floor L):
+    fl(fl(g + L) * 0.5), or L itself when that leaves g unchanged."""
+    g = np.asarray(g, dtype=np.float32)
+    L = np.asarray(L, dtype=np.float32)
+    h = (g + L).astype(np.float32) * np.float32(0.5)
+    return np.where(h == g, L, h).astype(np.float32)
+
+
+def halving_count(fhat: np.ndarray, g: np.ndarray, L: np.ndarray, limit: int = 256) -> np.ndarray:
+    """Number of halvings that take fhat_i to g_i (-1 where g_i is not on the chain)."""
+    cur = np.asarray(fhat, dtype=np.float32).copy()
+    g = np.asarray(g, dtype=np.float32)
+    k = np.zeros(cur.shape, dtype=np.int64)
+    for _ in range(limit):
+        act = (cur != g) & (cur > g)
+        if not act.any():
+            break
+        cur[act] = halve32(cur[act], L[act])
+        k[act] += 1
+    k[cur != g] = -1
+    return k
+
+
+def warm_start(p: np.ndarray, fhat: np.ndarray, L: np.ndarray, p_min: float) -> np.ndarray:
+    """g0_i = fhat_i halved k_i times, k_i = floor(fl32(p_i - p_min)) + 1 clamped to
+    [0, MAX_WARM_HALVINGS] (0 where p_i is not a number)."""
+    q = np.floor((np.asarray(p, np.float32) - np.float32(p_min)).astype(np.float32)) + 1.0
+    q = np.where(np.isnan(q), 0.0, q)
+    k = np.clip(q, 0, MAX_WARM_HALVINGS).astype(np.int64)
+    g = np.asarray(fhat, dtype=np.float32).copy()
+    for j in range(MAX_WARM_HALVINGS):
+        act = k > j
+        if not act.any():
+            break
+        g[act] = halve32(g[act], L[act])
+    return g
 
 
 def adam_step(w, g, m, v, step: int, lr: float, b1: float = 0.9, b2: float = 0.999,

@@ -22,8 +22,8 @@ OK, EINVAL, ENONFINITE, EBOUND, ESTALL, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3
 CASE_NAMES = ("fp_max", "fp_min", "fn_max", "fn_min")
 PHASES = ("validate", "dirs", "dirs_detect", "detect", "apply", "label_tile", "label_jump",
           "label_final", "detect_r", "delta", "net")
-NET_PARAMS = 10833
-NET_FEATURES = 8
+NET_PARAMS = 14289
+NET_FEATURES = 16
 N_PHASES = len(PHASES)
 FLAG_TIMING = 1
 
@@ -109,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.msz_learned_workspace_bytes.restype = ctypes.c_size_t
         L.msz_net_features.argtypes = [P, P, Dims, F, P, P, ctypes.c_size_t, P]
         L.msz_net_forward.argtypes = [P, P, Dims, P, P, P, P, ctypes.c_size_t, P]
+        L.msz_net_halvings.argtypes = [P, P, P, Dims, F, P, P, ctypes.c_size_t, P]
         L.msz_net_gradients.argtypes = [P, P, P, F, Dims, P, ctypes.POINTER(ctypes.c_float), P,
                                         ctypes.c_size_t, P]
         L.msz_net_adam.argtypes = [P, P, P, P, I32, I32, F, P]
@@ -116,7 +117,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(Stats), P]
         for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants,
                    L.msz_net_features, L.msz_net_forward, L.msz_net_gradients, L.msz_net_adam,
-                   L.msz_fix_learned):
+                   L.msz_fix_learned, L.msz_net_halvings):
             fn.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -220,22 +221,33 @@ def count_false(f, g, stream=None) -> dict:
     return {k: int(getattr(c, k)) for k, _ in FalseCounts._fields_}
 
 
-def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles=None, stream=None):
+def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles="auto", outs=None,
+              stream=None):
     """Corrects a list of (f, fhat, xi) together in one persistent launch.
 
-    ``tiles`` optionally gives each field's direction tile variant (see
-    autotune.py).  Returns ``(status, [(status_j, delta_j, g_j, stats_j), ...])``.
+    ``tiles``: each field's direction tile variant, "auto" (the autotuner's
+    table, autotune.py) or None (the default tile).  ``outs`` optionally gives
+    preallocated (delta_j, g_j) pairs.  Returns
+    ``(status, [(status_j, delta_j, g_j, stats_j), ...])``.
     """
     import torch
     n = len(fields)
+    if isinstance(tiles, str):
+        if tiles != "auto":
+            raise ValueError(f"tiles must be 'auto', None or a list, got {tiles!r}")
+        from . import autotune
+        tiles = autotune.tiles_for([f.shape for f, _, _ in fields])
     jobs = (Job * n)()
     stats = [Stats() for _ in range(n)]
-    outs = []
+    pairs = []
     for j, (f, fh, xi) in enumerate(fields):
         _check_field(f, f"f[{j}]")
         _check_field(fh, f"fhat[{j}]")
-        e = torch.empty_like(f)
-        g = torch.empty_like(f) if want_g else None
+        if outs is not None:
+            e, g = outs[j]
+        else:
+            e = torch.empty_like(f)
+            g = torch.empty_like(f) if want_g else None
         jobs[j].f, jobs[j].fhat = f.data_ptr(), fh.data_ptr()
         jobs[j].d = dims_of(f.shape)
         jobs[j].xi = float(xi)
@@ -243,14 +255,14 @@ def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=Non
         jobs[j].edits_out = e.data_ptr()
         jobs[j].g_out = g.data_ptr() if g is not None else None
         jobs[j].stats = ctypes.pointer(stats[j])
-        outs.append((e, g))
+        pairs.append((e, g))
     opt = Options()
     opt.max_rounds = int(max_rounds)
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
     rc = lib().msz_fix_batch(jobs, n, ctypes.byref(opt), _stream(stream))
-    res = [(stats[j].status, outs[j][0], outs[j][1], stats[j].as_dict()) for j in range(n)]
+    res = [(stats[j].status, pairs[j][0], pairs[j][1], stats[j].as_dict()) for j in range(n)]
     return int(rc), res
 
 
@@ -279,7 +291,7 @@ def learned_workspace_bytes(shape) -> int:
 
 
 def net_features(f, fhat, xi: float, *, workspace=None, stream=None):
-    """BF16 features [n][8] of (f, fhat, xi), returned as an int16 tensor of raw bits."""
+    """BF16 features [n][16] of (f, fhat, xi), returned as an int16 tensor of raw bits."""
     import torch
     _check_field(f, "f")
     _check_field(fhat, "fhat")
@@ -322,6 +334,19 @@ def net_gradients(params, feat, target, shape, *, edit_weight: float = 0.0, grad
     if rc != OK:
         raise MszError(rc, "msz_net_gradients")
     return float(loss.value), g
+
+
+def net_halvings(f, fhat, g, xi: float, *, workspace=None, stream=None):
+    """Per-vertex number of halvings from fhat to g (-1 off the chain), float32."""
+    import torch
+    _check_field(g, "g")
+    k = torch.empty_like(g)
+    wp, wb = _ws_arg(workspace)
+    rc = lib().msz_net_halvings(f.data_ptr(), fhat.data_ptr(), g.data_ptr(), dims_of(f.shape), float(xi),
+                                k.data_ptr(), wp, wb, _stream(stream))
+    if rc != OK:
+        raise MszError(rc, "msz_net_halvings")
+    return k
 
 
 def net_adam(params, grad, m, v, step: int, lr: float, stream=None):

@@ -147,16 +147,40 @@ __device__ __forceinline__ unsigned c_cases(unsigned df, unsigned dg, int i, int
     return c0 | (c1 << 1) | (c2 << 2) | (c3 << 3);
 }
 
-// Counts every C type and marks the targets of `type`.
-__device__ __forceinline__ void detect_vertex(bool valid, unsigned df, unsigned dg, int i, int type,
-                                              const Grid& gr, uint8_t* marks, unsigned (&c)[4]) {
-    int t = 0;
-    const unsigned bits = valid ? c_cases(df, dg, i, type, gr, t) : 0u;
-    c[0] += bits & 1u;
-    c[1] += (bits >> 1) & 1u;
-    c[2] += (bits >> 2) & 1u;
-    c[3] += (bits >> 3) & 1u;
-    if ((bits >> type) & 1u) mark(marks, t);
+// Four packed direction bytes at once (byte k = vertex i0 + k): bit 4 of
+// byte k is set when that vertex's ascent (hi) or descent (lo) nibble is the
+// self slot 0xF.  A nibble y' = 15 - nibble is 0 exactly then, and
+// y' + 15 < 32 carries into bit 4 exactly when y' > 0; no byte carries into
+// the next.
+__device__ __forceinline__ unsigned hi_self4(unsigned d) {
+    return ~(((~d >> 4) & 0x0F0F0F0Fu) + 0x0F0F0F0Fu) & 0x10101010u;
+}
+__device__ __forceinline__ unsigned lo_self4(unsigned d) {
+    return ~((~d & 0x0F0F0F0Fu) + 0x0F0F0F0Fu) & 0x10101010u;
+}
+
+// C-loop detection (Defs. 1-3) of four vertices i0..i0+3 from their packed
+// directions in f (df4) and g (dg4); a byte of 0xFF in both (a vertex outside
+// the grid) has no case.  Counts every type and marks the targets of `type`
+// (Eqs. 2-5; FPmin lowers dn_f, FNmax lowers up_g).
+__device__ __forceinline__ void detect4(unsigned df4, unsigned dg4, int i0, int type, const Grid& gr,
+                                        uint8_t* __restrict__ marks, unsigned (&c)[4]) {
+    const unsigned ug = hi_self4(dg4), uf = hi_self4(df4), ng = lo_self4(dg4), nf = lo_self4(df4);
+    const unsigned fpmax = ug & ~uf, fpmin = ng & ~nf, fnmax = uf & ~ug, fnmin = nf & ~ng;
+    c[0] += __popc(fpmax);
+    c[1] += __popc(fpmin);
+    c[2] += __popc(fnmax);
+    c[3] += __popc(fnmin);
+    unsigned m = type == 0 ? fpmax : type == 1 ? fpmin : type == 2 ? fnmax : fnmin;
+    while (m) {
+        const int k = (__ffs(m) - 1) >> 3;
+        m &= m - 1u;
+        const int i = i0 + k;
+        int t = i;
+        if (type == 1) t = i + gr.off[(df4 >> (8 * k)) & 15u];
+        else if (type == 2) t = i + gr.off[(dg4 >> (8 * k + 4)) & 15u];
+        mark(marks, t);
+    }
 }
 
 // --------------------------------------------------- steepest directions ---
@@ -203,9 +227,16 @@ struct Steepest {
     }
 };
 
+// LDS plane layout: rows of W = 72 floats; column 4 + c holds x = x0 + c
+// (c = 0..63), column 3 the left halo x0 - 1, column 68 the right halo
+// x0 + 64, so every 4-vertex group starts on a 16-byte boundary.  H = TY + 2
+// rows (y0 - 1 .. y0 + TY).  A plane is loaded as 16 float4 per row plus two
+// halo floats per row.
 template <int NDIM, int TY, int ZC>
 struct DirsGeom {
-    static constexpr int W = kTileX + 2, H = TY + 2, P = W * H, NL = (P + 255) / 256, RPT = TY / 16;
+    static constexpr int W = 72, H = TY + 2, P = W * H, RPT = TY / 16;
+    static constexpr int NV = 16 * H, NH = 2 * H;               // float4 and halo loads per plane
+    static constexpr int LV = (NV + 255) / 256, LH = (NH + 255) / 256;
     static constexpr int NP = NDIM == 3 ? 3 : 1;     // LDS ring of planes
     static constexpr int ZCH = NDIM == 3 ? ZC : 1;   // planes computed per work item
     int tiles_x, tiles_y, tiles_z;
@@ -229,32 +260,61 @@ struct DirsGeom {
     }
 };
 
+// Registers holding one plane between its load and its LDS store.
+template <int NDIM, int TY, int ZC>
+struct PlaneRegs {
+    using G = DirsGeom<NDIM, TY, ZC>;
+    float4 v[G::LV];
+    float h[G::LH];
+    unsigned d[G::RPT];  // MODE 1: dirs_f words of the plane computed next
+};
+
 // Issues the loads of plane j of item it into registers (and, in MODE 1, the
 // dirs_f words of the plane that is computed once this one is in LDS).
+// Outside the grid a value is NaN, which never wins a comparison.  vec4: rows
+// start 16-byte aligned (nx % 4 == 0 and an aligned base), so whole in-grid
+// groups of four are one dwordx4 load.
 template <int NDIM, int TY, int ZC, int MODE>
 __device__ __forceinline__ void dirs_load(const float* __restrict__ h, const uint8_t* __restrict__ dirs_f,
-                                          const Grid& gr, const DirsGeom<NDIM, TY, ZC>& geo, int it, int j,
-                                          float (&pre)[DirsGeom<NDIM, TY, ZC>::NL],
-                                          unsigned (&dpre)[DirsGeom<NDIM, TY, ZC>::RPT]) {
+                                          const Grid& gr, const DirsGeom<NDIM, TY, ZC>& geo, bool vec4, int it,
+                                          int j, PlaneRegs<NDIM, TY, ZC>& pr) {
     using G = DirsGeom<NDIM, TY, ZC>;
     int x0, y0, z0;
     geo.origin(it, x0, y0, z0);
     const int z = NDIM == 3 ? z0 - 1 + j : 0;
     const bool zin = z >= 0 && z < gr.nz;
-    const long base = static_cast<long>(z) * gr.nxy;
+    const float* plane = h + static_cast<long>(z) * gr.nxy;
+    const float nan = __builtin_nanf("");
 #pragma unroll
-    for (int k = 0; k < G::NL; ++k) {
-        const int idx = threadIdx.x + 256 * k;
-        const int r = idx / G::W, c = idx - r * G::W;
-        const int x = x0 + c - 1, y = y0 + r - 1;
-        float v = __builtin_nanf("");
-        if (idx < G::P && zin && x >= 0 && x < gr.nx && y >= 0 && y < gr.ny)
-            v = h[base + x + static_cast<long>(gr.nx) * y];
-        pre[k] = v;
+    for (int k = 0; k < G::LV; ++k) {
+        const int u = threadIdx.x + 256 * k;
+        const int r = u >> 4, x = x0 + 4 * (u & 15), y = y0 + r - 1;
+        float4 v = make_float4(nan, nan, nan, nan);
+        if (u < G::NV && zin && y >= 0 && y < gr.ny && x < gr.nx) {
+            const float* src = plane + static_cast<long>(gr.nx) * y + x;
+            if (vec4 && x + 3 < gr.nx) {
+                v = *reinterpret_cast<const float4*>(src);
+            } else {
+                v.x = src[0];
+                if (x + 1 < gr.nx) v.y = src[1];
+                if (x + 2 < gr.nx) v.z = src[2];
+                if (x + 3 < gr.nx) v.w = src[3];
+            }
+        }
+        pr.v[k] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < G::LH; ++k) {
+        const int u = threadIdx.x + 256 * k;
+        const int r = u >> 1, x = (u & 1) ? x0 + kTileX : x0 - 1, y = y0 + r - 1;
+        float v = nan;
+        if (u < G::NH && zin && y >= 0 && y < gr.ny && x >= 0 && x < gr.nx)
+            v = plane[static_cast<long>(gr.nx) * y + x];
+        pr.h[k] = v;
     }
     if constexpr (MODE == 1) {
         const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-        const bool vec4 = (gr.nx & 3) == 0;
+        const bool dvec = (gr.nx & 3) == 0;
         const int zc = NDIM == 3 ? z - 1 : 0;
         const bool zok = NDIM == 3 ? (j >= 2 && zc < gr.nz) : true;
 #pragma unroll
@@ -263,7 +323,7 @@ __device__ __forceinline__ void dirs_load(const float* __restrict__ h, const uin
             const long i0 = static_cast<long>(zc) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
             unsigned d = 0xFFFFFFFFu;
             if (zok && y < gr.ny) {
-                if (vec4 && xa + 3 < gr.nx) {
+                if (dvec && xa + 3 < gr.nx) {
                     d = *reinterpret_cast<const unsigned*>(dirs_f + i0);
                 } else {
 #pragma unroll
@@ -271,10 +331,42 @@ __device__ __forceinline__ void dirs_load(const float* __restrict__ h, const uin
                         if (xa + k < gr.nx) d = (d & ~(0xFFu << (8 * k))) | (static_cast<unsigned>(dirs_f[i0 + k]) << (8 * k));
                 }
             }
-            dpre[q] = d;
+            pr.d[q] = d;
         }
     }
 }
+
+// Stores a loaded plane into its LDS slot.
+template <int NDIM, int TY, int ZC>
+__device__ __forceinline__ void dirs_store(float* slot, const PlaneRegs<NDIM, TY, ZC>& pr) {
+    using G = DirsGeom<NDIM, TY, ZC>;
+#pragma unroll
+    for (int k = 0; k < G::LV; ++k) {
+        const int u = threadIdx.x + 256 * k;
+        if (u < G::NV) *reinterpret_cast<float4*>(slot + (u >> 4) * G::W + 4 + 4 * (u & 15)) = pr.v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < G::LH; ++k) {
+        const int u = threadIdx.x + 256 * k;
+        if (u < G::NH) slot[(u >> 1) * G::W + ((u & 1) ? 4 + kTileX : 3)] = pr.h[k];
+    }
+}
+
+// Six consecutive LDS values of a row around a 4-vertex group: the group
+// (one 16-byte read) and its left and right neighbours.
+struct Row6 {
+    float l, a, b, c, d, r;
+    __device__ __forceinline__ explicit Row6(const float* p) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        l = p[-1];
+        a = v.x, b = v.y, c = v.z, d = v.w;
+        r = p[4];
+    }
+    // value at column offset o in -1..4 (o is a compile-time constant after unrolling)
+    __device__ __forceinline__ float at(int o) const {
+        return o < 0 ? l : o == 0 ? a : o == 1 ? b : o == 2 ? c : o == 3 ? d : r;
+    }
+};
 
 // Directions (and, in MODE 1, detection) of plane z of item it, from the LDS
 // planes C (z), A (z + 1) and B (z - 1).
@@ -295,42 +387,48 @@ __device__ __forceinline__ void dirs_compute(const float* C, const float* A, con
         const int y = y0 + ty + 16 * q, xa = x0 + tx * 4, r = ty + 16 * q + 1;
         const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
         const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
+        const int col = 4 + 4 * tx;
+        const Row6 cm(C + (r - 1) * W + col), c0(C + r * W + col), cp(C + (r + 1) * W + col);
+        Row6 bm = c0, b0 = c0, a0 = c0, ap = c0;
+        if constexpr (NDIM == 3) {
+            bm = Row6(B + (r - 1) * W + col);
+            b0 = Row6(B + r * W + col);
+            a0 = Row6(A + r * W + col);
+            ap = Row6(A + (r + 1) * W + col);
+        }
         unsigned out4 = 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int cc = tx * 4 + k + 1;
             const bool valid = xa + k < gr.nx && y < gr.ny;
-            unsigned packed = 0xFFu;
             if (valid) {
-                const float v = C[r * W + cc];
+                const float v = c0.at(k);
                 Steepest b{v, v, kSelf, kSelf};
                 // below-centre ids, nearest first, then above-centre ids, nearest first
-                b.below(C[r * W + cc - 1], 1);
-                b.below(C[(r - 1) * W + cc], 3);
-                b.below(C[(r - 1) * W + cc - 1], 5);
+                b.below(c0.at(k - 1), 1);
+                b.below(cm.at(k), 3);
+                b.below(cm.at(k - 1), 5);
                 if constexpr (NDIM == 3) {
-                    b.below(B[r * W + cc], 7);
-                    b.below(B[r * W + cc - 1], 9);
-                    b.below(B[(r - 1) * W + cc], 11);
-                    b.below(B[(r - 1) * W + cc - 1], 13);
+                    b.below(b0.at(k), 7);
+                    b.below(b0.at(k - 1), 9);
+                    b.below(bm.at(k), 11);
+                    b.below(bm.at(k - 1), 13);
                 }
-                b.above(C[r * W + cc + 1], 0);
-                b.above(C[(r + 1) * W + cc], 2);
-                b.above(C[(r + 1) * W + cc + 1], 4);
+                b.above(c0.at(k + 1), 0);
+                b.above(cp.at(k), 2);
+                b.above(cp.at(k + 1), 4);
                 if constexpr (NDIM == 3) {
-                    b.above(A[r * W + cc], 6);
-                    b.above(A[r * W + cc + 1], 8);
-                    b.above(A[(r + 1) * W + cc], 10);
-                    b.above(A[(r + 1) * W + cc + 1], 12);
+                    b.above(a0.at(k), 6);
+                    b.above(a0.at(k + 1), 8);
+                    b.above(ap.at(k), 10);
+                    b.above(ap.at(k + 1), 12);
                 }
-                packed = (b.us << 4) | b.ds;
+                const unsigned packed = (b.us << 4) | b.ds;
                 out4 = (out4 & ~(0xFFu << (8 * k))) | (packed << (8 * k));
                 if (!full) dirs_out[i0 + k] = static_cast<uint8_t>(packed);
             }
-            if constexpr (MODE == 1)
-                detect_vertex(valid, (df4[q] >> (8 * k)) & 0xFFu, packed, static_cast<int>(i0) + k, type, gr, marks, c);
         }
         if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
+        if constexpr (MODE == 1) detect4(df4[q], out4, static_cast<int>(i0), type, gr, marks, c);
     }
 }
 
@@ -343,20 +441,16 @@ __device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const G
                                             int type, uint8_t* __restrict__ marks, float* sm, unsigned (&c)[4]) {
     using G = DirsGeom<NDIM, TY, ZC>;
     const G geo(gr);
-    float pre[G::NL];
-    unsigned dpre[G::RPT];
+    const bool vec4 = (gr.nx & 3) == 0 && (reinterpret_cast<uintptr_t>(h) & 15u) == 0;
+    PlaneRegs<NDIM, TY, ZC> pr;
     int it = range.first, j = 0;
-    if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, it, 0, pre, dpre);
-    int ring = 0;  // LDS slot of the plane held in pre[]
+    if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, vec4, it, 0, pr);
+    int ring = 0;  // LDS slot of the plane held in registers
     while (it < range.hi) {
-#pragma unroll
-        for (int k = 0; k < G::NL; ++k) {
-            const int idx = threadIdx.x + 256 * k;
-            if (idx < G::P) sm[ring * G::P + idx] = pre[k];
-        }
+        dirs_store<NDIM, TY, ZC>(sm + ring * G::P, pr);
         unsigned df4[G::RPT];
 #pragma unroll
-        for (int q = 0; q < G::RPT; ++q) df4[q] = dpre[q];
+        for (int q = 0; q < G::RPT; ++q) df4[q] = pr.d[q];
         __syncthreads();
         // advance the stream and prefetch the next plane while this one is computed
         const int cur_it = it, cur_j = j, cur_ring = ring;
@@ -365,7 +459,7 @@ __device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const G
             it += range.stride;
         }
         ring = G::NP == 3 ? (ring + 1) % 3 : 0;
-        if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, it, j, pre, dpre);
+        if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, vec4, it, j, pr);
         if (NDIM == 2 || cur_j >= 2) {
             int x0, y0, z0;
             geo.origin(cur_it, x0, y0, z0);
@@ -387,7 +481,7 @@ __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid 
                                               unsigned* __restrict__ cnt) {
     using G = DirsGeom<NDIM, TY, ZC>;
     static_assert(TY % 16 == 0, "a thread row covers 16 tile rows");
-    __shared__ float sm[G::NP * G::P];
+    __shared__ __align__(16) float sm[G::NP * G::P];
     unsigned c[4] = {0u, 0u, 0u, 0u};
     dirs_stream<NDIM, TY, ZC, MODE>(h, gr, xcd_items(G(gr).items()), dirs_out, dirs_f, type, marks, sm, c);
     if constexpr (MODE == 1) {
@@ -397,24 +491,22 @@ __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid 
 }
 
 // Detection from stored directions (g unchanged since they were computed).
-// Sixteen vertices per thread: one dwordx4 of each direction array.  The
-// direction arrays live in 256-byte padded workspace segments, so the last
-// partial group can be read whole; vertices past n are masked.
-// C-loop detection of the 16-vertex group w from stored directions.  The
-// direction arrays live in 256-byte padded workspace segments, so the last
-// partial group can be read whole; vertices past n are masked.
+// C-loop detection of the 16-vertex group w from stored directions (one
+// dwordx4 of each direction array).  The direction arrays live in 256-byte
+// padded workspace segments, so the last partial group can be read whole;
+// vertices past n are masked to "no case".
 __device__ __forceinline__ void detect_group(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                              const Grid& gr, int type, uint8_t* __restrict__ marks, int w,
                                              unsigned (&c)[4]) {
     const uint4 a = reinterpret_cast<const uint4*>(dirs_f)[w], b = reinterpret_cast<const uint4*>(dirs_g)[w];
     const unsigned fa[4] = {a.x, a.y, a.z, a.w}, ga[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = 16 * w + 4 * q + j;
-            detect_vertex(i < gr.n, (fa[q] >> (8 * j)) & 0xFFu, (ga[q] >> (8 * j)) & 0xFFu, i, type, gr, marks, c);
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int i0 = 16 * w + 4 * q;
+        const int left = gr.n - i0;  // vertices of this word inside the field
+        const unsigned pad = left >= 4 ? 0u : (left <= 0 ? 0xFFFFFFFFu : 0xFFFFFFFFu << (8 * left));
+        detect4(fa[q] | pad, ga[q] | pad, i0, type, gr, marks, c);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__ dirs_f,
@@ -1384,6 +1476,7 @@ __global__ void __launch_bounds__(256) k_engine(const EngField* __restrict__ fie
                                                 EngStats* stats, unsigned* tickets, unsigned* bar, int nf,
                                                 int max_steps) {
     __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the engine's LDS");
     __shared__ int pre[kEngMaxFields + 1];
     unsigned gen = 0;
     for (int step = 0; step < max_steps; ++step) {

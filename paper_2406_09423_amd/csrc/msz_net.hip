@@ -3,12 +3,11 @@
 // and judges).  BF16 weights and activations, FP32 accumulation, on MFMA.
 //
 // Parameters (FP32 master copy, one flat array, MSZ_NET_PARAMS floats):
-//   W0[27][8][16]  b0[16]      features (6 used, 8 stored) -> 16
+//   W0[27][16][16] b0[16]      features (12 used, 16 stored) -> 16
 //   W1[27][16][16] b1[16]      16 -> 16
 //   W2[27][16]     b2[1]       16 -> 1
 // tap = (dz+1)*9 + (dy+1)*3 + (dx+1); zero padding outside the grid.
-// Activations: BF16, channel-last [vertex][C] (C = 8 for the features, 16
-// for hidden layers), vertex id x + nx*(y + ny*z).
+// Activations: BF16, channel-last [vertex][16], vertex id x + nx*(y + ny*z).
 //
 // Convolution as GEMM on v_mfma_f32_16x16x32_bf16: M = 16 output channels,
 // N = 16 x-consecutive vertices, K = 32 (tap, input channel) pairs per
@@ -28,7 +27,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kNetC = 16;
-constexpr int kOffW0 = 0, kOffB0 = kOffW0 + 27 * 8 * 16, kOffW1 = kOffB0 + 16, kOffB1 = kOffW1 + 27 * 16 * 16,
+constexpr int kOffW0 = 0, kOffB0 = kOffW0 + 27 * 16 * 16, kOffW1 = kOffB0 + 16, kOffB1 = kOffW1 + 27 * 16 * 16,
               kOffW2 = kOffB1 + 16, kOffB2 = kOffW2 + 27 * 16, kNetParams = kOffB2 + 1;
 static_assert(kNetParams == MSZ_NET_PARAMS, "parameter layout");
 
@@ -274,34 +273,72 @@ __global__ void __launch_bounds__(256) k_reduce_dw(const float* __restrict__ par
     }
 }
 
-// Input channels of the net (see oracle/net_ref.py: features).
-__global__ void __launch_bounds__(256) k_features(const float* __restrict__ fhat, const uint8_t* __restrict__ dirs_f,
+// Input channels of the net (16 stored per vertex, 12 used; the box is the
+// 3x3x3 block around the vertex clipped to the grid, the clamps are [-8, 8]):
+//   0 (fhat - box mean of fhat) / xi     1 log10(xi / value range) / 4 + 1
+//   2..5 FPmax, FPmin, FNmax, FNmin of fhat against f
+//   6 (fhat - f) / xi                    7 (f - box mean of f) / xi
+//   8 dn_f(u) = i for an FPmin neighbour u       9 up_fhat(u) = i for an FNmax neighbour u
+//   10 dn_f(u) = i for a neighbour u with dn_fhat(u) != dn_f(u)
+//   11 up_fhat(u) = i for a neighbour u with up_fhat(u) != up_f(u)
+// Channels 8..11 gather over the neighbour slots: neighbour j = i + off[s]
+// points back at i through the opposite slot s ^ 1.
+__global__ void __launch_bounds__(256) k_features(const float* __restrict__ f, const float* __restrict__ fhat,
+                                                  const uint8_t* __restrict__ dirs_f,
                                                   const uint8_t* __restrict__ dirs_h, Grid gr, float xi, float xi_ch,
                                                   uint16_t* __restrict__ feat) {
+    constexpr int DX[14] = {1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1};
+    constexpr int DY[14] = {0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+    constexpr int DZ[14] = {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+    const int nslots = gr.ndim == 3 ? 14 : 6;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < gr.n; i += gridDim.x * blockDim.x) {
         const int x = i % gr.nx, y = (i / gr.nx) % gr.ny, z = i / gr.nxy;
-        double s = 0.0;
+        double sh = 0.0, sf = 0.0;
         int c = 0;
         for (int dz = -1; dz <= 1; ++dz)
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int xx = x + dx, yy = y + dy, zz = z + dz;
                     if (xx < 0 || xx >= gr.nx || yy < 0 || yy >= gr.ny || zz < 0 || zz >= gr.nz) continue;
-                    s += fhat[xx + gr.nx * yy + gr.nxy * zz];
+                    const int j = xx + gr.nx * yy + gr.nxy * zz;
+                    sh += fhat[j];
+                    sf += f[j];
                     ++c;
                 }
-        const float local = static_cast<float>((static_cast<double>(fhat[i]) - s / c) / xi);
-        const float ch0 = fminf(fmaxf(local, -8.0f), 8.0f);
+        const double hi = fhat[i], fi = f[i];
+        const float ch0 = fminf(fmaxf(static_cast<float>((hi - sh / c) / xi), -8.0f), 8.0f);
+        const float ch6 = fminf(fmaxf(static_cast<float>((hi - fi) / xi), -8.0f), 8.0f);
+        const float ch7 = fminf(fmaxf(static_cast<float>((fi - sf / c) / xi), -8.0f), 8.0f);
         const unsigned df = dirs_f[i], dh = dirs_h[i];
         const unsigned uf = df >> 4, nf = df & 15u, uh = dh >> 4, nh = dh & 15u;
         const float fl[4] = {static_cast<float>((uh == kSelf) & (uf != kSelf)), static_cast<float>((nh == kSelf) & (nf != kSelf)),
                              static_cast<float>((uf == kSelf) & (uh != kSelf)), static_cast<float>((nf == kSelf) & (nh != kSelf))};
-        uint4 o;
-        o.x = static_cast<unsigned>(bf16_bits(ch0)) | (static_cast<unsigned>(bf16_bits(xi_ch)) << 16);
-        o.y = static_cast<unsigned>(bf16_bits(fl[0])) | (static_cast<unsigned>(bf16_bits(fl[1])) << 16);
-        o.z = static_cast<unsigned>(bf16_bits(fl[2])) | (static_cast<unsigned>(bf16_bits(fl[3])) << 16);
-        o.w = 0u;
-        reinterpret_cast<uint4*>(feat)[i] = o;
+        unsigned tg = 0;  // bits 0..3: channels 8..11
+        for (int sl = 0; sl < nslots; ++sl) {
+            const int xx = x + DX[sl], yy = y + DY[sl], zz = z + DZ[sl];
+            if (xx < 0 || xx >= gr.nx || yy < 0 || yy >= gr.ny || zz < 0 || zz >= gr.nz) continue;
+            const int j = i + gr.off[sl];
+            const unsigned back = static_cast<unsigned>(sl ^ 1);
+            const unsigned fj = dirs_f[j], hj = dirs_h[j];
+            const unsigned ufj = fj >> 4, nfj = fj & 15u, uhj = hj >> 4, nhj = hj & 15u;
+            if (nhj == kSelf && nfj == back) tg |= 1u;  // FPmin at j targets dn_f(j)
+            if (ufj == kSelf && uhj == back) tg |= 2u;  // FNmax at j targets up_fhat(j)
+            if (nhj != nfj && nfj == back) tg |= 4u;
+            if (uhj != ufj && uhj == back) tg |= 8u;
+        }
+        const unsigned one = bf16_bits(1.0f);
+        uint4 o0, o1;
+        o0.x = static_cast<unsigned>(bf16_bits(ch0)) | (static_cast<unsigned>(bf16_bits(xi_ch)) << 16);
+        o0.y = static_cast<unsigned>(bf16_bits(fl[0])) | (static_cast<unsigned>(bf16_bits(fl[1])) << 16);
+        o0.z = static_cast<unsigned>(bf16_bits(fl[2])) | (static_cast<unsigned>(bf16_bits(fl[3])) << 16);
+        o0.w = static_cast<unsigned>(bf16_bits(ch6)) | (static_cast<unsigned>(bf16_bits(ch7)) << 16);
+        o1.x = ((tg & 1u) ? one : 0u) | (((tg & 2u) ? one : 0u) << 16);
+        o1.y = ((tg & 4u) ? one : 0u) | (((tg & 8u) ? one : 0u) << 16);
+        o1.z = 0u;
+        o1.w = 0u;
+        uint4* dst = reinterpret_cast<uint4*>(feat) + 2 * static_cast<long>(i);
+        dst[0] = o0;
+        dst[1] = o1;
     }
 }
 
@@ -344,15 +381,47 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, const float
     }
 }
 
-// Warm start: g0 = clamp(fl(fhat - fl(p * xi)), L, fhat) where p > p_min, else fhat.
+// One decreasing edit (Eqs. 2-6 with the float floor L): halfway to the
+// floor, snapped to it when float32 rounding would leave g unchanged.
+__device__ __forceinline__ float halve_to(float g, float L) {
+    const float h = __fmul_rn(__fadd_rn(g, L), 0.5f);
+    return h == g ? L : h;
+}
+
+// Warm start: fhat halved k times, k = floor(fl(p - p_min)) + 1 clamped to
+// [0, kMaxWarmHalvings] (0 where p is not a number).
+constexpr int kMaxWarmHalvings = 64;
 __global__ void __launch_bounds__(256) k_warm_start(const float* __restrict__ p, const float* __restrict__ L,
-                                                    const float* __restrict__ fhat, float xi, float p_min, int n,
+                                                    const float* __restrict__ fhat, float p_min, int n,
                                                     float* __restrict__ g0) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const float h = fhat[i];
-        const float pi = p[i];
-        const float v = __fsub_rn(h, __fmul_rn(pi, xi));
-        g0[i] = pi > p_min ? fminf(fmaxf(v, L[i]), h) : h;
+        const float q = floorf(__fsub_rn(p[i], p_min)) + 1.0f;
+        const int k = q > 0.0f ? (q < static_cast<float>(kMaxWarmHalvings) ? static_cast<int>(q) : kMaxWarmHalvings) : 0;
+        float g = fhat[i];
+        if (k > 0) {
+            const float l = L[i];
+            for (int j = 0; j < k; ++j) g = halve_to(g, l);
+        }
+        g0[i] = g;
+    }
+}
+
+// Training target: the number of halvings that take fhat_i to g_i (-1 when
+// g_i is not on that chain within kMaxCount steps).
+constexpr int kMaxCount = 256;
+__global__ void __launch_bounds__(256) k_halvings(const float* __restrict__ L, const float* __restrict__ fhat,
+                                                  const float* __restrict__ g, int n, float* __restrict__ k_out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float gi = g[i], l = L[i];
+        float cur = fhat[i];
+        int k = 0;
+        while (cur > gi && k < kMaxCount) {
+            const float nx = halve_to(cur, l);
+            if (!(nx < cur)) break;  // at the floor (or an invalid floor): no further progress
+            cur = nx;
+            ++k;
+        }
+        k_out[i] = cur == gi ? static_cast<float>(k) : -1.0f;
     }
 }
 
@@ -418,7 +487,7 @@ NetLayout net_layout(const Grid& gr) {
     };
     l.dirs_f = take(n + 16);
     l.dirs_h = take(n + 16);
-    l.feat = take(n * 16);
+    l.feat = take(n * 32);
     l.a1 = take(n * 32);
     l.a2 = take(n * 32);
     l.p = take(n * 4);
@@ -458,7 +527,7 @@ struct Scratch2 {
 
 WeightView layer_view(const float* P, int layer) {
     switch (layer) {
-        case 0: return {P + kOffW0, P + kOffB0, 128, 16, 1, 8, 16, 0};
+        case 0: return {P + kOffW0, P + kOffB0, 256, 16, 1, 16, 16, 0};
         case 1: return {P + kOffW1, P + kOffB1, 256, 16, 1, 16, 16, 0};
         default: return {P + kOffW2, P + kOffB2, 16, 1, 0, 16, 1, 0};
     }
@@ -472,7 +541,7 @@ WeightView layer_back_view(const float* P, int layer) {
 
 void net_forward(const float* P, const uint16_t* feat, const Grid& gr, uint16_t* a1, uint16_t* a2, float* p,
                  hipStream_t s) {
-    launch_conv_t<8, kConvHidden>(feat, gr, layer_view(P, 0), nullptr, a1, nullptr, s);
+    launch_conv_t<16, kConvHidden>(feat, gr, layer_view(P, 0), nullptr, a1, nullptr, s);
     launch_conv_t<16, kConvHidden>(a1, gr, layer_view(P, 1), nullptr, a2, nullptr, s);
     launch_conv_t<16, kConvFinal>(a2, gr, layer_view(P, 2), nullptr, nullptr, p, s);
 }
@@ -524,7 +593,7 @@ int features_impl(const float* f, const float* fhat, const Grid& gr, float xi, u
     const float xi_ch = static_cast<float>(std::log10(static_cast<double>(xi) / range) / 4.0 + 1.0);
     launch_dirs(f, gr, 0, df, s);
     launch_dirs(fhat, gr, 0, dh, s);
-    hipLaunchKernelGGL(k_features, dim3(blocks_n(gr.n)), dim3(256), 0, s, fhat, df, dh, gr, xi, xi_ch, feat);
+    hipLaunchKernelGGL(k_features, dim3(blocks_n(gr.n)), dim3(256), 0, s, f, fhat, df, dh, gr, xi, xi_ch, feat);
     return hipGetLastError() == hipSuccess ? MSZ_OK : MSZ_EDEVICE;
 }
 
@@ -556,6 +625,21 @@ int msz_net_features(const float* f, const float* fhat, msz_dims d, float xi, ui
     if (int rc = ws.get(workspace, workspace_bytes, l.total, s)) return rc;
     const int rc = features_impl(f, fhat, gr, xi, feat, static_cast<char*>(ws.p), l, s);
     if (rc) return rc;
+    return hipStreamSynchronize(s) == hipSuccess ? MSZ_OK : MSZ_EDEVICE;
+}
+
+int msz_net_halvings(const float* f, const float* fhat, const float* g, msz_dims d, float xi, float* k_out,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    Grid gr;
+    if (!make_grid(d, gr) || !f || !fhat || !g || !k_out) return MSZ_EINVAL;
+    if (!(xi > 0.0f) || !(xi <= kValueLimit)) return MSZ_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Scratch2 ws;
+    if (int rc = ws.get(workspace, workspace_bytes, a256(static_cast<size_t>(gr.n) * sizeof(float)), s)) return rc;
+    float* L = static_cast<float*>(ws.p);
+    hipLaunchKernelGGL(k_floor, dim3(blocks_n(gr.n)), dim3(256), 0, s, f, xi, gr.n, L);
+    hipLaunchKernelGGL(k_halvings, dim3(blocks_n(gr.n)), dim3(256), 0, s, L, fhat, g, gr.n, k_out);
+    if (hipGetLastError() != hipSuccess) return MSZ_EDEVICE;
     return hipStreamSynchronize(s) == hipSuccess ? MSZ_OK : MSZ_EDEVICE;
 }
 
@@ -609,8 +693,8 @@ int msz_net_gradients(const float* params, const uint16_t* feat, const float* ta
                        grad_out + kOffB1);
     launch_conv_t<16, kConvBackData>(dzb, gr, layer_back_view(params, 1), a1, dza, nullptr, s);
     // layer 0
-    launch_dw_t<8>(feat, dza, gr, part, part_b, s);
-    hipLaunchKernelGGL(k_reduce_dw, dim3(rb), dim3(256), 0, s, part, part_b, nt, 8, 16, 16, grad_out + kOffW0,
+    launch_dw_t<16>(feat, dza, gr, part, part_b, s);
+    hipLaunchKernelGGL(k_reduce_dw, dim3(rb), dim3(256), 0, s, part, part_b, nt, 16, 16, 16, grad_out + kOffW0,
                        grad_out + kOffB0);
     if (hipGetLastError() != hipSuccess) return MSZ_EDEVICE;
     std::vector<float> host(nb);
@@ -666,7 +750,7 @@ int msz_fix_learned(const float* f, const float* fhat, msz_dims d, float xi, con
     if (rc == MSZ_OK) {
         net_forward(params, feat, gr, reinterpret_cast<uint16_t*>(w + l.a1), reinterpret_cast<uint16_t*>(w + l.a2), p, s);
         hipLaunchKernelGGL(k_floor, dim3(blocks_n(gr.n)), dim3(256), 0, s, f, xi, gr.n, L);
-        hipLaunchKernelGGL(k_warm_start, dim3(blocks_n(gr.n)), dim3(256), 0, s, p, L, fhat, xi, p_min, gr.n, g0);
+        hipLaunchKernelGGL(k_warm_start, dim3(blocks_n(gr.n)), dim3(256), 0, s, p, L, fhat, p_min, gr.n, g0);
         if (hipGetLastError() != hipSuccess) rc = MSZ_EDEVICE;
     }
     if (timing) (void)hipEventRecord(e1, s);

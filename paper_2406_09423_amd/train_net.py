@@ -1,9 +1,9 @@
 """Trains the warm-start network on the GPU with the library's own kernels.
 
 Training pairs come from the plain correction loop: for each seeded 128^3
-field, the target of vertex i is its final edit in units of xi,
-t_i = (fhat_i - g_i) / xi >= 0, and the inputs are the library's features of
-(f, fhat, xi).  Loss: mean squared error in which vertices with a non-zero
+field, the target of vertex i is the number of halvings the loop applied to
+it (msz_net_halvings: its edit, exactly), and the inputs are the library's
+features of (f, fhat, xi).  Loss: mean squared error in which vertices with a non-zero
 target weigh 1 + edit_weight (edited vertices are a few percent of a field,
 so an unweighted loss settles on a small positive edit everywhere);
 optimiser: Adam on FP32 master weights; forward and backward run in BF16 on
@@ -39,7 +39,7 @@ def init_params(seed: int = 0) -> np.ndarray:
     """He-uniform weights, small positive biases, in the library's flat layout."""
     rng = np.random.default_rng(seed)
     parts = []
-    for cin, cstore, cout, last in ((6, 8, 16, False), (16, 16, 16, False), (16, 16, 1, True)):
+    for cin, cstore, cout, last in ((12, 16, 16, False), (16, 16, 16, False), (16, 16, 1, True)):
         bound = np.sqrt(6.0 / (cin * 27))
         W = np.zeros((27, cstore, 16 if not last else 1))
         W[:, :cin, :cout] = rng.uniform(-bound, bound, size=(27, cin, cout))
@@ -47,6 +47,17 @@ def init_params(seed: int = 0) -> np.ndarray:
     flat = np.concatenate(parts).astype(np.float32)
     assert flat.size == msz.NET_PARAMS
     return flat
+
+
+INFO_PATH = os.path.splitext(WEIGHTS_PATH)[0] + ".json"
+
+
+def stored_p_min(path: str = INFO_PATH) -> float:
+    """The count threshold chosen when the stored weights were trained (0.5 if unrecorded)."""
+    if not os.path.exists(path):
+        return 0.5
+    with open(path) as fh:
+        return float(json.load(fh).get("p_min", 0.5))
 
 
 def load_weights(path: str = WEIGHTS_PATH):
@@ -63,7 +74,9 @@ def make_pair(f, fh, xi, ws):
     rc, d, g, st = msz.fix(fd, fhd, xi, workspace=ws)
     if rc != msz.OK:
         raise RuntimeError(f"plain loop failed: {msz.strerror(rc)}")
-    t = ((fhd.double() - g.double()) / float(xi)).float().reshape(-1)
+    t = msz.net_halvings(fd, fhd, g, xi).reshape(-1)
+    if bool((t < 0).any()):
+        raise RuntimeError("an edit of the plain loop is off its halving chain")
     feat = msz.net_features(fd, fhd, xi)
     return feat, t, st
 
@@ -154,6 +167,13 @@ def main():
     np.save(args.out, params.cpu().numpy())
     held = [synth.heldout_field(k, n=args.side) for k in range(args.eval)]
     info["heldout"] = evaluate(params, held, p_mins=args.p_min)
+    # the threshold with the lowest mean time over the held-out fields
+    mean_ms = {pm: float(np.mean([r[f"learned@{pm:g}"]["ms"] for r in info["heldout"]])) for pm in args.p_min}
+    info["p_min"] = min(mean_ms, key=mean_ms.get)
+    info["plain_ms_mean"] = float(np.mean([r["plain"]["ms"] for r in info["heldout"]]))
+    info["learned_ms_mean"] = mean_ms
+    with open(os.path.splitext(args.out)[0] + ".json", "w") as fh:
+        json.dump(info, fh, indent=1)
     print(json.dumps(info), flush=True)
 
 

@@ -32,7 +32,7 @@ def msz():
 def flat_params(params) -> np.ndarray:
     """Oracle (W[co][ci][3][3][3], b) per layer -> the library's flat FP32 layout."""
     out = []
-    cin_store = (8, 16, 16)
+    cin_store = (16, 16, 16)
     for li, (W, b) in enumerate(params):
         co, ci = W.shape[:2]
         Wt = W.reshape(co, ci, 27).transpose(2, 1, 0)           # [tap][ci][co]
@@ -43,7 +43,7 @@ def flat_params(params) -> np.ndarray:
         else:
             out += [Wt[:, :, 0].ravel(), b.astype(np.float64)]
     flat = np.concatenate(out).astype(np.float32)
-    assert flat.size == 10833
+    assert flat.size == 14289
     return flat
 
 
@@ -51,7 +51,7 @@ def unflat_grads(g: np.ndarray):
     """Library gradient layout -> oracle shapes (dW[co][ci][3][3][3], db)."""
     o = 0
     res = []
-    for li, (cin, cstore, cout) in enumerate(((6, 8, 16), (16, 16, 16), (16, 16, 1))):
+    for li, (cin, cstore, cout) in enumerate(((12, 16, 16), (16, 16, 16), (16, 16, 1))):
         if li < 2:
             W = g[o:o + 27 * cstore * 16].reshape(27, cstore, 16)[:, :cin, :cout]
             o += 27 * cstore * 16
@@ -79,14 +79,14 @@ def feature_case(shape, seed, xi=0.01):
     fh = (f + rng.uniform(-xi, xi, size=shape)).astype(np.float32)
     fh = np.where(np.abs(f.astype(np.float64) - fh) > xi, f, fh).astype(np.float32)
     bits = oracle.case_flags(f, fh) if len(shape) == 3 else oracle.case_flags(f[0], fh[0])[None]
-    x = nr.features(fh, xi, bits & 15, float(f.max()) - float(f.min()))
+    x = nr.features(f, fh, xi, bits & 15, float(f.max()) - float(f.min()), oracle.dirs(f), oracle.dirs(fh))
     return f, fh, np.float32(xi), x
 
 
 def to_dev_feat(x: np.ndarray):
     n = x[0].size
-    feat = np.zeros((n, 8), np.float64)
-    feat[:, :6] = x.reshape(6, -1).T
+    feat = np.zeros((n, 16))
+    feat[:, :12] = x.reshape(12, -1).T
     return torch.from_numpy(bf16_bits(feat)).cuda()
 
 
@@ -104,11 +104,13 @@ def test_features_match_oracle(msz, shape):
     f, fh, xi, x = feature_case(shape, 1)
     got = msz.net_features(torch.from_numpy(f).cuda(), torch.from_numpy(fh).cuda(), xi).cpu().numpy()
     g = bits_to_float(got)
-    ref = nr.bf16(x).reshape(6, -1).T
-    assert np.array_equal(g[:, 1:6], ref[:, 1:6])                 # xi channel and flags exactly
-    assert np.all(g[:, 6:] == 0)
-    # channel 0: same double-precision formula summed in another order; one BF16 ulp at most
-    assert np.all(np.abs(g[:, 0] - ref[:, 0]) <= 2.0 ** -7 * np.abs(ref[:, 0]) + 1e-30)
+    ref = nr.bf16(x).reshape(12, -1).T
+    assert np.array_equal(g[:, 1:7], ref[:, 1:7])                 # xi channel, flags, fhat - f exactly
+    assert np.array_equal(g[:, 8:12], ref[:, 8:12])               # edit-target flags exactly
+    assert np.all(g[:, 12:] == 0)
+    # box-mean channels: the same double-precision formula summed in another order; one BF16 ulp at most
+    for c in (0, 7):
+        assert np.all(np.abs(g[:, c] - ref[:, c]) <= 2.0 ** -7 * np.abs(ref[:, c]) + 1e-30), c
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -165,12 +167,12 @@ def test_gradients_match_oracle(msz):
 
 def test_adam_matches_oracle(msz):
     rng = np.random.default_rng(7)
-    w0 = rng.normal(size=10833)
-    g = [rng.normal(size=10833) for _ in range(3)]
+    w0 = rng.normal(size=14289)
+    g = [rng.normal(size=14289) for _ in range(3)]
     w = torch.from_numpy(w0.astype(np.float32)).cuda()
     m = torch.zeros_like(w)
     v = torch.zeros_like(w)
-    wr, mr, vr = w0.astype(np.float32).astype(np.float64), np.zeros(10833), np.zeros(10833)
+    wr, mr, vr = w0.astype(np.float32).astype(np.float64), np.zeros(14289), np.zeros(14289)
     for k, gk in enumerate(g, start=1):
         gt = torch.from_numpy(gk.astype(np.float32)).cuda()
         msz.net_adam(w, gt, m, v, k, 1e-3)
@@ -192,3 +194,46 @@ def test_fix_learned_converges(msz):
     gh = g.cpu().numpy()
     assert (np.abs(f.astype(np.float64) - gh) <= float(xi)).all()
     assert st["timing"]["net"]["launches"] == 1
+
+
+def test_halvings_match_oracle(msz):
+    rng = np.random.default_rng(11)
+    shape = (7, 13, 40)
+    f = rng.uniform(0, 1, size=shape).astype(np.float32)
+    xi = np.float32(0.02)
+    fh = (f + rng.uniform(-xi, xi, size=shape)).astype(np.float32)
+    fh = np.where(np.abs(f.astype(np.float64) - fh) > xi, f, fh).astype(np.float32)
+    L = oracle.lower_bound(f, xi)
+    k = rng.integers(0, 5, size=shape)
+    k[0, 0, :8] = 40                                   # runs into the floor
+    g = fh.copy()
+    for j in range(int(k.max())):
+        act = k > j
+        g[act] = nr.halve32(g[act], L[act])
+    g[1, 1, 1] = np.nextafter(fh[1, 1, 1], np.float32(2))  # above fhat: off the chain
+    want = nr.halving_count(fh, g, L)
+    got = msz.net_halvings(torch.from_numpy(f).cuda(), torch.from_numpy(fh).cuda(), torch.from_numpy(g).cuda(), xi)
+    assert np.array_equal(got.cpu().numpy().astype(np.int64), want)
+    assert want[1, 1, 1] == -1
+
+
+@pytest.mark.parametrize("p_min", [0.5, 0.25, 1.5])
+def test_fix_learned_bit_exact_with_oracle(msz, p_min):
+    """The warm start from the GPU's own prediction p, recomputed by the oracle,
+    then the oracle's loop from it: edits, g and round counts bit-identical."""
+    import synth
+    f, fh, xi = synth.turb3d(n=32, nblobs=4)[0]
+    params = random_params(12)
+    flat = torch.from_numpy(flat_params(params)).cuda()
+    fd, fhd = torch.from_numpy(f).cuda(), torch.from_numpy(fh).cuda()
+    feat = msz.net_features(fd, fhd, xi)
+    p = msz.net_forward(flat, feat, f.shape).cpu().numpy().reshape(f.shape)
+    L = oracle.lower_bound(f, xi)
+    g0 = nr.warm_start(p, fh, L, p_min)
+    assert (g0 != fh).any()
+    rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi, warm_start=g0)
+    rc, d, g, st = msz.fix_learned(fd, fhd, xi, flat, p_min=p_min)
+    assert rc == rc_o == msz.OK
+    assert np.array_equal(d.cpu().numpy().view(np.uint32), d_o.view(np.uint32))
+    assert np.array_equal(g.cpu().numpy().view(np.uint32), g_o.view(np.uint32))
+    assert list(st["rounds"]) == list(st_o["rounds"]) and st["rounds_r"] == st_o["rounds_r"]
