@@ -105,14 +105,9 @@ def bench_plain(msz, torch, dev, args):
         step()
     torch.cuda.synchronize()
     log(f"bench: timing {args.steps} steps")
-    phase_ms, phase_n = {}, {}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        sts = step(timing=True)
-        for st in sts:
-            for name, v in st["timing"].items():
-                phase_ms[name] = phase_ms.get(name, 0.0) + v["ms"]
-                phase_n[name] = phase_n.get(name, 0) + v["launches"]
+        sts = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -120,6 +115,18 @@ def bench_plain(msz, torch, dev, args):
     log(f"bench: plain {ms_per_step:.3f} ms/step, {verts / ms_per_step / 1e6:.3f} Gvertices/s")
     for (f, fh, xi), (e, g) in zip(fields, outs):
         checked(msz, f, g, xi)
+    # the same steps again with a hipEvent pair around every device step (on
+    # the library's stream): per-kernel durations for the roofline
+    log(f"bench: {args.steps} instrumented steps")
+    phase_ms, phase_n = {}, {}
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        for st in step(timing=True):
+            for name, v in st["timing"].items():
+                phase_ms[name] = phase_ms.get(name, 0.0) + v["ms"]
+                phase_n[name] = phase_n.get(name, 0) + v["launches"]
+    torch.cuda.synchronize()
+    ms_instrumented = (time.perf_counter() - t2) * 1e3 / args.steps
 
     dominant = max((k for k in phase_ms if phase_n.get(k)), key=lambda k: phase_ms[k])
     avg_ms = phase_ms[dominant] / phase_n[dominant]
@@ -137,6 +144,8 @@ def bench_plain(msz, torch, dev, args):
         "avg_launch_us": round(avg_ms * 1e3, 2),
         "bytes_per_launch": bpl,
         "launches_per_step": phase_n[dominant] / args.steps,
+        "timing": "hipEvents around every step of the instrumented pass "
+                  f"({ms_instrumented:.3f} ms/step with the events)",
     }
     phases = {}
     for k in phase_ms:

@@ -52,7 +52,9 @@ enum {
     MSZ_ENOMEM = -7      /* the library could not allocate scratch memory */
 };
 
-/* Kernels timed under MSZ_FLAG_TIMING (indices of msz_stats.phase_ms). */
+/* Steps timed under MSZ_FLAG_TIMING (indices of msz_stats.phase_ms).  The
+ * loop runs as a sequence of device-scheduled steps; each step runs one
+ * operation, timed by hipEvents recorded around it. */
 enum {
     MSZ_PHASE_VALIDATE = 0,     /* input contract, floors L, start field */
     MSZ_PHASE_DIRS = 1,         /* steepest directions of f */
@@ -69,7 +71,7 @@ enum {
 };
 
 /* msz_options.flags bits. */
-#define MSZ_FLAG_TIMING 1 /* record hipEvents around every launch (adds a little overhead) */
+#define MSZ_FLAG_TIMING 1 /* record hipEvents around every step (adds a little overhead) */
 
 typedef struct {
     int32_t ndim;        /* 2 or 3 */

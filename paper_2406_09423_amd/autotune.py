@@ -26,7 +26,7 @@ TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tile_tabl
 # Upper bounds (exclusive) of the vertex-count classes; the last class is open.
 EDGES = {2: (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22), 3: (1 << 15, 1 << 18, 1 << 21, 1 << 24)}
 # Phases whose kernels run the direction stencil (the only ones a variant changes).
-STENCIL_PHASES = ("dirs", "dirs_detect")
+STENCIL_PHASES = ("dirs_detect",)
 
 
 def n_classes(ndim: int) -> int:

@@ -1,13 +1,16 @@
 // msz_api.hip -- host driver and C ABI of libmsz (declared in include/msz.h).
 //
-// The correction loop is driven from the host, one synchronisation per round:
-// the detection of a round leaves its counters in a 256-byte block that is
-// read back together with the number of values the previous apply changed,
-// and the host decides the next step of the schedule (Sec. 5):
+// The schedule of the correction loop (Sec. 5) runs on the device (the
+// engine in msz_kernels.hip): every step runs one operation per field and a
+// decide kernel picks each field's next operation from its counters --
 //   C phase  sub-loops FPmax, FPmin, FNmax, FNmin, each until it finds no case
 //            of its type; repeated until no false critical point remains;
 //   R phase  labels of g, troublemaker detection, one apply; back to the C
 //            phase whenever the apply created a false critical point.
+// The host captures kGraphSteps steps in a HIP graph and relaunches it until
+// no field is active, reading one word back per launch.  msz_fix is the
+// one-field case of msz_fix_batch.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -77,94 +80,6 @@ Layout layout_for(int64_t n) {
     return l;
 }
 
-// Optional hipEvent timing of every launch, summed per kernel kind.
-struct Timing {
-    bool on = false;
-    std::vector<hipEvent_t> pool;
-    size_t used = 0;
-    std::vector<int> phase_of;  // one entry per recorded (start, stop) pair
-    double ms[MSZ_N_PHASES] = {};
-    int64_t n[MSZ_N_PHASES] = {};
-    hipEvent_t take() {
-        if (used == pool.size()) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
-            pool.push_back(e);
-        }
-        return pool[used++];
-    }
-    void begin(int ph, hipStream_t s) {
-        if (!on) return;
-        hipEvent_t a = take();
-        hipEvent_t b = take();  // reserved for end()
-        if (!a || !b) {
-            on = false;
-            return;
-        }
-        (void)b;
-        phase_of.push_back(ph);
-        (void)hipEventRecord(a, s);
-    }
-    void end(hipStream_t s) {
-        if (!on) return;
-        (void)hipEventRecord(pool[2 * phase_of.size() - 1], s);
-    }
-    void collect() {  // call after the stream has been synchronised
-        if (!on) return;
-        for (size_t k = 0; k < phase_of.size(); ++k) {
-            float t = 0.f;
-            if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
-                ms[phase_of[k]] += t;
-                n[phase_of[k]]++;
-            }
-        }
-        phase_of.clear();
-        used = 0;
-    }
-    void store(msz_stats* st) const {
-        for (int k = 0; k < MSZ_N_PHASES; ++k) {
-            st->phase_ms[k] = static_cast<float>(ms[k]);
-            st->phase_launches[k] = static_cast<int32_t>(n[k]);
-        }
-    }
-    ~Timing() {
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-#define TIMED(F, ph, s, call)      \
-    do {                           \
-        (F).tm->begin((ph), (s));  \
-        call;                      \
-        (F).tm->end(s);            \
-    } while (0)
-
-struct Field {
-    Timing* tm;
-    Grid gr;
-    int variant;
-    const float *f, *fhat, *warm;
-    float xi;
-    float *edits, *g_out;
-    float *L, *g;
-    uint8_t *dirs_f, *dirs_g, *marks;
-    int *Mf, *mf, *qu, *qd;
-    unsigned* cnt;
-};
-
-void bind(Field& F, char* ws, const Layout& l) {
-    F.cnt = reinterpret_cast<unsigned*>(ws + l.cnt);
-    F.L = reinterpret_cast<float*>(ws + l.L);
-    F.g = reinterpret_cast<float*>(ws + l.g);
-    F.dirs_f = reinterpret_cast<uint8_t*>(ws + l.dirs_f);
-    F.dirs_g = reinterpret_cast<uint8_t*>(ws + l.dirs_g);
-    F.marks = reinterpret_cast<uint8_t*>(ws + l.marks);
-    F.Mf = reinterpret_cast<int*>(ws + l.Mf);
-    F.mf = reinterpret_cast<int*>(ws + l.mf);
-    F.qu = reinterpret_cast<int*>(ws + l.qu);
-    F.qd = reinterpret_cast<int*>(ws + l.qd);
-}
-
 // Pinned host copy of the counter block (all slots, then the summed counters
 // in the last kCntSlots words), one per host thread.
 unsigned* host_counters() {
@@ -180,7 +95,7 @@ unsigned* host_counters() {
 }
 
 // Copies the counter slots back, waits, and sums them into host[0..kCntSlots).
-int read_counters(const unsigned* dev, unsigned* host, hipStream_t s, Timing* tm = nullptr) {
+int read_counters(const unsigned* dev, unsigned* host, hipStream_t s) {
     unsigned* raw = host - kCntBlockWords;
     MSZ_HIP(hipGetLastError());
     MSZ_HIP(hipMemcpyAsync(raw, dev, kCntBlockWords * sizeof(unsigned), hipMemcpyDeviceToHost, s));
@@ -190,7 +105,6 @@ int read_counters(const unsigned* dev, unsigned* host, hipStream_t s, Timing* tm
         const unsigned* slot = raw + b * kSlotStride;
         for (int k = 0; k < kCntSlots; ++k) host[k] = k == kCntErr ? (host[k] | slot[k]) : host[k] + slot[k];
     }
-    if (tm) tm->collect();
     return MSZ_OK;
 }
 
@@ -223,133 +137,291 @@ struct Scratch {
     }
 };
 
-// Validation, floors, start field, directions and labels of f.
-int precompute(Field& F, unsigned* hc, hipStream_t s) {
-    const int n = F.gr.n;
-    if (clear_counters(F.cnt, s)) return MSZ_EDEVICE;
-    MSZ_HIP(hipMemsetAsync(F.marks, 0, (n + 15) & ~15, s));
-    TIMED(F, MSZ_PHASE_VALIDATE, s, launch_validate_init(F.f, F.fhat, F.warm, F.xi, n, F.L, F.g, F.cnt, s));
-    TIMED(F, MSZ_PHASE_DIRS, s, launch_dirs(F.f, F.gr, F.variant, F.dirs_f, s));
-    TIMED(F, MSZ_PHASE_LABEL_TILE, s, launch_label_tile(F.dirs_f, F.gr, F.qu, F.qd, s));
-    TIMED(F, MSZ_PHASE_LABEL_JUMP, s, launch_label_compress(F.gr, F.qu, F.qd, F.cnt, s));
-    TIMED(F, MSZ_PHASE_LABEL_FINAL, s, launch_label_final(F.qu, F.qd, F.gr, F.Mf, F.mf, s));
-    int rc = read_counters(F.cnt, hc, s, F.tm);
-    if (rc) return rc;
-    const unsigned e = hc[kCntErr];
-    if (e & kErrWalk) return MSZ_EDEVICE;
-    if (e & kErrNonFinite) return MSZ_ENONFINITE;
-    if (e & kErrBound) return MSZ_EBOUND;
-    if (e & kErrWarmNonFinite) return MSZ_ENONFINITE;
-    if (e & kErrWarmBound) return MSZ_EBOUND;
-    return MSZ_OK;
-}
-
-// The schedule.  Returns the status; stats are filled as it goes.
-int run_loop(Field& F, int64_t cap, msz_stats* st, unsigned* hc, hipStream_t s) {
-    const Grid& gr = F.gr;
-    unsigned c[kCntSlots];
-    auto step_read = [&]() -> int {
-        int rc = read_counters(F.cnt, hc, s, F.tm);
-        if (rc) return rc;
-        std::memcpy(c, hc, sizeof(c));
-        return MSZ_OK;
-    };
-    auto begin = [&]() { return clear_counters(F.cnt, s); };
-
-    int type = 0;
-    if (begin()) return MSZ_EDEVICE;
-    TIMED(F, MSZ_PHASE_DIRS_DETECT, s,
-          launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.cnt, s));
-    if (int rc = step_read()) return rc;
-    for (int t = 0; t < 4; ++t) st->false_init[t] = c[kCntCase + t];
-
-    int64_t rounds = 0;
-    bool in_c = true;
-    st->outer_iters = 1;
-    for (;;) {
-        if (in_c) {
-            if (c[kCntCase + type] > 0) {
-                if (rounds >= cap) return MSZ_ENOCONV;
-                if (begin()) return MSZ_EDEVICE;
-                TIMED(F, MSZ_PHASE_APPLY, s,
-                      launch_apply(F.g, F.L, F.marks, gr.n, F.cnt, s));
-                TIMED(F, MSZ_PHASE_DIRS_DETECT, s,
-                      launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.cnt, s));
-                if (int rc = step_read()) return rc;
-                if (c[kCntChanged] == 0) return MSZ_ESTALL;
-                ++rounds;
-                st->rounds[type]++;
-                continue;
-            }
-            if (type < 3) {
-                ++type;
-            } else if (c[kCntCase + 0] + c[kCntCase + 1] + c[kCntCase + 2] > 0) {
-                type = 0;  // the C phase repeats until no type has a case
-            } else {
-                in_c = false;
-            }
-            if (in_c) {
-                if (begin()) return MSZ_EDEVICE;
-                TIMED(F, MSZ_PHASE_DETECT, s,
-                      launch_detect_only(F.dirs_f, F.dirs_g, gr, type, F.marks, F.cnt, s));
-                if (int rc = step_read()) return rc;
-                continue;
-            }
-        }
-        // R phase: labels of g from its current directions, then troublemakers
-        if (begin()) return MSZ_EDEVICE;
-        TIMED(F, MSZ_PHASE_LABEL_TILE, s, launch_label_tile(F.dirs_g, gr, F.qu, F.qd, s));
-        TIMED(F, MSZ_PHASE_LABEL_JUMP, s, launch_label_compress(gr, F.qu, F.qd, F.cnt, s));
-        TIMED(F, MSZ_PHASE_DETECT_R, s,
-              launch_detect_r(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, F.marks, F.cnt, s));
-        if (int rc = step_read()) return rc;
-        if (c[kCntErr] & kErrWalk) return MSZ_EDEVICE;
-        if (c[kCntWrong] == 0) return MSZ_OK;
-        if (rounds >= cap) return MSZ_ENOCONV;
-        if (begin()) return MSZ_EDEVICE;
-        TIMED(F, MSZ_PHASE_APPLY, s,
-              launch_apply(F.g, F.L, F.marks, gr.n, F.cnt, s));
-        type = 0;
-        TIMED(F, MSZ_PHASE_DIRS_DETECT, s,
-              launch_dirs_detect(F.g, gr, F.variant, F.dirs_g, F.dirs_f, type, F.marks, F.cnt, s));
-        if (int rc = step_read()) return rc;
-        if (c[kCntChanged] == 0) return MSZ_ESTALL;
-        ++rounds;
-        st->rounds_r++;
-        if (c[kCntCase + 0] + c[kCntCase + 1] + c[kCntCase + 2] + c[kCntCase + 3] > 0) {
-            in_c = true;  // Sec. 5.3: the R edit created false critical points
-            st->outer_iters++;
-        }
-    }
-}
-
-int finish(Field& F, msz_stats* st, unsigned* hc, hipStream_t s) {
-    if (clear_counters(F.cnt, s)) return MSZ_EDEVICE;
-    TIMED(F, MSZ_PHASE_DELTA, s, launch_delta(F.g, F.fhat, F.gr.n, F.edits, F.g_out, F.cnt, s));
-    if (int rc = read_counters(F.cnt, hc, s, F.tm)) return rc;
-    st->n_edited = hc[kCntEdited];
-    st->n_inexact = hc[kCntInexact];
-    return MSZ_OK;
-}
-
 int check_xi(float xi) {
     if (!(std::fabs(xi) <= kValueLimit)) return MSZ_ENONFINITE;
     if (xi < 0.0f) return MSZ_EINVAL;
     return MSZ_OK;
 }
 
-int fix_one(Field& F, int64_t cap, msz_stats* st, unsigned* hc, hipStream_t s) {
-    int rc = precompute(F, hc, s);
-    if (rc == MSZ_OK) {
-        const int status = run_loop(F, cap, st, hc, s);
-        rc = status;
-        if (status != MSZ_EDEVICE) {
-            const int frc = finish(F, st, hc, s);
-            if (frc) rc = frc;
-        }
+// ------------------------------------------------------------- engine ---
+
+constexpr int kGraphSteps = 16;  // steps per graph launch (even: parities line up)
+
+// Per host thread and device: the engine's control block (device), a pinned
+// read-back word, and the graph of kGraphSteps steps for the last topology.
+struct EngineCtx {
+    int device = -1;
+    char* ctl_mem = nullptr;  // fields, states, stats, pre2, pre3, ctl, oplog
+    EngField* fields = nullptr;
+    EngState* states = nullptr;
+    EngStats* stats = nullptr;
+    int *pre2 = nullptr, *pre3 = nullptr, *ctl = nullptr, *oplog = nullptr;
+    int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog
+    // cached graph
+    int g_nf = -1, g_grid2 = 0, g_grid3 = 0;
+    bool g_has2 = false, g_has3 = false, g_timing = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> events;
+
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        events.clear();
+        g_nf = -1;
     }
-    F.tm->store(st);
-    return rc;
+    // No destructor work: at process exit the HIP runtime may already be torn
+    // down, and the device memory (about 0.4 MB per host thread) is reclaimed
+    // with the process.
+
+    int init(int dev) {
+        if (device == dev && ctl_mem) return MSZ_OK;
+        drop_graph();
+        if (ctl_mem) (void)hipFree(ctl_mem);
+        ctl_mem = nullptr;
+        size_t o = 0;
+        auto take = [&](size_t b) {
+            const size_t r = o;
+            o += align256(b);
+            return r;
+        };
+        const size_t of = take(sizeof(EngField) * kEngMaxFields);
+        const size_t os = take(sizeof(EngState) * 2 * kEngMaxFields);
+        const size_t ost = take(sizeof(EngStats) * kEngMaxFields);
+        const size_t op2 = take(sizeof(int) * (kEngMaxFields + 1));
+        const size_t op3 = take(sizeof(int) * (kEngMaxFields + 1));
+        const size_t oc = take(sizeof(int) * 4);
+        const size_t ol = take(sizeof(int) * kGraphSteps);
+        void* p = nullptr;
+        if (hipMalloc(&p, o) != hipSuccess) return MSZ_ENOMEM;
+        ctl_mem = static_cast<char*>(p);
+        fields = reinterpret_cast<EngField*>(ctl_mem + of);
+        states = reinterpret_cast<EngState*>(ctl_mem + os);
+        stats = reinterpret_cast<EngStats*>(ctl_mem + ost);
+        pre2 = reinterpret_cast<int*>(ctl_mem + op2);
+        pre3 = reinterpret_cast<int*>(ctl_mem + op3);
+        ctl = reinterpret_cast<int*>(ctl_mem + oc);
+        oplog = reinterpret_cast<int*>(ctl_mem + ol);
+        if (!host) {
+            void* h = nullptr;
+            if (hipHostMalloc(&h, sizeof(int) * (1 + kGraphSteps), hipHostMallocDefault) != hipSuccess)
+                return MSZ_ENOMEM;
+            host = static_cast<int*>(h);
+        }
+        device = dev;
+        return MSZ_OK;
+    }
+
+    // (Re)builds the graph when the topology changed.
+    int graph_for(int nf, bool has2, bool has3, bool timing, int grid2, int grid3) {
+        if (exec && g_nf == nf && g_has2 == has2 && g_has3 == has3 && g_timing == timing && g_grid2 == grid2 &&
+            g_grid3 == grid3)
+            return MSZ_OK;
+        drop_graph();
+        if (hipGraphCreate(&graph, 0) != hipSuccess) return MSZ_EDEVICE;
+        hipGraphNode_t last = nullptr;
+        auto chain = [&](hipGraphNode_t n) { last = n; };
+        auto add_kernel = [&](const void* fn, dim3 g, dim3 b, void** args) -> bool {
+            hipKernelNodeParams p{};
+            p.func = const_cast<void*>(fn);
+            p.gridDim = g;
+            p.blockDim = b;
+            p.sharedMemBytes = 0;
+            p.kernelParams = args;
+            hipGraphNode_t n = nullptr;
+            if (hipGraphAddKernelNode(&n, graph, last ? &last : nullptr, last ? 1 : 0, &p) != hipSuccess) return false;
+            chain(n);
+            return true;
+        };
+        auto add_event = [&]() -> bool {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return false;
+            events.push_back(e);
+            hipGraphNode_t n = nullptr;
+            if (hipGraphAddEventRecordNode(&n, graph, last ? &last : nullptr, last ? 1 : 0, e) != hipSuccess) return false;
+            chain(n);
+            return true;
+        };
+        for (int st = 0; st < kGraphSteps; ++st) {
+            const int par = st & 1;
+            EngState* cur = states + par * nf;
+            EngState* nxt = states + (par ^ 1) * nf;
+            if (timing && !add_event()) return MSZ_EDEVICE;
+            if (has2) {
+                void* a[] = {&fields, &cur, &pre2, &nf};
+                if (!add_kernel(eng_step_kernel(2), dim3(grid2), dim3(256), a)) return MSZ_EDEVICE;
+            }
+            if (has3) {
+                void* a[] = {&fields, &cur, &pre3, &nf};
+                if (!add_kernel(eng_step_kernel(3), dim3(grid3), dim3(256), a)) return MSZ_EDEVICE;
+            }
+            if (timing && !add_event()) return MSZ_EDEVICE;
+            int* log = timing ? oplog : nullptr;
+            int stp = st;
+            void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp};
+            if (!add_kernel(eng_decide_kernel(), dim3(nf), dim3(256), d)) return MSZ_EDEVICE;
+            if (nf > 1) {
+                void* c[] = {&fields, &nxt, &nf, &pre2, &pre3, &ctl};
+                if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
+            }
+        }
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
+        g_nf = nf;
+        g_has2 = has2;
+        g_has3 = has3;
+        g_timing = timing;
+        g_grid2 = grid2;
+        g_grid3 = grid3;
+        return MSZ_OK;
+    }
+};
+
+EngineCtx& engine_ctx() {
+    thread_local EngineCtx ctx;
+    return ctx;
+}
+
+int phase_of_op(int op) {
+    switch (op) {
+        case kOpPreA: return MSZ_PHASE_VALIDATE;
+        case kOpPreA2: return MSZ_PHASE_DIRS;
+        case kOpPreB: case kOpRTile: return MSZ_PHASE_LABEL_TILE;
+        case kOpPreC: case kOpRJump: return MSZ_PHASE_LABEL_JUMP;
+        case kOpPreD: return MSZ_PHASE_LABEL_FINAL;
+        case kOpApplyC: case kOpApplyR: return MSZ_PHASE_APPLY;
+        case kOpPreE: case kOpDdC: case kOpDdR: return MSZ_PHASE_DIRS_DETECT;
+        case kOpDetect: return MSZ_PHASE_DETECT;
+        case kOpRDetect: return MSZ_PHASE_DETECT_R;
+        case kOpDelta: return MSZ_PHASE_DELTA;
+        default: return -1;
+    }
+}
+
+// Step-kernel grid of one dimension: the blocks that fit on the device at once.
+int step_grid(int dev, int ndim) {
+    thread_local int cached_dev = -1, cached[2] = {0, 0};
+    if (cached_dev != dev) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
+        for (int k = 0; k < 2; ++k) {
+            int b = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, eng_step_kernel(2 + k), 256, 0) != hipSuccess) return 0;
+            cached[k] = cus * std::max(1, b);
+        }
+        cached_dev = dev;
+    }
+    return cached[ndim == 3 ? 1 : 0];
+}
+
+// One engine run over hf.size() fields whose workspaces are already bound.
+// Fills st[] (one per field); with timing (one field only) adds the per-step
+// durations to ms[] / launches[] by phase.
+int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing, double* ms, int64_t* launches,
+               int64_t max_steps, hipStream_t s) {
+    const int nf = static_cast<int>(hf.size());
+    int dev = 0;
+    MSZ_HIP(hipGetDevice(&dev));
+    EngineCtx& E = engine_ctx();
+    if (int rc = E.init(dev)) return rc;
+    const int grid2 = step_grid(dev, 2), grid3 = step_grid(dev, 3);
+    if (grid2 < 1 || grid3 < 1) return MSZ_EDEVICE;
+    bool has2 = false, has3 = false;
+    std::vector<EngState> hs(2 * nf);
+    std::vector<int> p2(nf + 1, 0), p3(nf + 1, 0);
+    for (int j = 0; j < nf; ++j) {
+        const int items = eng_items_host(hf[j], kOpPreA);
+        hs[j] = EngState{kOpPreA, 0, items, 0};
+        hs[nf + j] = EngState{kOpDone, 0, 0, 0};
+        const bool three = hf[j].gr.ndim == 3;
+        has2 = has2 || !three;
+        has3 = has3 || three;
+        p2[j + 1] = p2[j] + (three ? 0 : items);
+        p3[j + 1] = p3[j] + (three ? items : 0);
+    }
+    timing = timing && nf == 1;
+    if (int rc = E.graph_for(nf, has2, has3, timing, grid2, grid3)) {
+        E.drop_graph();
+        return rc;
+    }
+    const int one = 1;
+    MSZ_HIP(hipMemcpyAsync(E.fields, hf.data(), sizeof(EngField) * nf, hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemcpyAsync(E.states, hs.data(), sizeof(EngState) * 2 * nf, hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemcpyAsync(E.ctl, &one, sizeof(int), hipMemcpyHostToDevice, s));
+    MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * nf, s));
+    int total = 0;
+    for (const EngField& F : hf) total = std::max(total, (F.gr.n + 15) >> 4);
+    {
+        EngField* fp = E.fields;
+        int nfv = nf;
+        void* a[] = {&fp, &nfv};
+        MSZ_HIP(hipLaunchKernel(eng_init_kernel(), dim3(std::max(1, std::min(2048, (total + 255) / 256))), dim3(256),
+                                a, 0, s));
+    }
+    int64_t steps = 0;
+    int rc = MSZ_OK;
+    for (;;) {
+        if (hipGraphLaunch(E.exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (hipMemcpyAsync(E.host, E.ctl, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (timing && hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) !=
+                          hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (timing) {
+            for (int k = 0; k < kGraphSteps; ++k) {
+                const int ph = phase_of_op(E.host[1 + k]);
+                float t = 0.f;
+                if (ph >= 0 && hipEventElapsedTime(&t, E.events[2 * k], E.events[2 * k + 1]) == hipSuccess) {
+                    ms[ph] += t;
+                    launches[ph] += 1;
+                }
+            }
+        }
+        steps += kGraphSteps;
+        if (E.host[0] == 0) break;
+        if (steps > max_steps) { rc = MSZ_EDEVICE; break; }
+    }
+    if (rc != MSZ_OK) {
+        E.drop_graph();
+        return rc;
+    }
+    st.resize(nf);
+    MSZ_HIP(hipMemcpyAsync(st.data(), E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
+    MSZ_HIP(hipStreamSynchronize(s));
+    return MSZ_OK;
+}
+
+void bind_field(EngField& F, char* w, int n) {
+    const Layout l = layout_for(n);
+    F.cnt = reinterpret_cast<unsigned*>(w + l.cnt);
+    F.L = reinterpret_cast<float*>(w + l.L);
+    F.g = reinterpret_cast<float*>(w + l.g);
+    F.dirs_f = reinterpret_cast<uint8_t*>(w + l.dirs_f);
+    F.dirs_g = reinterpret_cast<uint8_t*>(w + l.dirs_g);
+    F.marks = reinterpret_cast<uint8_t*>(w + l.marks);
+    F.Mf = reinterpret_cast<int*>(w + l.Mf);
+    F.mf = reinterpret_cast<int*>(w + l.mf);
+    F.qu = reinterpret_cast<int*>(w + l.qu);
+    F.qd = reinterpret_cast<int*>(w + l.qd);
+}
+
+void copy_stats(const EngStats& e, msz_stats* out) {
+    for (int t = 0; t < 4; ++t) out->rounds[t] = e.rounds[t], out->false_init[t] = e.false_init[t];
+    out->rounds_r = e.rounds_r;
+    out->outer_iters = e.outer_iters;
+    out->n_edited = e.n_edited;
+    out->n_inexact = e.n_inexact;
+    out->status = e.status;
+}
+
+// Upper bound on steps: every round takes at most 8 steps; the bound only
+// stops a runaway schedule.
+int64_t step_bound(int64_t cap) {
+    const int64_t b = 16 * std::min<int64_t>(cap, int64_t(1) << 24) + 4096;
+    return std::min<int64_t>(b, int64_t(1) << 26);
 }
 
 }  // namespace
@@ -403,117 +475,53 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
         o.tile_override > tile_variant_count(d.ndim))
         return done(MSZ_EINVAL);
     if (int rc = check_xi(xi)) return done(rc);
-    unsigned* hc = host_counters();
-    if (!hc) return done(MSZ_EDEVICE);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Layout l = layout_for(gr.n);
     Scratch ws;
     if (int rc = ws.get(o.workspace, o.workspace_bytes, l.total, s)) return done(rc);
-    Timing tm;
-    tm.on = (o.flags & MSZ_FLAG_TIMING) != 0;
-    Field F{};
-    F.tm = &tm;
+    std::vector<EngField> hf(1);
+    EngField& F = hf[0];
+    F = EngField{};
     F.gr = gr;
     F.variant = o.tile_override;
+    F.xi = xi;
+    F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
     F.f = f;
     F.fhat = fhat;
     F.warm = o.warm_start;
-    F.xi = xi;
     F.edits = edits_out;
     F.g_out = o.g_out;
-    bind(F, static_cast<char*>(ws.p), l);
-    const int64_t cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
-    return done(fix_one(F, cap, stats, hc, s));
-}
-
-namespace {
-
-// Batch workspace: the engine's tables, then one field workspace per job.
-struct BatchLayout {
-    size_t fields, states, stats, tickets, bar, field0, total;
-    std::vector<size_t> field_off;
-};
-
-bool batch_layout(const msz_job* jobs, int32_t n, BatchLayout& bl) {
-    size_t o = 0;
-    auto take = [&](size_t b) {
-        const size_t r = o;
-        o += align256(b);
-        return r;
-    };
-    bl.fields = take(sizeof(EngField) * n);
-    bl.states = take(sizeof(EngState) * 2 * n);
-    bl.stats = take(sizeof(EngStats) * n);
-    bl.tickets = take(sizeof(unsigned) * 2 * n);
-    bl.bar = take(sizeof(unsigned) * 4);
-    bl.field0 = o;
-    bl.field_off.resize(n);
-    for (int j = 0; j < n; ++j) {
-        Grid gr;
-        if (!make_grid(jobs[j].d, gr)) return false;
-        bl.field_off[j] = take(layout_for(gr.n).total + align256(2 * kEngSet * sizeof(unsigned)));
+    bind_field(F, static_cast<char*>(ws.p), gr.n);
+    const bool timing = (o.flags & MSZ_FLAG_TIMING) != 0;
+    double ms[MSZ_N_PHASES] = {};
+    int64_t launches[MSZ_N_PHASES] = {};
+    std::vector<EngStats> st;
+    if (int rc = run_engine(hf, st, timing, ms, launches, step_bound(F.cap), s)) return done(rc);
+    copy_stats(st[0], stats);
+    for (int k = 0; k < MSZ_N_PHASES; ++k) {
+        stats->phase_ms[k] = static_cast<float>(ms[k]);
+        stats->phase_launches[k] = static_cast<int32_t>(launches[k]);
     }
-    bl.total = o;
-    return true;
+    return stats->status;
 }
-
-int run_engine(const EngField* dev_fields, EngState* states, EngStats* stats, unsigned* tickets, unsigned* bar,
-               int nf, int max_steps, hipStream_t s) {
-    int dev = 0, cus = 0, bpc = 0, coop = 0;
-    MSZ_HIP(hipGetDevice(&dev));
-    MSZ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    MSZ_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
-    MSZ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, engine_kernel(), 256, 0));
-    if (!coop || bpc < 1 || cus < 1) return MSZ_EDEVICE;
-    const int grid = cus * (bpc < 2 ? bpc : 2);  // every block resident: the barrier needs it
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int rc = MSZ_OK;
-    if (hipGraphCreate(&graph, 0) != hipSuccess) return MSZ_EDEVICE;
-    do {
-        // node 1: clear marks, counters, tickets and the barrier (a kernel, not a memset node)
-        hipGraphNode_t init = nullptr, eng = nullptr;
-        void* a1[] = {const_cast<EngField**>(&dev_fields), &nf, &tickets, &bar};
-        hipKernelNodeParams p1{};
-        p1.func = const_cast<void*>(engine_init_kernel());
-        p1.gridDim = dim3(1024);
-        p1.blockDim = dim3(256);
-        p1.kernelParams = a1;
-        if (hipGraphAddKernelNode(&init, graph, nullptr, 0, &p1) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        // node 2: the persistent engine, one cooperative launch
-        void* a2[] = {const_cast<EngField**>(&dev_fields), &states, &stats, &tickets, &bar, &nf, &max_steps};
-        hipKernelNodeParams p2{};
-        p2.func = const_cast<void*>(engine_kernel());
-        p2.gridDim = dim3(grid);
-        p2.blockDim = dim3(256);
-        p2.kernelParams = a2;
-        if (hipGraphAddKernelNode(&eng, graph, &init, 1, &p2) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        hipKernelNodeAttrValue v{};
-        v.cooperative = 1;
-        if (hipGraphKernelNodeSetAttribute(eng, hipKernelNodeAttributeCooperative, &v) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (hipGraphLaunch(exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-    } while (false);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    return rc;
-}
-
-}  // namespace
 
 size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs) {
     if (!jobs || n_jobs <= 0 || n_jobs > kEngMaxFields) return 0;
-    BatchLayout bl;
-    if (!batch_layout(jobs, n_jobs, bl)) return 0;
-    return bl.total;
+    size_t total = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        Grid gr;
+        if (!make_grid(jobs[j].d, gr)) return 0;
+        total += layout_for(gr.n).total;
+    }
+    return total;
 }
 
 int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, void* stream) {
     if (!jobs || n_jobs <= 0 || n_jobs > kEngMaxFields) return MSZ_EINVAL;
     msz_options o{};
     if (opt) o = *opt;
-    if (o.warm_start || o.g_out || (o.flags & ~MSZ_FLAG_TIMING) || o.tile_override) return MSZ_EINVAL;
+    if (o.warm_start || o.g_out || (o.flags & ~MSZ_FLAG_TIMING) || o.tile_override || !aligned16(o.workspace))
+        return MSZ_EINVAL;
     for (int j = 0; j < n_jobs; ++j) {
         Grid gr;
         const msz_job& J = jobs[j];
@@ -522,84 +530,43 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
             J.tile > tile_variant_count(J.d.ndim))
             return MSZ_EINVAL;
         std::memset(J.stats, 0, sizeof(msz_stats));
-        if (int rc = check_xi(J.xi)) {
-            J.stats->status = rc;
+    }
+    for (int j = 0; j < n_jobs; ++j)
+        if (int rc = check_xi(jobs[j].xi)) {
+            jobs[j].stats->status = rc;
             return rc;
         }
-    }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    BatchLayout bl;
-    if (!batch_layout(jobs, n_jobs, bl)) return MSZ_EINVAL;
+    const size_t need = msz_batch_workspace_bytes(jobs, n_jobs);
+    if (need == 0) return MSZ_EINVAL;
     Scratch ws;
-    if (int rc = ws.get(o.workspace, o.workspace_bytes, bl.total, s)) return rc;
-    char* base = static_cast<char*>(ws.p);
-    const long long cap = o.max_rounds > 0 ? o.max_rounds : (1ll << 30);
+    if (int rc = ws.get(o.workspace, o.workspace_bytes, need, s)) return rc;
+    char* w = static_cast<char*>(ws.p);
+    const int64_t cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
     std::vector<EngField> hf(n_jobs);
-    std::vector<EngState> hs(2 * n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
         const msz_job& J = jobs[j];
         EngField& F = hf[j];
+        F = EngField{};
         make_grid(J.d, F.gr);
         F.variant = J.tile;
         F.xi = J.xi;
         F.cap = cap;
         F.f = J.f;
         F.fhat = J.fhat;
+        F.warm = nullptr;
         F.edits = J.edits_out;
         F.g_out = J.g_out;
-        char* w = base + bl.field_off[j];
-        const Layout l = layout_for(F.gr.n);
-        F.L = reinterpret_cast<float*>(w + l.L);
-        F.g = reinterpret_cast<float*>(w + l.g);
-        F.dirs_f = reinterpret_cast<uint8_t*>(w + l.dirs_f);
-        F.dirs_g = reinterpret_cast<uint8_t*>(w + l.dirs_g);
-        F.marks = reinterpret_cast<uint8_t*>(w + l.marks);
-        F.Mf = reinterpret_cast<int*>(w + l.Mf);
-        F.mf = reinterpret_cast<int*>(w + l.mf);
-        F.qu = reinterpret_cast<int*>(w + l.qu);
-        F.qd = reinterpret_cast<int*>(w + l.qd);
-        F.cnt = reinterpret_cast<unsigned*>(w + l.total);
-        hs[j] = EngState{kOpPreA, 0, eng_items_host(F, kOpPreA), 0};
-        hs[n_jobs + j] = EngState{kOpDone, 0, 0, 0};
+        bind_field(F, w, F.gr.n);
+        w += layout_for(F.gr.n).total;
     }
-    EngField* dev_fields = reinterpret_cast<EngField*>(base + bl.fields);
-    EngState* states = reinterpret_cast<EngState*>(base + bl.states);
-    EngStats* stats = reinterpret_cast<EngStats*>(base + bl.stats);
-    unsigned* tickets = reinterpret_cast<unsigned*>(base + bl.tickets);
-    unsigned* bar = reinterpret_cast<unsigned*>(base + bl.bar);
-    MSZ_HIP(hipMemcpyAsync(dev_fields, hf.data(), sizeof(EngField) * n_jobs, hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemcpyAsync(states, hs.data(), sizeof(EngState) * 2 * n_jobs, hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemsetAsync(stats, 0, sizeof(EngStats) * n_jobs, s));
-    // every round takes at most 8 steps; the bound only stops a runaway batch
-    const long long steps = 16 * cap + 4096;
-    const int max_steps = static_cast<int>(steps < (1 << 20) ? steps : (1 << 20));
-    int rc = run_engine(dev_fields, states, stats, tickets, bar, n_jobs, max_steps, s);
-    std::vector<EngStats> st(n_jobs);
-    std::vector<EngState> fin(2 * n_jobs);
-    unsigned hbar[4] = {0, 0, 0, 0};
-    if (rc == MSZ_OK) {
-        MSZ_HIP(hipMemcpyAsync(st.data(), stats, sizeof(EngStats) * n_jobs, hipMemcpyDeviceToHost, s));
-        MSZ_HIP(hipMemcpyAsync(fin.data(), states, sizeof(EngState) * 2 * n_jobs, hipMemcpyDeviceToHost, s));
-        MSZ_HIP(hipMemcpyAsync(hbar, bar, sizeof(hbar), hipMemcpyDeviceToHost, s));
-        MSZ_HIP(hipStreamSynchronize(s));
-    }
+    std::vector<EngStats> st;
+    int rc = run_engine(hf, st, false, nullptr, nullptr, step_bound(cap), s);
     int first = rc;
     for (int j = 0; j < n_jobs; ++j) {
         msz_stats* out = jobs[j].stats;
-        if (rc == MSZ_OK) {
-            const EngStats& e = st[j];
-            for (int t = 0; t < 4; ++t) out->rounds[t] = e.rounds[t], out->false_init[t] = e.false_init[t];
-            out->rounds_r = e.rounds_r;
-            out->outer_iters = e.outer_iters;
-            out->n_edited = e.n_edited;
-            out->n_inexact = e.n_inexact;
-            out->status = e.status;
-            // a field the engine did not finish (aborted barrier or step bound) is an error
-            const bool done = fin[0 * n_jobs + j].op == kOpDone || fin[1 * n_jobs + j].op == kOpDone;
-            if (hbar[2] || !done) out->status = MSZ_EDEVICE;
-        } else {
-            out->status = rc;
-        }
+        if (rc == MSZ_OK) copy_stats(st[j], out);
+        else out->status = rc;
         if (first == MSZ_OK && out->status != MSZ_OK) first = out->status;
     }
     return first;

@@ -138,19 +138,19 @@ void launch_delta(const float* g, const float* fhat, int n, float* delta, float*
 namespace msz {
 
 // ------------------------------------------------------------ batch engine ---
-// One cooperative persistent kernel advances every field of a batch by one
-// operation per grid-wide step (see k_engine).
-constexpr int kEngSlots = 16;                       // counter slots per set
-constexpr int kEngStride = 16;                      // words per slot
-constexpr int kEngSet = kEngSlots * kEngStride;     // words per counter set (two sets per field)
+// The correction schedule on the device: per step, k_eng_step<2>/<3> run the
+// current operation of every field, k_eng_decide picks each field's next one,
+// k_eng_scan sums the next step's items (see the engine in msz_kernels.hip).
 constexpr int kEngMaxFields = 1024;
 constexpr int kEngChunk = 4096;                     // vertices per flat work item
 
 enum EngOp : int {
-    kOpPreA = 0,   // validate + directions of f
+    kOpPreA = 0,   // validation, floors, start field
+    kOpPreA2,      // directions of f
     kOpPreB,       // label tiles of f
     kOpPreC,       // compression of f's tile faces
-    kOpPreD,       // labels of f + directions/detection of g (type 0)
+    kOpPreD,       // labels of f
+    kOpPreE,       // first directions/detection of g (type 0)
     kOpApplyC,     // C-loop apply
     kOpDdC,        // directions/detection of g after a C apply
     kOpDetect,     // detection from stored directions
@@ -168,12 +168,12 @@ struct EngField {
     int variant;
     float xi;
     long long cap;
-    const float *f, *fhat;
+    const float *f, *fhat, *warm;
     float *edits, *g_out;
     float *L, *g;
     uint8_t *dirs_f, *dirs_g, *marks;
     int *Mf, *mf, *qu, *qd;
-    unsigned* cnt;  // 2 * kEngSet words
+    unsigned* cnt;  // kCntBlockWords words (kSlots slots)
 };
 
 struct EngState {
@@ -187,7 +187,9 @@ struct EngStats {
 
 // Number of work items of operation op for one field (device and host).
 int eng_items_host(const EngField& F, int op);
-const void* engine_kernel();       // k_engine(fields, states, stats, tickets, bar, nf, max_steps)
-const void* engine_init_kernel();  // k_engine_init(fields, nf, tickets, bar)
+const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf)
+const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step)
+const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl)
+const void* eng_init_kernel();          // k_eng_init(fields, nf)
 
 }  // namespace msz

@@ -900,57 +900,63 @@ __global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int*
 }
 
 // Troublemaker detection, tile by tile (see k_label_final for the order).
-template <int NDIM>
+// The tile's G groups are loaded GB at a time (all at once in the standalone
+// kernel; fewer where registers are scarce).
+template <int NDIM, int GB = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024>
 __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
                                               const int* __restrict__ Mf, const int* __restrict__ mf, const Grid& gr,
                                               int tile, uint8_t* __restrict__ marks, unsigned& wrong, unsigned& cases) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
-    int qu[G][4], qd[G][4], Mv[G][4], mv[G][4];
-    unsigned df4[G], dg4[G];
-    TileGroup<NDIM> tg[G];
+    static_assert(G % GB == 0, "whole batches of groups");
+#pragma unroll 1
+    for (int k0 = 0; k0 < G; k0 += GB) {
+        int qu[GB][4], qd[GB][4], Mv[GB][4], mv[GB][4];
+        unsigned df4[GB], dg4[GB];
+        TileGroup<NDIM> tg[GB];
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
-        tg[k] = tile_group<NDIM>(gr, tile, k);
-        const int i0 = tg[k].i0;
-        df4[k] = dg4[k] = 0xFFFFFFFFu;
+        for (int k = 0; k < GB; ++k) {
+            tg[k] = tile_group<NDIM>(gr, tile, k0 + k);
+            const int i0 = tg[k].i0;
+            df4[k] = dg4[k] = 0xFFFFFFFFu;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) qu[k][j] = qd[k][j] = Mv[k][j] = mv[k][j] = 0;
-        if (tg[k].vec) {
-            df4[k] = *reinterpret_cast<const unsigned*>(dirs_f + i0);
-            dg4[k] = *reinterpret_cast<const unsigned*>(dirs_g + i0);
-            const int4 u = *reinterpret_cast<const int4*>(q_up + i0);
-            const int4 d = *reinterpret_cast<const int4*>(q_dn + i0);
-            const int4 U = *reinterpret_cast<const int4*>(Mf + i0);
-            const int4 D = *reinterpret_cast<const int4*>(mf + i0);
-            qu[k][0] = u.x, qu[k][1] = u.y, qu[k][2] = u.z, qu[k][3] = u.w;
-            qd[k][0] = d.x, qd[k][1] = d.y, qd[k][2] = d.z, qd[k][3] = d.w;
-            Mv[k][0] = U.x, Mv[k][1] = U.y, Mv[k][2] = U.z, Mv[k][3] = U.w;
-            mv[k][0] = D.x, mv[k][1] = D.y, mv[k][2] = D.z, mv[k][3] = D.w;
-        } else {
-            for (int j = 0; j < tg[k].count; ++j) {
-                const int i = i0 + j;
-                df4[k] = (df4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_f[i]) << (8 * j));
-                dg4[k] = (dg4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_g[i]) << (8 * j));
-                qu[k][j] = q_up[i], qd[k][j] = q_dn[i], Mv[k][j] = Mf[i], mv[k][j] = mf[i];
+            for (int j = 0; j < 4; ++j) qu[k][j] = qd[k][j] = Mv[k][j] = mv[k][j] = 0;
+            if (tg[k].vec) {
+                df4[k] = *reinterpret_cast<const unsigned*>(dirs_f + i0);
+                dg4[k] = *reinterpret_cast<const unsigned*>(dirs_g + i0);
+                const int4 u = *reinterpret_cast<const int4*>(q_up + i0);
+                const int4 d = *reinterpret_cast<const int4*>(q_dn + i0);
+                const int4 U = *reinterpret_cast<const int4*>(Mf + i0);
+                const int4 D = *reinterpret_cast<const int4*>(mf + i0);
+                qu[k][0] = u.x, qu[k][1] = u.y, qu[k][2] = u.z, qu[k][3] = u.w;
+                qd[k][0] = d.x, qd[k][1] = d.y, qd[k][2] = d.z, qd[k][3] = d.w;
+                Mv[k][0] = U.x, Mv[k][1] = U.y, Mv[k][2] = U.z, Mv[k][3] = U.w;
+                mv[k][0] = D.x, mv[k][1] = D.y, mv[k][2] = D.z, mv[k][3] = D.w;
+            } else {
+                for (int j = 0; j < tg[k].count; ++j) {
+                    const int i = i0 + j;
+                    df4[k] = (df4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_f[i]) << (8 * j));
+                    dg4[k] = (dg4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_g[i]) << (8 * j));
+                    qu[k][j] = q_up[i], qd[k][j] = q_dn[i], Mv[k][j] = Mf[i], mv[k][j] = mf[i];
+                }
             }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
+        for (int k = 0; k < GB; ++k) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j >= tg[k].count) continue;
-            const int i = tg[k].i0 + j;
-            const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
-            const bool wM = q_up[qu[k][j]] != Mv[k][j];
-            const bool wm = q_dn[qd[k][j]] != mv[k][j];
-            wrong += wM || wm;
-            const bool rmin = wm && ((dg & 15u) != (df & 15u));
-            const bool rmax = wM && ((dg >> 4) != (df >> 4));
-            cases += rmin + rmax;
-            if (rmin) mark(marks, i + gr.off[df & 15u]);
-            if (rmax) mark(marks, i + gr.off[dg >> 4]);
+            for (int j = 0; j < 4; ++j) {
+                if (j >= tg[k].count) continue;
+                const int i = tg[k].i0 + j;
+                const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
+                const bool wM = q_up[qu[k][j]] != Mv[k][j];
+                const bool wm = q_dn[qd[k][j]] != mv[k][j];
+                wrong += wM || wm;
+                const bool rmin = wm && ((dg & 15u) != (df & 15u));
+                const bool rmax = wM && ((dg >> 4) != (df >> 4));
+                cases += rmin + rmax;
+                if (rmin) mark(marks, i + gr.off[df & 15u]);
+                if (rmax) mark(marks, i + gr.off[dg >> 4]);
+            }
         }
     }
 }
@@ -1199,14 +1205,18 @@ void launch_delta(const float* g, const float* fhat, int n, float* delta, float*
 
 // ============================================================ batch engine ==
 //
-// k_engine corrects a batch of fields in one persistent launch.  Every step,
-// each unfinished field performs one operation of its schedule (the same
-// sequence of operations msz_fix runs, so each field's result is
-// bit-identical to its own msz_fix); the operations' work items of all fields
-// form one index space that the blocks walk.  The block that completes a
-// field's last item of the step (completion ticket) reads that field's
-// counters and writes its next operation; a grid-wide barrier then separates
-// the steps.  Counters and states are double-buffered by step parity.
+// The schedule of the correction loop (Sec. 5) runs on the device.  A step
+// advances every unfinished field of a batch by one operation of its own
+// schedule -- the same sequence of operations for every field as for a field
+// corrected alone, so results are identical.  k_eng_step<NDIM> runs the work
+// items of all fields of one dimension as one index space, cut into one
+// contiguous range per block (XCD-aware, so neighbouring items share an L2);
+// k_eng_decide reduces each field's counters and writes its next operation;
+// k_eng_scan forms the prefix sums of the next step's items.  The host
+// captures a fixed number of steps in a HIP graph and relaunches it until no
+// field is active.  Kernel boundaries order the steps: every write of a step
+// is visible to the next one without device-scope fences inside a kernel
+// (which on MI355X write back and invalidate the L2 of each XCD).
 
 __host__ __device__ inline int dirs_items_of(const Grid& gr, int variant) {
     const DirsVariant v = variant_of(gr.ndim, variant);
@@ -1220,24 +1230,22 @@ __host__ __device__ inline int eng_items(const EngField& F, int op) {
     const int tiles = label_tiles_of(F.gr);
     const int dirs = dirs_items_of(F.gr, F.variant);
     switch (op) {
-        case kOpPreA: return chunks + dirs;
-        case kOpPreB: case kOpPreC: case kOpRTile: case kOpRJump: case kOpRDetect: return tiles;
-        case kOpPreD: return tiles + dirs;
-        case kOpApplyC: case kOpApplyR: case kOpDetect: case kOpDelta: return chunks;
-        case kOpDdC: case kOpDdR: return dirs;
+        case kOpPreA: case kOpApplyC: case kOpApplyR: case kOpDetect: case kOpDelta: return chunks;
+        case kOpPreB: case kOpPreC: case kOpPreD: case kOpRTile: case kOpRJump: case kOpRDetect: return tiles;
+        case kOpPreA2: case kOpPreE: case kOpDdC: case kOpDdR: return dirs;
         default: return 0;
     }
 }
 
 int eng_items_host(const EngField& F, int op) { return eng_items(F, op); }
 
-// One direction work item of field F with its variant's tile shape.
-template <int MODE>
-__device__ __forceinline__ void eng_dirs_item(const EngField& F, const float* h, uint8_t* out, int type, int item,
-                                              float* sm, unsigned (&c)[4]) {
-    const ItemRange r{item, item + 1, 1};
+// Direction work items [a, b) of field F with its variant's tile shape.
+template <int NDIM, int MODE>
+__device__ __forceinline__ void eng_dirs(const EngField& F, const float* h, uint8_t* out, int type, int a, int b,
+                                         float* sm, unsigned (&c)[4]) {
+    const ItemRange r{a, b, 1};
     const Grid& gr = F.gr;
-    if (gr.ndim == 2) {
+    if constexpr (NDIM == 2) {
         if (variant_of(2, F.variant).ty == 32) dirs_stream<2, 32, 1, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
         else dirs_stream<2, 16, 1, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
     } else {
@@ -1249,118 +1257,144 @@ __device__ __forceinline__ void eng_dirs_item(const EngField& F, const float* h,
     }
 }
 
-// Runs work item `local` of the field's current operation (block-wide).
-__device__ void eng_run(const EngField& F, const EngState& st, int local, char* smem, unsigned* cset) {
+// Runs work items [lo, hi) of the field's current operation (block-wide; lo,
+// hi uniform over the block) and adds the block's counts to the field's
+// counter block.
+template <int NDIM>
+__device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem) {
     const Grid& gr = F.gr;
     const int chunks = (gr.n + kEngChunk - 1) / kEngChunk;
-    const int tiles = label_tiles_of(gr);
     int* su = reinterpret_cast<int*>(smem);
     int* sd = su + 4096;
     float* sm = reinterpret_cast<float*>(smem);
     const int cidx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
+    unsigned* cnt = F.cnt;
     switch (st.op) {
-        case kOpPreA:
-            if (local < chunks) {
-                unsigned bad = 0;
-                const int ng = (gr.n + 3) >> 2;
+        case kOpPreA: {
+            unsigned bad = 0;
+            const int ng = (gr.n + 3) >> 2;
+            for (int item = lo; item < hi; ++item)
                 for (int k = 0; k < kEngChunk / 1024; ++k) {
-                    const int w = local * (kEngChunk / 4) + threadIdx.x + 256 * k;
-                    if (w < ng) validate_group(F.f, F.fhat, nullptr, F.xi, gr.n, F.L, F.g, w, bad);
+                    const int w = item * (kEngChunk / 4) + threadIdx.x + 256 * k;
+                    if (w < ng) validate_group(F.f, F.fhat, F.warm, F.xi, gr.n, F.L, F.g, w, bad);
                 }
-                if (bad) atomicOr(cset + kCntErr, bad);
-            } else {
-                unsigned c[4] = {0u, 0u, 0u, 0u};
-                eng_dirs_item<0>(F, F.f, F.dirs_f, 0, local - chunks, sm, c);
-            }
+            if (bad) atomicOr(cnt + kCntErr, bad);
             break;
+        }
+        case kOpPreA2: {
+            unsigned c[4] = {0u, 0u, 0u, 0u};
+            eng_dirs<NDIM, 0>(F, F.f, F.dirs_f, 0, lo, hi, sm, c);
+            break;
+        }
         case kOpPreB:
         case kOpRTile: {
             const uint8_t* d = st.op == kOpPreB ? F.dirs_f : F.dirs_g;
-            if (gr.ndim == 2) label_tile_body<2>(d, gr, local, F.qu, F.qd, su, sd);
-            else label_tile_body<3>(d, gr, local, F.qu, F.qd, su, sd);
+            for (int item = lo; item < hi; ++item) {
+                label_tile_body<NDIM>(d, gr, item, F.qu, F.qd, su, sd);
+                __syncthreads();
+            }
             break;
         }
         case kOpPreC:
         case kOpRJump: {
-            const bool ok = gr.ndim == 2 ? compress_tile<2>(gr, local, F.qu, F.qd) : compress_tile<3>(gr, local, F.qu, F.qd);
-            if (!ok) atomicOr(cset + kCntErr, kErrWalk);
+            bool ok = true;
+            for (int item = lo; item < hi; ++item) ok = compress_tile<NDIM>(gr, item, F.qu, F.qd) && ok;
+            if (!ok) atomicOr(cnt + kCntErr, kErrWalk);
             break;
         }
         case kOpPreD:
-            if (local < tiles) {
-                if (gr.ndim == 2) label_final_tile<2>(F.qu, F.qd, gr, local, F.Mf, F.mf);
-                else label_final_tile<3>(F.qu, F.qd, gr, local, F.Mf, F.mf);
-            } else {
-                unsigned c[4] = {0u, 0u, 0u, 0u};
-                eng_dirs_item<1>(F, F.g, F.dirs_g, 0, local - tiles, sm, c);
-                block_add<4>(c, cset, cidx, kEngSlots, kEngStride);
-            }
+            for (int item = lo; item < hi; ++item) label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf);
             break;
         case kOpApplyC:
         case kOpApplyR: {
             unsigned changed = 0;
-            const int w = local * (kEngChunk / 16) + threadIdx.x;
-            if (w < (gr.n + 15) >> 4) apply_group(F.g, F.L, F.marks, w, changed);
+            const int nw = (gr.n + 15) >> 4;
+            for (int item = lo; item < hi; ++item) {
+                const int w = item * (kEngChunk / 16) + threadIdx.x;
+                if (w < nw) apply_group(F.g, F.L, F.marks, w, changed);
+            }
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
-            block_add<1>(v, cset, idx, kEngSlots, kEngStride);
+            block_add<1>(v, cnt, idx);
             break;
         }
+        case kOpPreE:
         case kOpDdC:
         case kOpDdR: {
             unsigned c[4] = {0u, 0u, 0u, 0u};
-            eng_dirs_item<1>(F, F.g, F.dirs_g, st.type, local, sm, c);
-            block_add<4>(c, cset, cidx, kEngSlots, kEngStride);
+            eng_dirs<NDIM, 1>(F, F.g, F.dirs_g, st.type, lo, hi, sm, c);
+            block_add<4>(c, cnt, cidx);
             break;
         }
         case kOpDetect: {
             unsigned c[4] = {0u, 0u, 0u, 0u};
-            const int w = local * (kEngChunk / 16) + threadIdx.x;
-            if (w < (gr.n + 15) >> 4) detect_group(F.dirs_f, F.dirs_g, gr, st.type, F.marks, w, c);
-            block_add<4>(c, cset, cidx, kEngSlots, kEngStride);
+            const int nw = (gr.n + 15) >> 4;
+            for (int item = lo; item < hi; ++item) {
+                const int w = item * (kEngChunk / 16) + threadIdx.x;
+                if (w < nw) detect_group(F.dirs_f, F.dirs_g, gr, st.type, F.marks, w, c);
+            }
+            block_add<4>(c, cnt, cidx);
             break;
         }
         case kOpRDetect: {
             unsigned wrong = 0, cases = 0;
-            if (gr.ndim == 2) detect_r_tile<2>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, local, F.marks, wrong, cases);
-            else detect_r_tile<3>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, local, F.marks, wrong, cases);
+            for (int item = lo; item < hi; ++item)
+                detect_r_tile<NDIM, 1>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, F.marks, wrong, cases);
             unsigned v[2] = {wrong, cases};
             const int idx[2] = {kCntWrong, kCntRCases};
-            block_add<2>(v, cset, idx, kEngSlots, kEngStride);
+            block_add<2>(v, cnt, idx);
             break;
         }
         case kOpDelta: {
             unsigned edited = 0, inexact = 0;
             const int ng = (gr.n + 3) >> 2;
-            for (int k = 0; k < kEngChunk / 1024; ++k) {
-                const int w = local * (kEngChunk / 4) + threadIdx.x + 256 * k;
-                if (w < ng) delta_group(F.g, F.fhat, gr.n, F.edits, F.g_out, w, edited, inexact);
-            }
+            for (int item = lo; item < hi; ++item)
+                for (int k = 0; k < kEngChunk / 1024; ++k) {
+                    const int w = item * (kEngChunk / 4) + threadIdx.x + 256 * k;
+                    if (w < ng) delta_group(F.g, F.fhat, gr.n, F.edits, F.g_out, w, edited, inexact);
+                }
             unsigned v[2] = {edited, inexact};
             const int idx[2] = {kCntEdited, kCntInexact};
-            block_add<2>(v, cset, idx, kEngSlots, kEngStride);
+            block_add<2>(v, cnt, idx);
             break;
         }
         default:
             break;
     }
-    // Every wave's stores and counter atomics complete and become visible
-    // device-wide before thread 0 takes the item's completion ticket.
-    __threadfence();
-    __syncthreads();  // the next item reuses the LDS
+    __syncthreads();  // the next range reuses the LDS
 }
 
-// The schedule (the host loop of msz_fix, step by step): reads the finished
-// step's counters of one field, clears them, and returns its next state.
-__device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, unsigned* cset) {
-    unsigned c[kCntSlots];
-    for (int k = 0; k < kCntSlots; ++k) c[k] = 0;
-    for (int b = 0; b < kEngSlots; ++b)
-        for (int k = 0; k < kCntSlots; ++k) {
-            const unsigned v = __hip_atomic_load(cset + b * kEngStride + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            c[k] = k == kCntErr ? (c[k] | v) : c[k] + v;
+// One step of every field of dimension NDIM.  pre[0..nf] are the prefix sums
+// of the fields' items in this step (fields of the other dimension count 0).
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
+                                                  const int* pre, int nf) {
+    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
+    const int total = __hip_atomic_load(pre + nf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (total == 0) return;
+    const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
+    const int per = (total + nb - 1) / nb;
+    int lo = b * per;
+    const int hi = min(total, lo + per);
+    while (lo < hi) {
+        int a = 0, z = nf - 1;  // the field whose items contain lo: largest f with pre[f] <= lo
+        while (a < z) {
+            const int mid = (a + z + 1) >> 1;
+            if (__hip_atomic_load(pre + mid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= lo) a = mid;
+            else z = mid - 1;
         }
-    for (int w = 0; w < kEngSet; ++w) cset[w] = 0u;
+        const int base = __hip_atomic_load(pre + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int end = min(hi, __hip_atomic_load(pre + a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const EngState st = cur[a];
+        eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem);
+        lo = end;
+    }
+}
+
+// The schedule (the host loop of a single correction, step by step): the next
+// state of one field from the counters of its finished step.
+__device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, const unsigned (&c)[kCntSlots]) {
     auto go = [&](int op) {
         st.op = op;
         st.items = eng_items(F, op);
@@ -1390,6 +1424,10 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, unsi
         case kOpPreA:
             if (c[kCntErr] & kErrNonFinite) return stop(MSZ_ENONFINITE);
             if (c[kCntErr] & kErrBound) return stop(MSZ_EBOUND);
+            if (c[kCntErr] & kErrWarmNonFinite) return stop(MSZ_ENONFINITE);
+            if (c[kCntErr] & kErrWarmBound) return stop(MSZ_EBOUND);
+            return go(kOpPreA2);
+        case kOpPreA2:
             return go(kOpPreB);
         case kOpPreB:
             return go(kOpPreC);
@@ -1397,6 +1435,9 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, unsi
             if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
             return go(kOpPreD);
         case kOpPreD:
+            st.type = 0;
+            return go(kOpPreE);
+        case kOpPreE:
             for (int t = 0; t < 4; ++t) S->false_init[t] = c[kCntCase + t];
             S->outer_iters = 1;
             st.type = 0;
@@ -1439,103 +1480,107 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, unsi
     }
 }
 
-// Grid-wide barrier: arrive on a counter, the last block bumps the generation.
-// All blocks are resident (the grid is sized to the occupancy limit and
-// launched cooperatively); a block that waits longer than ~4 s raises the
-// abort flag instead of hanging, and every block leaves at the next barrier.
-__device__ __forceinline__ bool eng_barrier(unsigned* bar, unsigned& gen) {
-    __shared__ int s_abort;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned arrived = atomicAdd(&bar[0], 1u) + 1u;
-        if (arrived == gridDim.x) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence();
-            __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const unsigned long long t0 = wall_clock64();
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
-                if (wall_clock64() - t0 > 400000000ull) {  // 4 s at the 100 MHz constant clock
-                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(4);
-            }
+// Block f decides field f: the 256 threads reduce the field's counter block
+// (kSlots slots of kCntSlots counters), clear it, and thread 0 writes the next
+// state.  With one field (single) it also writes the next prefix sums, the
+// active count and, if oplog is set, the operation this step ran.
+__global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__ fields, const EngState* cur,
+                                                    EngState* nxt, EngStats* stats, int nf, int* pre2, int* pre3,
+                                                    int* ctl, int* oplog, int step) {
+    __shared__ unsigned part[256];
+    __shared__ unsigned red[kCntSlots];
+    const int f = blockIdx.x;
+    const EngState st = cur[f];
+    if (nf == 1 && oplog && threadIdx.x == 0) oplog[step] = st.items > 0 ? st.op : kOpDone;
+    EngState ns = st;
+    if (st.items > 0) {
+        const EngField& F = fields[f];
+        // thread t sums counter (t % 16) over the slots t / 16, t / 16 + 16, ...
+        const int k = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
+        unsigned acc = 0;
+        for (int sl = s0; sl < kSlots; sl += 256 / kCntSlots) {
+            unsigned* w = F.cnt + sl * kSlotStride + k;
+            const unsigned v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc = k == kCntErr ? (acc | v) : acc + v;
+            __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __threadfence();
-        gen += 1u;
-        s_abort = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-    }
-    __syncthreads();
-    return s_abort == 0;
-}
-
-__global__ void __launch_bounds__(256) k_engine(const EngField* __restrict__ fields, EngState* states,
-                                                EngStats* stats, unsigned* tickets, unsigned* bar, int nf,
-                                                int max_steps) {
-    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
-    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the engine's LDS");
-    __shared__ int pre[kEngMaxFields + 1];
-    unsigned gen = 0;
-    for (int step = 0; step < max_steps; ++step) {
-        const int par = step & 1;
-        const EngState* cur = states + par * nf;
-        EngState* nxt = states + (par ^ 1) * nf;
-        for (int f = threadIdx.x; f < nf; f += blockDim.x) pre[f + 1] = cur[f].items;
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x < kCntSlots) {
+            unsigned a = 0;
+            for (int j = threadIdx.x; j < 256; j += kCntSlots) a = threadIdx.x == kCntErr ? (a | part[j]) : a + part[j];
+            red[threadIdx.x] = a;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            pre[0] = 0;
-            for (int f = 0; f < nf; ++f) pre[f + 1] += pre[f];
+            unsigned c[kCntSlots];
+            for (int j = 0; j < kCntSlots; ++j) c[j] = red[j];
+            ns = eng_decide(F, st, stats + f, c);
         }
-        __syncthreads();
-        const int total = pre[nf];
-        if (total == 0) break;  // every field is done (the same for all blocks)
-        if (blockIdx.x == 0)
-            for (int f = threadIdx.x; f < nf; f += blockDim.x)
-                if (cur[f].items == 0) nxt[f] = cur[f];  // finished fields keep their state
-        for (int item = blockIdx.x; item < total; item += gridDim.x) {
-            int lo = 0, hi = nf - 1;  // the field whose items contain `item`
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= item) lo = mid;
-                else hi = mid - 1;
-            }
-            const EngField& F = fields[lo];
-            const EngState st = cur[lo];
-            unsigned* cset = F.cnt + par * kEngSet;
-            eng_run(F, st, item - pre[lo], smem, cset);
-            if (threadIdx.x == 0) {
-                __threadfence();
-                const unsigned done = atomicAdd(&tickets[2 * lo + par], 1u);
-                if (done + 1u == static_cast<unsigned>(st.items)) {
-                    __threadfence();
-                    tickets[2 * lo + par] = 0u;
-                    nxt[lo] = eng_decide(F, st, stats + lo, cset);
-                }
-            }
+    }
+    if (threadIdx.x == 0) {
+        nxt[f] = ns;
+        if (nf == 1) {
+            const bool three = fields[0].gr.ndim == 3;
+            pre2[0] = 0;
+            pre3[0] = 0;
+            pre2[1] = three ? 0 : ns.items;
+            pre3[1] = three ? ns.items : 0;
+            ctl[0] = ns.items > 0 ? 1 : 0;
         }
-        if (!eng_barrier(bar, gen)) return;
     }
 }
 
-// Zeroes the per-field marks and counters and the engine's control words.
-__global__ void __launch_bounds__(256) k_engine_init(const EngField* __restrict__ fields, int nf, unsigned* tickets,
-                                                     unsigned* bar) {
+// Prefix sums of the next step's items per dimension, and the active count
+// (one block of kEngMaxFields threads, one field each).
+__global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
+                                                           int nf, int* pre2, int* pre3, int* ctl) {
+    __shared__ int s2[kEngMaxFields], s3[kEngMaxFields];
+    const int f = threadIdx.x;
+    int a2 = 0, a3 = 0;
+    if (f < nf) {
+        const int it = nxt[f].items;
+        if (fields[f].gr.ndim == 3) a3 = it;
+        else a2 = it;
+    }
+    s2[f] = a2;
+    s3[f] = a3;
+    __syncthreads();
+    for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive Hillis-Steele scan
+        const int v2 = f >= o ? s2[f - o] : 0, v3 = f >= o ? s3[f - o] : 0;
+        __syncthreads();
+        s2[f] += v2;
+        s3[f] += v3;
+        __syncthreads();
+    }
+    if (f < nf) {
+        pre2[f + 1] = s2[f];
+        pre3[f + 1] = s3[f];
+    }
+    if (f == 0) {
+        pre2[0] = 0;
+        pre3[0] = 0;
+        ctl[0] = (s2[nf - 1] + s3[nf - 1]) > 0 ? 1 : 0;
+    }
+}
+
+// Clears every field's marks and counter block.
+__global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ fields, int nf) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     for (int f = 0; f < nf; ++f) {
         const EngField& F = fields[f];
         uint4* m = reinterpret_cast<uint4*>(F.marks);
         const int nw = (F.gr.n + 15) >> 4;
         for (int w = tid; w < nw; w += nthr) m[w] = make_uint4(0u, 0u, 0u, 0u);
-        for (int w = tid; w < 2 * kEngSet; w += nthr) F.cnt[w] = 0u;
+        for (int w = tid; w < kCntBlockWords; w += nthr) F.cnt[w] = 0u;
     }
-    for (int w = tid; w < 2 * nf; w += nthr) tickets[w] = 0u;
-    if (tid < 4) bar[tid] = 0u;
 }
 
-const void* engine_kernel() { return reinterpret_cast<const void*>(&k_engine); }
-const void* engine_init_kernel() { return reinterpret_cast<const void*>(&k_engine_init); }
+const void* eng_step_kernel(int ndim) {
+    return ndim == 3 ? reinterpret_cast<const void*>(&k_eng_step<3>) : reinterpret_cast<const void*>(&k_eng_step<2>);
+}
+const void* eng_decide_kernel() { return reinterpret_cast<const void*>(&k_eng_decide); }
+const void* eng_scan_kernel() { return reinterpret_cast<const void*>(&k_eng_scan); }
+const void* eng_init_kernel() { return reinterpret_cast<const void*>(&k_eng_init); }
 
 }  // namespace msz

@@ -48,4 +48,4 @@ def test_host_only_entry_points():
     assert msz.lib().msz_workspace_bytes(msz.Dims(3, 2048, 2048, 512)) == 0   # n >= 2^31
     assert msz.tile_variants(2) >= 1 and msz.tile_variants(3) >= 1
     both = msz.workspace_bytes((64, 80)) + msz.workspace_bytes((16, 16, 16))
-    assert both < msz.batch_workspace_bytes([(64, 80), (16, 16, 16)]) < both + 64 * 1024
+    assert msz.batch_workspace_bytes([(64, 80), (16, 16, 16)]) == both   # the fields' own workspaces
