@@ -12,7 +12,7 @@ Every result is checked for zero segmentation error outside the clock.
 Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,batched,learned]
-                  [--no-cpu-baseline] [--calib-copy]
+                  [--no-cpu-baseline] [--calib-copy] [--schedule-out FILE]
 """
 from __future__ import annotations
 
@@ -91,12 +91,17 @@ def bench_plain(msz, torch, dev, args):
     ws = torch.empty(msz.workspace_bytes(fields[0][0].shape), dtype=torch.uint8, device=dev)
     outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
 
+    schedules = []  # with --schedule-out: every call timed, its step schedule kept
+
     def step(timing=False):
         res = []
         for (f, fh, xi), (e, g) in zip(fields, outs):
-            rc, _, _, st = msz.fix(f, fh, xi, workspace=ws, edits_out=e, g_out=g, timing=timing)
+            rc, _, _, st = msz.fix(f, fh, xi, workspace=ws, edits_out=e, g_out=g,
+                                   timing=timing or args.schedule_out is not None)
             if rc != msz.OK:
                 raise RuntimeError(f"msz_fix failed: {msz.strerror(rc)}")
+            if args.schedule_out is not None:
+                schedules.append({"xi": xi, "phases": msz.last_schedule()})
             res.append(st)
         return res
 
@@ -115,8 +120,9 @@ def bench_plain(msz, torch, dev, args):
     log(f"bench: plain {ms_per_step:.3f} ms/step, {verts / ms_per_step / 1e6:.3f} Gvertices/s")
     for (f, fh, xi), (e, g) in zip(fields, outs):
         checked(msz, f, g, xi)
-    # the same steps again with a hipEvent pair around every device step (on
-    # the library's stream): per-kernel durations for the roofline
+    # the same steps again with every device step timed (the step kernel stamps
+    # its first block's start and its last block's end with the GPU's
+    # constant-rate clock): per-kernel durations for the roofline
     log(f"bench: {args.steps} instrumented steps")
     phase_ms, phase_n = {}, {}
     t2 = time.perf_counter()
@@ -144,8 +150,8 @@ def bench_plain(msz, torch, dev, args):
         "avg_launch_us": round(avg_ms * 1e3, 2),
         "bytes_per_launch": bpl,
         "launches_per_step": phase_n[dominant] / args.steps,
-        "timing": "hipEvents around every step of the instrumented pass "
-                  f"({ms_instrumented:.3f} ms/step with the events)",
+        "timing": "GPU clock stamps of every step kernel in an instrumented pass of the same steps "
+                  f"({ms_instrumented:.3f} ms/step with the stamps)",
     }
     phases = {}
     for k in phase_ms:
@@ -158,6 +164,9 @@ def bench_plain(msz, torch, dev, args):
                      "algorithmic_GBps": round(b * n_per / (us * 1e-6) / 1e9, 1) if b else None}
     rounds = [{"xi": xi, "rounds": st["rounds"], "rounds_r": st["rounds_r"], "outer_iters": st["outer_iters"],
                "n_edited": st["n_edited"]} for (_, _, xi), st in zip(fields, sts)]
+    if args.schedule_out is not None:
+        with open(args.schedule_out, "w") as fh:
+            json.dump({"phase_names": list(msz.PHASES), "calls": schedules}, fh)
     return pairs, verts, ms_per_step, roofline, phases, rounds
 
 
@@ -268,6 +277,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--schedule-out", default=None,
+                    help="time every plain-form call and write each call's step schedule to this JSON file "
+                         "(to attribute the step kernels of a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: one field's "

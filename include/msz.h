@@ -53,8 +53,9 @@ enum {
 };
 
 /* Steps timed under MSZ_FLAG_TIMING (indices of msz_stats.phase_ms).  The
- * loop runs as a sequence of device-scheduled steps; each step runs one
- * operation, timed by hipEvents recorded around it. */
+ * loop runs as a sequence of device-scheduled steps, each running one
+ * operation; a timed step kernel stamps its first block's start and its last
+ * block's end with the GPU's constant-rate clock. */
 enum {
     MSZ_PHASE_VALIDATE = 0,     /* input contract, floors L, start field */
     MSZ_PHASE_DIRS = 1,         /* steepest directions of f */
@@ -71,7 +72,7 @@ enum {
 };
 
 /* msz_options.flags bits. */
-#define MSZ_FLAG_TIMING 1 /* record hipEvents around every step (adds a little overhead) */
+#define MSZ_FLAG_TIMING 1 /* time every step (single-field calls; adds a little overhead) */
 
 typedef struct {
     int32_t ndim;        /* 2 or 3 */
@@ -138,6 +139,15 @@ typedef struct {
  */
 int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edits_out,
             const msz_options* opt, msz_stats* stats, void* stream);
+
+/* Profiling aid: the step schedule of the calling host thread's last msz_fix
+ * that ran with MSZ_FLAG_TIMING.  Every step of the device schedule runs one
+ * operation; step k is phases_out[k] (an MSZ_PHASE_* index, or -1 for the
+ * idle steps that end the last graph launch).  Writes at most max entries
+ * (phases_out may be NULL) and returns the number of steps recorded.  The
+ * entries line up one to one with the step-kernel dispatches of that call
+ * in a kernel trace. */
+int32_t msz_last_schedule(int32_t* phases_out, int32_t max);
 
 /*
  * msz_labels -- ascending / descending segmentation labels of one field

@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
         L.msz_batch_workspace_bytes.argtypes = [ctypes.POINTER(Job), I32]
         L.msz_batch_workspace_bytes.restype = ctypes.c_size_t
         L.msz_tile_variants.argtypes = [I32]
+        L.msz_last_schedule.argtypes = [P, I32]
+        L.msz_last_schedule.restype = I32
         L.msz_strerror.argtypes = [ctypes.c_int]
         L.msz_strerror.restype = ctypes.c_char_p
         L.msz_net_workspace_bytes.argtypes = [Dims]
@@ -195,6 +197,14 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: boo
     if timing:
         out["timing"] = st.timing()
     return int(rc), edits, g, out
+
+
+def last_schedule() -> list:
+    """Phase index of every step of this thread's last timed fix (-1: idle step)."""
+    n = int(lib().msz_last_schedule(None, 0))
+    buf = (ctypes.c_int32 * max(n, 1))()
+    lib().msz_last_schedule(ctypes.cast(buf, ctypes.c_void_p), n)
+    return [int(buf[k]) for k in range(n)]
 
 
 def labels(field, stream=None):

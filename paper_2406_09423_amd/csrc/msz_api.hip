@@ -145,7 +145,8 @@ int check_xi(float xi) {
 
 // ------------------------------------------------------------- engine ---
 
-constexpr int kGraphSteps = 16;  // steps per graph launch (even: parities line up)
+constexpr int kGraphSteps = kEngTimeSlots;  // steps per graph launch (even: parities line up)
+static_assert(kGraphSteps % 2 == 0, "states alternate between two buffers");
 
 // Per host thread and device: the engine's control block (device), a pinned
 // read-back word, and the graph of kGraphSteps steps for the last topology.
@@ -156,26 +157,27 @@ struct EngineCtx {
     EngState* states = nullptr;
     EngStats* stats = nullptr;
     int *pre2 = nullptr, *pre3 = nullptr, *ctl = nullptr, *oplog = nullptr;
-    int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog
+    unsigned long long* tstamp = nullptr;  // profiling: step starts [0, kGraphSteps), ends after
+    int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog, then 2 * kGraphSteps stamps
     // cached graph
     int g_nf = -1, g_grid2 = 0, g_grid3 = 0;
     bool g_has2 = false, g_has3 = false, g_timing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<hipEvent_t> events;
 
     void drop_graph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
         graph = nullptr;
-        for (hipEvent_t e : events) (void)hipEventDestroy(e);
-        events.clear();
         g_nf = -1;
     }
     // No destructor work: at process exit the HIP runtime may already be torn
     // down, and the device memory (about 0.4 MB per host thread) is reclaimed
     // with the process.
+
+    static size_t host_bytes() { return 256 + sizeof(unsigned long long) * 2 * kGraphSteps; }
+    unsigned long long* host_stamps() const { return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(host) + 256); }
 
     int init(int dev) {
         if (device == dev && ctl_mem) return MSZ_OK;
@@ -195,6 +197,7 @@ struct EngineCtx {
         const size_t op3 = take(sizeof(int) * (kEngMaxFields + 1));
         const size_t oc = take(sizeof(int) * 4);
         const size_t ol = take(sizeof(int) * kGraphSteps);
+        const size_t ot = take(sizeof(unsigned long long) * 2 * kGraphSteps);
         void* p = nullptr;
         if (hipMalloc(&p, o) != hipSuccess) return MSZ_ENOMEM;
         ctl_mem = static_cast<char*>(p);
@@ -205,9 +208,10 @@ struct EngineCtx {
         pre3 = reinterpret_cast<int*>(ctl_mem + op3);
         ctl = reinterpret_cast<int*>(ctl_mem + oc);
         oplog = reinterpret_cast<int*>(ctl_mem + ol);
+        tstamp = reinterpret_cast<unsigned long long*>(ctl_mem + ot);
         if (!host) {
             void* h = nullptr;
-            if (hipHostMalloc(&h, sizeof(int) * (1 + kGraphSteps), hipHostMallocDefault) != hipSuccess)
+            if (hipHostMalloc(&h, host_bytes(), hipHostMallocDefault) != hipSuccess)
                 return MSZ_ENOMEM;
             host = static_cast<int*>(h);
         }
@@ -236,29 +240,19 @@ struct EngineCtx {
             chain(n);
             return true;
         };
-        auto add_event = [&]() -> bool {
-            hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return false;
-            events.push_back(e);
-            hipGraphNode_t n = nullptr;
-            if (hipGraphAddEventRecordNode(&n, graph, last ? &last : nullptr, last ? 1 : 0, e) != hipSuccess) return false;
-            chain(n);
-            return true;
-        };
         for (int st = 0; st < kGraphSteps; ++st) {
             const int par = st & 1;
             EngState* cur = states + par * nf;
             EngState* nxt = states + (par ^ 1) * nf;
-            if (timing && !add_event()) return MSZ_EDEVICE;
+            unsigned long long* ts = timing ? tstamp + st : nullptr;
             if (has2) {
-                void* a[] = {&fields, &cur, &pre2, &nf};
+                void* a[] = {&fields, &cur, &pre2, &nf, &ts};
                 if (!add_kernel(eng_step_kernel(2), dim3(grid2), dim3(256), a)) return MSZ_EDEVICE;
             }
             if (has3) {
-                void* a[] = {&fields, &cur, &pre3, &nf};
+                void* a[] = {&fields, &cur, &pre3, &nf, &ts};
                 if (!add_kernel(eng_step_kernel(3), dim3(grid3), dim3(256), a)) return MSZ_EDEVICE;
             }
-            if (timing && !add_event()) return MSZ_EDEVICE;
             int* log = timing ? oplog : nullptr;
             int stp = st;
             void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp};
@@ -316,6 +310,13 @@ int step_grid(int dev, int ndim) {
     return cached[ndim == 3 ? 1 : 0];
 }
 
+// Schedule of the calling thread's last timed single-field run: the phase of
+// every step (-1 for the idle steps that close the last graph launch).
+std::vector<int32_t>& last_schedule() {
+    thread_local std::vector<int32_t> v;
+    return v;
+}
+
 // One engine run over hf.size() fields whose workspaces are already bound.
 // Fills st[] (one per field); with timing (one field only) adds the per-step
 // durations to ms[] / launches[] by phase.
@@ -342,6 +343,7 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         p3[j + 1] = p3[j] + (three ? items : 0);
     }
     timing = timing && nf == 1;
+    if (timing) last_schedule().clear();
     if (int rc = E.graph_for(nf, has2, has3, timing, grid2, grid3)) {
         E.drop_graph();
         return rc;
@@ -362,20 +364,31 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         MSZ_HIP(hipLaunchKernel(eng_init_kernel(), dim3(std::max(1, std::min(2048, (total + 255) / 256))), dim3(256),
                                 a, 0, s));
     }
+    int wall_khz = 0;
+    if (timing && (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0))
+        return MSZ_EDEVICE;
+    const size_t half = sizeof(unsigned long long) * kGraphSteps;
     int64_t steps = 0;
     int rc = MSZ_OK;
     for (;;) {
+        if (timing && (hipMemsetAsync(E.tstamp, 0xFF, half, s) != hipSuccess ||
+                       hipMemsetAsync(E.tstamp + kGraphSteps, 0, half, s) != hipSuccess)) { rc = MSZ_EDEVICE; break; }
         if (hipGraphLaunch(E.exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (hipMemcpyAsync(E.host, E.ctl, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (timing && hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) !=
-                          hipSuccess) { rc = MSZ_EDEVICE; break; }
+        if (timing && (hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) !=
+                           hipSuccess ||
+                       hipMemcpyAsync(E.host_stamps(), E.tstamp, 2 * half, hipMemcpyDeviceToHost, s) != hipSuccess)) {
+            rc = MSZ_EDEVICE;
+            break;
+        }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (timing) {
+            const unsigned long long* t = E.host_stamps();
             for (int k = 0; k < kGraphSteps; ++k) {
                 const int ph = phase_of_op(E.host[1 + k]);
-                float t = 0.f;
-                if (ph >= 0 && hipEventElapsedTime(&t, E.events[2 * k], E.events[2 * k + 1]) == hipSuccess) {
-                    ms[ph] += t;
+                last_schedule().push_back(ph);
+                if (ph >= 0 && t[kGraphSteps + k] >= t[k]) {
+                    ms[ph] += static_cast<double>(t[kGraphSteps + k] - t[k]) / wall_khz;
                     launches[ph] += 1;
                 }
             }
@@ -503,6 +516,14 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
         stats->phase_launches[k] = static_cast<int32_t>(launches[k]);
     }
     return stats->status;
+}
+
+int32_t msz_last_schedule(int32_t* phases_out, int32_t max) {
+    const std::vector<int32_t>& v = last_schedule();
+    const int32_t n = static_cast<int32_t>(v.size());
+    if (phases_out)
+        for (int32_t k = 0; k < n && k < max; ++k) phases_out[k] = v[k];
+    return n;
 }
 
 size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs) {

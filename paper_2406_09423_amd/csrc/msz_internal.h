@@ -142,6 +142,7 @@ namespace msz {
 // current operation of every field, k_eng_decide picks each field's next one,
 // k_eng_scan sums the next step's items (see the engine in msz_kernels.hip).
 constexpr int kEngMaxFields = 1024;
+constexpr int kEngTimeSlots = 16;                   // steps per graph launch (profiling stamps per launch)
 constexpr int kEngChunk = 4096;                     // vertices per flat work item
 
 enum EngOp : int {
@@ -187,7 +188,7 @@ struct EngStats {
 
 // Number of work items of operation op for one field (device and host).
 int eng_items_host(const EngField& F, int op);
-const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf)
+const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step)
 const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl)
 const void* eng_init_kernel();          // k_eng_init(fields, nf)

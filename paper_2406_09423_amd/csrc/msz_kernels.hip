@@ -1367,10 +1367,8 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
 // One step of every field of dimension NDIM.  pre[0..nf] are the prefix sums
 // of the fields' items in this step (fields of the other dimension count 0).
 template <int NDIM>
-__global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
-                                                  const int* pre, int nf) {
-    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
-    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
+__device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
+                                              int nf, char* smem) {
     const int total = __hip_atomic_load(pre + nf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (total == 0) return;
     const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
@@ -1389,6 +1387,22 @@ __global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ f
         const EngState st = cur[a];
         eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem);
         lo = end;
+    }
+}
+
+
+// ts (optional, profiling): ts[0] receives the start of block 0 and
+// ts[kEngTimeSlots] the latest block end, both from the constant-rate GPU clock.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
+                                                  const int* pre, int nf, unsigned long long* ts) {
+    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
+    if (ts && blockIdx.x == 0 && threadIdx.x == 0) atomicMin(ts, static_cast<unsigned long long>(wall_clock64()));
+    eng_step_body<NDIM>(fields, cur, pre, nf, smem);
+    if (ts) {
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(ts + kEngTimeSlots, static_cast<unsigned long long>(wall_clock64()));
     }
 }
 
