@@ -269,22 +269,68 @@ struct PlaneRegs {
     unsigned d[G::RPT];  // MODE 1: dirs_f words of the plane computed next
 };
 
-// Issues the loads of plane j of item it into registers (and, in MODE 1, the
-// dirs_f words of the plane that is computed once this one is in LDS).
-// Outside the grid a value is NaN, which never wins a comparison.  vec4: rows
-// start 16-byte aligned (nx % 4 == 0 and an aligned base), so whole in-grid
-// groups of four are one dwordx4 load.
+// A work item's origin, plane count and whether all of it and its halo lie
+// inside the grid (then no load or store needs a bounds check).  Uniform
+// over the block.
+struct ItemPos {
+    int x0, y0, z0, planes;
+    bool interior;
+};
+
+template <int NDIM, int TY, int ZC>
+__device__ __forceinline__ ItemPos item_pos(const DirsGeom<NDIM, TY, ZC>& geo, const Grid& gr, int it, bool vec4) {
+    ItemPos p;
+    geo.origin(it, p.x0, p.y0, p.z0);
+    p.planes = geo.planes(gr, it);
+    const bool zin = NDIM == 2 || (p.z0 >= 1 && p.z0 + ZC < gr.nz);
+    p.interior = vec4 && zin && p.x0 >= 1 && p.x0 + kTileX < gr.nx && p.y0 >= 1 && p.y0 + TY < gr.ny;
+    return p;
+}
+
+// Issues the loads of plane j of the item at pos into registers (and, in
+// MODE 1, the dirs_f words of the plane that is computed once this one is in
+// LDS).  Outside the grid a value is NaN, which never wins a comparison.
+// vec4: rows start 16-byte aligned (nx % 4 == 0 and an aligned base), so
+// whole in-grid groups of four are one dwordx4 load.
 template <int NDIM, int TY, int ZC, int MODE>
 __device__ __forceinline__ void dirs_load(const float* __restrict__ h, const uint8_t* __restrict__ dirs_f,
-                                          const Grid& gr, const DirsGeom<NDIM, TY, ZC>& geo, bool vec4, int it,
-                                          int j, PlaneRegs<NDIM, TY, ZC>& pr) {
+                                          const Grid& gr, const ItemPos& pos, bool vec4, int j,
+                                          PlaneRegs<NDIM, TY, ZC>& pr) {
     using G = DirsGeom<NDIM, TY, ZC>;
-    int x0, y0, z0;
-    geo.origin(it, x0, y0, z0);
-    const int z = NDIM == 3 ? z0 - 1 + j : 0;
-    const bool zin = z >= 0 && z < gr.nz;
+    const int x0 = pos.x0, y0 = pos.y0;
+    const int z = NDIM == 3 ? pos.z0 - 1 + j : 0;
     const float* plane = h + static_cast<long>(z) * gr.nxy;
     const float nan = __builtin_nanf("");
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int zc = NDIM == 3 ? z - 1 : 0;
+    if (pos.interior) {
+#pragma unroll
+        for (int k = 0; k < G::LV; ++k) {
+            const int u = threadIdx.x + 256 * k;
+            float4 v = make_float4(nan, nan, nan, nan);
+            if (G::NV % 256 == 0 || u < G::NV)
+                v = *reinterpret_cast<const float4*>(plane + static_cast<long>(gr.nx) * (y0 + (u >> 4) - 1) + x0 +
+                                                     4 * (u & 15));
+            pr.v[k] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < G::LH; ++k) {
+            const int u = threadIdx.x + 256 * k;
+            float v = nan;
+            if (u < G::NH) v = plane[static_cast<long>(gr.nx) * (y0 + (u >> 1) - 1) + ((u & 1) ? x0 + kTileX : x0 - 1)];
+            pr.h[k] = v;
+        }
+        if constexpr (MODE == 1) {
+            if (NDIM == 2 || j >= 2) {
+#pragma unroll
+                for (int q = 0; q < G::RPT; ++q)
+                    pr.d[q] = *reinterpret_cast<const unsigned*>(
+                        dirs_f + static_cast<long>(zc) * gr.nxy + static_cast<long>(gr.nx) * (y0 + ty + 16 * q) + x0 + 4 * tx);
+            }
+        }
+        return;
+    }
+    const bool zin = z >= 0 && z < gr.nz;
 #pragma unroll
     for (int k = 0; k < G::LV; ++k) {
         const int u = threadIdx.x + 256 * k;
@@ -313,9 +359,7 @@ __device__ __forceinline__ void dirs_load(const float* __restrict__ h, const uin
         pr.h[k] = v;
     }
     if constexpr (MODE == 1) {
-        const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
         const bool dvec = (gr.nx & 3) == 0;
-        const int zc = NDIM == 3 ? z - 1 : 0;
         const bool zok = NDIM == 3 ? (j >= 2 && zc < gr.nz) : true;
 #pragma unroll
         for (int q = 0; q < G::RPT; ++q) {
@@ -368,11 +412,11 @@ struct Row6 {
     }
 };
 
-// Directions (and, in MODE 1, detection) of plane z of item it, from the LDS
-// planes C (z), A (z + 1) and B (z - 1).
+// Directions (and, in MODE 1, detection) of plane z of the item at pos, from
+// the LDS planes C (z), A (z + 1) and B (z - 1).
 template <int NDIM, int TY, int ZC, int MODE>
 __device__ __forceinline__ void dirs_compute(const float* C, const float* A, const float* B, const Grid& gr,
-                                             const DirsGeom<NDIM, TY, ZC>& geo, int it, int z,
+                                             const ItemPos& pos, int z,
                                              const unsigned (&df4)[DirsGeom<NDIM, TY, ZC>::RPT],
                                              uint8_t* __restrict__ dirs_out, int type, uint8_t* __restrict__ marks,
                                              unsigned (&c)[4]) {
@@ -380,13 +424,11 @@ __device__ __forceinline__ void dirs_compute(const float* C, const float* A, con
     constexpr int W = G::W;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const bool vec4 = (gr.nx & 3) == 0;
-    int x0, y0, z0;
-    geo.origin(it, x0, y0, z0);
 #pragma unroll
     for (int q = 0; q < G::RPT; ++q) {
-        const int y = y0 + ty + 16 * q, xa = x0 + tx * 4, r = ty + 16 * q + 1;
+        const int y = pos.y0 + ty + 16 * q, xa = pos.x0 + tx * 4, r = ty + 16 * q + 1;
         const long i0 = static_cast<long>(z) * gr.nxy + static_cast<long>(gr.nx) * y + xa;
-        const bool full = vec4 && xa + 3 < gr.nx && y < gr.ny;
+        const bool full = pos.interior || (vec4 && xa + 3 < gr.nx && y < gr.ny);
         const int col = 4 + 4 * tx;
         const Row6 cm(C + (r - 1) * W + col), c0(C + r * W + col), cp(C + (r + 1) * W + col);
         Row6 bm = c0, b0 = c0, a0 = c0, ap = c0;
@@ -399,7 +441,7 @@ __device__ __forceinline__ void dirs_compute(const float* C, const float* A, con
         unsigned out4 = 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const bool valid = xa + k < gr.nx && y < gr.ny;
+            const bool valid = pos.interior || (xa + k < gr.nx && y < gr.ny);
             if (valid) {
                 const float v = c0.at(k);
                 Steepest b{v, v, kSelf, kSelf};
@@ -441,10 +483,16 @@ __device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const G
                                             int type, uint8_t* __restrict__ marks, float* sm, unsigned (&c)[4]) {
     using G = DirsGeom<NDIM, TY, ZC>;
     const G geo(gr);
-    const bool vec4 = (gr.nx & 3) == 0 && (reinterpret_cast<uintptr_t>(h) & 15u) == 0;
+    const bool vec4 = (gr.nx & 3) == 0 && (reinterpret_cast<uintptr_t>(h) & 15u) == 0 &&
+                      (MODE == 0 || (reinterpret_cast<uintptr_t>(dirs_f) & 3u) == 0) &&
+                      (reinterpret_cast<uintptr_t>(dirs_out) & 3u) == 0;
     PlaneRegs<NDIM, TY, ZC> pr;
     int it = range.first, j = 0;
-    if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, vec4, it, 0, pr);
+    ItemPos pos{};
+    if (it < range.hi) {
+        pos = item_pos(geo, gr, it, vec4);
+        dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, pos, vec4, 0, pr);
+    }
     int ring = 0;  // LDS slot of the plane held in registers
     while (it < range.hi) {
         dirs_store<NDIM, TY, ZC>(sm + ring * G::P, pr);
@@ -453,21 +501,21 @@ __device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const G
         for (int q = 0; q < G::RPT; ++q) df4[q] = pr.d[q];
         __syncthreads();
         // advance the stream and prefetch the next plane while this one is computed
-        const int cur_it = it, cur_j = j, cur_ring = ring;
-        if (++j == geo.planes(gr, it)) {
+        const ItemPos cur = pos;
+        const int cur_j = j, cur_ring = ring;
+        if (++j == pos.planes) {
             j = 0;
             it += range.stride;
+            if (it < range.hi) pos = item_pos(geo, gr, it, vec4);
         }
         ring = G::NP == 3 ? (ring + 1) % 3 : 0;
-        if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, geo, vec4, it, j, pr);
+        if (it < range.hi) dirs_load<NDIM, TY, ZC, MODE>(h, dirs_f, gr, pos, vec4, j, pr);
         if (NDIM == 2 || cur_j >= 2) {
-            int x0, y0, z0;
-            geo.origin(cur_it, x0, y0, z0);
-            const int z = NDIM == 3 ? z0 + cur_j - 2 : 0;
+            const int z = NDIM == 3 ? cur.z0 + cur_j - 2 : 0;
             const float* A = sm + cur_ring * G::P;                             // plane z + 1
             const float* C = sm + (G::NP == 3 ? (cur_ring + 2) % 3 : 0) * G::P; // plane z
             const float* B = sm + (G::NP == 3 ? (cur_ring + 1) % 3 : 0) * G::P; // plane z - 1
-            dirs_compute<NDIM, TY, ZC, MODE>(C, A, B, gr, geo, cur_it, z, df4, dirs_out, type, marks, c);
+            dirs_compute<NDIM, TY, ZC, MODE>(C, A, B, gr, cur, z, df4, dirs_out, type, marks, c);
         }
         __syncthreads();  // the slot written next is the oldest plane
     }
@@ -495,10 +543,8 @@ __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid 
 // dwordx4 of each direction array).  The direction arrays live in 256-byte
 // padded workspace segments, so the last partial group can be read whole;
 // vertices past n are masked to "no case".
-__device__ __forceinline__ void detect_group(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
-                                             const Grid& gr, int type, uint8_t* __restrict__ marks, int w,
-                                             unsigned (&c)[4]) {
-    const uint4 a = reinterpret_cast<const uint4*>(dirs_f)[w], b = reinterpret_cast<const uint4*>(dirs_g)[w];
+__device__ __forceinline__ void detect_loaded(const uint4 a, const uint4 b, const Grid& gr, int type,
+                                              uint8_t* __restrict__ marks, int w, unsigned (&c)[4]) {
     const unsigned fa[4] = {a.x, a.y, a.z, a.w}, ga[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -507,6 +553,13 @@ __device__ __forceinline__ void detect_group(const uint8_t* __restrict__ dirs_f,
         const unsigned pad = left >= 4 ? 0u : (left <= 0 ? 0xFFFFFFFFu : 0xFFFFFFFFu << (8 * left));
         detect4(fa[q] | pad, ga[q] | pad, i0, type, gr, marks, c);
     }
+}
+
+__device__ __forceinline__ void detect_group(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
+                                             const Grid& gr, int type, uint8_t* __restrict__ marks, int w,
+                                             unsigned (&c)[4]) {
+    detect_loaded(reinterpret_cast<const uint4*>(dirs_f)[w], reinterpret_cast<const uint4*>(dirs_g)[w], gr, type,
+                  marks, w, c);
 }
 
 __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__ dirs_f,
@@ -527,11 +580,10 @@ __global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__
 // its mark.  Marks are scanned 16 at a time; the padding bytes are never set.
 // Halves every marked vertex of the 16-vertex group w once and clears the
 // marks (padding bytes past n are never set).
-__device__ __forceinline__ void apply_group(float* __restrict__ g, const float* __restrict__ L,
-                                            uint8_t* __restrict__ marks, int w, unsigned& changed) {
+// The halvings of group w given its (already loaded, non-zero) marks m.
+__device__ __forceinline__ void apply_marks(float* __restrict__ g, const float* __restrict__ L,
+                                            uint8_t* __restrict__ marks, int w, const uint4 m, unsigned& changed) {
     uint4* mw = reinterpret_cast<uint4*>(marks);
-    const uint4 m = mw[w];
-    if ((m.x | m.y | m.z | m.w) == 0u) return;
     const unsigned part[4] = {m.x, m.y, m.z, m.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -548,6 +600,12 @@ __device__ __forceinline__ void apply_group(float* __restrict__ g, const float* 
         }
     }
     mw[w] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__device__ __forceinline__ void apply_group(float* __restrict__ g, const float* __restrict__ L,
+                                            uint8_t* __restrict__ marks, int w, unsigned& changed) {
+    const uint4 m = reinterpret_cast<const uint4*>(marks)[w];
+    if ((m.x | m.y | m.z | m.w) != 0u) apply_marks(g, L, marks, w, m, changed);
 }
 
 __global__ void __launch_bounds__(256) k_apply(float* __restrict__ g, const float* __restrict__ L,
@@ -737,41 +795,26 @@ __host__ __device__ constexpr int face_count() {
                      : 2 * T::X * T::Y + 2 * T::X * (T::Z - 2) + 2 * (T::Y - 2) * (T::Z - 2);
 }
 
-// b-th face-layer vertex of a tile, in local coordinates.
+// b-th face-layer vertex of a tile, in local coordinates (branch-free selects,
+// so nothing is kept in private memory).
 template <int NDIM>
-__device__ __forceinline__ void face_vertex(int b, int& lx, int& ly, int& lz) {
+__device__ __forceinline__ int3 face_vertex(int b) {
     using T = LabelTile<NDIM>;
     if constexpr (NDIM == 2) {
-        lz = 0;
-        if (b < 2 * T::X) {
-            lx = b % T::X;
-            ly = (b / T::X) ? T::Y - 1 : 0;
-        } else {
-            b -= 2 * T::X;
-            ly = 1 + b % (T::Y - 2);
-            lx = (b / (T::Y - 2)) ? T::X - 1 : 0;
-        }
+        const bool row = b < 2 * T::X;
+        const int c = b - 2 * T::X;
+        const int lx = row ? b % T::X : ((c / (T::Y - 2)) ? T::X - 1 : 0);
+        const int ly = row ? ((b / T::X) ? T::Y - 1 : 0) : 1 + c % (T::Y - 2);
+        return make_int3(lx, ly, 0);
     } else {
-        const int A = T::X * T::Y;
-        if (b < 2 * A) {  // z faces
-            lx = b % T::X;
-            ly = (b / T::X) % T::Y;
-            lz = (b / A) ? T::Z - 1 : 0;
-            return;
-        }
-        b -= 2 * A;
-        const int Bn = T::X * (T::Z - 2);
-        if (b < 2 * Bn) {  // y faces
-            lx = b % T::X;
-            lz = 1 + (b / T::X) % (T::Z - 2);
-            ly = (b / Bn) ? T::Y - 1 : 0;
-            return;
-        }
-        b -= 2 * Bn;
-        const int Cn = (T::Y - 2) * (T::Z - 2);  // x faces
-        ly = 1 + b % (T::Y - 2);
-        lz = 1 + (b / (T::Y - 2)) % (T::Z - 2);
-        lx = (b / Cn) ? T::X - 1 : 0;
+        constexpr int A = T::X * T::Y, Bn = T::X * (T::Z - 2);
+        const int b1 = b - 2 * A, b2 = b1 - 2 * Bn;
+        const int zf_x = b % T::X, zf_y = (b / T::X) % T::Y, zf_z = (b / A) ? T::Z - 1 : 0;
+        const int yf_x = b1 % T::X, yf_z = 1 + (b1 / T::X) % (T::Z - 2), yf_y = (b1 / Bn) ? T::Y - 1 : 0;
+        const int xf_y = 1 + b2 % (T::Y - 2), xf_z = 1 + (b2 / (T::Y - 2)) % (T::Z - 2);
+        const int xf_x = (b2 / ((T::Y - 2) * (T::Z - 2))) ? T::X - 1 : 0;
+        const bool zf = b < 2 * A, yf = !zf && b1 < 2 * Bn;
+        return make_int3(zf ? zf_x : yf ? yf_x : xf_x, zf ? zf_y : yf ? yf_y : xf_y, zf ? zf_z : yf ? yf_z : xf_z);
     }
 }
 
@@ -809,9 +852,8 @@ __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __r
     const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
     bool ok = true;
     for (int b = threadIdx.x; b < FC; b += blockDim.x) {
-        int lx, ly, lz;
-        face_vertex<NDIM>(b, lx, ly, lz);
-        const int x = bx * T::X + lx, y = by * T::Y + ly, z = bz * T::Z + lz;
+        const int3 l = face_vertex<NDIM>(b);
+        const int x = bx * T::X + l.x, y = by * T::Y + l.y, z = bz * T::Z + l.z;
         if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
         const int i = x + gr.nx * y + gr.nxy * z;
         const bool ok_up = compress_one(q_up, i);
@@ -1263,7 +1305,6 @@ __device__ __forceinline__ void eng_dirs(const EngField& F, const float* h, uint
 template <int NDIM>
 __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem) {
     const Grid& gr = F.gr;
-    const int chunks = (gr.n + kEngChunk - 1) / kEngChunk;
     int* su = reinterpret_cast<int*>(smem);
     int* sd = su + 4096;
     float* sm = reinterpret_cast<float*>(smem);
@@ -1307,11 +1348,21 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         case kOpApplyC:
         case kOpApplyR: {
+            // the marks of up to four items are loaded before any is applied
             unsigned changed = 0;
             const int nw = (gr.n + 15) >> 4;
-            for (int item = lo; item < hi; ++item) {
-                const int w = item * (kEngChunk / 16) + threadIdx.x;
-                if (w < nw) apply_group(F.g, F.L, F.marks, w, changed);
+            const uint4* mw = reinterpret_cast<const uint4*>(F.marks);
+            for (int base = lo; base < hi; base += 4) {
+                uint4 m[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int w = (base + k) * (kEngChunk / 16) + threadIdx.x;
+                    m[k] = (base + k < hi && w < nw) ? mw[w] : make_uint4(0u, 0u, 0u, 0u);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if ((m[k].x | m[k].y | m[k].z | m[k].w) != 0u)
+                        apply_marks(F.g, F.L, F.marks, (base + k) * (kEngChunk / 16) + threadIdx.x, m[k], changed);
             }
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
@@ -1327,11 +1378,24 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         }
         case kOpDetect: {
+            // both direction words of up to four items are loaded before any is tested
             unsigned c[4] = {0u, 0u, 0u, 0u};
             const int nw = (gr.n + 15) >> 4;
-            for (int item = lo; item < hi; ++item) {
-                const int w = item * (kEngChunk / 16) + threadIdx.x;
-                if (w < nw) detect_group(F.dirs_f, F.dirs_g, gr, st.type, F.marks, w, c);
+            const uint4* fw = reinterpret_cast<const uint4*>(F.dirs_f);
+            const uint4* gw = reinterpret_cast<const uint4*>(F.dirs_g);
+            for (int base = lo; base < hi; base += 4) {
+                uint4 a[4], b[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int w = (base + k) * (kEngChunk / 16) + threadIdx.x;
+                    const bool in = base + k < hi && w < nw;
+                    a[k] = in ? fw[w] : make_uint4(~0u, ~0u, ~0u, ~0u);
+                    b[k] = in ? gw[w] : make_uint4(~0u, ~0u, ~0u, ~0u);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (base + k < hi && (base + k) * (kEngChunk / 16) + threadIdx.x < nw)
+                        detect_loaded(a[k], b[k], gr, st.type, F.marks, (base + k) * (kEngChunk / 16) + threadIdx.x, c);
             }
             block_add<4>(c, cnt, cidx);
             break;
@@ -1369,7 +1433,19 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
 template <int NDIM>
 __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
                                               int nf, char* smem) {
-    const int total = __hip_atomic_load(pre + nf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // The tables were written by the previous kernel of the stream, so plain
+    // loads see them; one field needs no search.
+    if (nf == 1) {
+        const int total = pre[1];
+        const EngState st = cur[0];
+        if (total == 0) return;
+        const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
+        const int per = (total + nb - 1) / nb;
+        const int lo = b * per, hi = min(total, lo + per);
+        if (lo < hi) eng_run_range<NDIM>(fields[0], st, lo, hi, smem);
+        return;
+    }
+    const int total = pre[nf];
     if (total == 0) return;
     const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
     const int per = (total + nb - 1) / nb;
@@ -1379,17 +1455,16 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         int a = 0, z = nf - 1;  // the field whose items contain lo: largest f with pre[f] <= lo
         while (a < z) {
             const int mid = (a + z + 1) >> 1;
-            if (__hip_atomic_load(pre + mid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= lo) a = mid;
+            if (pre[mid] <= lo) a = mid;
             else z = mid - 1;
         }
-        const int base = __hip_atomic_load(pre + a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int end = min(hi, __hip_atomic_load(pre + a + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const int base = pre[a];
+        const int end = min(hi, pre[a + 1]);
         const EngState st = cur[a];
         eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem);
         lo = end;
     }
 }
-
 
 // ts (optional, profiling): ts[0] receives the start of block 0 and
 // ts[kEngTimeSlots] the latest block end, both from the constant-rate GPU clock.
@@ -1512,11 +1587,16 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
         // thread t sums counter (t % 16) over the slots t / 16, t / 16 + 16, ...
         const int k = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
         unsigned acc = 0;
-        for (int sl = s0; sl < kSlots; sl += 256 / kCntSlots) {
-            unsigned* w = F.cnt + sl * kSlotStride + k;
-            const unsigned v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            acc = k == kCntErr ? (acc | v) : acc + v;
-            __hip_atomic_store(w, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the step kernel's counter atomics completed with that kernel: plain
+        // loads see them; all loads are issued before the clearing stores
+        constexpr int PER = kSlots / (256 / kCntSlots);
+        unsigned v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) v[q] = F.cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            acc = k == kCntErr ? (acc | v[q]) : acc + v[q];
+            F.cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k] = 0u;
         }
         part[threadIdx.x] = acc;
         __syncthreads();
