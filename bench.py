@@ -210,7 +210,7 @@ def bench_batched(msz, torch, dev, steps):
     log(f"bench: batched {ms:.2f} ms ({verts / ms / 1e6:.3f} Gv/s), one by one {ms_seq:.2f} ms")
     rounds = [sum(st["rounds"]) + st["rounds_r"] for _, _, _, st in res]
     return {"workload": "96 uneven k^-3 fields: 64 2D (sides U{64..2048}), 32 3D (U{32..192}^3), "
-                        "xi in {1e-4,1e-3,1e-2} x range; one persistent launch",
+                        "xi in {1e-4,1e-3,1e-2} x range; one device-scheduled run",
             "vertices": verts, "ms": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
             "steps": steps, "sequential_ms": round(ms_seq, 3),
             "speedup_vs_sequential": round(ms_seq / ms, 3), "max_rounds": max(rounds),

@@ -24,12 +24,21 @@
  *    before the call returns.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  *    stream).  All work is enqueued on it; each call synchronises on it
- *    before returning (the loop makes host decisions between rounds).
- *  - Errors: the return code is the only error channel; no global state.
- *    msz_strerror() names a code.  Inputs must be finite with magnitude at
- *    most 2^100 (so that no edit can overflow float32).
+ *    before returning.  The schedule of the loop runs on the device: a HIP
+ *    graph of 16 steps is launched until no field is active, and one word is
+ *    read back per launch.
+ *  - Memory: the library allocates scratch per call when no workspace is
+ *    given (hipMallocAsync on the stream), and keeps one small control block
+ *    (about 0.4 MB: field table, step states, statistics, the cached graph)
+ *    per host thread and device for the life of the process.
+ *  - Errors: the return code is the only error channel; no global state
+ *    besides the control block above.  msz_strerror() names a code.  Inputs
+ *    must be finite with magnitude at most 2^100 (so that no edit can
+ *    overflow float32).
  *  - Concurrency: calls on different streams with separate workspaces are
- *    independent.  Calls sharing a workspace must not overlap.
+ *    independent; calls from one host thread run one after another (each
+ *    returns after its device work).  Calls sharing a workspace must not
+ *    overlap.
  */
 #ifndef MSZ_H
 #define MSZ_H
@@ -181,10 +190,12 @@ typedef struct {
 
 /*
  * msz_fix_batch -- corrects n_jobs (<= 1024) independent fields of uneven
- * sizes in ONE persistent kernel launch (a cooperative kernel node of a HIP
- * graph): every grid-wide step advances each unfinished field by one
- * operation of the schedule msz_fix follows, so each field's result is
- * bit-identical to its own msz_fix.  opt->workspace (if given) must hold
+ * sizes together: every device step advances each unfinished field by one
+ * operation of the schedule msz_fix follows (one step kernel per dimension
+ * runs the work items of all fields as one index space; a decide kernel picks
+ * each field's next operation), so each field's result is bit-identical to
+ * its own msz_fix.  The steps run from a HIP graph relaunched until no field
+ * is active.  opt->workspace (if given) must hold
  * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
  * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);
  * opt->max_rounds applies to every field (MSZ_FLAG_TIMING is ignored).

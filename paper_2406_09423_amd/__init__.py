@@ -233,7 +233,7 @@ def count_false(f, g, stream=None) -> dict:
 
 def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles="auto", outs=None,
               stream=None):
-    """Corrects a list of (f, fhat, xi) together in one persistent launch.
+    """Corrects a list of (f, fhat, xi) together in one device-scheduled run (msz_fix_batch).
 
     ``tiles``: each field's direction tile variant, "auto" (the autotuner's
     table, autotune.py) or None (the default tile).  ``outs`` optionally gives
