@@ -28,9 +28,9 @@
  *    graph of 16 steps is launched until no field is active, and one word is
  *    read back per launch.
  *  - Memory: the library allocates scratch per call when no workspace is
- *    given (hipMallocAsync on the stream), and keeps one small control block
- *    (about 0.4 MB: field table, step states, statistics, the cached graph)
- *    per host thread and device for the life of the process.
+ *    given (hipMallocAsync on the stream), and keeps one control block
+ *    (about 9 MB: field table, step states, round counters, statistics, the
+ *    cached graph) per host thread and device for the life of the process.
  *  - Errors: the return code is the only error channel; no global state
  *    besides the control block above.  msz_strerror() names a code.  Inputs
  *    must be finite with magnitude at most 2^100 (so that no edit can

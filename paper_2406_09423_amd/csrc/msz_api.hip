@@ -55,7 +55,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, Mf, mf, qu, qd, cnt, total;
+    size_t L, g, dirs_f, dirs_g, marks, Mf, mf, qu, qd, total;
 };
 
 Layout layout_for(int64_t n) {
@@ -66,7 +66,6 @@ Layout layout_for(int64_t n) {
         o += align256(bytes);
         return r;
     };
-    l.cnt = take(kCntBlockWords * sizeof(unsigned));
     l.L = take(n * 4);
     l.g = take(n * 4);
     l.dirs_f = take(n);
@@ -157,7 +156,8 @@ struct EngineCtx {
     EngState* states = nullptr;
     EngStats* stats = nullptr;
     int *pre2 = nullptr, *pre3 = nullptr, *ctl = nullptr, *oplog = nullptr;
-    unsigned long long* tstamp = nullptr;  // profiling: step starts [0, kGraphSteps), ends after
+    unsigned long long* tstamp = nullptr;  // profiling: kEngStampWords words per step
+    unsigned* counters = nullptr;          // kCntBlockWords per field
     int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog, then 2 * kGraphSteps stamps
     // cached graph
     int g_nf = -1, g_grid2 = 0, g_grid3 = 0;
@@ -176,7 +176,8 @@ struct EngineCtx {
     // down, and the device memory (about 0.4 MB per host thread) is reclaimed
     // with the process.
 
-    static size_t host_bytes() { return 256 + sizeof(unsigned long long) * 2 * kGraphSteps; }
+    static size_t host_bytes() { return 256 + stamp_bytes(); }
+    static size_t stamp_bytes() { return sizeof(unsigned long long) * kEngStampWords * kGraphSteps; }
     unsigned long long* host_stamps() const { return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(host) + 256); }
 
     int init(int dev) {
@@ -197,7 +198,8 @@ struct EngineCtx {
         const size_t op3 = take(sizeof(int) * (kEngMaxFields + 1));
         const size_t oc = take(sizeof(int) * 4);
         const size_t ol = take(sizeof(int) * kGraphSteps);
-        const size_t ot = take(sizeof(unsigned long long) * 2 * kGraphSteps);
+        const size_t ot = take(stamp_bytes());
+        const size_t oc2 = take(sizeof(unsigned) * kCntBlockWords * kEngMaxFields);
         void* p = nullptr;
         if (hipMalloc(&p, o) != hipSuccess) return MSZ_ENOMEM;
         ctl_mem = static_cast<char*>(p);
@@ -209,6 +211,7 @@ struct EngineCtx {
         ctl = reinterpret_cast<int*>(ctl_mem + oc);
         oplog = reinterpret_cast<int*>(ctl_mem + ol);
         tstamp = reinterpret_cast<unsigned long long*>(ctl_mem + ot);
+        counters = reinterpret_cast<unsigned*>(ctl_mem + oc2);
         if (!host) {
             void* h = nullptr;
             if (hipHostMalloc(&h, host_bytes(), hipHostMallocDefault) != hipSuccess)
@@ -244,7 +247,7 @@ struct EngineCtx {
             const int par = st & 1;
             EngState* cur = states + par * nf;
             EngState* nxt = states + (par ^ 1) * nf;
-            unsigned long long* ts = timing ? tstamp + st : nullptr;
+            unsigned long long* ts = timing ? tstamp + st * kEngStampWords : nullptr;
             if (has2) {
                 void* a[] = {&fields, &cur, &pre2, &nf, &ts};
                 if (!add_kernel(eng_step_kernel(2), dim3(grid2), dim3(256), a)) return MSZ_EDEVICE;
@@ -255,7 +258,7 @@ struct EngineCtx {
             }
             int* log = timing ? oplog : nullptr;
             int stp = st;
-            void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp};
+            void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp, &counters};
             if (!add_kernel(eng_decide_kernel(), dim3(nf), dim3(256), d)) return MSZ_EDEVICE;
             if (nf > 1) {
                 void* c[] = {&fields, &nxt, &nf, &pre2, &pre3, &ctl};
@@ -344,6 +347,7 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     }
     timing = timing && nf == 1;
     if (timing) last_schedule().clear();
+    for (int j = 0; j < nf; ++j) hf[j].cnt = E.counters + static_cast<size_t>(j) * kCntBlockWords;
     if (int rc = E.graph_for(nf, has2, has3, timing, grid2, grid3)) {
         E.drop_graph();
         return rc;
@@ -367,28 +371,29 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     int wall_khz = 0;
     if (timing && (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0))
         return MSZ_EDEVICE;
-    const size_t half = sizeof(unsigned long long) * kGraphSteps;
     int64_t steps = 0;
     int rc = MSZ_OK;
     for (;;) {
-        if (timing && (hipMemsetAsync(E.tstamp, 0xFF, half, s) != hipSuccess ||
-                       hipMemsetAsync(E.tstamp + kGraphSteps, 0, half, s) != hipSuccess)) { rc = MSZ_EDEVICE; break; }
+        if (timing && hipMemsetAsync(E.tstamp, 0, EngineCtx::stamp_bytes(), s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (hipGraphLaunch(E.exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (hipMemcpyAsync(E.host, E.ctl, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (timing && (hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) !=
                            hipSuccess ||
-                       hipMemcpyAsync(E.host_stamps(), E.tstamp, 2 * half, hipMemcpyDeviceToHost, s) != hipSuccess)) {
+                       hipMemcpyAsync(E.host_stamps(), E.tstamp, EngineCtx::stamp_bytes(), hipMemcpyDeviceToHost, s) !=
+                           hipSuccess)) {
             rc = MSZ_EDEVICE;
             break;
         }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (timing) {
-            const unsigned long long* t = E.host_stamps();
             for (int k = 0; k < kGraphSteps; ++k) {
                 const int ph = phase_of_op(E.host[1 + k]);
                 last_schedule().push_back(ph);
-                if (ph >= 0 && t[kGraphSteps + k] >= t[k]) {
-                    ms[ph] += static_cast<double>(t[kGraphSteps + k] - t[k]) / wall_khz;
+                const unsigned long long* t = E.host_stamps() + k * kEngStampWords;
+                unsigned long long end = 0;
+                for (int w = 1; w < kEngStampWords; ++w) end = std::max(end, t[w]);
+                if (ph >= 0 && end >= t[0]) {
+                    ms[ph] += static_cast<double>(end - t[0]) / wall_khz;
                     launches[ph] += 1;
                 }
             }
@@ -409,7 +414,6 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
 
 void bind_field(EngField& F, char* w, int n) {
     const Layout l = layout_for(n);
-    F.cnt = reinterpret_cast<unsigned*>(w + l.cnt);
     F.L = reinterpret_cast<float*>(w + l.L);
     F.g = reinterpret_cast<float*>(w + l.g);
     F.dirs_f = reinterpret_cast<uint8_t*>(w + l.dirs_f);

@@ -143,6 +143,7 @@ namespace msz {
 // k_eng_scan sums the next step's items (see the engine in msz_kernels.hip).
 constexpr int kEngMaxFields = 1024;
 constexpr int kEngTimeSlots = 16;                   // steps per graph launch (profiling stamps per launch)
+constexpr int kEngStampWords = 65;                  // per timed step: start, then 64 slots of block ends
 constexpr int kEngChunk = 4096;                     // vertices per flat work item
 
 enum EngOp : int {
@@ -174,7 +175,7 @@ struct EngField {
     float *L, *g;
     uint8_t *dirs_f, *dirs_g, *marks;
     int *Mf, *mf, *qu, *qd;
-    unsigned* cnt;  // kCntBlockWords words (kSlots slots)
+    unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
 
 struct EngState {
@@ -189,7 +190,7 @@ struct EngStats {
 // Number of work items of operation op for one field (device and host).
 int eng_items_host(const EngField& F, int op);
 const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
-const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step)
+const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)
 const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl)
 const void* eng_init_kernel();          // k_eng_init(fields, nf)
 

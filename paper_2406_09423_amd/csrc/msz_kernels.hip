@@ -1466,18 +1466,21 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
     }
 }
 
-// ts (optional, profiling): ts[0] receives the start of block 0 and
-// ts[kEngTimeSlots] the latest block end, both from the constant-rate GPU clock.
+// ts (optional, profiling; kEngStampWords zeroed words): block 0 stores its
+// start in ts[0]; every block raises ts[1 + blockIdx % 64] to its end.  Both
+// come from the constant-rate GPU clock; 64 end slots keep the atomics from
+// queueing on one address.
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
                                                   const int* pre, int nf, unsigned long long* ts) {
     __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
     static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
-    if (ts && blockIdx.x == 0 && threadIdx.x == 0) atomicMin(ts, static_cast<unsigned long long>(wall_clock64()));
+    if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = static_cast<unsigned long long>(wall_clock64());
     eng_step_body<NDIM>(fields, cur, pre, nf, smem);
     if (ts) {
         __syncthreads();
-        if (threadIdx.x == 0) atomicMax(ts + kEngTimeSlots, static_cast<unsigned long long>(wall_clock64()));
+        if (threadIdx.x == 0)
+            atomicMax(ts + 1 + blockIdx.x % (kEngStampWords - 1), static_cast<unsigned long long>(wall_clock64()));
     }
 }
 
@@ -1570,33 +1573,35 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, cons
 }
 
 // Block f decides field f: the 256 threads reduce the field's counter block
-// (kSlots slots of kCntSlots counters), clear it, and thread 0 writes the next
-// state.  With one field (single) it also writes the next prefix sums, the
+// (kSlots slots of kCntSlots counters, at cnt_all + f * kCntBlockWords), clear
+// it, and thread 0 writes the next state.  Every load (state, counters,
+// statistics) is issued before any is used, so a decision costs one memory
+// round trip.  With one field it also writes the next prefix sums, the
 // active count and, if oplog is set, the operation this step ran.
 __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__ fields, const EngState* cur,
                                                     EngState* nxt, EngStats* stats, int nf, int* pre2, int* pre3,
-                                                    int* ctl, int* oplog, int step) {
+                                                    int* ctl, int* oplog, int step, unsigned* cnt_all) {
     __shared__ unsigned part[256];
     __shared__ unsigned red[kCntSlots];
     const int f = blockIdx.x;
+    unsigned* cnt = cnt_all + static_cast<long>(f) * kCntBlockWords;
+    // thread t sums counter (t % 16) over the slots t / 16, t / 16 + 16, ...
+    const int k = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
+    constexpr int PER = kSlots / (256 / kCntSlots);
+    unsigned v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k];
     const EngState st = cur[f];
+    EngStats S;
+    if (threadIdx.x == 0) S = stats[f];
     if (nf == 1 && oplog && threadIdx.x == 0) oplog[step] = st.items > 0 ? st.op : kOpDone;
     EngState ns = st;
     if (st.items > 0) {
-        const EngField& F = fields[f];
-        // thread t sums counter (t % 16) over the slots t / 16, t / 16 + 16, ...
-        const int k = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
         unsigned acc = 0;
-        // the step kernel's counter atomics completed with that kernel: plain
-        // loads see them; all loads are issued before the clearing stores
-        constexpr int PER = kSlots / (256 / kCntSlots);
-        unsigned v[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) v[q] = F.cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             acc = k == kCntErr ? (acc | v[q]) : acc + v[q];
-            F.cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k] = 0u;
+            cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k] = 0u;
         }
         part[threadIdx.x] = acc;
         __syncthreads();
@@ -1609,7 +1614,8 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
         if (threadIdx.x == 0) {
             unsigned c[kCntSlots];
             for (int j = 0; j < kCntSlots; ++j) c[j] = red[j];
-            ns = eng_decide(F, st, stats + f, c);
+            ns = eng_decide(fields[f], st, &S, c);
+            stats[f] = S;
         }
     }
     if (threadIdx.x == 0) {
