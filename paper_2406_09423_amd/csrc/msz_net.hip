@@ -66,6 +66,31 @@ __device__ __forceinline__ float weight_at(const WeightView& wv, int tap, int in
     return wv.W[t * wv.s_tap + in * wv.s_in + out * wv.s_out];
 }
 
+// Loads the input tile t (16 x TY x TZ vertices plus a one-vertex halo, CH16
+// 16-byte chunks per vertex, zeros outside the grid) into registers.
+template <int TY, int TZ, int CH16, int PER>
+__device__ __forceinline__ void conv_tile_load(const uint16_t* __restrict__ in, const Grid& gr, int t, int tx_n,
+                                               int ty_n, uint4 (&buf)[PER]) {
+    using T = ConvTile<TY, TZ>;
+    constexpr int NCH = T::HALO * CH16;
+    const int X0 = (t % tx_n) * T::X, Y0 = ((t / tx_n) % ty_n) * T::Y, Z0 = (t / (tx_n * ty_n)) * T::Z;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (e < NCH) {
+            const int hv = e / CH16, ch = e - hv * CH16;
+            const int hx = hv % T::HX, hy = (hv / T::HX) % T::HY, hz = hv / (T::HX * T::HY);
+            const int x = X0 + hx - 1, y = Y0 + hy - 1, z = Z0 + hz - 1;
+            if (x >= 0 && x < gr.nx && y >= 0 && y < gr.ny && z >= 0 && z < gr.nz) {
+                const long vid = x + static_cast<long>(gr.nx) * y + static_cast<long>(gr.nxy) * z;
+                v = reinterpret_cast<const uint4*>(in)[vid * CH16 + ch];
+            }
+        }
+        buf[k] = v;
+    }
+}
+
 enum : int { kConvHidden = 0, kConvFinal = 1, kConvBackData = 2 };
 
 // out = conv(in) for CIN input channels stored per vertex.
@@ -111,27 +136,14 @@ __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ in, G
     const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y, tz_n = (gr.nz + T::Z - 1) / T::Z;
     const int ntiles = tx_n * ty_n * tz_n;
     const ItemRange range = xcd_items(ntiles);
+    // the input tile (with halo) of the next tile is loaded into registers
+    // while the current one is computed from LDS
+    constexpr int NCH = T::HALO * CH16;
+    constexpr int PER = (NCH + 255) / 256;
+    uint4 buf[PER];
+    if (range.first < range.hi) conv_tile_load<TY, TZ, CH16, PER>(in, gr, range.first, tx_n, ty_n, buf);
     for (int t = range.first; t < range.hi; t += range.stride) {
         const int X0 = (t % tx_n) * T::X, Y0 = ((t / tx_n) % ty_n) * T::Y, Z0 = (t / (tx_n * ty_n)) * T::Z;
-        // stage the input tile with its halo (zeros outside the grid), loads batched per thread
-        constexpr int NCH = T::HALO * CH16;
-        constexpr int PER = (NCH + 255) / 256;
-        uint4 buf[PER];
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int e = threadIdx.x + 256 * k;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (e < NCH) {
-                const int hv = e / CH16, ch = e - hv * CH16;
-                const int hx = hv % T::HX, hy = (hv / T::HX) % T::HY, hz = hv / (T::HX * T::HY);
-                const int x = X0 + hx - 1, y = Y0 + hy - 1, z = Z0 + hz - 1;
-                if (x >= 0 && x < gr.nx && y >= 0 && y < gr.ny && z >= 0 && z < gr.nz) {
-                    const long vid = x + static_cast<long>(gr.nx) * y + static_cast<long>(gr.nxy) * z;
-                    v = reinterpret_cast<const uint4*>(in)[vid * CH16 + ch];
-                }
-            }
-            buf[k] = v;
-        }
         __syncthreads();  // the previous tile's reads are done
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
@@ -139,6 +151,7 @@ __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ in, G
             if (e < NCH) tile[e] = buf[k];
         }
         __syncthreads();
+        if (t + range.stride < range.hi) conv_tile_load<TY, TZ, CH16, PER>(in, gr, t + range.stride, tx_n, ty_n, buf);
 
         for (int row = wave; row < T::ROWS; row += 4) {
             const int ly = row % T::Y, lz = row / T::Y;
@@ -181,6 +194,90 @@ __global__ void __launch_bounds__(256) k_conv(const uint16_t* __restrict__ in, G
                 pk.x = static_cast<unsigned>(o[0]) | (static_cast<unsigned>(o[1]) << 16);
                 pk.y = static_cast<unsigned>(o[2]) | (static_cast<unsigned>(o[3]) << 16);
                 reinterpret_cast<uint2*>(out16)[vid * 4 + g] = pk;
+            }
+        }
+    }
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// The output layer (16 -> 1 channels) with packed BF16 dot products on the
+// VALU (v_dot2 accumulates two products into an FP32 sum): on the 16x16 MFMA
+// tile it would use one of 16 output rows.  Same tile and halo staging as
+// k_conv; a thread computes OPT x-consecutive outputs of one row, reading the
+// OPT + 2 input columns of each (dy, dz) once.
+template <int TY, int TZ>
+__global__ void __launch_bounds__(256) k_conv_out(const uint16_t* __restrict__ in, Grid gr,
+                                                  const float* __restrict__ W2, const float* __restrict__ b2,
+                                                  float* __restrict__ out1) {
+    using T = ConvTile<TY, TZ>;
+    constexpr int CH16 = 2;
+    constexpr int OPT = 16 * T::ROWS / 256;  // outputs per thread: 4 for 8 x 8 rows, 2 for 32 x 1
+    constexpr int GX = 16 / OPT;             // threads per row
+    static_assert(OPT * 256 == 16 * T::ROWS, "every output has one thread");
+    __shared__ uint4 tile[T::HALO * CH16];
+    __shared__ unsigned wpk[27 * 8];  // BF16 weight pairs (channels 2p, 2p + 1) of every tap
+    for (int e = threadIdx.x; e < 27 * 8; e += 256) {
+        const int tap = e / 8, q = e % 8;
+        wpk[e] = static_cast<unsigned>(bf16_bits(W2[tap * 16 + 2 * q])) |
+                 (static_cast<unsigned>(bf16_bits(W2[tap * 16 + 2 * q + 1])) << 16);
+    }
+    const float bias = b2[0];
+    const int xg = threadIdx.x % GX, row = threadIdx.x / GX;
+    const int ly = row % T::Y, lz = row / T::Y;
+
+    const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y, tz_n = (gr.nz + T::Z - 1) / T::Z;
+    const ItemRange range = xcd_items(tx_n * ty_n * tz_n);
+    constexpr int NCH = T::HALO * CH16;
+    constexpr int PER = (NCH + 255) / 256;
+    uint4 buf[PER];
+    if (range.first < range.hi) conv_tile_load<TY, TZ, CH16, PER>(in, gr, range.first, tx_n, ty_n, buf);
+    for (int t = range.first; t < range.hi; t += range.stride) {
+        const int X0 = (t % tx_n) * T::X, Y0 = ((t / tx_n) % ty_n) * T::Y, Z0 = (t / (tx_n * ty_n)) * T::Z;
+        __syncthreads();  // the previous tile's reads (and the weight packing) are done
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + 256 * k;
+            if (e < NCH) tile[e] = buf[k];
+        }
+        __syncthreads();
+        if (t + range.stride < range.hi) conv_tile_load<TY, TZ, CH16, PER>(in, gr, t + range.stride, tx_n, ty_n, buf);
+        float acc[OPT];
+#pragma unroll
+        for (int i = 0; i < OPT; ++i) acc[i] = bias;
+        // one (dy, dz) row group at a time keeps OPT + 2 columns live
+#pragma unroll 1
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll 1
+            for (int dy = -1; dy <= 1; ++dy) {
+                unsigned col[OPT + 2][8];
+#pragma unroll
+                for (int c = 0; c < OPT + 2; ++c) {
+                    const int hv = (xg * OPT + c) + T::HX * ((ly + dy + 1) + T::HY * (lz + dz + 1));
+                    const uint4 u0 = tile[hv * CH16], u1 = tile[hv * CH16 + 1];
+                    col[c][0] = u0.x, col[c][1] = u0.y, col[c][2] = u0.z, col[c][3] = u0.w;
+                    col[c][4] = u1.x, col[c][5] = u1.y, col[c][6] = u1.z, col[c][7] = u1.w;
+                }
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int tap = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    unsigned w[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) w[q] = wpk[tap * 8 + q];
+#pragma unroll
+                    for (int i = 0; i < OPT; ++i)
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            acc[i] = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, col[i + dx + 1][q]),
+                                                                     __builtin_bit_cast(bf16x2, w[q]), acc[i], false);
+                }
+            }
+        const int y = Y0 + ly, z = Z0 + lz;
+        if (y < gr.ny && z < gr.nz) {
+#pragma unroll
+            for (int i = 0; i < OPT; ++i) {
+                const int x = X0 + xg * OPT + i;
+                if (x < gr.nx) out1[x + static_cast<long>(gr.nx) * y + static_cast<long>(gr.nxy) * z] = acc[i];
             }
         }
     }
@@ -585,7 +682,17 @@ void net_forward(const float* P, const uint16_t* feat, const Grid& gr, uint16_t*
                  hipStream_t s) {
     launch_conv_t<16, kConvHidden>(feat, gr, layer_view(P, 0), nullptr, a1, nullptr, s);
     launch_conv_t<16, kConvHidden>(a1, gr, layer_view(P, 1), nullptr, a2, nullptr, s);
-    launch_conv_t<16, kConvFinal>(a2, gr, layer_view(P, 2), nullptr, nullptr, p, s);
+    if (gr.nz == 1) {
+        using T = ConvTile<32, 1>;
+        const int nt = ((gr.nx + 15) / 16) * ((gr.ny + T::Y - 1) / T::Y);
+        hipLaunchKernelGGL((k_conv_out<32, 1>), dim3(nt < kConvBlocks ? nt : kConvBlocks), dim3(256), 0, s, a2, gr,
+                           P + kOffW2, P + kOffB2, p);
+    } else {
+        using T = ConvTile<8, 8>;
+        const int nt = ((gr.nx + 15) / 16) * ((gr.ny + T::Y - 1) / T::Y) * ((gr.nz + T::Z - 1) / T::Z);
+        hipLaunchKernelGGL((k_conv_out<8, 8>), dim3(nt < kConvBlocks ? nt : kConvBlocks), dim3(256), 0, s, a2, gr,
+                           P + kOffW2, P + kOffB2, p);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_minmax(const float* __restrict__ f, int n, float* __restrict__ out) {
