@@ -243,7 +243,18 @@ struct EngineCtx {
             chain(n);
             return true;
         };
-        for (int st = 0; st < kGraphSteps; ++st) {
+        if (nf == 1) {  // one field: one step kernel per step, deciding for itself
+            const void* fn = eng_step1_kernel(has3 ? 3 : 2);
+            const int grid = has3 ? grid3 : grid2;
+            for (int st = 0; st < kGraphSteps; ++st) {
+                unsigned long long* ts = timing ? tstamp + st * kEngStampWords : nullptr;
+                int* log = timing ? oplog : nullptr;
+                int stp = st;
+                void* a[] = {&fields, &states, &stats, &counters, &ctl, &log, &stp, &ts};
+                if (!add_kernel(fn, dim3(grid), dim3(256), a)) return MSZ_EDEVICE;
+            }
+        }
+        for (int st = 0; nf > 1 && st < kGraphSteps; ++st) {
             const int par = st & 1;
             EngState* cur = states + par * nf;
             EngState* nxt = states + (par ^ 1) * nf;
@@ -298,19 +309,21 @@ int phase_of_op(int op) {
 }
 
 // Step-kernel grid of one dimension: the blocks that fit on the device at once.
-int step_grid(int dev, int ndim) {
-    thread_local int cached_dev = -1, cached[2] = {0, 0};
+// (single: the one-field step kernel.)
+int step_grid(int dev, int ndim, bool single) {
+    thread_local int cached_dev = -1, cached[4] = {0, 0, 0, 0};
     if (cached_dev != dev) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 0;
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 4; ++k) {
             int b = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, eng_step_kernel(2 + k), 256, 0) != hipSuccess) return 0;
+            const void* fn = k < 2 ? eng_step_kernel(2 + k) : eng_step1_kernel(k);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, 256, 0) != hipSuccess) return 0;
             cached[k] = cus * std::max(1, b);
         }
         cached_dev = dev;
     }
-    return cached[ndim == 3 ? 1 : 0];
+    return cached[(single ? 2 : 0) + (ndim == 3 ? 1 : 0)];
 }
 
 // Schedule of the calling thread's last timed single-field run: the phase of
@@ -330,7 +343,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     MSZ_HIP(hipGetDevice(&dev));
     EngineCtx& E = engine_ctx();
     if (int rc = E.init(dev)) return rc;
-    const int grid2 = step_grid(dev, 2), grid3 = step_grid(dev, 3);
+    const bool single = nf == 1;
+    const int grid2 = step_grid(dev, 2, single), grid3 = step_grid(dev, 3, single);
     if (grid2 < 1 || grid3 < 1) return MSZ_EDEVICE;
     bool has2 = false, has3 = false;
     std::vector<EngState> hs(2 * nf);
@@ -352,13 +366,18 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         E.drop_graph();
         return rc;
     }
+    if (single) {  // the step kernel decides from "step -1": state Start, zero counters
+        hs[0] = EngState{kOpDone, 0, 0, 0};
+        hs[1] = EngState{kOpStart, 0, 1, 0};
+        MSZ_HIP(hipMemsetAsync(E.counters, 0, sizeof(unsigned) * 3 * kCntBlockWords, s));
+    }
     const int one = 1;
     MSZ_HIP(hipMemcpyAsync(E.fields, hf.data(), sizeof(EngField) * nf, hipMemcpyHostToDevice, s));
     MSZ_HIP(hipMemcpyAsync(E.states, hs.data(), sizeof(EngState) * 2 * nf, hipMemcpyHostToDevice, s));
     MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
     MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
     MSZ_HIP(hipMemcpyAsync(E.ctl, &one, sizeof(int), hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * nf, s));
+    MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * std::max(nf, 3), s));
     int total = 0;
     for (const EngField& F : hf) total = std::max(total, (F.gr.n + 15) >> 4);
     {
@@ -407,7 +426,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         return rc;
     }
     st.resize(nf);
-    MSZ_HIP(hipMemcpyAsync(st.data(), E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
+    // one field: the statistics the step kernel stored when the field was done
+    MSZ_HIP(hipMemcpyAsync(st.data(), single ? E.stats + 2 : E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
     MSZ_HIP(hipStreamSynchronize(s));
     return MSZ_OK;
 }

@@ -142,7 +142,7 @@ namespace msz {
 // current operation of every field, k_eng_decide picks each field's next one,
 // k_eng_scan sums the next step's items (see the engine in msz_kernels.hip).
 constexpr int kEngMaxFields = 1024;
-constexpr int kEngTimeSlots = 16;                   // steps per graph launch (profiling stamps per launch)
+constexpr int kEngTimeSlots = 48;                   // steps per graph launch (a multiple of 2 and 3)
 constexpr int kEngStampWords = 65;                  // per timed step: start, then 64 slots of block ends
 constexpr int kEngChunk = 4096;                     // vertices per flat work item
 
@@ -162,7 +162,8 @@ enum EngOp : int {
     kOpApplyR,     // R-loop apply
     kOpDdR,        // directions/detection of g (type 0) after an R apply
     kOpDelta,      // output
-    kOpDone
+    kOpDone,
+    kOpStart       // before the first step (its successor is kOpPreA)
 };
 
 struct EngField {
@@ -193,5 +194,6 @@ const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)
 const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl)
 const void* eng_init_kernel();          // k_eng_init(fields, nf)
+const void* eng_step1_kernel(int ndim); // k_eng_step1<ndim>(fields, states, stats, cnt3, ctl, oplog, k, ts)
 
 }  // namespace msz

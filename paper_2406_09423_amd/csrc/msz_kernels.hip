@@ -1303,13 +1303,13 @@ __device__ __forceinline__ void eng_dirs(const EngField& F, const float* h, uint
 // hi uniform over the block) and adds the block's counts to the field's
 // counter block.
 template <int NDIM>
-__device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem) {
+__device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem,
+                                              unsigned* cnt) {
     const Grid& gr = F.gr;
     int* su = reinterpret_cast<int*>(smem);
     int* sd = su + 4096;
     float* sm = reinterpret_cast<float*>(smem);
     const int cidx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
-    unsigned* cnt = F.cnt;
     switch (st.op) {
         case kOpPreA: {
             unsigned bad = 0;
@@ -1442,7 +1442,7 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
         const int per = (total + nb - 1) / nb;
         const int lo = b * per, hi = min(total, lo + per);
-        if (lo < hi) eng_run_range<NDIM>(fields[0], st, lo, hi, smem);
+        if (lo < hi) eng_run_range<NDIM>(fields[0], st, lo, hi, smem, fields[0].cnt);
         return;
     }
     const int total = pre[nf];
@@ -1461,7 +1461,7 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         const int base = pre[a];
         const int end = min(hi, pre[a + 1]);
         const EngState st = cur[a];
-        eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem);
+        eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem, fields[a].cnt);
         lo = end;
     }
 }
@@ -1486,7 +1486,8 @@ __global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ f
 
 // The schedule (the host loop of a single correction, step by step): the next
 // state of one field from the counters of its finished step.
-__device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, const unsigned (&c)[kCntSlots]) {
+__device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, EngStats* S,
+                                                const unsigned (&c)[kCntSlots]) {
     auto go = [&](int op) {
         st.op = op;
         st.items = eng_items(F, op);
@@ -1500,8 +1501,13 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, cons
         S->status = status;
         return go(kOpDone);
     };
+    // counts and round tallies of the current type, by selects (no dynamic
+    // indexing of local arrays, which would go to private memory)
+    auto cases_of = [&](int t) {
+        return t == 0 ? c[kCntCase + 0] : t == 1 ? c[kCntCase + 1] : t == 2 ? c[kCntCase + 2] : c[kCntCase + 3];
+    };
     auto c_decide = [&]() {
-        if (c[kCntCase + st.type] > 0) return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
+        if (cases_of(st.type) > 0) return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
         if (st.type < 3) {
             st.type += 1;
             return go(kOpDetect);
@@ -1513,6 +1519,8 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, cons
         return go(kOpRTile);
     };
     switch (st.op) {
+        case kOpStart:
+            return go(kOpPreA);
         case kOpPreA:
             if (c[kCntErr] & kErrNonFinite) return stop(MSZ_ENONFINITE);
             if (c[kCntErr] & kErrBound) return stop(MSZ_EBOUND);
@@ -1540,7 +1548,10 @@ __device__ EngState eng_decide(const EngField& F, EngState st, EngStats* S, cons
         case kOpApplyC:
             if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
             S->rounds_total += 1;
-            S->rounds[st.type] += 1;
+            if (st.type == 0) S->rounds[0] += 1;
+            else if (st.type == 1) S->rounds[1] += 1;
+            else if (st.type == 2) S->rounds[2] += 1;
+            else S->rounds[3] += 1;
             return go(kOpDdC);
         case kOpRTile:
             return go(kOpRJump);
@@ -1631,6 +1642,86 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
     }
 }
 
+// One field, one kernel per step: every block takes the schedule decision
+// itself (the same one: the same inputs, the same arithmetic) from the state
+// and statistics of step k - 1 and the counters that step left, then runs its
+// range of the chosen operation.  Buffers by step: states and stats by k % 2
+// (a step reads k - 1's and block 0 writes k's); counter sets by k % 3 (a step
+// reads set k - 1, adds into set k and clears set k + 1, which step k - 1
+// read and step k + 1 fills).  stats[2] receives the statistics once the
+// field is done.  A graph holds kEngTimeSlots (a multiple of 6) steps, so the
+// parities continue across launches.
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ fields, EngState* states,
+                                                   EngStats* stats, unsigned* cnt3, int* ctl, int* oplog, int k,
+                                                   unsigned long long* ts) {
+    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    __shared__ unsigned part[256];
+    __shared__ unsigned red[kCntSlots];
+    __shared__ EngState s_next;
+    __shared__ EngStats s_stats;
+    static_assert(kEngTimeSlots % 6 == 0, "parities of 2 and 3 continue across graph launches");
+    static_assert(sizeof(EngStats) % 4 == 0 && sizeof(EngStats) / 4 <= 256, "statistics copied word by word");
+    if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = static_cast<unsigned long long>(wall_clock64());
+    const int p = k & 1;
+    unsigned* c_prev = cnt3 + ((k + 2) % 3) * kCntBlockWords;
+    unsigned* c_cur = cnt3 + (k % 3) * kCntBlockWords;
+    unsigned* c_next = cnt3 + ((k + 1) % 3) * kCntBlockWords;
+    // all loads first: the counters of step k - 1, its state and statistics
+    const int kc = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
+    constexpr int PER = kSlots / (256 / kCntSlots);
+    unsigned v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = c_prev[(s0 + q * (256 / kCntSlots)) * kSlotStride + kc];
+    const EngState prev = states[p ^ 1];
+    constexpr int SW = sizeof(EngStats) / 4;
+    if (threadIdx.x < SW)  // the statistics of step k - 1, word by word into LDS
+        reinterpret_cast<unsigned*>(&s_stats)[threadIdx.x] = reinterpret_cast<const unsigned*>(stats + (p ^ 1))[threadIdx.x];
+    unsigned acc = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) acc = kc == kCntErr ? (acc | v[q]) : acc + v[q];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < kCntSlots) {
+        unsigned a = 0;
+        for (int j = threadIdx.x; j < 256; j += kCntSlots) a = threadIdx.x == kCntErr ? (a | part[j]) : a + part[j];
+        red[threadIdx.x] = a;
+    }
+    __syncthreads();
+    const EngField& F = fields[0];
+    if (threadIdx.x == 0) {
+        EngState ns = prev;
+        if (prev.items > 0 || prev.op == kOpStart) {
+            unsigned c[kCntSlots];
+            for (int j = 0; j < kCntSlots; ++j) c[j] = red[j];
+            ns = eng_decide(F, prev, &s_stats, c);
+        }
+        s_next = ns;
+        if (blockIdx.x == 0) {
+            states[p] = ns;
+            stats[p] = s_stats;
+            if (ns.items == 0) stats[2] = s_stats;
+            ctl[0] = ns.items > 0 ? 1 : 0;
+            if (oplog) oplog[k] = ns.items > 0 ? ns.op : kOpDone;
+        }
+    }
+    // clear the counter set of step k + 1 (read by step k - 1, filled by step k + 1)
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < kCntBlockWords; w += gridDim.x * blockDim.x) c_next[w] = 0u;
+    __syncthreads();
+    const EngState st = s_next;
+    if (st.items > 0) {
+        const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
+        const int per = (st.items + nb - 1) / nb;
+        const int lo = b * per, hi = min(st.items, lo + per);
+        if (lo < hi) eng_run_range<NDIM>(F, st, lo, hi, smem, c_cur);
+    }
+    if (ts) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+            atomicMax(ts + 1 + blockIdx.x % (kEngStampWords - 1), static_cast<unsigned long long>(wall_clock64()));
+    }
+}
+
 // Prefix sums of the next step's items per dimension, and the active count
 // (one block of kEngMaxFields threads, one field each).
 __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
@@ -1680,6 +1771,9 @@ const void* eng_step_kernel(int ndim) {
     return ndim == 3 ? reinterpret_cast<const void*>(&k_eng_step<3>) : reinterpret_cast<const void*>(&k_eng_step<2>);
 }
 const void* eng_decide_kernel() { return reinterpret_cast<const void*>(&k_eng_decide); }
+const void* eng_step1_kernel(int ndim) {
+    return ndim == 3 ? reinterpret_cast<const void*>(&k_eng_step1<3>) : reinterpret_cast<const void*>(&k_eng_step1<2>);
+}
 const void* eng_scan_kernel() { return reinterpret_cast<const void*>(&k_eng_scan); }
 const void* eng_init_kernel() { return reinterpret_cast<const void*>(&k_eng_init); }
 
