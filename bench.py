@@ -35,10 +35,10 @@ CALIB_BYTES = 1 << 30   # bytes read (and written) by the calibration copy
 
 # Algorithmic (compulsory) HBM bytes per vertex of each kernel kind, per launch.
 BYTES_PER_VERTEX = {
-    "dirs_detect": 4 + 1 + 1,   # read g, read dirs_f, write dirs_g (targets are sparse)
+    "dirs_detect": 4 + 1 + 1 + 1 + 2,  # read g, dirs_f; write dirs_g, case bytes; clear dirty flags and marks
     "dirs": 4 + 1,              # read the field, write dirs
-    "detect": 1 + 1,            # read dirs_f and dirs_g
-    "apply": 1,                 # read the marks (edited vertices are sparse)
+    "refresh": 1,               # read the dirty flags (the refreshed vertices are sparse)
+    "apply": 1,                 # read the case bytes or marks (edited vertices are sparse)
     "label_tile": 1 + 8,        # read dirs, write both pointer arrays
     "label_jump": 0,            # touches only the tiles' face layers
     "detect_r": 2 + 8 + 8 + 8,  # dirs x2, pointers x2, pointer-of-pointer x2, labels of f x2

@@ -25,7 +25,7 @@
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  *    stream).  All work is enqueued on it; each call synchronises on it
  *    before returning.  The schedule of the loop runs on the device: a HIP
- *    graph of 16 steps is launched until no field is active, and one word is
+ *    graph of 48 steps is launched until no field is active, and one word is
  *    read back per launch.
  *  - Memory: the library allocates scratch per call when no workspace is
  *    given (hipMallocAsync on the stream), and keeps one control block
@@ -68,9 +68,9 @@ enum {
 enum {
     MSZ_PHASE_VALIDATE = 0,     /* input contract, floors L, start field */
     MSZ_PHASE_DIRS = 1,         /* steepest directions of f */
-    MSZ_PHASE_DIRS_DETECT = 2,  /* directions of g fused with C-loop detection */
-    MSZ_PHASE_DETECT = 3,       /* C-loop detection from stored directions */
-    MSZ_PHASE_APPLY = 4,        /* halving of the round's targets */
+    MSZ_PHASE_DIRS_DETECT = 2,  /* directions and case bytes of every vertex of g */
+    MSZ_PHASE_REFRESH = 3,      /* directions and case bytes around the last edits */
+    MSZ_PHASE_APPLY = 4,        /* halving of the round's targets (from case bytes or marks) */
     MSZ_PHASE_LABEL_TILE = 5,   /* in-LDS pointer jumping per tile */
     MSZ_PHASE_LABEL_JUMP = 6,   /* pointer compression of tile-face vertices */
     MSZ_PHASE_LABEL_FINAL = 7,  /* labels of f */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmsz.so")
 
 OK, EINVAL, ENONFINITE, EBOUND, ESTALL, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
 CASE_NAMES = ("fp_max", "fp_min", "fn_max", "fn_min")
-PHASES = ("validate", "dirs", "dirs_detect", "detect", "apply", "label_tile", "label_jump",
+PHASES = ("validate", "dirs", "dirs_detect", "refresh", "apply", "label_tile", "label_jump",
           "label_final", "detect_r", "delta", "net")
 NET_PARAMS = 14289
 NET_FEATURES = 16

@@ -55,7 +55,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, Mf, mf, qu, qd, total;
+    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, Mf, mf, qu, qd, total;
 };
 
 Layout layout_for(int64_t n) {
@@ -71,6 +71,8 @@ Layout layout_for(int64_t n) {
     l.dirs_f = take(n);
     l.dirs_g = take(n);
     l.marks = take((n + 15) & ~int64_t(15));
+    l.cases = take((n + 15) & ~int64_t(15));
+    l.dirty = take((n + 15) & ~int64_t(15));
     l.Mf = take(n * 4);
     l.mf = take(n * 4);
     l.qu = take(n * 4);
@@ -300,8 +302,8 @@ int phase_of_op(int op) {
         case kOpPreC: case kOpRJump: return MSZ_PHASE_LABEL_JUMP;
         case kOpPreD: return MSZ_PHASE_LABEL_FINAL;
         case kOpApplyC: case kOpApplyR: return MSZ_PHASE_APPLY;
-        case kOpPreE: case kOpDdC: case kOpDdR: return MSZ_PHASE_DIRS_DETECT;
-        case kOpDetect: return MSZ_PHASE_DETECT;
+        case kOpPreE: case kOpFullC: case kOpFullR: return MSZ_PHASE_DIRS_DETECT;
+        case kOpRefreshC: case kOpRefreshR: return MSZ_PHASE_REFRESH;
         case kOpRDetect: return MSZ_PHASE_DETECT_R;
         case kOpDelta: return MSZ_PHASE_DELTA;
         default: return -1;
@@ -439,6 +441,8 @@ void bind_field(EngField& F, char* w, int n) {
     F.dirs_f = reinterpret_cast<uint8_t*>(w + l.dirs_f);
     F.dirs_g = reinterpret_cast<uint8_t*>(w + l.dirs_g);
     F.marks = reinterpret_cast<uint8_t*>(w + l.marks);
+    F.cases = reinterpret_cast<uint8_t*>(w + l.cases);
+    F.dirty = reinterpret_cast<uint8_t*>(w + l.dirty);
     F.Mf = reinterpret_cast<int*>(w + l.Mf);
     F.mf = reinterpret_cast<int*>(w + l.mf);
     F.qu = reinterpret_cast<int*>(w + l.qu);

@@ -17,7 +17,7 @@ constexpr int kSlotStride = 32;
 constexpr int kCntBlockWords = kSlots * kSlotStride;
 constexpr int kGridCap = 2048;  // grid-stride kernels: 8 blocks per compute unit
 enum : int {
-    kCntCase = 0,      // 0..3: false critical points per C type in the last detection
+    kCntCase = 0,      // 0..3: false critical points per C type (a full pass), or their change (a refresh)
     kCntChanged = 5,   // values changed by the last apply
     kCntWrong = 6,     // mislabelled vertices (R detection) / wrong_any (compare)
     kCntRCases = 7,    // R-loop troublemaker hits
@@ -115,11 +115,6 @@ void launch_validate_init(const float* f, const float* fhat, const float* warm, 
                           float* L, float* g, unsigned* cnt, hipStream_t s);
 void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s);
 void launch_dirs(const float* h, const Grid& gr, int variant, uint8_t* dirs_out, hipStream_t s);
-void launch_dirs_detect(const float* g, const Grid& gr, int variant, uint8_t* dirs_g,
-                        const uint8_t* dirs_f, int type, uint8_t* marks, unsigned* cnt, hipStream_t s);
-void launch_detect_only(const uint8_t* dirs_f, const uint8_t* dirs_g, const Grid& gr, int type,
-                        uint8_t* marks, unsigned* cnt, hipStream_t s);
-void launch_apply(float* g, const float* L, uint8_t* marks, int n, unsigned* cnt, hipStream_t s);
 void launch_label_tile(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, hipStream_t s);
 void launch_label_compress(const Grid& gr, int* q_up, int* q_dn, unsigned* cnt, hipStream_t s);
 void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, unsigned* cnt,
@@ -152,15 +147,16 @@ enum EngOp : int {
     kOpPreB,       // label tiles of f
     kOpPreC,       // compression of f's tile faces
     kOpPreD,       // labels of f
-    kOpPreE,       // first directions/detection of g (type 0)
-    kOpApplyC,     // C-loop apply
-    kOpDdC,        // directions/detection of g after a C apply
-    kOpDetect,     // detection from stored directions
+    kOpPreE,       // directions of g and the case bytes of every vertex
+    kOpApplyC,     // C-loop apply: the targets of every case of the current type
+    kOpRefreshC,   // directions and cases of the vertices around the last C edits
+    kOpFullC,      // the same for every vertex (after an apply that changed many)
     kOpRTile,      // label tiles of g
     kOpRJump,      // compression of g's tile faces
     kOpRDetect,    // troublemakers
     kOpApplyR,     // R-loop apply
-    kOpDdR,        // directions/detection of g (type 0) after an R apply
+    kOpRefreshR,   // directions and cases of the vertices around the last R edits
+    kOpFullR,      // the same for every vertex
     kOpDelta,      // output
     kOpDone,
     kOpStart       // before the first step (its successor is kOpPreA)
@@ -175,6 +171,8 @@ struct EngField {
     float *edits, *g_out;
     float *L, *g;
     uint8_t *dirs_f, *dirs_g, *marks;
+    uint8_t *cases;  // per vertex: bit t set when it is a case of type t (FPmax, FPmin, FNmax, FNmin)
+    uint8_t *dirty;  // per vertex: its directions in g must be recomputed (it or a neighbour was edited)
     int *Mf, *mf, *qu, *qd;
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
@@ -185,6 +183,7 @@ struct EngState {
 
 struct EngStats {
     long long rounds[4], rounds_r, outer_iters, n_edited, false_init[4], n_inexact, rounds_total;
+    int cases[4];  // current number of cases of each type (kept up to date by the refresh steps)
     int status, pad;
 };
 

@@ -128,22 +128,16 @@ __global__ void __launch_bounds__(256) k_check_finite(const float* __restrict__ 
 
 // ------------------------------------------------------------ detection ---
 
-// The four C-loop predicates (Defs. 1-3) of vertex i from its packed
-// directions in f (df) and g (dg); returns a bit per type and the edit
-// target of type `type` (Eqs. 2-5; FPmin lowers dn_f, FNmax lowers up_g).
-__device__ __forceinline__ unsigned c_cases(unsigned df, unsigned dg, int i, int type,
-                                            const Grid& gr, int& target) {
+// The four C-loop predicates (Defs. 1-3) of a vertex from its packed
+// directions in f (df) and g (dg): bit t set when it is a case of type t
+// (0 FPmax, 1 FPmin, 2 FNmax, 3 FNmin).  The edit target of a case (Eqs. 2-5)
+// is the vertex itself for FPmax and FNmin, dn_f for FPmin and up_g for FNmax.
+__device__ __forceinline__ unsigned case_bits(unsigned df, unsigned dg) {
     const unsigned uf = df >> 4, nf = df & 15u, ug = dg >> 4, ng = dg & 15u;
     const unsigned c0 = (ug == kSelf) & (uf != kSelf);   // FPmax
     const unsigned c1 = (ng == kSelf) & (nf != kSelf);   // FPmin
     const unsigned c2 = (uf == kSelf) & (ug != kSelf);   // FNmax
     const unsigned c3 = (nf == kSelf) & (ng != kSelf);   // FNmin
-    switch (type) {
-        case 0: target = i; break;
-        case 1: target = i + gr.off[nf]; break;
-        case 2: target = i + gr.off[ug]; break;
-        default: target = i; break;
-    }
     return c0 | (c1 << 1) | (c2 << 2) | (c3 << 3);
 }
 
@@ -159,29 +153,26 @@ __device__ __forceinline__ unsigned lo_self4(unsigned d) {
     return ~((~d & 0x0F0F0F0Fu) + 0x0F0F0F0Fu) & 0x10101010u;
 }
 
-// C-loop detection (Defs. 1-3) of four vertices i0..i0+3 from their packed
+// case_bits of four vertices at once (byte k = vertex k) from their packed
 // directions in f (df4) and g (dg4); a byte of 0xFF in both (a vertex outside
-// the grid) has no case.  Counts every type and marks the targets of `type`
-// (Eqs. 2-5; FPmin lowers dn_f, FNmax lowers up_g).
-__device__ __forceinline__ void detect4(unsigned df4, unsigned dg4, int i0, int type, const Grid& gr,
-                                        uint8_t* __restrict__ marks, unsigned (&c)[4]) {
+// the grid) has no case.  Adds the count of each type to c.
+__device__ __forceinline__ unsigned cases4(unsigned df4, unsigned dg4, unsigned (&c)[4]) {
     const unsigned ug = hi_self4(dg4), uf = hi_self4(df4), ng = lo_self4(dg4), nf = lo_self4(df4);
     const unsigned fpmax = ug & ~uf, fpmin = ng & ~nf, fnmax = uf & ~ug, fnmin = nf & ~ng;
     c[0] += __popc(fpmax);
     c[1] += __popc(fpmin);
     c[2] += __popc(fnmax);
     c[3] += __popc(fnmin);
-    unsigned m = type == 0 ? fpmax : type == 1 ? fpmin : type == 2 ? fnmax : fnmin;
-    while (m) {
-        const int k = (__ffs(m) - 1) >> 3;
-        m &= m - 1u;
-        const int i = i0 + k;
-        int t = i;
-        if (type == 1) t = i + gr.off[(df4 >> (8 * k)) & 15u];
-        else if (type == 2) t = i + gr.off[(dg4 >> (8 * k + 4)) & 15u];
-        mark(marks, t);
-    }
+    // bit 4 of each byte moves to bit t of the same byte
+    return (fpmax >> 4) | (fpmin >> 3) | (fnmax >> 2) | (fnmin >> 1);
 }
+
+// Per-vertex byte arrays written by the full direction pass of g (MODE 1):
+// the case bits, and the dirty flags and claim marks of the incremental
+// refresh, which the full pass clears.
+struct CaseArrays {
+    uint8_t *cases, *dirty, *marks;
+};
 
 // --------------------------------------------------- steepest directions ---
 //
@@ -194,8 +185,8 @@ __device__ __forceinline__ void detect4(unsigned df4, unsigned dg4, int i0, int 
 // x-consecutive vertices of TY/16 rows.  Loads are issued as a batch before
 // the previous plane is computed, which keeps HBM busy.
 //
-// MODE 0: write dirs only.  MODE 1: write dirs and run the C-loop detection
-// of `type` against dirs_f.
+// MODE 0: write dirs only.  MODE 1: also write the case bits of every vertex
+// against dirs_f, count each type and clear the dirty flags and marks.
 
 // Maps the hardware block id to a tile so that consecutive tiles land on the
 // same XCD (blocks are dealt to the 8 XCDs round-robin).
@@ -418,7 +409,7 @@ template <int NDIM, int TY, int ZC, int MODE>
 __device__ __forceinline__ void dirs_compute(const float* C, const float* A, const float* B, const Grid& gr,
                                              const ItemPos& pos, int z,
                                              const unsigned (&df4)[DirsGeom<NDIM, TY, ZC>::RPT],
-                                             uint8_t* __restrict__ dirs_out, int type, uint8_t* __restrict__ marks,
+                                             uint8_t* __restrict__ dirs_out, const CaseArrays& ca,
                                              unsigned (&c)[4]) {
     using G = DirsGeom<NDIM, TY, ZC>;
     constexpr int W = G::W;
@@ -470,7 +461,24 @@ __device__ __forceinline__ void dirs_compute(const float* C, const float* A, con
             }
         }
         if (full) *reinterpret_cast<unsigned*>(dirs_out + i0) = out4;
-        if constexpr (MODE == 1) detect4(df4[q], out4, static_cast<int>(i0), type, gr, marks, c);
+        if constexpr (MODE == 1) {
+            // 32-bit offsets (n < 2^31) keep the three stores on one address register
+            const unsigned u0 = static_cast<unsigned>(i0);
+            const unsigned cw = cases4(df4[q], out4, c);
+            if (full) {
+                *reinterpret_cast<unsigned*>(ca.cases + u0) = cw;
+                *reinterpret_cast<unsigned*>(ca.dirty + u0) = 0u;
+                *reinterpret_cast<unsigned*>(ca.marks + u0) = 0u;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    if (pos.interior || (xa + k < gr.nx && y < gr.ny)) {
+                        ca.cases[u0 + k] = static_cast<uint8_t>(cw >> (8 * k));
+                        ca.dirty[u0 + k] = 0;
+                        ca.marks[u0 + k] = 0;
+                    }
+            }
+        }
     }
 }
 
@@ -480,7 +488,7 @@ __device__ __forceinline__ void dirs_compute(const float* C, const float* A, con
 template <int NDIM, int TY, int ZC, int MODE>
 __device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const Grid& gr, ItemRange range,
                                             uint8_t* __restrict__ dirs_out, const uint8_t* __restrict__ dirs_f,
-                                            int type, uint8_t* __restrict__ marks, float* sm, unsigned (&c)[4]) {
+                                            const CaseArrays& ca, float* sm, unsigned (&c)[4]) {
     using G = DirsGeom<NDIM, TY, ZC>;
     const G geo(gr);
     const bool vec4 = (gr.nx & 3) == 0 && (reinterpret_cast<uintptr_t>(h) & 15u) == 0 &&
@@ -515,109 +523,119 @@ __device__ __forceinline__ void dirs_stream(const float* __restrict__ h, const G
             const float* A = sm + cur_ring * G::P;                             // plane z + 1
             const float* C = sm + (G::NP == 3 ? (cur_ring + 2) % 3 : 0) * G::P; // plane z
             const float* B = sm + (G::NP == 3 ? (cur_ring + 1) % 3 : 0) * G::P; // plane z - 1
-            dirs_compute<NDIM, TY, ZC, MODE>(C, A, B, gr, cur, z, df4, dirs_out, type, marks, c);
+            dirs_compute<NDIM, TY, ZC, MODE>(C, A, B, gr, cur, z, df4, dirs_out, ca, c);
         }
         __syncthreads();  // the slot written next is the oldest plane
     }
 }
 
-template <int NDIM, int TY, int ZC, int MODE>
-__global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid gr,
-                                              uint8_t* __restrict__ dirs_out,
-                                              const uint8_t* __restrict__ dirs_f, int type,
-                                              uint8_t* __restrict__ marks,
-                                              unsigned* __restrict__ cnt) {
+// Directions only (msz_labels, msz_count_false and the network features).
+template <int NDIM, int TY, int ZC>
+__global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid gr, uint8_t* __restrict__ dirs_out) {
     using G = DirsGeom<NDIM, TY, ZC>;
     static_assert(TY % 16 == 0, "a thread row covers 16 tile rows");
     __shared__ __align__(16) float sm[G::NP * G::P];
     unsigned c[4] = {0u, 0u, 0u, 0u};
-    dirs_stream<NDIM, TY, ZC, MODE>(h, gr, xcd_items(G(gr).items()), dirs_out, dirs_f, type, marks, sm, c);
-    if constexpr (MODE == 1) {
-        const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
-        block_add<4>(c, cnt, idx);
-    }
-}
-
-// Detection from stored directions (g unchanged since they were computed).
-// C-loop detection of the 16-vertex group w from stored directions (one
-// dwordx4 of each direction array).  The direction arrays live in 256-byte
-// padded workspace segments, so the last partial group can be read whole;
-// vertices past n are masked to "no case".
-__device__ __forceinline__ void detect_loaded(const uint4 a, const uint4 b, const Grid& gr, int type,
-                                              uint8_t* __restrict__ marks, int w, unsigned (&c)[4]) {
-    const unsigned fa[4] = {a.x, a.y, a.z, a.w}, ga[4] = {b.x, b.y, b.z, b.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i0 = 16 * w + 4 * q;
-        const int left = gr.n - i0;  // vertices of this word inside the field
-        const unsigned pad = left >= 4 ? 0u : (left <= 0 ? 0xFFFFFFFFu : 0xFFFFFFFFu << (8 * left));
-        detect4(fa[q] | pad, ga[q] | pad, i0, type, gr, marks, c);
-    }
-}
-
-__device__ __forceinline__ void detect_group(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
-                                             const Grid& gr, int type, uint8_t* __restrict__ marks, int w,
-                                             unsigned (&c)[4]) {
-    detect_loaded(reinterpret_cast<const uint4*>(dirs_f)[w], reinterpret_cast<const uint4*>(dirs_g)[w], gr, type,
-                  marks, w, c);
-}
-
-__global__ void __launch_bounds__(256) k_detect_only(const uint8_t* __restrict__ dirs_f,
-                                                     const uint8_t* __restrict__ dirs_g, Grid gr,
-                                                     int type, uint8_t* __restrict__ marks,
-                                                     unsigned* __restrict__ cnt) {
-    unsigned c[4] = {0u, 0u, 0u, 0u};
-    const int ng = (gr.n + 15) >> 4;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x)
-        detect_group(dirs_f, dirs_g, gr, type, marks, w, c);
-    const int idx[4] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3};
-    block_add<4>(c, cnt, idx);
+    const CaseArrays none{nullptr, nullptr, nullptr};
+    dirs_stream<NDIM, TY, ZC, 0>(h, gr, xcd_items(G(gr).items()), dirs_out, nullptr, none, sm, c);
 }
 
 // ---------------------------------------------------------------- apply ---
+//
+// One decreasing edit (Eqs. 2-6) per target and round.  The correction loop
+// keeps, besides the directions of g, a case byte per vertex (case_bits), so
+// an apply step needs no detection pass: it scans the case bytes for the
+// current type (C loop) or the marks of the troublemakers (R loop) and edits
+// the targets.  Every edited vertex and, when its value changed, every
+// neighbour is flagged dirty: only their directions can have changed, and the
+// refresh step recomputes exactly those (the synchronous round is unchanged,
+// so results are identical to a full recomputation).
 
-// Halves every marked vertex once (the round's union of proposals) and clears
-// its mark.  Marks are scanned 16 at a time; the padding bytes are never set.
-// Halves every marked vertex of the 16-vertex group w once and clears the
-// marks (padding bytes past n are never set).
-// The halvings of group w given its (already loaded, non-zero) marks m.
+// Slot deltas in the order of the neighbour table at the top of this file.
+__device__ __forceinline__ void slot_delta(unsigned s, int& dx, int& dy, int& dz) {
+    constexpr int DX[14] = {1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1};
+    constexpr int DY[14] = {0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+    constexpr int DZ[14] = {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+    dx = DX[s];
+    dy = DY[s];
+    dz = DZ[s];
+}
+
+// Whether neighbour slot s of the vertex at (x, y, z) lies in the grid.
+template <int NDIM>
+__device__ __forceinline__ bool slot_in_grid(const Grid& gr, int x, int y, int z, int s) {
+    int dx, dy, dz;
+    slot_delta(s, dx, dy, dz);
+    const bool in2 = x + dx >= 0 && x + dx < gr.nx && y + dy >= 0 && y + dy < gr.ny;
+    return NDIM == 2 ? in2 : in2 && z + dz >= 0 && z + dz < gr.nz;
+}
+
+// Halves g[t] once; flags t (so the refresh clears its mark) and, if the
+// value changed, its neighbours.
+template <int NDIM>
+__device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* __restrict__ L,
+                                            uint8_t* __restrict__ dirty, const Grid& gr, int t, unsigned& changed) {
+    const float old = g[t];
+    const float nv = halve(old, L[t]);
+    dirty[t] = 1;
+    if (nv == old) return;
+    g[t] = nv;
+    ++changed;
+    const int x = t % gr.nx, y = (t / gr.nx) % gr.ny, z = NDIM == 3 ? t / gr.nxy : 0;
+    constexpr int NS = NDIM == 3 ? 14 : 6;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
+}
+
+// R loop: edits every marked vertex of the 16-vertex group w once (the
+// round's union of proposals) and clears the group's marks.  m: the group's
+// marks, already loaded and not all zero; padding bytes past n are never set.
+template <int NDIM>
 __device__ __forceinline__ void apply_marks(float* __restrict__ g, const float* __restrict__ L,
-                                            uint8_t* __restrict__ marks, int w, const uint4 m, unsigned& changed) {
-    uint4* mw = reinterpret_cast<uint4*>(marks);
+                                            uint8_t* __restrict__ marks, uint8_t* __restrict__ dirty,
+                                            const Grid& gr, int w, const uint4 m, unsigned& changed) {
     const unsigned part[4] = {m.x, m.y, m.z, m.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (!part[q]) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if ((part[q] >> (8 * b)) & 0xFFu) {
-                const int t = w * 16 + q * 4 + b;
-                const float old = g[t];
-                const float nv = halve(old, L[t]);
-                g[t] = nv;
-                changed += nv != old;
-            }
+        unsigned bits = part[q];
+        while (bits) {
+            const int b = (__ffs(bits) - 1) >> 3;
+            bits &= ~(0xFFu << (8 * b));
+            edit_vertex<NDIM>(g, L, dirty, gr, w * 16 + q * 4 + b, changed);
         }
     }
-    mw[w] = make_uint4(0u, 0u, 0u, 0u);
+    reinterpret_cast<uint4*>(marks)[w] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-__device__ __forceinline__ void apply_group(float* __restrict__ g, const float* __restrict__ L,
-                                            uint8_t* __restrict__ marks, int w, unsigned& changed) {
-    const uint4 m = reinterpret_cast<const uint4*>(marks)[w];
-    if ((m.x | m.y | m.z | m.w) != 0u) apply_marks(g, L, marks, w, m, changed);
-}
-
-__global__ void __launch_bounds__(256) k_apply(float* __restrict__ g, const float* __restrict__ L,
-                                               uint8_t* __restrict__ marks, int n,
-                                               unsigned* __restrict__ cnt) {
-    unsigned changed = 0;
-    const int nw = (n + 15) >> 4;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += gridDim.x * blockDim.x)
-        apply_group(g, L, marks, w, changed);
-    unsigned v[1] = {changed};
-    const int idx[1] = {kCntChanged};
-    block_add<1>(v, cnt, idx);
+// C loop: edits the targets of the cases of `type` among the 16-vertex group
+// w (its case bytes m, already loaded).  FPmax and FNmin edit the vertex
+// itself; FPmin and FNmax edit a neighbour, which several cases may share, so
+// the first to set the target's mark (an atomic OR on its word) edits it.
+template <int NDIM>
+__device__ __forceinline__ void apply_cases(float* __restrict__ g, const float* __restrict__ L,
+                                            const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
+                                            uint8_t* __restrict__ marks, uint8_t* __restrict__ dirty,
+                                            const Grid& gr, int w, const uint4 m, int type, unsigned& changed) {
+    const unsigned part[4] = {m.x, m.y, m.z, m.w};
+    const unsigned sel = 0x01010101u << type;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        unsigned bits = part[q] & sel;
+        while (bits) {
+            const int b = (__ffs(bits) - 1) >> 3;
+            bits &= bits - 1u;
+            const int i = w * 16 + q * 4 + b;
+            if (type == 0 || type == 3) {
+                edit_vertex<NDIM>(g, L, dirty, gr, i, changed);
+                continue;
+            }
+            const int t = i + gr.off[type == 1 ? (dirs_f[i] & 15u) : (dirs_g[i] >> 4)];
+            const unsigned bit = 1u << (8 * (t & 3));
+            if ((atomicOr(reinterpret_cast<unsigned*>(marks + (t & ~3)), bit) & bit) == 0u)
+                edit_vertex<NDIM>(g, L, dirty, gr, t, changed);
+        }
+    }
 }
 
 // --------------------------------------------------------------- labels ---
@@ -649,16 +667,6 @@ __host__ __device__ __forceinline__ int label_tiles_of(const Grid& gr) {
     }
     using T = LabelTile<3>;
     return ((gr.nx + T::X - 1) / T::X) * ((gr.ny + T::Y - 1) / T::Y) * ((gr.nz + T::Z - 1) / T::Z);
-}
-
-__device__ __forceinline__ void slot_delta(unsigned s, int& dx, int& dy, int& dz) {
-    // slots in the order of the table at the top of this file
-    constexpr int DX[14] = {1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1};
-    constexpr int DY[14] = {0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
-    constexpr int DZ[14] = {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
-    dx = DX[s];
-    dy = DY[s];
-    dz = DZ[s];
 }
 
 // One label tile; su, sd: LDS arrays of the tile's vertex count.  The caller
@@ -1030,10 +1038,8 @@ __global__ void __launch_bounds__(256) k_compare(const uint8_t* __restrict__ dir
                                                  const int* __restrict__ qgd, int n,
                                                  unsigned* __restrict__ cnt) {
     unsigned c[7] = {0, 0, 0, 0, 0, 0, 0};
-    Grid dummy{};
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int t;
-        const unsigned bits = c_cases(dirs_f[i], dirs_g[i], i, 0, dummy, t);
+        const unsigned bits = case_bits(dirs_f[i], dirs_g[i]);
         c[0] += bits & 1u;
         c[1] += (bits >> 1) & 1u;
         c[2] += (bits >> 2) & 1u;
@@ -1137,55 +1143,28 @@ int tile_variant_count(int ndim) { return ndim == 2 ? 2 : 4; }
 // a contiguous run of work items of its XCD.
 constexpr int kDirsBlocks = 2048;
 
-template <int NDIM, int TY, int ZC, int MODE>
-static void launch_dirs_t(const float* h, const Grid& gr, uint8_t* dirs_out, const uint8_t* dirs_f,
-                          int type, uint8_t* marks, unsigned* cnt, hipStream_t s) {
+template <int NDIM, int TY, int ZC>
+static void launch_dirs_t(const float* h, const Grid& gr, uint8_t* dirs_out, hipStream_t s) {
     const int tx = (gr.nx + kTileX - 1) / kTileX;
     const int ty = (gr.ny + TY - 1) / TY;
     const int tz = NDIM == 3 ? (gr.nz + ZC - 1) / ZC : 1;
     const int items = tx * ty * tz;
     const int nb = items < kDirsBlocks ? items : kDirsBlocks;
-    hipLaunchKernelGGL((k_dirs<NDIM, TY, ZC, MODE>), dim3(nb), dim3(256), 0, s, h, gr, dirs_out, dirs_f, type,
-                       marks, cnt);
-}
-
-template <int MODE>
-static void launch_dirs_mode(const float* h, const Grid& gr, int variant, uint8_t* dirs_out,
-                             const uint8_t* dirs_f, int type, uint8_t* marks,
-                             unsigned* cnt, hipStream_t s) {
-    if (gr.ndim == 2) {
-        if (variant_of(2, variant).ty == 32) launch_dirs_t<2, 32, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else launch_dirs_t<2, 16, 1, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-    } else {
-        const DirsVariant v = variant_of(3, variant);
-        if (v.ty == 32) launch_dirs_t<3, 32, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else if (v.zc == 8) launch_dirs_t<3, 16, 8, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else if (v.zc == 32) launch_dirs_t<3, 16, 32, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-        else launch_dirs_t<3, 16, 16, MODE>(h, gr, dirs_out, dirs_f, type, marks, cnt, s);
-    }
+    hipLaunchKernelGGL((k_dirs<NDIM, TY, ZC>), dim3(nb), dim3(256), 0, s, h, gr, dirs_out);
 }
 
 void launch_dirs(const float* h, const Grid& gr, int variant, uint8_t* dirs_out, hipStream_t s) {
-    launch_dirs_mode<0>(h, gr, variant, dirs_out, nullptr, 0, nullptr, nullptr, s);
+    if (gr.ndim == 2) {
+        if (variant_of(2, variant).ty == 32) launch_dirs_t<2, 32, 1>(h, gr, dirs_out, s);
+        else launch_dirs_t<2, 16, 1>(h, gr, dirs_out, s);
+    } else {
+        const DirsVariant v = variant_of(3, variant);
+        if (v.ty == 32) launch_dirs_t<3, 32, 16>(h, gr, dirs_out, s);
+        else if (v.zc == 8) launch_dirs_t<3, 16, 8>(h, gr, dirs_out, s);
+        else if (v.zc == 32) launch_dirs_t<3, 16, 32>(h, gr, dirs_out, s);
+        else launch_dirs_t<3, 16, 16>(h, gr, dirs_out, s);
+    }
 }
-
-void launch_dirs_detect(const float* g, const Grid& gr, int variant, uint8_t* dirs_g,
-                        const uint8_t* dirs_f, int type, uint8_t* marks, unsigned* cnt,
-                        hipStream_t s) {
-    launch_dirs_mode<1>(g, gr, variant, dirs_g, dirs_f, type, marks, cnt, s);
-}
-
-void launch_detect_only(const uint8_t* dirs_f, const uint8_t* dirs_g, const Grid& gr, int type,
-                        uint8_t* marks, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_detect_only, dim3(blocks_for((gr.n + 15) / 16, 256, kGridCap)), dim3(256), 0, s, dirs_f,
-                       dirs_g, gr, type, marks, cnt);
-}
-
-void launch_apply(float* g, const float* L, uint8_t* marks, int n, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_apply, dim3(blocks_for((n + 15) / 16, 256, kGridCap)), dim3(256), 0, s, g, L,
-                       marks, n, cnt);
-}
-
 
 void launch_label_tile(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, hipStream_t s) {
     const int nb = label_tiles_of(gr);
@@ -1272,9 +1251,10 @@ __host__ __device__ inline int eng_items(const EngField& F, int op) {
     const int tiles = label_tiles_of(F.gr);
     const int dirs = dirs_items_of(F.gr, F.variant);
     switch (op) {
-        case kOpPreA: case kOpApplyC: case kOpApplyR: case kOpDetect: case kOpDelta: return chunks;
+        case kOpPreA: case kOpApplyC: case kOpApplyR: case kOpRefreshC: case kOpRefreshR: case kOpDelta:
+            return chunks;
         case kOpPreB: case kOpPreC: case kOpPreD: case kOpRTile: case kOpRJump: case kOpRDetect: return tiles;
-        case kOpPreA2: case kOpPreE: case kOpDdC: case kOpDdR: return dirs;
+        case kOpPreA2: case kOpPreE: case kOpFullC: case kOpFullR: return dirs;
         default: return 0;
     }
 }
@@ -1283,25 +1263,103 @@ int eng_items_host(const EngField& F, int op) { return eng_items(F, op); }
 
 // Direction work items [a, b) of field F with its variant's tile shape.
 template <int NDIM, int MODE>
-__device__ __forceinline__ void eng_dirs(const EngField& F, const float* h, uint8_t* out, int type, int a, int b,
-                                         float* sm, unsigned (&c)[4]) {
+__device__ __forceinline__ void eng_dirs(const EngField& F, const float* h, uint8_t* out, int a, int b, float* sm,
+                                         unsigned (&c)[4]) {
     const ItemRange r{a, b, 1};
     const Grid& gr = F.gr;
+    const CaseArrays ca{F.cases, F.dirty, F.marks};
     if constexpr (NDIM == 2) {
-        if (variant_of(2, F.variant).ty == 32) dirs_stream<2, 32, 1, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
-        else dirs_stream<2, 16, 1, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+        if (variant_of(2, F.variant).ty == 32) dirs_stream<2, 32, 1, MODE>(h, gr, r, out, F.dirs_f, ca, sm, c);
+        else dirs_stream<2, 16, 1, MODE>(h, gr, r, out, F.dirs_f, ca, sm, c);
     } else {
         const DirsVariant v = variant_of(3, F.variant);
-        if (v.ty == 32) dirs_stream<3, 32, 16, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
-        else if (v.zc == 8) dirs_stream<3, 16, 8, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
-        else if (v.zc == 32) dirs_stream<3, 16, 32, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
-        else dirs_stream<3, 16, 16, MODE>(h, gr, r, out, F.dirs_f, type, F.marks, sm, c);
+        if (v.ty == 32) dirs_stream<3, 32, 16, MODE>(h, gr, r, out, F.dirs_f, ca, sm, c);
+        else if (v.zc == 8) dirs_stream<3, 16, 8, MODE>(h, gr, r, out, F.dirs_f, ca, sm, c);
+        else if (v.zc == 32) dirs_stream<3, 16, 32, MODE>(h, gr, r, out, F.dirs_f, ca, sm, c);
+        else dirs_stream<3, 16, 16, MODE>(h, gr, r, out, F.dirs_f, ca, sm, c);
     }
 }
 
-// Runs work items [lo, hi) of the field's current operation (block-wide; lo,
-// hi uniform over the block) and adds the block's counts to the field's
-// counter block.
+// Steepest ascent and descent of vertex i in g, read straight from memory
+// (the refresh of a few vertices): the same neighbour order and comparisons
+// as the stencil (odd slots have the smaller ids, even slots the larger ones,
+// each nearest first), with neighbours outside the grid left out.
+template <int NDIM>
+__device__ __forceinline__ unsigned steepest_at(const float* __restrict__ g, const Grid& gr, int i) {
+    constexpr int NS = NDIM == 3 ? 14 : 6;
+    const int x = i % gr.nx, y = (i / gr.nx) % gr.ny, z = NDIM == 3 ? i / gr.nxy : 0;
+    const float nan = __builtin_nanf("");
+    float w[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) w[s] = slot_in_grid<NDIM>(gr, x, y, z, s) ? g[i + gr.off[s]] : nan;
+    const float v = g[i];
+    Steepest b{v, v, kSelf, kSelf};
+#pragma unroll
+    for (int s = 1; s < NS; s += 2) b.below(w[s], s);
+#pragma unroll
+    for (int s = 0; s < NS; s += 2) b.above(w[s], s);
+    return (b.us << 4) | b.ds;
+}
+
+// Refresh of one 4096-vertex chunk: its dirty vertices are gathered into an
+// LDS list (so the block's threads share them evenly), their directions and
+// case bytes recomputed, and the dirty flags and marks of the chunk cleared.
+// c receives the changes of the case counts (modulo 2^32).
+template <int NDIM>
+__device__ __forceinline__ void refresh_chunk(const EngField& F, int item, int* list, int* wsum, unsigned (&c)[4]) {
+    const int w = item * (kEngChunk / 16) + threadIdx.x;
+    const bool in = w < ((F.gr.n + 15) >> 4);
+    const uint4 d = in ? reinterpret_cast<const uint4*>(F.dirty)[w] : make_uint4(0u, 0u, 0u, 0u);
+    const unsigned part[4] = {d.x & 0x01010101u, d.y & 0x01010101u, d.z & 0x01010101u, d.w & 0x01010101u};
+    const int cnt = __popc(part[0]) + __popc(part[1]) + __popc(part[2]) + __popc(part[3]);
+    // exclusive prefix of cnt over the block: within the wave, then over the waves
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int t = wsum[k];
+        base += k < wave ? t : 0;
+        total += t;
+    }
+    if (total == 0) {
+        __syncthreads();  // wsum is rewritten by the next chunk
+        return;
+    }
+    int pos = base + incl - cnt;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        unsigned bits = part[q];
+        while (bits) {
+            const int b = (__ffs(bits) - 1) >> 3;
+            bits &= bits - 1u;
+            list[pos++] = w * 16 + q * 4 + b;
+        }
+    }
+    if (cnt) {
+        reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int j = list[e];
+        const unsigned dg = steepest_at<NDIM>(F.g, F.gr, j);
+        const unsigned now = case_bits(F.dirs_f[j], dg), was = F.cases[j];
+        F.dirs_g[j] = static_cast<uint8_t>(dg);
+        F.cases[j] = static_cast<uint8_t>(now);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) c[t] += ((now >> t) & 1u) - ((was >> t) & 1u);
+    }
+    __syncthreads();  // the list and wsum are rewritten by the next chunk
+}
+
 template <int NDIM>
 __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem,
                                               unsigned* cnt) {
@@ -1324,7 +1382,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
         }
         case kOpPreA2: {
             unsigned c[4] = {0u, 0u, 0u, 0u};
-            eng_dirs<NDIM, 0>(F, F.f, F.dirs_f, 0, lo, hi, sm, c);
+            eng_dirs<NDIM, 0>(F, F.f, F.dirs_f, lo, hi, sm, c);
             break;
         }
         case kOpPreB:
@@ -1348,21 +1406,30 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         case kOpApplyC:
         case kOpApplyR: {
-            // the marks of up to four items are loaded before any is applied
+            // the case bytes (C) or marks (R) of up to four items are loaded before any is applied
             unsigned changed = 0;
             const int nw = (gr.n + 15) >> 4;
-            const uint4* mw = reinterpret_cast<const uint4*>(F.marks);
+            const bool c_loop = st.op == kOpApplyC;
+            const uint4* mw = reinterpret_cast<const uint4*>(c_loop ? F.cases : F.marks);
+            const unsigned sel = c_loop ? 0x01010101u << st.type : 0xFFFFFFFFu;
+            auto load = [&](int item) {
+                const int w = item * (kEngChunk / 16) + threadIdx.x;
+                return (item < hi && w < nw) ? mw[w] : make_uint4(0u, 0u, 0u, 0u);
+            };
+            auto run = [&](int item, const uint4 m) {
+                if (((m.x | m.y | m.z | m.w) & sel) == 0u) return;
+                const int w = item * (kEngChunk / 16) + threadIdx.x;
+                if (c_loop)
+                    apply_cases<NDIM>(F.g, F.L, F.dirs_f, F.dirs_g, F.marks, F.dirty, gr, w, m, st.type, changed);
+                else
+                    apply_marks<NDIM>(F.g, F.L, F.marks, F.dirty, gr, w, m, changed);
+            };
             for (int base = lo; base < hi; base += 4) {
-                uint4 m[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int w = (base + k) * (kEngChunk / 16) + threadIdx.x;
-                    m[k] = (base + k < hi && w < nw) ? mw[w] : make_uint4(0u, 0u, 0u, 0u);
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if ((m[k].x | m[k].y | m[k].z | m[k].w) != 0u)
-                        apply_marks(F.g, F.L, F.marks, (base + k) * (kEngChunk / 16) + threadIdx.x, m[k], changed);
+                const uint4 m0 = load(base), m1 = load(base + 1), m2 = load(base + 2), m3 = load(base + 3);
+                run(base, m0);
+                run(base + 1, m1);
+                run(base + 2, m2);
+                run(base + 3, m3);
             }
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
@@ -1370,33 +1437,19 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         }
         case kOpPreE:
-        case kOpDdC:
-        case kOpDdR: {
+        case kOpFullC:
+        case kOpFullR: {
             unsigned c[4] = {0u, 0u, 0u, 0u};
-            eng_dirs<NDIM, 1>(F, F.g, F.dirs_g, st.type, lo, hi, sm, c);
+            eng_dirs<NDIM, 1>(F, F.g, F.dirs_g, lo, hi, sm, c);
             block_add<4>(c, cnt, cidx);
             break;
         }
-        case kOpDetect: {
-            // both direction words of up to four items are loaded before any is tested
+        case kOpRefreshC:
+        case kOpRefreshR: {
             unsigned c[4] = {0u, 0u, 0u, 0u};
-            const int nw = (gr.n + 15) >> 4;
-            const uint4* fw = reinterpret_cast<const uint4*>(F.dirs_f);
-            const uint4* gw = reinterpret_cast<const uint4*>(F.dirs_g);
-            for (int base = lo; base < hi; base += 4) {
-                uint4 a[4], b[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int w = (base + k) * (kEngChunk / 16) + threadIdx.x;
-                    const bool in = base + k < hi && w < nw;
-                    a[k] = in ? fw[w] : make_uint4(~0u, ~0u, ~0u, ~0u);
-                    b[k] = in ? gw[w] : make_uint4(~0u, ~0u, ~0u, ~0u);
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    if (base + k < hi && (base + k) * (kEngChunk / 16) + threadIdx.x < nw)
-                        detect_loaded(a[k], b[k], gr, st.type, F.marks, (base + k) * (kEngChunk / 16) + threadIdx.x, c);
-            }
+            int* list = reinterpret_cast<int*>(smem);
+            int* wsum = list + kEngChunk;
+            for (int item = lo; item < hi; ++item) refresh_chunk<NDIM>(F, item, list, wsum, c);
             block_add<4>(c, cnt, cidx);
             break;
         }
@@ -1485,7 +1538,11 @@ __global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ f
 }
 
 // The schedule (the host loop of a single correction, step by step): the next
-// state of one field from the counters of its finished step.
+// state of one field from the counters of its finished step.  The current case
+// counts live in S->cases: a full pass sets them, a refresh adds its changes.
+// An apply step is followed by a refresh of the vertices around its edits, or
+// by a full pass when so many values changed that streaming the whole field is
+// cheaper (the outcome is the same either way).
 __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, EngStats* S,
                                                 const unsigned (&c)[kCntSlots]) {
     auto go = [&](int op) {
@@ -1501,22 +1558,35 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
         S->status = status;
         return go(kOpDone);
     };
-    // counts and round tallies of the current type, by selects (no dynamic
-    // indexing of local arrays, which would go to private memory)
+    // the case count of type t, by selects (no dynamic indexing of local
+    // arrays, which would go to private memory)
     auto cases_of = [&](int t) {
-        return t == 0 ? c[kCntCase + 0] : t == 1 ? c[kCntCase + 1] : t == 2 ? c[kCntCase + 2] : c[kCntCase + 3];
+        return t == 0 ? S->cases[0] : t == 1 ? S->cases[1] : t == 2 ? S->cases[2] : S->cases[3];
     };
+    auto set_cases = [&](bool full) {
+        for (int t = 0; t < 4; ++t)
+            S->cases[t] = (full ? 0 : S->cases[t]) + static_cast<int>(c[kCntCase + t]);
+    };
+    // C loop: the current type while it has cases, then the next types in
+    // turn, back to FPmax while any of the first three has cases; then labels.
     auto c_decide = [&]() {
-        if (cases_of(st.type) > 0) return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
-        if (st.type < 3) {
-            st.type += 1;
-            return go(kOpDetect);
-        }
-        if (c[kCntCase + 0] + c[kCntCase + 1] + c[kCntCase + 2] > 0) {
-            st.type = 0;
-            return go(kOpDetect);
+        for (int guard = 0; guard < 8; ++guard) {
+            if (cases_of(st.type) > 0) return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
+            if (st.type < 3) {
+                st.type += 1;
+            } else if (S->cases[0] + S->cases[1] + S->cases[2] > 0) {
+                st.type = 0;
+            } else {
+                break;
+            }
         }
         return go(kOpRTile);
+    };
+    // refresh around the changed vertices, or a full pass when they (and
+    // their neighbours) would cover more than a quarter of the field
+    auto after_apply = [&](int sparse, int full) {
+        const long long ring = F.gr.ndim == 3 ? 15 : 7;
+        return go(static_cast<long long>(c[kCntChanged]) * ring * 4 > F.gr.n ? full : sparse);
     };
     switch (st.op) {
         case kOpStart:
@@ -1538,12 +1608,14 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             st.type = 0;
             return go(kOpPreE);
         case kOpPreE:
+            set_cases(true);
             for (int t = 0; t < 4; ++t) S->false_init[t] = c[kCntCase + t];
             S->outer_iters = 1;
             st.type = 0;
             return c_decide();
-        case kOpDdC:
-        case kOpDetect:
+        case kOpRefreshC:
+        case kOpFullC:
+            set_cases(st.op == kOpFullC);
             return c_decide();
         case kOpApplyC:
             if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
@@ -1552,7 +1624,7 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             else if (st.type == 1) S->rounds[1] += 1;
             else if (st.type == 2) S->rounds[2] += 1;
             else S->rounds[3] += 1;
-            return go(kOpDdC);
+            return after_apply(kOpRefreshC, kOpFullC);
         case kOpRTile:
             return go(kOpRJump);
         case kOpRJump:
@@ -1567,9 +1639,11 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             S->rounds_total += 1;
             S->rounds_r += 1;
             st.type = 0;
-            return go(kOpDdR);
-        case kOpDdR:
-            if (c[kCntCase + 0] + c[kCntCase + 1] + c[kCntCase + 2] + c[kCntCase + 3] > 0) {
+            return after_apply(kOpRefreshR, kOpFullR);
+        case kOpRefreshR:
+        case kOpFullR:
+            set_cases(st.op == kOpFullR);
+            if (S->cases[0] + S->cases[1] + S->cases[2] + S->cases[3] > 0) {
                 S->outer_iters += 1;
                 return c_decide();
             }
@@ -1674,6 +1748,15 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
 #pragma unroll
     for (int q = 0; q < PER; ++q) v[q] = c_prev[(s0 + q * (256 / kCntSlots)) * kSlotStride + kc];
     const EngState prev = states[p ^ 1];
+    if (prev.items == 0 && prev.op != kOpStart) {
+        // the field is done (the rest of this graph launch): carry the state over
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            states[p] = prev;
+            ctl[0] = 0;
+            if (oplog) oplog[k] = kOpDone;
+        }
+        return;
+    }
     constexpr int SW = sizeof(EngStats) / 4;
     if (threadIdx.x < SW)  // the statistics of step k - 1, word by word into LDS
         reinterpret_cast<unsigned*>(&s_stats)[threadIdx.x] = reinterpret_cast<const unsigned*>(stats + (p ^ 1))[threadIdx.x];
@@ -1755,14 +1838,20 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
     }
 }
 
-// Clears every field's marks and counter block.
+// Clears every field's marks, case bytes, dirty flags and counter block.
 __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ fields, int nf) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     for (int f = 0; f < nf; ++f) {
         const EngField& F = fields[f];
         uint4* m = reinterpret_cast<uint4*>(F.marks);
+        uint4* cs = reinterpret_cast<uint4*>(F.cases);
+        uint4* dt = reinterpret_cast<uint4*>(F.dirty);
         const int nw = (F.gr.n + 15) >> 4;
-        for (int w = tid; w < nw; w += nthr) m[w] = make_uint4(0u, 0u, 0u, 0u);
+        for (int w = tid; w < nw; w += nthr) {
+            m[w] = make_uint4(0u, 0u, 0u, 0u);
+            cs[w] = make_uint4(0u, 0u, 0u, 0u);
+            dt[w] = make_uint4(0u, 0u, 0u, 0u);
+        }
         for (int w = tid; w < kCntBlockWords; w += nthr) F.cnt[w] = 0u;
     }
 }
