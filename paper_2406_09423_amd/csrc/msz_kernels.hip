@@ -671,45 +671,57 @@ __host__ __device__ __forceinline__ int label_tiles_of(const Grid& gr) {
 
 // One label tile; su, sd: LDS arrays of the tile's vertex count.  The caller
 // separates consecutive tiles of one block with a barrier.
+//
+// Thread t owns the 4-vertex row groups starting at l = 4 t + 1024 k and
+// keeps their pointers in registers; the LDS copy is what other threads read.
+// Terminal pointers are stored as -(global id) - 1.
 template <int NDIM>
 __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs, const Grid& gr, int tile,
                                                 int* __restrict__ q_up, int* __restrict__ q_dn, int* su, int* sd) {
     using T = LabelTile<NDIM>;
     constexpr int NT = T::X * T::Y * T::Z;
-    constexpr int PER = NT / 256;
+    constexpr int G = NT / 1024;  // row groups per thread
 
     const int tx_n = (gr.nx + T::X - 1) / T::X;
     const int ty_n = (gr.ny + T::Y - 1) / T::Y;
     const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
     const int X0 = bx * T::X, Y0 = by * T::Y, Z0 = bz * T::Z;
 
-    // Thread t owns the 4-vertex row groups starting at l = 4 t + 1024 k.
-    // Terminal pointers are stored as -(global id) - 1.
     const bool vec4 = (gr.nx & 3) == 0;
+    int pu[G][4], pd[G][4];
+    unsigned d4[G];
 #pragma unroll
-    for (int k = 0; k < PER / 4; ++k) {
+    for (int k = 0; k < G; ++k) {  // the direction words first, all in flight together
         const int l0 = 4 * threadIdx.x + 1024 * k;
         const int lx0 = l0 % T::X, ly = (l0 / T::X) % T::Y, lz = l0 / (T::X * T::Y);
         const int xa = X0 + lx0, y = Y0 + ly, z = Z0 + lz;
         const bool row_in = y < gr.ny && z < gr.nz;
         const int i0 = xa + gr.nx * y + gr.nxy * z;
-        unsigned d4 = 0xFFFFFFFFu;
+        d4[k] = 0xFFFFFFFFu;
         if (row_in && vec4 && xa + 3 < gr.nx) {
-            d4 = *reinterpret_cast<const unsigned*>(dirs + i0);
+            d4[k] = *reinterpret_cast<const unsigned*>(dirs + i0);
         } else if (row_in) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (xa + j < gr.nx) d4 = (d4 & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs[i0 + j]) << (8 * j));
+                if (xa + j < gr.nx)
+                    d4[k] = (d4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs[i0 + j]) << (8 * j));
         }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const int l0 = 4 * threadIdx.x + 1024 * k;
+        const int lx0 = l0 % T::X, ly = (l0 / T::X) % T::Y, lz = l0 / (T::X * T::Y);
+        const int xa = X0 + lx0, y = Y0 + ly, z = Z0 + lz;
+        const bool row_in = y < gr.ny && z < gr.nz;
+        const int i0 = xa + gr.nx * y + gr.nxy * z;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int l = l0 + j, lx = lx0 + j;
-            int pu = -1, pd = -1;
+            const int lx = lx0 + j;
+            int p[2] = {-1, -1};
             if (row_in && xa + j < gr.nx) {
                 const int i = i0 + j;
-                const unsigned d = (d4 >> (8 * j)) & 0xFFu;
+                const unsigned d = (d4[k] >> (8 * j)) & 0xFFu;
                 const unsigned s2[2] = {d >> 4, d & 15u};
-                int p[2];
 #pragma unroll
                 for (int w = 0; w < 2; ++w) {
                     const unsigned s = s2[w];
@@ -725,36 +737,46 @@ __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs
                             p[w] = -(i + gr.off[s]) - 1;
                     }
                 }
-                pu = p[0];
-                pd = p[1];
             }
-            su[l] = pu;
-            sd[l] = pd;
+            pu[k][j] = p[0];
+            pd[k][j] = p[1];
         }
+        *reinterpret_cast<int4*>(su + l0) = make_int4(pu[k][0], pu[k][1], pu[k][2], pu[k][3]);
+        *reinterpret_cast<int4*>(sd + l0) = make_int4(pd[k][0], pd[k][1], pd[k][2], pd[k][3]);
     }
     __syncthreads();
-    // Pointer jumping in LDS: each thread jumps the pointers of its own
-    // vertices until they are terminal.  A value read from another thread's
-    // entry is always an ancestor (entries only ever move up their forest),
-    // so no barrier is needed between jumps and every jump makes progress; a
-    // pointer needs at most one jump per vertex of its in-tile path.
+    // Pointer jumping in LDS: each thread replaces each of its non-terminal
+    // pointers by the pointer stored at its target, then publishes a group's
+    // four entries with one 16-byte write.  Any entry read is an ancestor of
+    // the reader on its integral line (entries only ever move up their
+    // forest), so no barrier is needed between jumps and every jump makes
+    // progress; a pointer needs at most one jump per vertex of its in-tile
+    // path.  A group is skipped once the whole wave's copies of it are
+    // terminal; otherwise its eight reads are issued together, branch-free
+    // (a terminal pointer reads entry 0 and keeps its value).
     for (int iter = 0; iter < NT; ++iter) {
-        int pending = 0;
+        bool pending = false;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int l = 4 * threadIdx.x + 1024 * (k >> 2) + (k & 3);
-            const int a = su[l];
-            if (a >= 0) {
-                const int a2 = su[a];
-                su[l] = a2;
-                pending |= a2 >= 0;
+        for (int k = 0; k < G; ++k) {
+            bool live = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) live |= (pu[k][j] & pd[k][j]) >= 0;  // either is non-terminal
+            if (!__any(live)) continue;
+            int nu[4], nd[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                nu[j] = su[max(pu[k][j], 0)];
+                nd[j] = sd[max(pd[k][j], 0)];
             }
-            const int b = sd[l];
-            if (b >= 0) {
-                const int b2 = sd[b];
-                sd[l] = b2;
-                pending |= b2 >= 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                pu[k][j] = pu[k][j] >= 0 ? nu[j] : pu[k][j];
+                pd[k][j] = pd[k][j] >= 0 ? nd[j] : pd[k][j];
+                pending |= (pu[k][j] & pd[k][j]) >= 0;
             }
+            const int l0 = 4 * threadIdx.x + 1024 * k;
+            *reinterpret_cast<int4*>(su + l0) = make_int4(pu[k][0], pu[k][1], pu[k][2], pu[k][3]);
+            *reinterpret_cast<int4*>(sd + l0) = make_int4(pd[k][0], pd[k][1], pd[k][2], pd[k][3]);
         }
         if (!pending) break;
     }
@@ -765,7 +787,7 @@ __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs
                      : X0 + a % T::X + gr.nx * (Y0 + (a / T::X) % T::Y) + gr.nxy * (Z0 + a / (T::X * T::Y));
     };
 #pragma unroll
-    for (int k = 0; k < PER / 4; ++k) {
+    for (int k = 0; k < G; ++k) {
         const int l0 = 4 * threadIdx.x + 1024 * k;
         const int lx0 = l0 % T::X, ly = (l0 / T::X) % T::Y, lz = l0 / (T::X * T::Y);
         const int xa = X0 + lx0, y = Y0 + ly, z = Z0 + lz;
@@ -773,14 +795,16 @@ __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs
         const int i0 = xa + gr.nx * y + gr.nxy * z;
         if (vec4 && xa + 3 < gr.nx) {
             *reinterpret_cast<int4*>(q_up + i0) =
-                make_int4(global_of(su[l0]), global_of(su[l0 + 1]), global_of(su[l0 + 2]), global_of(su[l0 + 3]));
+                make_int4(global_of(pu[k][0]), global_of(pu[k][1]), global_of(pu[k][2]), global_of(pu[k][3]));
             *reinterpret_cast<int4*>(q_dn + i0) =
-                make_int4(global_of(sd[l0]), global_of(sd[l0 + 1]), global_of(sd[l0 + 2]), global_of(sd[l0 + 3]));
+                make_int4(global_of(pd[k][0]), global_of(pd[k][1]), global_of(pd[k][2]), global_of(pd[k][3]));
         } else {
-            for (int j = 0; j < 4 && xa + j < gr.nx; ++j) {
-                q_up[i0 + j] = global_of(su[l0 + j]);
-                q_dn[i0 + j] = global_of(sd[l0 + j]);
-            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (xa + j < gr.nx) {
+                    q_up[i0 + j] = global_of(pu[k][j]);
+                    q_dn[i0 + j] = global_of(pd[k][j]);
+                }
         }
     }
 }
@@ -790,8 +814,8 @@ __global__ void __launch_bounds__(256) k_label_tile(const uint8_t* __restrict__ 
                                                     int* __restrict__ q_up,
                                                     int* __restrict__ q_dn) {
     constexpr int NT = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z;
-    __shared__ int su[NT];
-    __shared__ int sd[NT];
+    __shared__ __align__(16) int su[NT];
+    __shared__ __align__(16) int sd[NT];
     label_tile_body<NDIM>(dirs, gr, xcd_logical_block(blockIdx.x, gridDim.x), q_up, q_dn, su, sd);
 }
 
