@@ -55,10 +55,12 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, Mf, mf, qu, qd, total;
+    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, tile_dirty, Mf, mf, qu, qd, qf_up, qf_dn, total;
 };
 
-Layout layout_for(int64_t n) {
+Layout layout_for(const Grid& gr) {
+    const int64_t n = gr.n;
+    const int64_t faces = label_face_words(gr);
     Layout l{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -73,10 +75,13 @@ Layout layout_for(int64_t n) {
     l.marks = take((n + 15) & ~int64_t(15));
     l.cases = take((n + 15) & ~int64_t(15));
     l.dirty = take((n + 15) & ~int64_t(15));
+    l.tile_dirty = take(label_tile_count(gr));
     l.Mf = take(n * 4);
     l.mf = take(n * 4);
     l.qu = take(n * 4);
     l.qd = take(n * 4);
+    l.qf_up = take(faces * 4);
+    l.qf_dn = take(faces * 4);
     l.total = o;
     return l;
 }
@@ -434,8 +439,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     return MSZ_OK;
 }
 
-void bind_field(EngField& F, char* w, int n) {
-    const Layout l = layout_for(n);
+void bind_field(EngField& F, char* w) {
+    const Layout l = layout_for(F.gr);
     F.L = reinterpret_cast<float*>(w + l.L);
     F.g = reinterpret_cast<float*>(w + l.g);
     F.dirs_f = reinterpret_cast<uint8_t*>(w + l.dirs_f);
@@ -443,6 +448,9 @@ void bind_field(EngField& F, char* w, int n) {
     F.marks = reinterpret_cast<uint8_t*>(w + l.marks);
     F.cases = reinterpret_cast<uint8_t*>(w + l.cases);
     F.dirty = reinterpret_cast<uint8_t*>(w + l.dirty);
+    F.tile_dirty = reinterpret_cast<uint8_t*>(w + l.tile_dirty);
+    F.qf_up = reinterpret_cast<int*>(w + l.qf_up);
+    F.qf_dn = reinterpret_cast<int*>(w + l.qf_dn);
     F.Mf = reinterpret_cast<int*>(w + l.Mf);
     F.mf = reinterpret_cast<int*>(w + l.mf);
     F.qu = reinterpret_cast<int*>(w + l.qu);
@@ -489,7 +497,7 @@ const char* msz_strerror(int code) {
 size_t msz_workspace_bytes(msz_dims d) {
     Grid gr;
     if (!make_grid(d, gr)) return 0;
-    return layout_for(gr.n).total;
+    return layout_for(gr).total;
 }
 
 int msz_tile_variants(int32_t ndim) {
@@ -517,7 +525,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
         return done(MSZ_EINVAL);
     if (int rc = check_xi(xi)) return done(rc);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Layout l = layout_for(gr.n);
+    const Layout l = layout_for(gr);
     Scratch ws;
     if (int rc = ws.get(o.workspace, o.workspace_bytes, l.total, s)) return done(rc);
     std::vector<EngField> hf(1);
@@ -532,7 +540,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     F.warm = o.warm_start;
     F.edits = edits_out;
     F.g_out = o.g_out;
-    bind_field(F, static_cast<char*>(ws.p), gr.n);
+    bind_field(F, static_cast<char*>(ws.p));
     const bool timing = (o.flags & MSZ_FLAG_TIMING) != 0;
     double ms[MSZ_N_PHASES] = {};
     int64_t launches[MSZ_N_PHASES] = {};
@@ -560,7 +568,7 @@ size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs) {
     for (int j = 0; j < n_jobs; ++j) {
         Grid gr;
         if (!make_grid(jobs[j].d, gr)) return 0;
-        total += layout_for(gr.n).total;
+        total += layout_for(gr).total;
     }
     return total;
 }
@@ -606,8 +614,8 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
         F.warm = nullptr;
         F.edits = J.edits_out;
         F.g_out = J.g_out;
-        bind_field(F, w, F.gr.n);
-        w += layout_for(F.gr.n).total;
+        bind_field(F, w);
+        w += layout_for(F.gr).total;
     }
     std::vector<EngStats> st;
     int rc = run_engine(hf, st, false, nullptr, nullptr, step_bound(cap), s);

@@ -173,7 +173,9 @@ struct EngField {
     uint8_t *dirs_f, *dirs_g, *marks;
     uint8_t *cases;  // per vertex: bit t set when it is a case of type t (FPmax, FPmin, FNmax, FNmin)
     uint8_t *dirty;  // per vertex: its directions in g must be recomputed (it or a neighbour was edited)
+    uint8_t *tile_dirty;  // per label tile: a direction of g in it changed since its last tile pass
     int *Mf, *mf, *qu, *qd;
+    int *qf_up, *qf_dn;   // per label tile and face-layer vertex: the tile pass's pointer (before compression)
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
 
@@ -189,6 +191,8 @@ struct EngStats {
 
 // Number of work items of operation op for one field (device and host).
 int eng_items_host(const EngField& F, int op);
+int label_tile_count(const Grid& gr);   // label tiles of the grid
+int label_face_words(const Grid& gr);   // label tiles x face-layer vertices of a full tile
 const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)
 const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl)

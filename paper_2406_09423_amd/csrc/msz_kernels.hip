@@ -850,25 +850,100 @@ __device__ __forceinline__ int3 face_vertex(int b) {
     }
 }
 
-__device__ __forceinline__ int load_relaxed(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_relaxed(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+int label_tile_count(const Grid& gr) { return label_tiles_of(gr); }
+int label_face_words(const Grid& gr) { return label_tiles_of(gr) * (gr.ndim == 3 ? face_count<3>() : face_count<2>()); }
+
+// Origin of a label tile.
+template <int NDIM>
+__device__ __forceinline__ int3 tile_origin(const Grid& gr, int tile) {
+    using T = LabelTile<NDIM>;
+    const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y;
+    return make_int3((tile % tx_n) * T::X, ((tile / tx_n) % ty_n) * T::Y, (tile / (tx_n * ty_n)) * T::Z);
 }
 
-// Walks q[x] to the root of x's forest, writing every step back.  The forests
-// are acyclic (every pointer goes strictly up, resp. down, the total order), so
-// the walk ends; the step cap only guards against corrupted input and is
-// reported as an error.
+// The label tile of vertex i.
+template <int NDIM>
+__device__ __forceinline__ int tile_of_vertex(const Grid& gr, int i) {
+    using T = LabelTile<NDIM>;
+    const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y;
+    const int x = i % gr.nx, y = (i / gr.nx) % gr.ny, z = NDIM == 3 ? i / gr.nxy : 0;
+    return x / T::X + tx_n * (y / T::Y + ty_n * (z / T::Z));
+}
+
+// After a tile pass of g (su, sd still hold the tile's final local pointers,
+// after a barrier): keeps the face-layer vertices' pointers, which the
+// compression then overwrites, so that a later pass over an unchanged tile
+// only has to put them back.
+template <int NDIM>
+__device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* su, const int* sd, int* qf_up,
+                                           int* qf_dn) {
+    using T = LabelTile<NDIM>;
+    constexpr int FC = face_count<NDIM>();
+    const int3 o = tile_origin<NDIM>(gr, tile);
+    auto global_of = [&](int a) {
+        return a < 0 ? -a - 1 : o.x + a % T::X + gr.nx * (o.y + (a / T::X) % T::Y) + gr.nxy * (o.z + a / (T::X * T::Y));
+    };
+    for (int b = threadIdx.x; b < FC; b += blockDim.x) {
+        const int3 l = face_vertex<NDIM>(b);
+        if (o.x + l.x >= gr.nx || o.y + l.y >= gr.ny || o.z + l.z >= gr.nz) continue;
+        const int a = l.x + T::X * (l.y + T::Y * l.z);
+        qf_up[tile * FC + b] = global_of(su[a]);
+        qf_dn[tile * FC + b] = global_of(sd[a]);
+    }
+}
+
+// The tile pass of an unchanged tile: its interior pointers are still those
+// of its last pass (the compression only writes face-layer vertices), so only
+// the face-layer pointers are put back.
+template <int NDIM>
+__device__ __forceinline__ void restore_faces(const Grid& gr, int tile, int* q_up, int* q_dn, const int* qf_up,
+                                              const int* qf_dn) {
+    constexpr int FC = face_count<NDIM>();
+    const int3 o = tile_origin<NDIM>(gr, tile);
+    for (int b = threadIdx.x; b < FC; b += blockDim.x) {
+        const int3 l = face_vertex<NDIM>(b);
+        const int x = o.x + l.x, y = o.y + l.y, z = o.z + l.z;
+        if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
+        const int i = x + gr.nx * y + gr.nxy * z;
+        q_up[i] = qf_up[tile * FC + b];
+        q_dn[i] = qf_dn[tile * FC + b];
+    }
+}
+
+// Pointer loads and stores of the compression walks.  Every value a walk can
+// read is an ancestor of the vertex it came from (what the tile pass wrote, or
+// a later shortcut on the same path), so the walks are correct whatever they
+// see of each other's writes; workgroup scope keeps them cacheable in each
+// XCD's L2 (the tile pass's results are there from the step before) instead
+// of going to memory on every hop.
+__device__ __forceinline__ int load_relaxed(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void store_relaxed(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Walks qu[x] and qd[x] to the roots of x's two forests together (two
+// independent chains, so their loads overlap), writing every step back.  The
+// forests are acyclic (every pointer goes strictly up, resp. down, the total
+// order), so the walks end; the step cap only guards against corrupted input
+// and is reported as an error.
 constexpr int kMaxWalk = 1 << 22;
-__device__ __forceinline__ bool compress_one(int* q, int x) {
-    int y = load_relaxed(q + x);
+__device__ __forceinline__ bool compress_both(int* qu, int* qd, int x) {
+    int yu = load_relaxed(qu + x), yd = load_relaxed(qd + x);
+    bool du = false, dd = false;
     for (int it = 0; it < kMaxWalk; ++it) {
-        const int z = load_relaxed(q + y);
-        if (z == y) return true;  // only roots point at themselves
-        store_relaxed(q + x, z);
-        y = z;
+        const int zu = du ? yu : load_relaxed(qu + yu);
+        const int zd = dd ? yd : load_relaxed(qd + yd);
+        if (!du) {
+            if (zu == yu) du = true;  // only roots point at themselves
+            else store_relaxed(qu + x, zu), yu = zu;
+        }
+        if (!dd) {
+            if (zd == yd) dd = true;
+            else store_relaxed(qd + x, zd), yd = zd;
+        }
+        if (du && dd) return true;
     }
     return false;
 }
@@ -888,9 +963,7 @@ __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __r
         const int x = bx * T::X + l.x, y = by * T::Y + l.y, z = bz * T::Z + l.z;
         if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
         const int i = x + gr.nx * y + gr.nxy * z;
-        const bool ok_up = compress_one(q_up, i);
-        const bool ok_dn = compress_one(q_dn, i);
-        ok = ok && ok_up && ok_dn;
+        ok = compress_both(q_up, q_dn, i) && ok;
     }
     return ok;
 }
@@ -1376,6 +1449,7 @@ __device__ __forceinline__ void refresh_chunk(const EngField& F, int item, int* 
         const int j = list[e];
         const unsigned dg = steepest_at<NDIM>(F.g, F.gr, j);
         const unsigned now = case_bits(F.dirs_f[j], dg), was = F.cases[j];
+        if (dg != F.dirs_g[j]) F.tile_dirty[tile_of_vertex<NDIM>(F.gr, j)] = 1;
         F.dirs_g[j] = static_cast<uint8_t>(dg);
         F.cases[j] = static_cast<uint8_t>(now);
 #pragma unroll
@@ -1410,14 +1484,26 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         }
         case kOpPreB:
-        case kOpRTile: {
-            const uint8_t* d = st.op == kOpPreB ? F.dirs_f : F.dirs_g;
             for (int item = lo; item < hi; ++item) {
-                label_tile_body<NDIM>(d, gr, item, F.qu, F.qd, su, sd);
+                label_tile_body<NDIM>(F.dirs_f, gr, item, F.qu, F.qd, su, sd);
                 __syncthreads();
             }
             break;
-        }
+        case kOpRTile:
+            // only tiles with a changed direction are redone; the others get
+            // their face-layer pointers back
+            for (int item = lo; item < hi; ++item) {
+                if (F.tile_dirty[item]) {
+                    label_tile_body<NDIM>(F.dirs_g, gr, item, F.qu, F.qd, su, sd);
+                    __syncthreads();
+                    save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn);
+                    if (threadIdx.x == 0) F.tile_dirty[item] = 0;
+                } else {
+                    restore_faces<NDIM>(gr, item, F.qu, F.qd, F.qf_up, F.qf_dn);
+                }
+                __syncthreads();
+            }
+            break;
         case kOpPreC:
         case kOpRJump: {
             bool ok = true;
@@ -1466,6 +1552,9 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             unsigned c[4] = {0u, 0u, 0u, 0u};
             eng_dirs<NDIM, 1>(F, F.g, F.dirs_g, lo, hi, sm, c);
             block_add<4>(c, cnt, cidx);
+            // every label tile is redone next time: this range's share of the flags
+            const long long nt = label_tiles_of(gr), items = eng_items(F, st.op);
+            for (long long t = lo * nt / items + threadIdx.x; t < hi * nt / items; t += blockDim.x) F.tile_dirty[t] = 1;
             break;
         }
         case kOpRefreshC:
