@@ -25,8 +25,8 @@
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  *    stream).  All work is enqueued on it; each call synchronises on it
  *    before returning.  The schedule of the loop runs on the device: a HIP
- *    graph of 48 steps is launched until no field is active, and one word is
- *    read back per launch.
+ *    graph of 48 steps is relaunched until the device clears a done word in
+ *    pinned host memory.
  *  - Memory: the library allocates scratch per call when no workspace is
  *    given (hipMallocAsync on the stream), and keeps one control block
  *    (about 9 MB: field table, step states, round counters, statistics, the

@@ -8,8 +8,8 @@
 //   R phase  labels of g, troublemaker detection, one apply; back to the C
 //            phase whenever the apply created a false critical point.
 // The host captures kGraphSteps steps in a HIP graph and relaunches it until
-// no field is active, reading one word back per launch.  msz_fix is the
-// one-field case of msz_fix_batch.
+// the device clears a done word in pinned host memory.
+// msz_fix is the one-field case of msz_fix_batch.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -166,6 +166,9 @@ struct EngineCtx {
     unsigned long long* tstamp = nullptr;  // profiling: kEngStampWords words per step
     unsigned* counters = nullptr;          // kCntBlockWords per field
     int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog, then 2 * kGraphSteps stamps
+    int* hflag = nullptr;      // pinned, device-mapped: 1 while a field is active (the device clears it)
+    int* hflag_dev = nullptr;  // its device address
+    hipEvent_t ev[1] = {nullptr};  // end of the last graph launch
     // cached graph
     int g_nf = -1, g_grid2 = 0, g_grid3 = 0;
     bool g_has2 = false, g_has3 = false, g_timing = false;
@@ -225,6 +228,16 @@ struct EngineCtx {
                 return MSZ_ENOMEM;
             host = static_cast<int*>(h);
         }
+        if (!hflag) {
+            void* h = nullptr;
+            void* d = nullptr;
+            if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return MSZ_ENOMEM;
+            if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) return MSZ_EDEVICE;
+            hflag = static_cast<int*>(h);
+            hflag_dev = static_cast<int*>(d);
+        }
+        for (hipEvent_t& e : ev)
+            if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MSZ_EDEVICE;
         device = dev;
         return MSZ_OK;
     }
@@ -257,7 +270,7 @@ struct EngineCtx {
                 unsigned long long* ts = timing ? tstamp + st * kEngStampWords : nullptr;
                 int* log = timing ? oplog : nullptr;
                 int stp = st;
-                void* a[] = {&fields, &states, &stats, &counters, &ctl, &log, &stp, &ts};
+                void* a[] = {&fields, &states, &states, &stats, &counters, &ctl, &hflag_dev, &log, &stp, &ts};
                 if (!add_kernel(fn, dim3(grid), dim3(256), a)) return MSZ_EDEVICE;
             }
         }
@@ -279,7 +292,7 @@ struct EngineCtx {
             void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp, &counters};
             if (!add_kernel(eng_decide_kernel(), dim3(nf), dim3(256), d)) return MSZ_EDEVICE;
             if (nf > 1) {
-                void* c[] = {&fields, &nxt, &nf, &pre2, &pre3, &ctl};
+                void* c[] = {&fields, &nxt, &nf, &pre2, &pre3, &ctl, &hflag_dev};
                 if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
             }
         }
@@ -399,29 +412,42 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         return MSZ_EDEVICE;
     int64_t steps = 0;
     int rc = MSZ_OK;
-    for (;;) {
-        if (timing && hipMemsetAsync(E.tstamp, 0, EngineCtx::stamp_bytes(), s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+    if (!timing) {
+        // Relaunch until the device clears the done word (pinned host memory):
+        // no read-back copy per launch.
+        volatile int* flag = E.hflag;
+        *flag = 1;
+        for (;;) {
+            if (hipGraphLaunch(E.exec, s) != hipSuccess || hipEventRecord(E.ev[0], s) != hipSuccess ||
+                hipEventSynchronize(E.ev[0]) != hipSuccess) {
+                rc = MSZ_EDEVICE;
+                break;
+            }
+            steps += kGraphSteps;
+            if (*flag == 0) break;
+            if (steps > max_steps) { rc = MSZ_EDEVICE; break; }
+        }
+    }
+    while (timing) {  // one launch at a time, with the schedule and clock stamps of each step read back
+        if (hipMemsetAsync(E.tstamp, 0, EngineCtx::stamp_bytes(), s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (hipGraphLaunch(E.exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (hipMemcpyAsync(E.host, E.ctl, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (timing && (hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) !=
-                           hipSuccess ||
-                       hipMemcpyAsync(E.host_stamps(), E.tstamp, EngineCtx::stamp_bytes(), hipMemcpyDeviceToHost, s) !=
-                           hipSuccess)) {
+        if (hipMemcpyAsync(E.host, E.ctl, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(E.host_stamps(), E.tstamp, EngineCtx::stamp_bytes(), hipMemcpyDeviceToHost, s) !=
+                hipSuccess) {
             rc = MSZ_EDEVICE;
             break;
         }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (timing) {
-            for (int k = 0; k < kGraphSteps; ++k) {
-                const int ph = phase_of_op(E.host[1 + k]);
-                last_schedule().push_back(ph);
-                const unsigned long long* t = E.host_stamps() + k * kEngStampWords;
-                unsigned long long end = 0;
-                for (int w = 1; w < kEngStampWords; ++w) end = std::max(end, t[w]);
-                if (ph >= 0 && end >= t[0]) {
-                    ms[ph] += static_cast<double>(end - t[0]) / wall_khz;
-                    launches[ph] += 1;
-                }
+        for (int k = 0; k < kGraphSteps; ++k) {
+            const int ph = phase_of_op(E.host[1 + k]);
+            last_schedule().push_back(ph);
+            const unsigned long long* t = E.host_stamps() + k * kEngStampWords;
+            unsigned long long end = 0;
+            for (int w = 1; w < kEngStampWords; ++w) end = std::max(end, t[w]);
+            if (ph >= 0 && end >= t[0]) {
+                ms[ph] += static_cast<double>(end - t[0]) / wall_khz;
+                launches[ph] += 1;
             }
         }
         steps += kGraphSteps;

@@ -195,8 +195,8 @@ int label_tile_count(const Grid& gr);   // label tiles of the grid
 int label_face_words(const Grid& gr);   // label tiles x face-layer vertices of a full tile
 const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)
-const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl)
+const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl, hflag)
 const void* eng_init_kernel();          // k_eng_init(fields, nf)
-const void* eng_step1_kernel(int ndim); // k_eng_step1<ndim>(fields, states, stats, cnt3, ctl, oplog, k, ts)
+const void* eng_step1_kernel(int ndim); // k_eng_step1<ndim>(fields, states, states, stats, cnt3, ctl, hflag, oplog, k, ts)
 
 }  // namespace msz

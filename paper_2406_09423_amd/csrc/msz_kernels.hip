@@ -1836,11 +1836,13 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
 // (a step reads k - 1's and block 0 writes k's); counter sets by k % 3 (a step
 // reads set k - 1, adds into set k and clears set k + 1, which step k - 1
 // read and step k + 1 fills).  stats[2] receives the statistics once the
-// field is done.  A graph holds kEngTimeSlots (a multiple of 6) steps, so the
-// parities continue across launches.
+// field is done, and hflag (pinned host memory, if set) is cleared then.  A
+// graph holds kEngTimeSlots (a multiple of 6) steps, so the parities continue
+// across launches.
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ fields, EngState* states,
-                                                   EngStats* stats, unsigned* cnt3, int* ctl, int* oplog, int k,
+                                                   const EngState* __restrict__ states_in, EngStats* stats,
+                                                   unsigned* cnt3, int* ctl, int* hflag, int* oplog, int k,
                                                    unsigned long long* ts) {
     __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
     __shared__ unsigned part[256];
@@ -1854,13 +1856,15 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
     unsigned* c_prev = cnt3 + ((k + 2) % 3) * kCntBlockWords;
     unsigned* c_cur = cnt3 + (k % 3) * kCntBlockWords;
     unsigned* c_next = cnt3 + ((k + 1) % 3) * kCntBlockWords;
-    // all loads first: the counters of step k - 1, its state and statistics
+    // all loads first: the state of step k - 1 (a scalar load: states_in is
+    // the same array, read-only here, as this step writes only states[p]),
+    // its counters and statistics
+    const EngState prev = states_in[p ^ 1];
     const int kc = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
     constexpr int PER = kSlots / (256 / kCntSlots);
     unsigned v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) v[q] = c_prev[(s0 + q * (256 / kCntSlots)) * kSlotStride + kc];
-    const EngState prev = states[p ^ 1];
     if (prev.items == 0 && prev.op != kOpStart) {
         // the field is done (the rest of this graph launch): carry the state over
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1898,6 +1902,8 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
             stats[p] = s_stats;
             if (ns.items == 0) stats[2] = s_stats;
             ctl[0] = ns.items > 0 ? 1 : 0;
+            // the host waits for this word (pinned host memory) to drop to 0
+            if (ns.items == 0 && hflag) __hip_atomic_store(hflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             if (oplog) oplog[k] = ns.items > 0 ? ns.op : kOpDone;
         }
     }
@@ -1921,7 +1927,7 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
 // Prefix sums of the next step's items per dimension, and the active count
 // (one block of kEngMaxFields threads, one field each).
 __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
-                                                           int nf, int* pre2, int* pre3, int* ctl) {
+                                                           int nf, int* pre2, int* pre3, int* ctl, int* hflag) {
     __shared__ int s2[kEngMaxFields], s3[kEngMaxFields];
     const int f = threadIdx.x;
     int a2 = 0, a3 = 0;
@@ -1947,7 +1953,9 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
     if (f == 0) {
         pre2[0] = 0;
         pre3[0] = 0;
-        ctl[0] = (s2[nf - 1] + s3[nf - 1]) > 0 ? 1 : 0;
+        const bool active = (s2[nf - 1] + s3[nf - 1]) > 0;
+        ctl[0] = active ? 1 : 0;
+        if (!active && hflag) __hip_atomic_store(hflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
