@@ -588,56 +588,6 @@ __device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* 
         if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
 }
 
-// R loop: edits every marked vertex of the 16-vertex group w once (the
-// round's union of proposals) and clears the group's marks.  m: the group's
-// marks, already loaded and not all zero; padding bytes past n are never set.
-template <int NDIM>
-__device__ __forceinline__ void apply_marks(float* __restrict__ g, const float* __restrict__ L,
-                                            uint8_t* __restrict__ marks, uint8_t* __restrict__ dirty,
-                                            const Grid& gr, int w, const uint4 m, unsigned& changed) {
-    const unsigned part[4] = {m.x, m.y, m.z, m.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        unsigned bits = part[q];
-        while (bits) {
-            const int b = (__ffs(bits) - 1) >> 3;
-            bits &= ~(0xFFu << (8 * b));
-            edit_vertex<NDIM>(g, L, dirty, gr, w * 16 + q * 4 + b, changed);
-        }
-    }
-    reinterpret_cast<uint4*>(marks)[w] = make_uint4(0u, 0u, 0u, 0u);
-}
-
-// C loop: edits the targets of the cases of `type` among the 16-vertex group
-// w (its case bytes m, already loaded).  FPmax and FNmin edit the vertex
-// itself; FPmin and FNmax edit a neighbour, which several cases may share, so
-// the first to set the target's mark (an atomic OR on its word) edits it.
-template <int NDIM>
-__device__ __forceinline__ void apply_cases(float* __restrict__ g, const float* __restrict__ L,
-                                            const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
-                                            uint8_t* __restrict__ marks, uint8_t* __restrict__ dirty,
-                                            const Grid& gr, int w, const uint4 m, int type, unsigned& changed) {
-    const unsigned part[4] = {m.x, m.y, m.z, m.w};
-    const unsigned sel = 0x01010101u << type;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        unsigned bits = part[q] & sel;
-        while (bits) {
-            const int b = (__ffs(bits) - 1) >> 3;
-            bits &= bits - 1u;
-            const int i = w * 16 + q * 4 + b;
-            if (type == 0 || type == 3) {
-                edit_vertex<NDIM>(g, L, dirty, gr, i, changed);
-                continue;
-            }
-            const int t = i + gr.off[type == 1 ? (dirs_f[i] & 15u) : (dirs_g[i] >> 4)];
-            const unsigned bit = 1u << (8 * (t & 3));
-            if ((atomicOr(reinterpret_cast<unsigned*>(marks + (t & ~3)), bit) & bit) == 0u)
-                edit_vertex<NDIM>(g, L, dirty, gr, t, changed);
-        }
-    }
-}
-
 // --------------------------------------------------------------- labels ---
 //
 // Pointer jumping along the forests of steepest ascent and descent (Sec. 6.2).
@@ -1398,64 +1348,100 @@ __device__ __forceinline__ unsigned steepest_at(const float* __restrict__ g, con
     return (b.us << 4) | b.ds;
 }
 
-// Refresh of one 4096-vertex chunk: its dirty vertices are gathered into an
-// LDS list (so the block's threads share them evenly), their directions and
-// case bytes recomputed, and the dirty flags and marks of the chunk cleared.
-// c receives the changes of the case counts (modulo 2^32).
-template <int NDIM>
-__device__ __forceinline__ void refresh_chunk(const EngField& F, int item, int* list, int* wsum, unsigned (&c)[4]) {
-    const int w = item * (kEngChunk / 16) + threadIdx.x;
-    const bool in = w < ((F.gr.n + 15) >> 4);
-    const uint4 d = in ? reinterpret_cast<const uint4*>(F.dirty)[w] : make_uint4(0u, 0u, 0u, 0u);
-    const unsigned part[4] = {d.x & 0x01010101u, d.y & 0x01010101u, d.z & 0x01010101u, d.w & 0x01010101u};
-    const int cnt = __popc(part[0]) + __popc(part[1]) + __popc(part[2]) + __popc(part[3]);
-    // exclusive prefix of cnt over the block: within the wave, then over the waves
+// Runs fn(v) for every flagged vertex v of the chunks [lo, hi) (kEngChunk
+// vertices each; thread t loads the 16 flag bytes t of a chunk, and a byte
+// flags its vertex when it has a bit of `mask` set; bytes past the grid are
+// never set).  The flagged vertices are first gathered into an LDS list so
+// that all threads of the block work on them at once: one memory round trip
+// for the whole range instead of one per vertex and thread.  after_load(w)
+// runs once per loaded word w that flagged something, after it was read.
+// list: LDS of kEngChunk ints; wsum: 4 ints.
+template <typename Fn, typename AfterLoad>
+__device__ __forceinline__ void for_flagged(const uint8_t* flags, int n, int lo, int hi, unsigned mask, int* list,
+                                            int* wsum, Fn&& fn, AfterLoad&& after_load) {
+    constexpr int MAXW = 4;  // chunks gathered together
+    const int nw = (n + 15) >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int incl = cnt;
+    for (int c0 = lo; c0 < hi; c0 += MAXW) {
+        unsigned m[MAXW][4];
+        int cnt = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int base = 0, total = 0;
+        for (int k = 0; k < MAXW; ++k) {
+            const int w = (c0 + k) * (kEngChunk / 16) + threadIdx.x;
+            const uint4 u = (c0 + k < hi && w < nw) ? reinterpret_cast<const uint4*>(flags)[w]
+                                                    : make_uint4(0u, 0u, 0u, 0u);
+            m[k][0] = u.x & mask, m[k][1] = u.y & mask, m[k][2] = u.z & mask, m[k][3] = u.w & mask;
+        }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int t = wsum[k];
-        base += k < wave ? t : 0;
-        total += t;
-    }
-    if (total == 0) {
-        __syncthreads();  // wsum is rewritten by the next chunk
-        return;
-    }
-    int pos = base + incl - cnt;
+        for (int k = 0; k < MAXW; ++k) {
+            const unsigned any = m[k][0] | m[k][1] | m[k][2] | m[k][3];
+            if (any) after_load((c0 + k) * (kEngChunk / 16) + threadIdx.x);
+            // one flagged vertex per byte: count the bytes with a bit set
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        unsigned bits = part[q];
-        while (bits) {
-            const int b = (__ffs(bits) - 1) >> 3;
-            bits &= bits - 1u;
-            list[pos++] = w * 16 + q * 4 + b;
+            for (int q = 0; q < 4; ++q) {
+                const unsigned b = m[k][q];
+                const unsigned nz = (b | (b >> 1) | (b >> 2) | (b >> 3) | (b >> 4) | (b >> 5) | (b >> 6) | (b >> 7)) &
+                                    0x01010101u;
+                m[k][q] = nz;
+                cnt += __popc(nz);
+            }
+        }
+        // exclusive prefix of cnt over the block
+        int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int base = 0, total = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int t = wsum[k];
+            base += k < wave ? t : 0;
+            total += t;
+        }
+        __syncthreads();  // wsum is rewritten by the next range
+        // the list holds kEngChunk entries; more are done in several passes
+        for (int pass = 0; pass * kEngChunk < total; ++pass) {
+            const int p0 = pass * kEngChunk;
+            int pos = base + incl - cnt;
+            if (pos < p0 + kEngChunk && pos + cnt > p0) {
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        unsigned bits = m[k][q];
+                        while (bits) {
+                            const int b = (__ffs(bits) - 1) >> 3;
+                            bits &= bits - 1u;
+                            if (pos >= p0 && pos < p0 + kEngChunk)
+                                list[pos - p0] = (c0 + k) * kEngChunk + 16 * threadIdx.x + 4 * q + b;
+                            ++pos;
+                        }
+                    }
+            }
+            __syncthreads();
+            const int np = min(kEngChunk, total - p0);
+            for (int e = threadIdx.x; e < np; e += blockDim.x) fn(list[e]);
+            __syncthreads();  // the list is rewritten next
         }
     }
-    if (cnt) {
-        reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
-        reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-        const int j = list[e];
-        const unsigned dg = steepest_at<NDIM>(F.g, F.gr, j);
-        const unsigned now = case_bits(F.dirs_f[j], dg), was = F.cases[j];
-        if (dg != F.dirs_g[j]) F.tile_dirty[tile_of_vertex<NDIM>(F.gr, j)] = 1;
-        F.dirs_g[j] = static_cast<uint8_t>(dg);
-        F.cases[j] = static_cast<uint8_t>(now);
+}
+
+// Directions and case byte of vertex j recomputed from g; c receives the
+// change of each case count (modulo 2^32), and j's label tile is flagged if
+// its direction changed.
+template <int NDIM>
+__device__ __forceinline__ void refresh_vertex(const EngField& F, int j, unsigned (&c)[4]) {
+    const unsigned dg = steepest_at<NDIM>(F.g, F.gr, j);
+    const unsigned now = case_bits(F.dirs_f[j], dg), was = F.cases[j];
+    if (dg != F.dirs_g[j]) F.tile_dirty[tile_of_vertex<NDIM>(F.gr, j)] = 1;
+    F.dirs_g[j] = static_cast<uint8_t>(dg);
+    F.cases[j] = static_cast<uint8_t>(now);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) c[t] += ((now >> t) & 1u) - ((was >> t) & 1u);
-    }
-    __syncthreads();  // the list and wsum are rewritten by the next chunk
+    for (int t = 0; t < 4; ++t) c[t] += ((now >> t) & 1u) - ((was >> t) & 1u);
 }
 
 template <int NDIM>
@@ -1514,33 +1500,39 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
         case kOpPreD:
             for (int item = lo; item < hi; ++item) label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf);
             break;
-        case kOpApplyC:
-        case kOpApplyR: {
-            // the case bytes (C) or marks (R) of up to four items are loaded before any is applied
+        case kOpApplyC: {
+            // the targets of the cases of the current type
             unsigned changed = 0;
-            const int nw = (gr.n + 15) >> 4;
-            const bool c_loop = st.op == kOpApplyC;
-            const uint4* mw = reinterpret_cast<const uint4*>(c_loop ? F.cases : F.marks);
-            const unsigned sel = c_loop ? 0x01010101u << st.type : 0xFFFFFFFFu;
-            auto load = [&](int item) {
-                const int w = item * (kEngChunk / 16) + threadIdx.x;
-                return (item < hi && w < nw) ? mw[w] : make_uint4(0u, 0u, 0u, 0u);
-            };
-            auto run = [&](int item, const uint4 m) {
-                if (((m.x | m.y | m.z | m.w) & sel) == 0u) return;
-                const int w = item * (kEngChunk / 16) + threadIdx.x;
-                if (c_loop)
-                    apply_cases<NDIM>(F.g, F.L, F.dirs_f, F.dirs_g, F.marks, F.dirty, gr, w, m, st.type, changed);
-                else
-                    apply_marks<NDIM>(F.g, F.L, F.marks, F.dirty, gr, w, m, changed);
-            };
-            for (int base = lo; base < hi; base += 4) {
-                const uint4 m0 = load(base), m1 = load(base + 1), m2 = load(base + 2), m3 = load(base + 3);
-                run(base, m0);
-                run(base + 1, m1);
-                run(base + 2, m2);
-                run(base + 3, m3);
-            }
+            int* list = reinterpret_cast<int*>(smem);
+            const int type = st.type;
+            for_flagged(
+                F.cases, gr.n, lo, hi, 0x01010101u << type, list, list + kEngChunk,
+                [&](int i) {
+                    if (type == 0 || type == 3) {
+                        edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, i, changed);
+                        return;
+                    }
+                    // FPmin and FNmax targets may be shared: the first to set
+                    // the target's mark (an atomic OR on its word) edits it
+                    const int t = i + gr.off[type == 1 ? (F.dirs_f[i] & 15u) : (F.dirs_g[i] >> 4)];
+                    const unsigned bit = 1u << (8 * (t & 3));
+                    if ((atomicOr(reinterpret_cast<unsigned*>(F.marks + (t & ~3)), bit) & bit) == 0u)
+                        edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, t, changed);
+                },
+                [](int) {});
+            unsigned v[1] = {changed};
+            const int idx[1] = {kCntChanged};
+            block_add<1>(v, cnt, idx);
+            break;
+        }
+        case kOpApplyR: {
+            // the marked troublemaker targets (each marked once), marks cleared
+            unsigned changed = 0;
+            int* list = reinterpret_cast<int*>(smem);
+            for_flagged(
+                F.marks, gr.n, lo, hi, 0xFFFFFFFFu, list, list + kEngChunk,
+                [&](int t) { edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, t, changed); },
+                [&](int w) { reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u); });
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
             block_add<1>(v, cnt, idx);
@@ -1559,10 +1551,17 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
         }
         case kOpRefreshC:
         case kOpRefreshR: {
+            // directions and cases of the flagged vertices; their flags and
+            // marks are cleared
             unsigned c[4] = {0u, 0u, 0u, 0u};
             int* list = reinterpret_cast<int*>(smem);
-            int* wsum = list + kEngChunk;
-            for (int item = lo; item < hi; ++item) refresh_chunk<NDIM>(F, item, list, wsum, c);
+            for_flagged(
+                F.dirty, gr.n, lo, hi, 0xFFFFFFFFu, list, list + kEngChunk,
+                [&](int j) { refresh_vertex<NDIM>(F, j, c); },
+                [&](int w) {
+                    reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
+                    reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
+                });
             block_add<4>(c, cnt, cidx);
             break;
         }
