@@ -166,7 +166,7 @@ struct EngineCtx {
     unsigned long long* tstamp = nullptr;  // profiling: kEngStampWords words per step
     unsigned* counters = nullptr;          // kCntBlockWords per field
     int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog, then 2 * kGraphSteps stamps
-    int* hflag = nullptr;      // pinned, device-mapped: 1 while a field is active (the device clears it)
+    int* hflag = nullptr;      // pinned, device-mapped: [0] 1 while active (the device clears it), final stats from word kHostStatsWord
     int* hflag_dev = nullptr;  // its device address
     hipEvent_t ev[1] = {nullptr};  // end of the last graph launch
     // cached graph
@@ -231,7 +231,8 @@ struct EngineCtx {
         if (!hflag) {
             void* h = nullptr;
             void* d = nullptr;
-            if (hipHostMalloc(&h, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return MSZ_ENOMEM;
+            static_assert((kHostStatsWord + sizeof(EngStats) / 4) * 4 <= 512, "host word block");
+            if (hipHostMalloc(&h, 512, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) return MSZ_ENOMEM;
             if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) return MSZ_EDEVICE;
             hflag = static_cast<int*>(h);
             hflag_dev = static_cast<int*>(d);
@@ -386,21 +387,31 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         E.drop_graph();
         return rc;
     }
-    if (single) {  // the step kernel decides from "step -1": state Start, zero counters
-        hs[0] = EngState{kOpDone, 0, 0, 0};
-        hs[1] = EngState{kOpStart, 0, 1, 0};
-        MSZ_HIP(hipMemsetAsync(E.counters, 0, sizeof(unsigned) * 3 * kCntBlockWords, s));
-    }
-    const int one = 1;
-    MSZ_HIP(hipMemcpyAsync(E.fields, hf.data(), sizeof(EngField) * nf, hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemcpyAsync(E.states, hs.data(), sizeof(EngState) * 2 * nf, hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemcpyAsync(E.ctl, &one, sizeof(int), hipMemcpyHostToDevice, s));
-    MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * std::max(nf, 3), s));
-    int total = 0;
-    for (const EngField& F : hf) total = std::max(total, (F.gr.n + 15) >> 4);
-    {
+    volatile int* flag = E.hflag;
+    *flag = 1;  // cleared by the device when the work is done
+    if (single) {
+        // one setup kernel: field entry, start states, counters, statistics,
+        // marks, case bytes and dirty flags (no uploads, no memsets)
+        EngField F = hf[0];
+        EngField* fp = E.fields;
+        EngState* sp = E.states;
+        EngStats* tp = E.stats;
+        unsigned* cp = E.counters;
+        int* lp = E.ctl;
+        void* a[] = {&F, &fp, &sp, &tp, &cp, &lp};
+        const int nw = (F.gr.n + 15) >> 4;
+        MSZ_HIP(hipLaunchKernel(eng_setup1_kernel(), dim3(std::max(1, std::min(2048, (nw + 255) / 256))), dim3(256),
+                                a, 0, s));
+    } else {
+        const int one = 1;
+        MSZ_HIP(hipMemcpyAsync(E.fields, hf.data(), sizeof(EngField) * nf, hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.states, hs.data(), sizeof(EngState) * 2 * nf, hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.ctl, &one, sizeof(int), hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * nf, s));
+        int total = 0;
+        for (const EngField& F : hf) total = std::max(total, (F.gr.n + 15) >> 4);
         EngField* fp = E.fields;
         int nfv = nf;
         void* a[] = {&fp, &nfv};
@@ -415,8 +426,6 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     if (!timing) {
         // Relaunch until the device clears the done word (pinned host memory):
         // no read-back copy per launch.
-        volatile int* flag = E.hflag;
-        *flag = 1;
         for (;;) {
             if (hipGraphLaunch(E.exec, s) != hipSuccess || hipEventRecord(E.ev[0], s) != hipSuccess ||
                 hipEventSynchronize(E.ev[0]) != hipSuccess) {
@@ -459,8 +468,14 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         return rc;
     }
     st.resize(nf);
-    // one field: the statistics the step kernel stored when the field was done
-    MSZ_HIP(hipMemcpyAsync(st.data(), single ? E.stats + 2 : E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
+    if (single) {
+        // the step kernel wrote the final statistics into the pinned host words
+        // before clearing the done word; the launch that did so has completed
+        if (timing) MSZ_HIP(hipStreamSynchronize(s));
+        std::memcpy(st.data(), const_cast<const int*>(E.hflag) + kHostStatsWord, sizeof(EngStats));
+        return MSZ_OK;
+    }
+    MSZ_HIP(hipMemcpyAsync(st.data(), E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
     MSZ_HIP(hipStreamSynchronize(s));
     return MSZ_OK;
 }

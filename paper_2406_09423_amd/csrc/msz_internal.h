@@ -140,6 +140,7 @@ constexpr int kEngMaxFields = 1024;
 constexpr int kEngTimeSlots = 48;                   // steps per graph launch (a multiple of 2 and 3)
 constexpr int kEngStampWords = 65;                  // per timed step: start, then 64 slots of block ends
 constexpr int kEngChunk = 4096;                     // vertices per flat work item
+constexpr int kHostStatsWord = 32;                  // final statistics in the host word block, from word 32
 
 enum EngOp : int {
     kOpPreA = 0,   // validation, floors, start field
@@ -197,6 +198,7 @@ const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)
 const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl, hflag)
 const void* eng_init_kernel();          // k_eng_init(fields, nf)
+const void* eng_setup1_kernel();        // k_eng_setup1(F, fields, states, stats, cnt3, ctl)
 const void* eng_step1_kernel(int ndim); // k_eng_step1<ndim>(fields, states, states, stats, cnt3, ctl, hflag, oplog, k, ts)
 
 }  // namespace msz

@@ -1901,8 +1901,16 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
             stats[p] = s_stats;
             if (ns.items == 0) stats[2] = s_stats;
             ctl[0] = ns.items > 0 ? 1 : 0;
-            // the host waits for this word (pinned host memory) to drop to 0
-            if (ns.items == 0 && hflag) __hip_atomic_store(hflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (ns.items == 0 && hflag) {
+                // the final statistics, then the done word, into pinned host
+                // memory (the host waits for the word to drop to 0)
+                constexpr int SW = sizeof(EngStats) / 4;
+                unsigned* hs = reinterpret_cast<unsigned*>(hflag) + kHostStatsWord;
+                for (int w = 0; w < SW; ++w)
+                    __hip_atomic_store(hs + w, reinterpret_cast<const unsigned*>(&s_stats)[w], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(hflag, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
             if (oplog) oplog[k] = ns.items > 0 ? ns.op : kOpDone;
         }
     }
@@ -1958,6 +1966,31 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
     }
 }
 
+// Start of a one-field run: the field table entry (passed by value), the
+// states of "step -1" (done) and step 0 (start), the three counter sets, the
+// statistics, the active word, and the field's marks, case bytes and dirty
+// flags -- everything the host would otherwise upload or clear one call at a
+// time.
+__global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* fields, EngState* states,
+                                                    EngStats* stats, unsigned* cnt3, int* ctl) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
+    if (tid == 0) {
+        fields[0] = F;
+        states[0] = EngState{kOpDone, 0, 0, 0};
+        states[1] = EngState{kOpStart, 0, 1, 0};
+        ctl[0] = 1;
+    }
+    for (int w = tid; w < 3 * kCntBlockWords; w += nthr) cnt3[w] = 0u;
+    constexpr int SW = 3 * static_cast<int>(sizeof(EngStats) / 4);
+    for (int w = tid; w < SW; w += nthr) reinterpret_cast<unsigned*>(stats)[w] = 0u;
+    const int nw = (F.gr.n + 15) >> 4;
+    for (int w = tid; w < nw; w += nthr) {
+        reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(F.cases)[w] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
 // Clears every field's marks, case bytes, dirty flags and counter block.
 __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ fields, int nf) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
@@ -1985,5 +2018,6 @@ const void* eng_step1_kernel(int ndim) {
 }
 const void* eng_scan_kernel() { return reinterpret_cast<const void*>(&k_eng_scan); }
 const void* eng_init_kernel() { return reinterpret_cast<const void*>(&k_eng_init); }
+const void* eng_setup1_kernel() { return reinterpret_cast<const void*>(&k_eng_setup1); }
 
 }  // namespace msz
