@@ -249,9 +249,20 @@ def bench_learned(msz, torch, dev, steps):
             raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
         checked(msz, fd, g, xi)
         _, _, _, stt = fn(True)
-        out[name] = {"ms": round(ms, 3), "value": round(fd.numel() / ms / 1e6, 4),
+        n = fd.numel()
+        phases = {}
+        for k, v in stt["timing"].items():  # one timed call: per-operation step times on 512^3
+            if not v["launches"] or k == "net":
+                continue
+            us = v["ms"] / v["launches"] * 1e3
+            b = BYTES_PER_VERTEX.get(k)
+            phases[k] = {"launches": v["launches"], "avg_us": round(us, 2),
+                         "algorithmic_GBps": round(b * n / (us * 1e-6) / 1e9, 1) if b else None,
+                         "frac_of_hbm_peak": round(b * n / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if b else None}
+        out[name] = {"ms": round(ms, 3), "value": round(n / ms / 1e6, 4),
                      "rounds": sum(st["rounds"]) + st["rounds_r"], "outer_iters": st["outer_iters"],
-                     "n_edited": st["n_edited"], "net_ms": round(stt["timing"]["net"]["ms"], 3)}
+                     "n_edited": st["n_edited"], "net_ms": round(stt["timing"]["net"]["ms"], 3),
+                     "phases": phases}
         log(f"bench: {name} 512^3 {ms:.2f} ms, rounds {out[name]['rounds']}")
     out["speedup"] = round(out["plain"]["ms"] / out["learned"]["ms"], 4)
     out["unit"] = "Gvertices/s"

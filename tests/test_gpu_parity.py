@@ -139,6 +139,29 @@ def test_fix_ragged_multi_tile_2d_and_3d(msz):
     assert assert_fix_parity(msz, f3, synth.quantize(f3, xi3), xi3)[0] == msz.OK
 
 
+def test_full_and_incremental_passes(msz):
+    """An apply that changes many values is followed by a full pass over g, one
+    that changes few by a refresh of the flagged vertices only (and R rounds
+    redo only the changed label tiles).  A fine checkerboard under a flat
+    decompression has false maxima at about a sixth of the vertices, so its
+    FNmax rounds start dense and thin out; the schedule shows both kinds of
+    pass and the result is still the oracle's, bit for bit."""
+    rng = np.random.default_rng(19)
+    for shape in ((90, 120), (20, 22, 24)):
+        parity = np.indices(shape).sum(axis=0) % 2
+        f = (0.5 + 1e-3 * parity + 1e-4 * rng.uniform(0, 1, size=shape)).astype(np.float32)
+        xi = np.float32(1e-2)
+        fh = synth.quantize(f, xi)
+        _say("fix checkerboard", shape)
+        rc, st = assert_fix_parity(msz, f, fh, xi)
+        assert rc == msz.OK and st["rounds_r"] >= 1 and st["false_init"][2] * 4 * (7 if len(shape) == 2 else 15) > f.size
+        rc2, _, _, st2 = msz.fix(dev(f), dev(fh), xi, timing=True)
+        assert rc2 == rc and st2["rounds"] == st["rounds"]
+        names = [msz.PHASES[k] for k in msz.last_schedule() if k >= 0]
+        assert names.count("dirs_detect") >= 2, names.count("dirs_detect")  # the first pass and a full one
+        assert names.count("refresh") >= 1
+
+
 def test_fix_turbulence_64(msz):
     f, fh, xi = synth.turb3d(n=64, nblobs=8)[0]
     _say("fix 3D 64^3 turbulence")
