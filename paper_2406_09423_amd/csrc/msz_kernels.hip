@@ -3,11 +3,15 @@
 // Data layout in HBM (one field of n vertices, x fastest):
 //   h / g / L      float32[n]
 //   dirs           uint8[n]   high nibble = ascent slot, low nibble = descent slot, 0xF = self
-//   marks          uint8[n]   1 = "halve this vertex in the pending round" (padded to 16 B)
+//   cases          uint8[n]   bit t: the vertex is a C-loop case of type t (padded to 16 B)
+//   marks          uint8[n]   troublemaker targets of the pending R round, or the claim
+//                             of a shared C-loop target (padded to 16 B)
+//   dirty          uint8[n]   directions to recompute after an apply (padded to 16 B)
 //   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests
-//   cnt            uint32[kSlots][kSlotStride] round counters, read back and summed by
-//                  the host; block b adds into slot b % kSlots so that no cache line
-//                  takes more than a few hundred atomics per launch
+//   qf_up, qf_dn   int32      per label tile and face-layer vertex, its tile-pass pointer
+//   cnt            uint32[kSlots][kSlotStride] round counters; block b adds into slot
+//                  b % kSlots so that no cache line takes more than a few hundred
+//                  atomics per launch
 //
 // Neighbour slots (Sec. 3 PL mesh; 2D uses slots 0..5, 3D all 14):
 //   0 (+1,0,0)  1 (-1,0,0)  2 (0,+1,0)  3 (0,-1,0)  4 (+1,+1,0)  5 (-1,-1,0)
@@ -47,8 +51,8 @@ __device__ __forceinline__ void block_add(unsigned (&v)[K], unsigned* dst, const
     }
 }
 
-// Proposals of one round form a set: every proposer of target t stores the
-// same byte, so plain (idempotent) byte stores need no atomics.
+// Troublemaker proposals of one R round form a set: every proposer of target
+// t stores the same byte, so plain (idempotent) byte stores need no atomics.
 __device__ __forceinline__ void mark(uint8_t* marks, int t) { marks[t] = 1; }
 
 // One decreasing edit (Eqs. 2-6): halfway to the floor, snapped to it when
