@@ -111,8 +111,6 @@ namespace msz {
 // Validates dims (ndim 2 or 3, nz == 1 in 2D, positive sides, n < 2^31) and fills gr.
 bool make_grid(const msz_dims& d, Grid& gr);
 
-void launch_validate_init(const float* f, const float* fhat, const float* warm, float xi, int n,
-                          float* L, float* g, unsigned* cnt, hipStream_t s);
 void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s);
 void launch_dirs(const float* h, const Grid& gr, int variant, uint8_t* dirs_out, hipStream_t s);
 void launch_label_tile(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, hipStream_t s);
@@ -120,13 +118,8 @@ void launch_label_compress(const Grid& gr, int* q_up, int* q_dn, unsigned* cnt, 
 void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, unsigned* cnt,
                           hipStream_t s);
 void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, hipStream_t s);
-void launch_detect_r(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* q_up, const int* q_dn,
-                     const int* Mf, const int* mf, const Grid& gr, uint8_t* marks, unsigned* cnt,
-                     hipStream_t s);
 void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu, const int* qfd,
                     const int* qgu, const int* qgd, int n, unsigned* cnt, hipStream_t s);
-void launch_delta(const float* g, const float* fhat, int n, float* delta, float* g_out, unsigned* cnt,
-                  hipStream_t s);
 
 }  // namespace msz
 

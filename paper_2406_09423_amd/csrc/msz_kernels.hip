@@ -108,19 +108,6 @@ __device__ __forceinline__ void validate_group(const float* __restrict__ f, cons
     }
 }
 
-__global__ void __launch_bounds__(256) k_validate_init(const float* __restrict__ f,
-                                                       const float* __restrict__ fhat,
-                                                       const float* __restrict__ warm, float xi,
-                                                       int n, float* __restrict__ L,
-                                                       float* __restrict__ g,
-                                                       unsigned* __restrict__ cnt) {
-    unsigned bad = 0;
-    const int ng = (n + 3) >> 2;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x)
-        validate_group(f, fhat, warm, xi, n, L, g, w, bad);
-    if (bad) atomicOr(cnt + kCntErr, bad);
-}
-
 // Finite-value check of a field handed to msz_labels / msz_count_false.
 __global__ void __launch_bounds__(256) k_check_finite(const float* __restrict__ h, int n,
                                                       unsigned* __restrict__ cnt) {
@@ -1001,8 +988,8 @@ __global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int*
 }
 
 // Troublemaker detection, tile by tile (see k_label_final for the order).
-// The tile's G groups are loaded GB at a time (all at once in the standalone
-// kernel; fewer where registers are scarce).
+// The tile's G groups are loaded GB at a time (the step kernel uses one: on
+// ocean2d more groups in flight measured slower).
 template <int NDIM, int GB = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024>
 __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
@@ -1060,24 +1047,6 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
             }
         }
     }
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(256) k_detect_r(const uint8_t* __restrict__ dirs_f,
-                                                  const uint8_t* __restrict__ dirs_g,
-                                                  const int* __restrict__ q_up,
-                                                  const int* __restrict__ q_dn,
-                                                  const int* __restrict__ Mf,
-                                                  const int* __restrict__ mf, Grid gr,
-                                                  uint8_t* __restrict__ marks,
-                                                  unsigned* __restrict__ cnt) {
-    unsigned wrong = 0, cases = 0;
-    const ItemRange range = xcd_items(label_tiles_of(gr));
-    for (int tile = range.first; tile < range.hi; tile += range.stride)
-        detect_r_tile<NDIM>(dirs_f, dirs_g, q_up, q_dn, Mf, mf, gr, tile, marks, wrong, cases);
-    unsigned v[2] = {wrong, cases};
-    const int idx[2] = {kCntWrong, kCntRCases};
-    block_add<2>(v, cnt, idx);
 }
 
 // ------------------------------------------------ count_false comparison ---
@@ -1148,20 +1117,6 @@ __device__ __forceinline__ void delta_group(const float* __restrict__ g, const f
             if (g_out) g_out[i] = gi;
         }
     }
-}
-
-__global__ void __launch_bounds__(256) k_delta(const float* __restrict__ g,
-                                               const float* __restrict__ fhat, int n,
-                                               float* __restrict__ delta,
-                                               float* __restrict__ g_out,
-                                               unsigned* __restrict__ cnt) {
-    unsigned edited = 0, inexact = 0;
-    const int ng = (n + 3) >> 2;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < ng; w += gridDim.x * blockDim.x)
-        delta_group(g, fhat, n, delta, g_out, w, edited, inexact);
-    unsigned v[2] = {edited, inexact};
-    const int idx[2] = {kCntEdited, kCntInexact};
-    block_add<2>(v, cnt, idx);
 }
 
 // ================================================================ launchers ==
@@ -1242,37 +1197,14 @@ void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M
     else hipLaunchKernelGGL(k_label_final<3>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m);
 }
 
-void launch_detect_r(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* q_up, const int* q_dn,
-                     const int* Mf, const int* mf, const Grid& gr, uint8_t* marks, unsigned* cnt,
-                     hipStream_t s) {
-    const int nt = label_tiles_of(gr);
-    const int nb = nt < kDirsBlocks ? nt : kDirsBlocks;
-    if (gr.ndim == 2)
-        hipLaunchKernelGGL(k_detect_r<2>, dim3(nb), dim3(256), 0, s, dirs_f, dirs_g, q_up, q_dn, Mf, mf, gr, marks, cnt);
-    else
-        hipLaunchKernelGGL(k_detect_r<3>, dim3(nb), dim3(256), 0, s, dirs_f, dirs_g, q_up, q_dn, Mf, mf, gr, marks, cnt);
-}
-
 void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu, const int* qfd,
                     const int* qgu, const int* qgd, int n, unsigned* cnt, hipStream_t s) {
     hipLaunchKernelGGL(k_compare, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, dirs_f, dirs_g,
                        qfu, qfd, qgu, qgd, n, cnt);
 }
 
-void launch_validate_init(const float* f, const float* fhat, const float* warm, float xi, int n,
-                          float* L, float* g, unsigned* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_init, dim3(blocks_for((n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, f, fhat,
-                       warm, xi, n, L, g, cnt);
-}
-
 void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s) {
     hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n, 256 * 4, kGridCap)), dim3(256), 0, s, h, n, cnt);
-}
-
-void launch_delta(const float* g, const float* fhat, int n, float* delta, float* g_out, unsigned* cnt,
-                  hipStream_t s) {
-    hipLaunchKernelGGL(k_delta, dim3(blocks_for((n + 3) / 4, 256, kGridCap)), dim3(256), 0, s, g, fhat, n, delta,
-                       g_out, cnt);
 }
 
 // ============================================================ batch engine ==
