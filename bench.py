@@ -3,7 +3,10 @@
 A step corrects the 3600x2400 k^-3 Gaussian-random-field pair (xi = 1e-4 and
 1e-3 of the value range) to zero segmentation error with the plain loop; the
 fields are resident in HBM before the clock starts.  The same run also times
-the two other forms on their own workloads (reported under "forms"):
+the two other forms on their own workloads, and the encoding of the edits
+(reported under "forms"):
+  edits    the plain loop's edits on the pair, losslessly encoded on the GPU
+           (sorted index gaps and values, Huffman coded) and decoded back
   batched  96 uneven k^-3 fields (64 2D with sides 64..2048, 32 3D cubes
            32^3..192^3, xi in {1e-4, 1e-3, 1e-2} x range) in one launch
   learned  a 512^3 k^-11/3 field at xi = 1e-3 x range: the warm-started loop
@@ -11,7 +14,7 @@ the two other forms on their own workloads (reported under "forms"):
 Every result is checked for zero segmentation error outside the clock.
 Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,batched,learned]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,edits,batched,learned]
                   [--no-cpu-baseline] [--calib-copy] [--schedule-out FILE]
 """
 from __future__ import annotations
@@ -167,7 +170,7 @@ def bench_plain(msz, torch, dev, args):
     if args.schedule_out is not None:
         with open(args.schedule_out, "w") as fh:
             json.dump({"phase_names": list(msz.PHASES), "calls": schedules}, fh)
-    return pairs, verts, ms_per_step, roofline, phases, rounds
+    return pairs, verts, ms_per_step, roofline, phases, rounds, [e for e, _ in outs]
 
 
 def bench_batched(msz, torch, dev, steps):
@@ -269,6 +272,44 @@ def bench_learned(msz, torch, dev, steps):
     return out
 
 
+def bench_edits(msz, torch, edits, pairs, reps=3):
+    """Lossless encoding of the plain loop's edits on the ocean2d pair (Sec. 6.3):
+    sizes, the edit ratio, and encode / decode times, each decode checked bit
+    for bit against the edits."""
+    out = []
+    for e, (_, _, xi) in zip(edits, pairs):
+        n = e.numel()
+        buf = torch.empty(msz.edits_bound(n), dtype=torch.uint8, device=e.device)
+        dec = torch.empty_like(e)
+        msz.encode_edits(e, out=buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc, blob, st = msz.encode_edits(e, out=buf)
+        torch.cuda.synchronize()
+        t_enc = (time.perf_counter() - t0) * 1e3 / reps
+        if rc != msz.OK:
+            raise RuntimeError(f"msz_encode_edits: {msz.strerror(rc)}")
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc, _ = msz.decode_edits(blob, e.shape, out=dec)
+        torch.cuda.synchronize()
+        t_dec = (time.perf_counter() - t0) * 1e3 / reps
+        if rc != msz.OK or not torch.equal(dec.view(torch.int32), e.view(torch.int32)):
+            raise RuntimeError("decoded edits differ")
+        m = st["n_edits"]
+        out.append({"xi": float(xi), "vertices": n, "edits": m, "edit_ratio": round(m / n, 6),
+                    "bytes": st["bytes"], "bits_per_edit": round(8 * st["bytes"] / max(m, 1), 3),
+                    "index_bits_per_edit": round(st["index_bits"] / max(m, 1), 3),
+                    "value_bits_per_edit": round(st["value_bits"] / max(m, 1), 3),
+                    "bits_per_vertex": round(8 * st["bytes"] / n, 5),
+                    "encode_ms": round(t_enc, 3), "decode_ms": round(t_dec, 3)})
+        log(f"bench: edits xi={float(xi):g}: {m} edits, {st['bytes']} bytes "
+            f"({8 * st['bytes'] / max(m, 1):.2f} bits/edit), encode {t_enc:.2f} ms, decode {t_dec:.2f} ms")
+    return {"workload": "edits of the plain loop on the ocean2d pair, encoded on the GPU and decoded back",
+            "fields": out}
+
+
 def calibration_copy(torch, dev):
     """A plain device copy of CALIB_BYTES, so that a counter run sees a kernel of known traffic."""
     a = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device=dev)
@@ -283,7 +324,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="plain,batched,learned")
+    ap.add_argument("--forms", default="plain,edits,batched,learned")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -308,10 +349,12 @@ def main():
     msz.lib()
     if args.calib_copy:
         calibration_copy(torch, dev)
-    pairs, verts, ms_per_step, roofline, phases, rounds = bench_plain(msz, torch, dev, args)
+    pairs, verts, ms_per_step, roofline, phases, rounds, edits = bench_plain(msz, torch, dev, args)
     value = verts / (ms_per_step * 1e-3) / 1e9
 
     extra = {}
+    if "edits" in forms:
+        extra["edits"] = bench_edits(msz, torch, edits, pairs)
     if "batched" in forms:
         extra["batched"] = bench_batched(msz, torch, dev, args.form_steps)
     if "learned" in forms:

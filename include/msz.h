@@ -99,8 +99,9 @@ typedef struct {
     int64_t n_inexact;     /* vertices where no float32 delta gives fl(fhat + delta) == g */
     int32_t status;        /* the return code of the call */
     int32_t pad;
-    /* Filled only with MSZ_FLAG_TIMING: summed GPU time (ms, hipEvents around each
-     * launch) and launch count of each kernel, indexed by MSZ_PHASE_*. */
+    /* Filled only with MSZ_FLAG_TIMING: summed GPU time (ms, from the GPU clock
+     * stamps of each device step) and step count of each operation, indexed by
+     * MSZ_PHASE_*. */
     float phase_ms[MSZ_N_PHASES];
     int32_t phase_launches[MSZ_N_PHASES];
 } msz_stats;
@@ -212,6 +213,55 @@ size_t msz_batch_workspace_bytes(const msz_job* jobs, int32_t n_jobs);
 
 /* Number of tile variants selectable through msz_options.tile_override for ndim. */
 int msz_tile_variants(int32_t ndim);
+
+/*
+ * Lossless encoding of the edits (Sec. 6.3: the edits are stored as key-value
+ * pairs; the keys, sorted, as their differences, entropy coded; the values
+ * separately).  An edit is an entry of edits[] whose bits are not those of +0
+ * (msz_fix leaves +0 at every unedited vertex).  Format (little-endian):
+ *   header, 576 bytes: uint32 magic "MSZE" (0x455A534D), version 1, n, m (the
+ *     number of edits), chunk count ceil(m / 4096), edits per chunk (4096);
+ *     then the code lengths (uint8) of the 32 gap symbols and of the 512 value
+ *     symbols; zero padding;
+ *   chunk table: per chunk {uint32 word offset in the bit stream, int32 index
+ *     of the chunk's first edit};
+ *   bit stream: uint32 words, each chunk starting on its own word.
+ * In index order, each edit of a chunk is: for all but the chunk's first, the
+ * Huffman code of b = floor(log2(d)), d = index - previous index, then the b
+ * low bits of d; then the Huffman code of the edit's 9 high bits (sign and
+ * exponent) and its 23 mantissa bits.  Fields are written most significant
+ * bit first; emitted bit j of a chunk is bit j % 32 of its word j / 32.  The
+ * Huffman codes are canonical (ordered by length, then symbol), at most 20
+ * bits long: built by merging the two lightest nodes (ties to the older node;
+ * leaves, by symbol, are older than merged nodes), and while a code is too long
+ * every count is halved rounding up and the code rebuilt.  Chunks decode
+ * independently (one GPU thread each).
+ */
+typedef struct {
+    int64_t n;           /* entries scanned */
+    int64_t n_edits;     /* edits found (m) */
+    int64_t bytes;       /* encoded size */
+    int64_t index_bits;  /* stream bits spent on index gaps */
+    int64_t value_bits;  /* stream bits spent on values */
+} msz_edit_stats;
+
+/* Upper bound of the encoded size of n entries (0 if n is out of range). */
+size_t msz_edits_bound(int64_t n);
+
+/* Encodes the edits of edits[0..n) (DEVICE float32, 16-byte aligned) into out
+ * (DEVICE, 16-byte aligned, capacity bytes).  *out_bytes (HOST) receives the
+ * encoded size; MSZ_EINVAL if it exceeds capacity (msz_edits_bound(n) always
+ * suffices).  stats (HOST) may be NULL.  Allocates its scratch per call
+ * (about 12 bytes per entry) on the stream and synchronises before returning. */
+int msz_encode_edits(const float* edits, int64_t n, void* out, size_t capacity, size_t* out_bytes,
+                     msz_edit_stats* stats, void* stream);
+
+/* Decodes in[0..in_bytes) (DEVICE, 16-byte aligned) into the dense edits_out
+ * (DEVICE float32[n], 16-byte aligned; +0 wherever no edit).  MSZ_EINVAL when
+ * the header does not match n, or the stream is malformed (a code outside the
+ * tables, a read past a chunk, an index outside [0, n)); the decoder never
+ * reads or writes outside the given buffers. */
+int msz_decode_edits(const void* in, size_t in_bytes, float* edits_out, int64_t n, void* stream);
 
 /* ------------------------------------------------------------------------
  * Learned edit proposal (warm start).  Every edit of the correction loop

@@ -75,6 +75,10 @@ class Job(ctypes.Structure):
                 ("g_out", ctypes.c_void_p), ("stats", ctypes.POINTER(Stats))]
 
 
+class EditStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_edits", "bytes", "index_bits", "value_bits")]
+
+
 class MszError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: {strerror(code)} ({code})")
@@ -117,9 +121,14 @@ def lib() -> ctypes.CDLL:
         L.msz_net_adam.argtypes = [P, P, P, P, I32, I32, F, P]
         L.msz_fix_learned.argtypes = [P, P, Dims, F, P, F, P, ctypes.POINTER(Options),
                                       ctypes.POINTER(Stats), P]
+        L.msz_edits_bound.argtypes = [ctypes.c_int64]
+        L.msz_edits_bound.restype = ctypes.c_size_t
+        L.msz_encode_edits.argtypes = [P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t),
+                                       ctypes.POINTER(EditStats), P]
+        L.msz_decode_edits.argtypes = [P, ctypes.c_size_t, P, ctypes.c_int64, P]
         for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants,
                    L.msz_net_features, L.msz_net_forward, L.msz_net_gradients, L.msz_net_adam,
-                   L.msz_fix_learned, L.msz_net_halvings):
+                   L.msz_fix_learned, L.msz_net_halvings, L.msz_encode_edits, L.msz_decode_edits):
             fn.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -229,6 +238,40 @@ def count_false(f, g, stream=None) -> dict:
     if rc != OK:
         raise MszError(rc, "msz_count_false")
     return {k: int(getattr(c, k)) for k, _ in FalseCounts._fields_}
+
+
+def edits_bound(n: int) -> int:
+    return int(lib().msz_edits_bound(int(n)))
+
+
+def encode_edits(edits, out=None, stream=None):
+    """Lossless encoding of an edit field (msz_encode_edits).  Returns
+    ``(status, blob, stats)``: ``blob`` a uint8 device tensor of the encoded
+    bytes (a view of ``out`` when given)."""
+    import torch
+    _check_field(edits, "edits")
+    n = edits.numel()
+    if out is None:
+        out = torch.empty(max(edits_bound(n), 16), dtype=torch.uint8, device=edits.device)
+    size = ctypes.c_size_t(0)
+    st = EditStats()
+    rc = lib().msz_encode_edits(edits.data_ptr(), n, out.data_ptr(), out.numel(), ctypes.byref(size),
+                                ctypes.byref(st), _stream(stream))
+    return int(rc), out[: size.value], {k: int(getattr(st, k)) for k, _ in EditStats._fields_}
+
+
+def decode_edits(blob, shape, out=None, stream=None):
+    """Dense float32 edits of ``shape`` from an encoded blob (msz_decode_edits)."""
+    import torch
+    if blob.dtype != torch.uint8 or not blob.is_cuda or not blob.is_contiguous():
+        raise ValueError("blob must be a contiguous uint8 CUDA tensor")
+    n = 1
+    for s_ in shape:
+        n *= int(s_)
+    if out is None:
+        out = torch.empty(tuple(int(s_) for s_ in shape), dtype=torch.float32, device=blob.device)
+    rc = lib().msz_decode_edits(blob.data_ptr(), blob.numel(), out.data_ptr(), n, _stream(stream))
+    return int(rc), out
 
 
 def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles="auto", outs=None,

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libmsz.so")
-SOURCES = ["msz_kernels.hip", "msz_api.hip", "msz_net.hip"]
+SOURCES = ["msz_kernels.hip", "msz_api.hip", "msz_net.hip", "msz_encode.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
