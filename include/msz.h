@@ -220,7 +220,7 @@ int msz_tile_variants(int32_t ndim);
  * separately).  An edit is an entry of edits[] whose bits are not those of +0
  * (msz_fix leaves +0 at every unedited vertex).  Format (little-endian):
  *   header, 576 bytes: uint32 magic "MSZE" (0x455A534D), version 1, n, m (the
- *     number of edits), chunk count ceil(m / 4096), edits per chunk (4096);
+ *     number of edits), chunk count ceil(m / 256), edits per chunk (256);
  *     then the code lengths (uint8) of the 32 gap symbols and of the 512 value
  *     symbols; zero padding;
  *   chunk table: per chunk {uint32 word offset in the bit stream, int32 index

@@ -20,7 +20,7 @@ import struct
 import numpy as np
 
 GAP_SYMS, VAL_SYMS, MAX_LEN = 32, 512, 20
-CHUNK = 4096
+CHUNK = 256
 HEADER = 576
 MAGIC, VERSION = 0x455A534D, 1
 

@@ -34,7 +34,7 @@
 namespace msz {
 
 constexpr int kEncGapSyms = 32, kEncValSyms = 512, kEncMaxLen = 20;
-constexpr int kEncChunk = 4096;        // edits per chunk
+constexpr int kEncChunk = 256;         // edits per chunk (one decoding thread each)
 constexpr int kEncBlock = 4096;        // dense entries per compaction block (256 threads x 16)
 constexpr int kEncHeader = 576;        // header bytes (24 fixed + 544 code lengths, padded)
 constexpr unsigned kEncMagic = 0x455A534Du;  // "MSZE"
@@ -161,28 +161,18 @@ __device__ __forceinline__ int edit_bits(const EncTables& T, const int* idx, con
     return nb;
 }
 
-// One block per chunk: bit offsets of the chunk's edits and the chunk's
-// length in words (into chunk_words[c]).
+// One block per chunk, one thread per edit: bit offsets of the chunk's
+// edits and the chunk's length in words (into chunk_words[c]).
+static_assert(kEncChunk == 256, "a chunk is one block of 256 threads");
 __global__ void __launch_bounds__(256) k_enc_offsets(const EncTables* __restrict__ T, const int* __restrict__ idx,
                                                      const unsigned* __restrict__ val, int m,
                                                      unsigned* __restrict__ bitoff, unsigned* __restrict__ chunk_words) {
     __shared__ unsigned s[256];
-    const int c = blockIdx.x;
-    const int k0 = c * kEncChunk + 16 * threadIdx.x;
-    unsigned nb[16];
-    unsigned sum = 0;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        nb[j] = k0 + j < m ? static_cast<unsigned>(edit_bits(*T, idx, val, k0 + j)) : 0u;
-        sum += nb[j];
-    }
-    unsigned o = block_exclusive(sum, s);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        if (k0 + j < m) bitoff[k0 + j] = o;
-        o += nb[j];
-    }
-    if (threadIdx.x == 255) chunk_words[c] = (o + 31) >> 5;
+    const int k = blockIdx.x * kEncChunk + threadIdx.x;
+    const unsigned nb = k < m ? static_cast<unsigned>(edit_bits(*T, idx, val, k)) : 0u;
+    const unsigned o = block_exclusive(nb, s);
+    if (k < m) bitoff[k] = o;
+    if (threadIdx.x == 255) chunk_words[blockIdx.x] = (o + nb + 31) >> 5;
 }
 
 // Appends `w` bits of v (most significant first) at bit position pos of a
@@ -251,18 +241,27 @@ struct DecTables {
     DecTable gap, val;
 };
 
-// Reads bits of a chunk; past `limit` it reads zeros and sets `over`.
+// Reads the bits of a chunk through a 64-bit register buffer (the next bit
+// in bit 0), a word at a time; past the chunk's end it reads zeros and sets
+// `over`.
 struct BitReader {
     const unsigned* w;
-    unsigned pos, limit;
+    unsigned next, end;  // next word to load, end of the chunk's words
+    unsigned long long buf;
+    int have;
     bool over;
     __device__ __forceinline__ unsigned bit() {
-        if (pos >= limit) {
-            over = true;
-            return 0u;
+        if (have == 0) {
+            if (next >= end) {
+                over = true;
+                return 0u;
+            }
+            buf = w[next++];
+            have = 32;
         }
-        const unsigned b = (w[pos >> 5] >> (pos & 31u)) & 1u;
-        ++pos;
+        const unsigned b = static_cast<unsigned>(buf & 1ull);
+        buf >>= 1;
+        --have;
         return b;
     }
     __device__ __forceinline__ unsigned bits(int n) {
@@ -284,12 +283,18 @@ __device__ __forceinline__ int decode_symbol(const DecTable& t, BitReader& r) {
 }
 
 // One thread per chunk: decodes its edits and writes them into the dense
-// (zeroed) output.  Malformed input (a bad code, an index outside [0, n) or
-// not increasing, a read past the stream) sets *bad.
-__global__ void __launch_bounds__(64) k_dec_chunks(const DecTables* __restrict__ T, const unsigned* __restrict__ table,
+// (zeroed) output.  Malformed input (a bad code, an index outside [0, n), a
+// read past the chunk) sets *bad.  The code tables are staged in LDS.
+__global__ void __launch_bounds__(64) k_dec_chunks(const DecTables* __restrict__ Tg, const unsigned* __restrict__ table,
                                                    const unsigned* __restrict__ stream, unsigned stream_words,
                                                    int nchunks, int m, long long n, unsigned* __restrict__ out,
                                                    unsigned* __restrict__ bad) {
+    __shared__ DecTables T_s;
+    static_assert(sizeof(DecTables) % 4 == 0, "tables copied word by word");
+    for (int i = threadIdx.x; i < static_cast<int>(sizeof(DecTables) / 4); i += blockDim.x)
+        reinterpret_cast<unsigned*>(&T_s)[i] = reinterpret_cast<const unsigned*>(Tg)[i];
+    __syncthreads();
+    const DecTables* T = &T_s;
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nchunks) return;
     const unsigned w0 = table[2 * c];
@@ -298,7 +303,7 @@ __global__ void __launch_bounds__(64) k_dec_chunks(const DecTables* __restrict__
         atomicOr(bad, 1u);
         return;
     }
-    BitReader r{stream + w0, 0u, (wend - w0) * 32u, false};
+    BitReader r{stream, w0, wend, 0ull, 0, false};
     const int k_end = min(m, (c + 1) * kEncChunk);
     long long i = static_cast<int>(table[2 * c + 1]);
     for (int k = c * kEncChunk; k < k_end; ++k) {

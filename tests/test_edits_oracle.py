@@ -23,7 +23,7 @@ def test_hand_worked_stream():
         glen[int(k)] = v
     for k, v in g["value_lengths"].items():
         vlen[int(k)] = v
-    head = struct.pack("<6I", 0x455A534D, 1, g["n"], len(g["indices"]), 1, 4096) + bytes(glen) + bytes(vlen)
+    head = struct.pack("<6I", 0x455A534D, 1, g["n"], len(g["indices"]), 1, 256) + bytes(glen) + bytes(vlen)
     head += bytes(576 - len(head))
     want = head + b"".join(struct.pack("<Ii", w, i) for w, i in g["chunk_table"])
     want += b"".join(struct.pack("<I", w) for w in g["stream_words"])
@@ -78,7 +78,7 @@ def _random_edits(rng, n, m):
     return x
 
 
-@pytest.mark.parametrize("n,m", [(1, 0), (1, 1), (100, 0), (4097, 4097), (20000, 9000), (3_000_000, 5000)])
+@pytest.mark.parametrize("n,m", [(1, 0), (1, 1), (100, 0), (257, 257), (4097, 4097), (20000, 9000), (3_000_000, 5000)])
 def test_round_trip(n, m):
     rng = np.random.default_rng(n + m)
     x = _random_edits(rng, n, m)

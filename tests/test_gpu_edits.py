@@ -41,7 +41,7 @@ def _check(msz, x):
     return st
 
 
-@pytest.mark.parametrize("n,m", [(1, 0), (1, 1), (4095, 4095), (4097, 4097), (20000, 9000), (70000, 12289),
+@pytest.mark.parametrize("n,m", [(1, 0), (1, 1), (255, 255), (257, 257), (4097, 4097), (20000, 9000), (70000, 12289),
                                  (3_000_000, 5000)])
 def test_random_edits_bit_exact(msz, n, m):
     _say("edits", n, m)
