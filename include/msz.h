@@ -251,7 +251,8 @@ size_t msz_edits_bound(int64_t n);
 /* Encodes the edits of edits[0..n) (DEVICE float32, 16-byte aligned) into out
  * (DEVICE, 16-byte aligned, capacity bytes).  *out_bytes (HOST) receives the
  * encoded size; MSZ_EINVAL if it exceeds capacity (msz_edits_bound(n) always
- * suffices).  stats (HOST) may be NULL.  Allocates its scratch per call
+ * suffices) or if the stream would pass 2^32 words (more than about 1.4e9
+ * edits).  stats (HOST) may be NULL.  Allocates its scratch per call
  * (about 12 bytes per entry) on the stream and synchronises before returning. */
 int msz_encode_edits(const float* edits, int64_t n, void* out, size_t capacity, size_t* out_bytes,
                      msz_edit_stats* stats, void* stream);

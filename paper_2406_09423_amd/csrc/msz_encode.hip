@@ -476,6 +476,10 @@ int msz_encode_edits(const float* edits, int64_t n, void* out, size_t capacity, 
             hipStreamSynchronize(s) != hipSuccess)
             return fail(MSZ_EDEVICE);
     }
+    // word offsets are 32-bit: the stream of m edits (at most 93 bits each) must fit
+    if (static_cast<unsigned long long>(m) * 93ull / 32ull + static_cast<unsigned long long>(m) / kEncChunk + 2 >
+        0xFFFFFFFFull)
+        return fail(MSZ_EINVAL);
     const int nchunks = static_cast<int>((m + kEncChunk - 1) / kEncChunk);
     std::vector<unsigned> h(kEncGapSyms + kEncValSyms, 0u);
     if (m > 0) {
