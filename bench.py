@@ -15,7 +15,7 @@ Every result is checked for zero segmentation error outside the clock.
 Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,edits,batched,learned]
-                  [--no-cpu-baseline] [--calib-copy] [--schedule-out FILE]
+                  [--no-cpu-baseline] [--batch-cpu-baseline] [--calib-copy] [--schedule-out FILE]
 """
 from __future__ import annotations
 
@@ -173,12 +173,32 @@ def bench_plain(msz, torch, dev, args):
     return pairs, verts, ms_per_step, roofline, phases, rounds, [e for e, _ in outs]
 
 
-def bench_batched(msz, torch, dev, steps):
+def batch_oracle_all_cores(host_fields):
+    """The serial C oracle over the whole batch, one field per task on a pool
+    of host threads (the oracle is a C library: ctypes releases the GIL)."""
+    import concurrent.futures
+
+    import oracle
+    oracle.build()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    verts = sum(f.size for f, _, _ in host_fields)
+    # largest fields first, so the slowest one does not start last
+    order = sorted(host_fields, key=lambda t: -t[0].size)
+    t0 = time.perf_counter()
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        rcs = list(ex.map(lambda t: oracle.fix(*t)[0], order))
+    dt = time.perf_counter() - t0
+    assert all(rc == 0 for rc in rcs)
+    return {"value": round(verts / dt / 1e9, 6), "unit": "Gvertices/s", "cores": workers, "kind": "oracle",
+            "sample": "the whole 96-field batch, one field per task on a pool of host threads", "seconds": round(dt, 2)}
+
+
+def bench_batched(msz, torch, dev, steps, cpu_all_cores=False):
     import synth
     from paper_2406_09423_amd import autotune
     log("bench: generating the 96-field batch")
-    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi))
-              for f, fh, xi in synth.batch_fields(0)]
+    host_fields = synth.batch_fields(0)
+    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)) for f, fh, xi in host_fields]
     shapes = [f.shape for f, _, _ in fields]
     tiles = autotune.tiles_for(shapes)
     verts = sum(f.numel() for f, _, _ in fields)
@@ -212,12 +232,18 @@ def bench_batched(msz, torch, dev, steps):
     ms_seq = (time.perf_counter() - t0) * 1e3
     log(f"bench: batched {ms:.2f} ms ({verts / ms / 1e6:.3f} Gv/s), one by one {ms_seq:.2f} ms")
     rounds = [sum(st["rounds"]) + st["rounds_r"] for _, _, _, st in res]
+    cpu = None
+    if cpu_all_cores:
+        log("bench: oracle over the batch on all host cores")
+        cpu = batch_oracle_all_cores(host_fields)
+        log(f"bench: oracle batch {cpu['seconds']} s on {cpu['cores']} threads")
+    del host_fields
     return {"workload": "96 uneven k^-3 fields: 64 2D (sides U{64..2048}), 32 3D (U{32..192}^3), "
                         "xi in {1e-4,1e-3,1e-2} x range; one device-scheduled run",
             "vertices": verts, "ms": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
             "steps": steps, "sequential_ms": round(ms_seq, 3),
             "speedup_vs_sequential": round(ms_seq / ms, 3), "max_rounds": max(rounds),
-            "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}}
+            "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}, "cpu_all_cores": cpu}
 
 
 def bench_learned(msz, torch, dev, steps):
@@ -327,6 +353,8 @@ def main():
     ap.add_argument("--forms", default="plain,edits,batched,learned")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-cpu-baseline", action="store_true",
+                    help="also time the oracle over the whole batch on all host cores (minutes)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--schedule-out", default=None,
@@ -356,7 +384,7 @@ def main():
     if "edits" in forms:
         extra["edits"] = bench_edits(msz, torch, edits, pairs)
     if "batched" in forms:
-        extra["batched"] = bench_batched(msz, torch, dev, args.form_steps)
+        extra["batched"] = bench_batched(msz, torch, dev, args.form_steps, args.batch_cpu_baseline)
     if "learned" in forms:
         extra["learned"] = bench_learned(msz, torch, dev, args.form_steps)
 
