@@ -55,7 +55,8 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, tile_dirty, Mf, mf, qu, qd, qf_up, qf_dn, total;
+    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, tile_dirty, tile_lab, tile_wrong, Mf, mf, qu, qd, qf_up, qf_dn,
+        root_up, root_dn, total;
 };
 
 Layout layout_for(const Grid& gr) {
@@ -76,12 +77,16 @@ Layout layout_for(const Grid& gr) {
     l.cases = take((n + 15) & ~int64_t(15));
     l.dirty = take((n + 15) & ~int64_t(15));
     l.tile_dirty = take(label_tile_count(gr));
+    l.tile_lab = take(label_tile_count(gr));
+    l.tile_wrong = take(label_tile_count(gr));
     l.Mf = take(n * 4);
     l.mf = take(n * 4);
     l.qu = take(n * 4);
     l.qd = take(n * 4);
     l.qf_up = take(faces * 4);
     l.qf_dn = take(faces * 4);
+    l.root_up = take(faces * 4);
+    l.root_dn = take(faces * 4);
     l.total = o;
     return l;
 }
@@ -492,6 +497,10 @@ void bind_field(EngField& F, char* w) {
     F.tile_dirty = reinterpret_cast<uint8_t*>(w + l.tile_dirty);
     F.qf_up = reinterpret_cast<int*>(w + l.qf_up);
     F.qf_dn = reinterpret_cast<int*>(w + l.qf_dn);
+    F.root_up = reinterpret_cast<int*>(w + l.root_up);
+    F.root_dn = reinterpret_cast<int*>(w + l.root_dn);
+    F.tile_lab = reinterpret_cast<uint8_t*>(w + l.tile_lab);
+    F.tile_wrong = reinterpret_cast<uint8_t*>(w + l.tile_wrong);
     F.Mf = reinterpret_cast<int*>(w + l.Mf);
     F.mf = reinterpret_cast<int*>(w + l.mf);
     F.qu = reinterpret_cast<int*>(w + l.qu);

@@ -170,6 +170,9 @@ struct EngField {
     uint8_t *tile_dirty;  // per label tile: a direction of g in it changed since its last tile pass
     int *Mf, *mf, *qu, *qd;
     int *qf_up, *qf_dn;   // per label tile and face-layer vertex: the tile pass's pointer (before compression)
+    int *root_up, *root_dn;  // per label tile and face-layer vertex: its roots after the last compression
+    uint8_t *tile_lab;    // per label tile: labels of g in it may have changed since its last troublemaker pass
+    uint8_t *tile_wrong;  // per label tile: its last troublemaker pass found a mislabelled vertex
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
 

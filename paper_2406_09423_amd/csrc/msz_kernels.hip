@@ -870,8 +870,10 @@ __device__ __forceinline__ void store_relaxed(int* p, int v) {
 // order), so the walks end; the step cap only guards against corrupted input
 // and is reported as an error.
 constexpr int kMaxWalk = 1 << 22;
-__device__ __forceinline__ bool compress_both(int* qu, int* qd, int x) {
+__device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, int& rd) {
     int yu = load_relaxed(qu + x), yd = load_relaxed(qd + x);
+    ru = yu;
+    rd = yd;
     bool du = false, dd = false;
     for (int it = 0; it < kMaxWalk; ++it) {
         const int zu = du ? yu : load_relaxed(qu + yu);
@@ -884,19 +886,30 @@ __device__ __forceinline__ bool compress_both(int* qu, int* qd, int x) {
             if (zd == yd) dd = true;
             else store_relaxed(qd + x, zd), yd = zd;
         }
-        if (du && dd) return true;
+        if (du && dd) {
+            ru = yu;
+            rd = yd;
+            return true;
+        }
     }
     return false;
 }
 
-// Compresses the pointers of one tile's face-layer vertices; false if a walk hit its cap.
+// Compresses the pointers of one tile's face-layer vertices; false if a walk
+// hit its cap.  With root_up set (the tile passes of g), each face vertex's
+// roots are compared with those of the last compression: if either changed,
+// the labels of the tile and of every tile holding a mesh neighbour of the
+// vertex (the only tiles whose exits can land on it) may have changed, and
+// tile_lab flags them.
 template <int NDIM>
 __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __restrict__ q_up,
-                                              int* __restrict__ q_dn) {
+                                              int* __restrict__ q_dn, int* root_up = nullptr,
+                                              int* root_dn = nullptr, uint8_t* tile_lab = nullptr) {
     using T = LabelTile<NDIM>;
     constexpr int FC = face_count<NDIM>();
     const int tx_n = (gr.nx + T::X - 1) / T::X;
     const int ty_n = (gr.ny + T::Y - 1) / T::Y;
+    const int tz_n = (gr.nz + T::Z - 1) / T::Z;
     const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
     bool ok = true;
     for (int b = threadIdx.x; b < FC; b += blockDim.x) {
@@ -904,7 +917,24 @@ __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __r
         const int x = bx * T::X + l.x, y = by * T::Y + l.y, z = bz * T::Z + l.z;
         if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
         const int i = x + gr.nx * y + gr.nxy * z;
-        ok = compress_both(q_up, q_dn, i) && ok;
+        int ru, rd;
+        ok = compress_both(q_up, q_dn, i, ru, rd) && ok;
+        if (!root_up) continue;
+        const long e = static_cast<long>(tile) * FC + b;
+        if (root_up[e] == ru && root_dn[e] == rd) continue;
+        root_up[e] = ru;
+        root_dn[e] = rd;
+        // tiles across the faces this vertex lies on, and the tile itself
+        const int ex0 = l.x == 0 ? -1 : 0, ex1 = l.x == T::X - 1 ? 1 : 0;
+        const int ey0 = l.y == 0 ? -1 : 0, ey1 = l.y == T::Y - 1 ? 1 : 0;
+        const int ez0 = NDIM == 3 && l.z == 0 ? -1 : 0, ez1 = NDIM == 3 && l.z == T::Z - 1 ? 1 : 0;
+        for (int dz = ez0; dz <= ez1; ++dz)
+            for (int dy = ey0; dy <= ey1; ++dy)
+                for (int dx = ex0; dx <= ex1; ++dx) {
+                    const int tx = bx + dx, ty = by + dy, tz = bz + dz;
+                    if (tx < 0 || tx >= tx_n || ty < 0 || ty >= ty_n || tz < 0 || tz >= tz_n) continue;
+                    tile_lab[tx + tx_n * (ty + ty_n * tz)] = 1;
+                }
     }
     return ok;
 }
@@ -1419,7 +1449,10 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                     label_tile_body<NDIM>(F.dirs_g, gr, item, F.qu, F.qd, su, sd);
                     __syncthreads();
                     save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn);
-                    if (threadIdx.x == 0) F.tile_dirty[item] = 0;
+                    if (threadIdx.x == 0) {
+                        F.tile_dirty[item] = 0;
+                        F.tile_lab[item] = 1;  // its own pointers changed
+                    }
                 } else {
                     restore_faces<NDIM>(gr, item, F.qu, F.qd, F.qf_up, F.qf_dn);
                 }
@@ -1429,7 +1462,10 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
         case kOpPreC:
         case kOpRJump: {
             bool ok = true;
-            for (int item = lo; item < hi; ++item) ok = compress_tile<NDIM>(gr, item, F.qu, F.qd) && ok;
+            const bool g_pass = st.op == kOpRJump;  // the forests of g: track root changes
+            for (int item = lo; item < hi; ++item)
+                ok = compress_tile<NDIM>(gr, item, F.qu, F.qd, g_pass ? F.root_up : nullptr,
+                                         g_pass ? F.root_dn : nullptr, F.tile_lab) && ok;
             if (!ok) atomicOr(cnt + kCntErr, kErrWalk);
             break;
         }
@@ -1502,9 +1538,19 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         }
         case kOpRDetect: {
+            // A tile whose labels cannot have changed and that had no
+            // mislabelled vertex last time has none now: skipped.
             unsigned wrong = 0, cases = 0;
-            for (int item = lo; item < hi; ++item)
+            for (int item = lo; item < hi; ++item) {
+                if (!F.tile_lab[item] && !F.tile_wrong[item]) continue;
+                const unsigned before = wrong;
                 detect_r_tile<NDIM, 1>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, F.marks, wrong, cases);
+                const int any = __syncthreads_or(wrong != before);
+                if (threadIdx.x == 0) {
+                    F.tile_wrong[item] = any ? 1 : 0;
+                    F.tile_lab[item] = 0;
+                }
+            }
             unsigned v[2] = {wrong, cases};
             const int idx[2] = {kCntWrong, kCntRCases};
             block_add<2>(v, cnt, idx);
