@@ -55,7 +55,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, tile_dirty, tile_lab, tile_wrong, Mf, mf, qu, qd, qf_up, qf_dn,
+    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, target, tile_dirty, tile_lab, tile_wrong, Mf, mf, qu, qd, qf_up, qf_dn,
         root_up, root_dn, total;
 };
 
@@ -76,6 +76,7 @@ Layout layout_for(const Grid& gr) {
     l.marks = take((n + 15) & ~int64_t(15));
     l.cases = take((n + 15) & ~int64_t(15));
     l.dirty = take((n + 15) & ~int64_t(15));
+    l.target = take((n + 15) & ~int64_t(15));
     l.tile_dirty = take(label_tile_count(gr));
     l.tile_lab = take(label_tile_count(gr));
     l.tile_wrong = take(label_tile_count(gr));
@@ -501,6 +502,7 @@ void bind_field(EngField& F, char* w) {
     F.root_dn = reinterpret_cast<int*>(w + l.root_dn);
     F.tile_lab = reinterpret_cast<uint8_t*>(w + l.tile_lab);
     F.tile_wrong = reinterpret_cast<uint8_t*>(w + l.tile_wrong);
+    F.target = reinterpret_cast<uint8_t*>(w + l.target);
     F.Mf = reinterpret_cast<int*>(w + l.Mf);
     F.mf = reinterpret_cast<int*>(w + l.mf);
     F.qu = reinterpret_cast<int*>(w + l.qu);

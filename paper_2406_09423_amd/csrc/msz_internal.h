@@ -173,6 +173,7 @@ struct EngField {
     int *root_up, *root_dn;  // per label tile and face-layer vertex: its roots after the last compression
     uint8_t *tile_lab;    // per label tile: labels of g in it may have changed since its last troublemaker pass
     uint8_t *tile_wrong;  // per label tile: its last troublemaker pass found a mislabelled vertex
+    uint8_t *target;      // per vertex: some tile pass of g made it a tile's exit (or extremum)
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
 

@@ -814,10 +814,13 @@ __device__ __forceinline__ int tile_of_vertex(const Grid& gr, int i) {
 // After a tile pass of g (su, sd still hold the tile's final local pointers,
 // after a barrier): keeps the face-layer vertices' pointers, which the
 // compression then overwrites, so that a later pass over an unchanged tile
-// only has to put them back.
+// only has to put them back, and flags their targets.  Every exit of the tile
+// (the first vertex outside it on some integral line) is the target of one of
+// its face-layer vertices (the last vertex of that line inside the tile), so
+// the flagged vertices are all the compression of g has to resolve.
 template <int NDIM>
 __device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* su, const int* sd, int* qf_up,
-                                           int* qf_dn) {
+                                           int* qf_dn, uint8_t* target) {
     using T = LabelTile<NDIM>;
     constexpr int FC = face_count<NDIM>();
     const int3 o = tile_origin<NDIM>(gr, tile);
@@ -828,8 +831,11 @@ __device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* 
         const int3 l = face_vertex<NDIM>(b);
         if (o.x + l.x >= gr.nx || o.y + l.y >= gr.ny || o.z + l.z >= gr.nz) continue;
         const int a = l.x + T::X * (l.y + T::Y * l.z);
-        qf_up[tile * FC + b] = global_of(su[a]);
-        qf_dn[tile * FC + b] = global_of(sd[a]);
+        const int tu = global_of(su[a]), td = global_of(sd[a]);
+        qf_up[tile * FC + b] = tu;
+        qf_dn[tile * FC + b] = td;
+        target[tu] = 1;
+        target[td] = 1;
     }
 }
 
@@ -895,8 +901,10 @@ __device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, 
     return false;
 }
 
-// Compresses the pointers of one tile's face-layer vertices; false if a walk
-// hit its cap.  With root_up set (the tile passes of g), each face vertex's
+// Compresses the pointers of one tile's face-layer vertices (with target set,
+// only the flagged ones: a label is q[q[i]], so only the vertices some
+// pointer can name need their roots); false if a walk hit its cap.  With
+// root_up set (the tile passes of g), each compressed face vertex's
 // roots are compared with those of the last compression: if either changed,
 // the labels of the tile and of every tile holding a mesh neighbour of the
 // vertex (the only tiles whose exits can land on it) may have changed, and
@@ -904,7 +912,8 @@ __device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, 
 template <int NDIM>
 __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __restrict__ q_up,
                                               int* __restrict__ q_dn, int* root_up = nullptr,
-                                              int* root_dn = nullptr, uint8_t* tile_lab = nullptr) {
+                                              int* root_dn = nullptr, uint8_t* tile_lab = nullptr,
+                                              const uint8_t* target = nullptr) {
     using T = LabelTile<NDIM>;
     constexpr int FC = face_count<NDIM>();
     const int tx_n = (gr.nx + T::X - 1) / T::X;
@@ -917,6 +926,7 @@ __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __r
         const int x = bx * T::X + l.x, y = by * T::Y + l.y, z = bz * T::Z + l.z;
         if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
         const int i = x + gr.nx * y + gr.nxy * z;
+        if (target && !target[i]) continue;
         int ru, rd;
         ok = compress_both(q_up, q_dn, i, ru, rd) && ok;
         if (!root_up) continue;
@@ -1448,7 +1458,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 if (F.tile_dirty[item]) {
                     label_tile_body<NDIM>(F.dirs_g, gr, item, F.qu, F.qd, su, sd);
                     __syncthreads();
-                    save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn);
+                    save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn, F.target);
                     if (threadIdx.x == 0) {
                         F.tile_dirty[item] = 0;
                         F.tile_lab[item] = 1;  // its own pointers changed
@@ -1465,7 +1475,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             const bool g_pass = st.op == kOpRJump;  // the forests of g: track root changes
             for (int item = lo; item < hi; ++item)
                 ok = compress_tile<NDIM>(gr, item, F.qu, F.qd, g_pass ? F.root_up : nullptr,
-                                         g_pass ? F.root_dn : nullptr, F.tile_lab) && ok;
+                                         g_pass ? F.root_dn : nullptr, F.tile_lab, g_pass ? F.target : nullptr) && ok;
             if (!ok) atomicOr(cnt + kCntErr, kErrWalk);
             break;
         }
@@ -1950,9 +1960,9 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
 
 // Start of a one-field run: the field table entry (passed by value), the
 // states of "step -1" (done) and step 0 (start), the three counter sets, the
-// statistics, the active word, and the field's marks, case bytes and dirty
-// flags -- everything the host would otherwise upload or clear one call at a
-// time.
+// statistics, the active word, and the field's marks, case bytes, dirty
+// flags and exit targets -- everything the host would otherwise upload or
+// clear one call at a time.
 __global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* fields, EngState* states,
                                                     EngStats* stats, unsigned* cnt3, int* ctl) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
@@ -1970,10 +1980,11 @@ __global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* 
         reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
         reinterpret_cast<uint4*>(F.cases)[w] = make_uint4(0u, 0u, 0u, 0u);
         reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
+        reinterpret_cast<uint4*>(F.target)[w] = make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
-// Clears every field's marks, case bytes, dirty flags and counter block.
+// Clears every field's marks, case bytes, dirty flags, exit targets and counter block.
 __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ fields, int nf) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     for (int f = 0; f < nf; ++f) {
@@ -1981,11 +1992,13 @@ __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ f
         uint4* m = reinterpret_cast<uint4*>(F.marks);
         uint4* cs = reinterpret_cast<uint4*>(F.cases);
         uint4* dt = reinterpret_cast<uint4*>(F.dirty);
+        uint4* tg = reinterpret_cast<uint4*>(F.target);
         const int nw = (F.gr.n + 15) >> 4;
         for (int w = tid; w < nw; w += nthr) {
             m[w] = make_uint4(0u, 0u, 0u, 0u);
             cs[w] = make_uint4(0u, 0u, 0u, 0u);
             dt[w] = make_uint4(0u, 0u, 0u, 0u);
+            tg[w] = make_uint4(0u, 0u, 0u, 0u);
         }
         for (int w = tid; w < kCntBlockWords; w += nthr) F.cnt[w] = 0u;
     }
