@@ -1,15 +1,16 @@
 // msz_api.hip -- host driver and C ABI of libmsz (declared in include/msz.h).
 //
 // The schedule of the correction loop (Sec. 5) runs on the device (the
-// engine in msz_kernels.hip): every step runs one operation per field and a
-// decide kernel picks each field's next operation from its counters --
+// engine in msz_kernels.hip): every step runs one operation per field, and
+// the next operation of each field follows from its counters (decided inside
+// the step kernel for one field, by a decide kernel for a batch) --
 //   C phase  sub-loops FPmax, FPmin, FNmax, FNmin, each until it finds no case
 //            of its type; repeated until no false critical point remains;
 //   R phase  labels of g, troublemaker detection, one apply; back to the C
 //            phase whenever the apply created a false critical point.
 // The host captures kGraphSteps steps in a HIP graph and relaunches it until
 // the device clears a done word in pinned host memory.
-// msz_fix is the one-field case of msz_fix_batch.
+// msz_fix runs the same schedule for one field.
 #include <algorithm>
 #include <cmath>
 #include <cstring>

@@ -1252,15 +1252,17 @@ void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s) {
 // The schedule of the correction loop (Sec. 5) runs on the device.  A step
 // advances every unfinished field of a batch by one operation of its own
 // schedule -- the same sequence of operations for every field as for a field
-// corrected alone, so results are identical.  k_eng_step<NDIM> runs the work
-// items of all fields of one dimension as one index space, cut into one
-// contiguous range per block (XCD-aware, so neighbouring items share an L2);
-// k_eng_decide reduces each field's counters and writes its next operation;
-// k_eng_scan forms the prefix sums of the next step's items.  The host
-// captures a fixed number of steps in a HIP graph and relaunches it until no
-// field is active.  Kernel boundaries order the steps: every write of a step
-// is visible to the next one without device-scope fences inside a kernel
-// (which on MI355X write back and invalidate the L2 of each XCD).
+// corrected alone, so results are identical.  One field: k_eng_step1 decides
+// in every block and runs the chosen operation, one kernel per step.  A
+// batch: k_eng_step<NDIM> runs the work items of all fields of one dimension
+// as one index space, cut into one contiguous range per block (XCD-aware, so
+// neighbouring items share an L2); k_eng_decide reduces each field's counters
+// and writes its next operation; k_eng_scan forms the prefix sums of the next
+// step's items.  The host captures a fixed number of steps in a HIP graph and
+// relaunches it until no field is active.  Kernel boundaries order the steps:
+// every write of a step is visible to the next one without device-scope
+// fences inside a kernel (which on MI355X write back and invalidate the L2 of
+// each XCD).
 
 __host__ __device__ inline int dirs_items_of(const Grid& gr, int variant) {
     const DirsVariant v = variant_of(gr.ndim, variant);
