@@ -30,7 +30,9 @@
  *  - Memory: the library allocates scratch per call when no workspace is
  *    given (hipMallocAsync on the stream), and keeps one control block
  *    (about 9 MB: field table, step states, round counters, statistics, the
- *    cached graph) per host thread and device for the life of the process.
+ *    cached graph) and 512 bytes of pinned, device-mapped host memory (the
+ *    done word and the final statistics of one-field runs) per host thread
+ *    and device for the life of the process.
  *  - Errors: the return code is the only error channel; no global state
  *    besides the control block above.  msz_strerror() names a code.  Inputs
  *    must be finite with magnitude at most 2^100 (so that no edit can
