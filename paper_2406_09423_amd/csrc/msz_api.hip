@@ -327,7 +327,7 @@ int phase_of_op(int op) {
         case kOpPreB: case kOpRTile: return MSZ_PHASE_LABEL_TILE;
         case kOpPreC: case kOpRJump: return MSZ_PHASE_LABEL_JUMP;
         case kOpPreD: return MSZ_PHASE_LABEL_FINAL;
-        case kOpApplyC: case kOpApplyR: return MSZ_PHASE_APPLY;
+        case kOpApplyC: return MSZ_PHASE_APPLY;
         case kOpPreE: case kOpFullC: case kOpFullR: return MSZ_PHASE_DIRS_DETECT;
         case kOpRefreshC: case kOpRefreshR: return MSZ_PHASE_REFRESH;
         case kOpRDetect: return MSZ_PHASE_DETECT_R;

@@ -147,8 +147,7 @@ enum EngOp : int {
     kOpFullC,      // the same for every vertex (after an apply that changed many)
     kOpRTile,      // label tiles of g
     kOpRJump,      // compression of g's tile faces
-    kOpRDetect,    // troublemakers
-    kOpApplyR,     // R-loop apply
+    kOpRDetect,    // troublemakers, and the edits of their targets
     kOpRefreshR,   // directions and cases of the vertices around the last R edits
     kOpFullR,      // the same for every vertex
     kOpDelta,      // output

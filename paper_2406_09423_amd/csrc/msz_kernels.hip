@@ -4,8 +4,8 @@
 //   h / g / L      float32[n]
 //   dirs           uint8[n]   high nibble = ascent slot, low nibble = descent slot, 0xF = self
 //   cases          uint8[n]   bit t: the vertex is a C-loop case of type t (padded to 16 B)
-//   marks          uint8[n]   troublemaker targets of the pending R round, or the claim
-//                             of a shared C-loop target (padded to 16 B)
+//   marks          uint8[n]   claims of the targets edited in the current round (an
+//                             edit shared by several cases is made once; padded to 16 B)
 //   dirty          uint8[n]   directions to recompute after an apply (padded to 16 B)
 //   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests
 //   qf_up, qf_dn   int32      per label tile and face-layer vertex, its tile-pass pointer
@@ -50,10 +50,6 @@ __device__ __forceinline__ void block_add(unsigned (&v)[K], unsigned* dst, const
         if (s) atomicAdd(dst + (blockIdx.x % nslots) * stride + idx[threadIdx.x], s);
     }
 }
-
-// Troublemaker proposals of one R round form a set: every proposer of target
-// t stores the same byte, so plain (idempotent) byte stores need no atomics.
-__device__ __forceinline__ void mark(uint8_t* marks, int t) { marks[t] = 1; }
 
 // One decreasing edit (Eqs. 2-6): halfway to the floor, snapped to it when
 // float32 rounding would leave the value unchanged.
@@ -536,8 +532,8 @@ __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid 
 // One decreasing edit (Eqs. 2-6) per target and round.  The correction loop
 // keeps, besides the directions of g, a case byte per vertex (case_bits), so
 // an apply step needs no detection pass: it scans the case bytes for the
-// current type (C loop) or the marks of the troublemakers (R loop) and edits
-// the targets.  Every edited vertex and, when its value changed, every
+// current type and edits the targets (the R loop edits the troublemakers'
+// targets in the detection step itself).  Every edited vertex and, when its value changed, every
 // neighbour is flagged dirty: only their directions can have changed, and the
 // refresh step recomputes exactly those (the synchronous round is unchanged,
 // so results are identical to a full recomputation).
@@ -577,6 +573,18 @@ __device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* 
 #pragma unroll
     for (int s = 0; s < NS; ++s)
         if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
+}
+
+// Edits target t unless another case of the same step already has: the first
+// to set t's mark (an atomic OR on its word) edits it.  The mark is cleared by
+// the refresh that follows (t is flagged by the edit).
+template <int NDIM>
+__device__ __forceinline__ void claim_edit(uint8_t* __restrict__ marks, float* __restrict__ g,
+                                           const float* __restrict__ L, uint8_t* __restrict__ dirty,
+                                           const Grid& gr, int t, unsigned& changed) {
+    const unsigned bit = 1u << (8 * (t & 3));
+    if ((atomicOr(reinterpret_cast<unsigned*>(marks + (t & ~3)), bit) & bit) == 0u)
+        edit_vertex<NDIM>(g, L, dirty, gr, t, changed);
 }
 
 // --------------------------------------------------------------- labels ---
@@ -1027,6 +1035,49 @@ __global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int*
     for (int tile = range.first; tile < range.hi; tile += range.stride) label_final_tile<NDIM>(q_up, q_dn, gr, tile, M, m);
 }
 
+// LDS of a step kernel: two flag-gather lists of kEngChunk vertices, the
+// stencil planes, or the troublemakers' targets.
+constexpr int kEngSmemBytes = 2 * kEngChunk * sizeof(int);
+
+// The troublemakers' targets found by one block, kept in LDS until its tiles
+// are done; a target beyond the list's capacity is edited at once.
+struct TargetList {
+    static constexpr int kCap = kEngSmemBytes / sizeof(int);
+    int* list;  // nullptr: count only
+    unsigned* count;
+    uint8_t* marks;
+    float* g;
+    const float* L;
+    uint8_t* dirty;
+    template <int NDIM>
+    __device__ __forceinline__ void put(const Grid& gr, unsigned k, int t, unsigned& changed) const {
+        if (k < static_cast<unsigned>(kCap)) list[k] = t;
+        else claim_edit<NDIM>(marks, g, L, dirty, gr, t, changed);
+    }
+    // Appends each lane's targets (-1: none; nloc of them): one LDS atomic per
+    // wave, positions from a prefix sum over the wave.
+    template <int NDIM>
+    __device__ __forceinline__ void add_wave(const Grid& gr, const int (&tn)[4], const int (&tx)[4], int nloc,
+                                             unsigned& changed) const {
+        if (!__any(nloc)) return;
+        const int lane = threadIdx.x & 63;
+        int incl = nloc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        unsigned base = 0;
+        if (lane == 63) base = atomicAdd(count, static_cast<unsigned>(incl));
+        unsigned k = __shfl(base, 63) + static_cast<unsigned>(incl - nloc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (tn[j] >= 0) put<NDIM>(gr, k++, tn[j], changed);
+            if (tx[j] >= 0) put<NDIM>(gr, k++, tx[j], changed);
+        }
+    }
+};
+
 // Troublemaker detection, tile by tile (see k_label_final for the order).
 // The tile's G groups are loaded GB at a time (the step kernel uses one: on
 // ocean2d more groups in flight measured slower).
@@ -1034,7 +1085,8 @@ template <int NDIM, int GB = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile
 __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
                                               const int* __restrict__ Mf, const int* __restrict__ mf, const Grid& gr,
-                                              int tile, uint8_t* __restrict__ marks, unsigned& wrong, unsigned& cases) {
+                                              int tile, const TargetList& tl, unsigned& wrong, unsigned& cases,
+                                              unsigned& changed) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
     static_assert(G % GB == 0, "whole batches of groups");
 #pragma unroll 1
@@ -1071,8 +1123,10 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
         }
 #pragma unroll
         for (int k = 0; k < GB; ++k) {
+            int tn[4], tx[4], nloc = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
+                tn[j] = tx[j] = -1;
                 if (j >= tg[k].count) continue;
                 const int i = tg[k].i0 + j;
                 const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
@@ -1082,9 +1136,11 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
                 const bool rmin = wm && ((dg & 15u) != (df & 15u));
                 const bool rmax = wM && ((dg >> 4) != (df >> 4));
                 cases += rmin + rmax;
-                if (rmin) mark(marks, i + gr.off[df & 15u]);
-                if (rmax) mark(marks, i + gr.off[dg >> 4]);
+                nloc += rmin + rmax;
+                if (rmin) tn[j] = i + gr.off[df & 15u];
+                if (rmax) tx[j] = i + gr.off[dg >> 4];
             }
+            if (tl.list) tl.add_wave<NDIM>(gr, tn, tx, nloc, changed);
         }
     }
 }
@@ -1276,7 +1332,7 @@ __host__ __device__ inline int eng_items(const EngField& F, int op) {
     const int tiles = label_tiles_of(F.gr);
     const int dirs = dirs_items_of(F.gr, F.variant);
     switch (op) {
-        case kOpPreA: case kOpApplyC: case kOpApplyR: case kOpRefreshC: case kOpRefreshR: case kOpDelta:
+        case kOpPreA: case kOpApplyC: case kOpRefreshC: case kOpRefreshR: case kOpDelta:
             return chunks;
         case kOpPreB: case kOpPreC: case kOpPreD: case kOpRTile: case kOpRJump: case kOpRDetect: return tiles;
         case kOpPreA2: case kOpPreE: case kOpFullC: case kOpFullR: return dirs;
@@ -1496,27 +1552,11 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                         edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, i, changed);
                         return;
                     }
-                    // FPmin and FNmax targets may be shared: the first to set
-                    // the target's mark (an atomic OR on its word) edits it
+                    // FPmin and FNmax targets may be shared
                     const int t = i + gr.off[type == 1 ? (F.dirs_f[i] & 15u) : (F.dirs_g[i] >> 4)];
-                    const unsigned bit = 1u << (8 * (t & 3));
-                    if ((atomicOr(reinterpret_cast<unsigned*>(F.marks + (t & ~3)), bit) & bit) == 0u)
-                        edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, t, changed);
+                    claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, t, changed);
                 },
                 [](int) {});
-            unsigned v[1] = {changed};
-            const int idx[1] = {kCntChanged};
-            block_add<1>(v, cnt, idx);
-            break;
-        }
-        case kOpApplyR: {
-            // the marked troublemaker targets (each marked once), marks cleared
-            unsigned changed = 0;
-            int* list = reinterpret_cast<int*>(smem);
-            for_flagged(
-                F.marks, gr.n, lo, hi, 0xFFFFFFFFu, list, list + kEngChunk,
-                [&](int t) { edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, t, changed); },
-                [&](int w) { reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u); });
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
             block_add<1>(v, cnt, idx);
@@ -1551,21 +1591,48 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
         }
         case kOpRDetect: {
             // A tile whose labels cannot have changed and that had no
-            // mislabelled vertex last time has none now: skipped.
-            unsigned wrong = 0, cases = 0;
+            // mislabelled vertex last time has none now: skipped.  The
+            // troublemakers' targets of the block's tiles go to an LDS list
+            // and are edited together once it is half full and at the end
+            // (type 0; type 1 only counts): detection reads directions and
+            // labels, never g.
+            __shared__ unsigned s_targets;
+            unsigned wrong = 0, cases = 0, changed = 0;
+            const TargetList tl{st.type == 0 ? reinterpret_cast<int*>(smem) : nullptr, &s_targets, F.marks, F.g,
+                                F.L, F.dirty};
+            // the listed targets, edited by all threads; ends with a barrier
+            auto edit_targets = [&]() {
+                const int nt = min(static_cast<int>(s_targets), TargetList::kCap);
+                for (int e = threadIdx.x; e < nt; e += blockDim.x)
+                    claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, tl.list[e], changed);
+                __syncthreads();
+            };
+            if (threadIdx.x == 0) s_targets = 0;
+            __syncthreads();
             for (int item = lo; item < hi; ++item) {
                 if (!F.tile_lab[item] && !F.tile_wrong[item]) continue;
                 const unsigned before = wrong;
-                detect_r_tile<NDIM, 1>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, F.marks, wrong, cases);
+                detect_r_tile<NDIM, 1>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, tl, wrong, cases,
+                                       changed);
                 const int any = __syncthreads_or(wrong != before);
                 if (threadIdx.x == 0) {
                     F.tile_wrong[item] = any ? 1 : 0;
                     F.tile_lab[item] = 0;
                 }
+                // past half the list: edit what it holds and empty it
+                if (tl.list && s_targets > TargetList::kCap / 2) {
+                    edit_targets();
+                    if (threadIdx.x == 0) s_targets = 0;
+                    __syncthreads();
+                }
             }
-            unsigned v[2] = {wrong, cases};
-            const int idx[2] = {kCntWrong, kCntRCases};
-            block_add<2>(v, cnt, idx);
+            if (tl.list) {
+                __syncthreads();
+                edit_targets();
+            }
+            unsigned v[3] = {wrong, cases, changed};
+            const int idx[3] = {kCntWrong, kCntRCases, kCntChanged};
+            block_add<3>(v, cnt, idx);
             break;
         }
         case kOpDelta: {
@@ -1632,7 +1699,7 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
                                                   const int* pre, int nf, unsigned long long* ts) {
-    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    __shared__ __align__(16) char smem[kEngSmemBytes];
     static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
     if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = static_cast<unsigned long long>(wall_clock64());
     eng_step_body<NDIM>(fields, cur, pre, nf, smem);
@@ -1735,12 +1802,11 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             return go(kOpRJump);
         case kOpRJump:
             if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
+            st.type = S->rounds_total >= F.cap ? 1 : 0;  // at the cap: detect without editing
             return go(kOpRDetect);
         case kOpRDetect:
             if (c[kCntWrong] == 0) return finish(MSZ_OK);
-            if (S->rounds_total >= F.cap) return finish(MSZ_ENOCONV);
-            return go(kOpApplyR);
-        case kOpApplyR:
+            if (st.type != 0) return finish(MSZ_ENOCONV);
             if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
             S->rounds_total += 1;
             S->rounds_r += 1;
@@ -1837,7 +1903,7 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
                                                    const EngState* __restrict__ states_in, EngStats* stats,
                                                    unsigned* cnt3, int* ctl, int* hflag, int* oplog, int k,
                                                    unsigned long long* ts) {
-    __shared__ __align__(16) char smem[4096 * 2 * sizeof(int)];
+    __shared__ __align__(16) char smem[kEngSmemBytes];
     __shared__ unsigned part[256];
     __shared__ unsigned red[kCntSlots];
     __shared__ EngState s_next;
