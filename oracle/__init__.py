@@ -40,7 +40,7 @@ def build() -> str:
 class _Options(ctypes.Structure):
     _fields_ = [("max_rounds", ctypes.c_int64), ("warm_start", ctypes.c_void_p),
                 ("g_out", ctypes.c_void_p), ("fpmin_literal", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("merged_c", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -173,7 +173,8 @@ def stats_dict(st: _Stats) -> dict:
     }
 
 
-def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, fpmin_literal: bool = False):
+def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, fpmin_literal: bool = False,
+        merged_c: bool = False):
     """Run the correction loop.  Returns (status, delta, g, stats)."""
     f, fhat = _f32(f), _f32(fhat)
     assert f.shape == fhat.shape
@@ -188,6 +189,7 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, fpmin_liter
         opt.warm_start = _ptr(ws)
     opt.g_out = _ptr(g)
     opt.fpmin_literal = 1 if fpmin_literal else 0
+    opt.merged_c = 1 if merged_c else 0
     st = _Stats()
     rc = lib().msz_ref_fix(_ptr(f), _ptr(fhat), *grid_args(f.shape), np.float32(xi), _ptr(edits),
                            ctypes.byref(opt), ctypes.byref(st))

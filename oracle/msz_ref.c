@@ -344,6 +344,10 @@ int msz_ref_delta(float g, float fhat, float* delta) {
 /*  - C phase (Sec. 5.1): sub-loops FPmax, FPmin, FNmax, FNmin in that order,*/
 /*    each repeated until it finds no case of its type; the C phase repeats  */
 /*    until no false critical point of any type remains.                     */
+/*  - Merged C phase (option merged_c; the parallel C-loop of Sec. 6.1): one */
+/*    round finds the false critical points of all four types on the same   */
+/*    snapshot and halves the union of their targets once; it repeats until */
+/*    no false critical point remains.                                       */
 /*  - R phase (Sec. 5.2): one round lowers the targets of both the min and   */
 /*    the max troublemakers; after it, if any false critical point appeared, */
 /*    control returns to the C phase (Sec. 5.3), else the R phase goes on.   */
@@ -465,7 +469,24 @@ int msz_ref_fix(const float* f, const float* fhat, int ndim, int nx, int ny, int
     for (;;) {
         /* C phase */
         stats->outer_iters++;
-        for (;;) {
+        while (o.merged_c) {
+            refresh_dirs(&s);
+            int64_t cnt[4], total = 0;
+            for (int t = 0; t < 4; ++t) total += cnt[t] = mark_c_targets(&s, t, o.fpmin_literal);
+            if (total == 0) break;
+            if (rounds >= cap) {
+                memset(mark, 0, (size_t)n);
+                status = MSZ_REF_ENOCONV;
+                goto done;
+            }
+            if (apply_marks(&s) == 0) {
+                status = MSZ_REF_ESTALL;
+                goto done;
+            }
+            ++rounds;
+            for (int t = 0; t < 4; ++t) stats->rounds[t] += cnt[t] > 0;
+        }
+        while (!o.merged_c) {
             for (int t = 0; t < 4; ++t) {
                 for (;;) {
                     refresh_dirs(&s);

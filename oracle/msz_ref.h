@@ -42,11 +42,12 @@ typedef struct {
     const float* warm_start;   /* optional start field g0 with L <= g0 <= fhat */
     float* g_out;              /* optional: receives the edited field g */
     int32_t fpmin_literal;     /* 1: FPmin lowers the highest neighbour (literal Eq. 3); test use */
-    int32_t pad;
+    int32_t merged_c;          /* 1: each C round fixes the cases of all four types at once (Sec. 6.1) */
 } msz_ref_options;
 
 typedef struct {
-    int64_t rounds[4];      /* productive rounds of each C sub-loop type */
+    int64_t rounds[4];      /* productive rounds of each C sub-loop type (merged_c: the C rounds
+                               in which that type had a case) */
     int64_t rounds_r;       /* productive R-loop rounds */
     int64_t outer_iters;    /* number of times the C phase was entered */
     int64_t n_edited;       /* vertices whose final g differs from fhat */

@@ -198,8 +198,10 @@ def r_targets(mesh, f, g, Mf, mf):
     return targets
 
 
-def fix(f, fhat, xi, rng: random.Random | None = None, max_rounds: int = 100000):
-    """The synchronous-round schedule; returns (status, g, stats) with status in {'ok','stall','noconv'}."""
+def fix(f, fhat, xi, rng: random.Random | None = None, max_rounds: int = 100000, merged: bool = False):
+    """The synchronous-round schedule; returns (status, g, stats) with status in {'ok','stall','noconv'}.
+    merged: every C round takes the cases of all four types from one snapshot
+    (the parallel C-loop of Sec. 6.1) instead of one type per sub-loop."""
     rng = rng or random.Random(0)
     shape = f.shape
     mesh = Mesh(shape)
@@ -227,7 +229,18 @@ def fix(f, fhat, xi, rng: random.Random | None = None, max_rounds: int = 100000)
 
     while True:
         stats["outer_iters"] += 1
-        while True:
+        while merged:
+            found = [[i for i in range(mesh.n) if PREDICATES[t](mesh, f, g, i)] for t in range(4)]
+            if not any(found):
+                break
+            if rounds >= max_rounds:
+                return "noconv", np.array(g, np.float32).reshape(shape), stats
+            if apply({c_target(mesh, t, f, g, i) for t in range(4) for i in found[t]}) == 0:
+                return "stall", np.array(g, np.float32).reshape(shape), stats
+            rounds += 1
+            for t in range(4):
+                stats["rounds"][t] += bool(found[t])
+        while not merged:
             for t in range(4):
                 while True:
                     cases = [i for i in range(mesh.n) if PREDICATES[t](mesh, f, g, i)]

@@ -314,6 +314,37 @@ def test_literal_loop_bit_exact_small_grids():
     assert total_rounds > cases  # the cases really exercise the loop
 
 
+def test_merged_c_rounds_bit_exact_with_literal():
+    """The merged C phase (all four types per round, Sec. 6.1) == the literal
+    restatement of that schedule, and it reaches zero segmentation error."""
+    rng = np.random.default_rng(81)
+    prng = random.Random(81)
+    total, fewer = 0, 0
+    for shape in [(3, 3), (4, 4), (3, 5), (5, 4), (2, 2, 2), (2, 3, 3), (3, 3, 3)]:
+        for levels in (0, 5):
+            for _ in range(5):
+                f, fh, xi = synth.random_small(rng, shape, xi=0.15, levels=levels)
+                rc, d, g, st = oracle.fix(f, fh, xi, merged_c=True)
+                status, lg, lst = lit.fix(f, fh, xi, rng=prng, merged=True)
+                assert status == {0: "ok", -4: "stall", -5: "noconv"}[rc]
+                assert (g.view(np.uint32) == lg.view(np.uint32)).all()
+                assert st["rounds"] == lst["rounds"] and st["rounds_r"] == lst["rounds_r"]
+                assert st["outer_iters"] == lst["outer_iters"]
+                if rc == oracle.OK:
+                    _check_invariants(f, fh, xi, rc, d, g, st)
+                rc1, _, _, st1 = oracle.fix(f, fh, xi)
+                total += 1
+                fewer += max(st["rounds"]) < sum(st1["rounds"])
+    assert fewer > 0  # some cases really had several types in one round
+
+
+def test_merged_c_rounds_bumps128():
+    f, fh, xi = synth.bumps128()[0]
+    rc, d, g, st = oracle.fix(f, fh, xi, merged_c=True)
+    _check_invariants(f, fh, xi, rc, d, g, st)
+    assert rc == oracle.OK and st["n_edited"] > 0
+
+
 def test_values_stay_on_halving_chain():
     """Every final g_i is reached from fhat_i by repeated halving toward L_i (Eq. 1)."""
     f, fh, xi = synth.bumps128()[0]
