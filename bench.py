@@ -7,6 +7,8 @@ the two other forms on their own workloads, and the encoding of the edits
 (reported under "forms"):
   edits    the plain loop's edits on the pair, losslessly encoded on the GPU
            (sorted index gaps and values, Huffman coded) and decoded back
+  merged   the same pair with merged C rounds (all four case types fixed in
+           one round, the parallel C-loop of Sec. 6.1)
   batched  96 uneven k^-3 fields (64 2D with sides 64..2048, 32 3D cubes
            32^3..192^3, xi in {1e-4, 1e-3, 1e-2} x range) in one launch
   learned  a 512^3 k^-11/3 field at xi = 1e-3 x range: the warm-started loop
@@ -14,7 +16,7 @@ the two other forms on their own workloads, and the encoding of the edits
 Every result is checked for zero segmentation error outside the clock.
 Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,edits,batched,learned]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,edits,merged,batched,learned]
                   [--no-cpu-baseline] [--batch-cpu-baseline] [--calib-copy] [--schedule-out FILE]
 """
 from __future__ import annotations
@@ -298,6 +300,41 @@ def bench_learned(msz, torch, dev, steps):
     return out
 
 
+def bench_merged(msz, torch, dev, pairs, steps, plain_ms):
+    """The ocean2d pair with merged C rounds (all four case types per round,
+    the parallel C-loop of Sec. 6.1): time per step, rounds, zero error."""
+    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)) for f, fh, xi in pairs]
+    ws = torch.empty(msz.workspace_bytes(fields[0][0].shape), dtype=torch.uint8, device=dev)
+    outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
+
+    def step(timing=False):
+        res = []
+        for (f, fh, xi), (e, g) in zip(fields, outs):
+            rc, _, _, st = msz.fix(f, fh, xi, workspace=ws, edits_out=e, g_out=g, merged=True, timing=timing)
+            if rc != msz.OK:
+                raise RuntimeError(f"msz_fix (merged C rounds) failed: {msz.strerror(rc)}")
+            res.append(st)
+        return res
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sts = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    for (f, fh, xi), (e, g) in zip(fields, outs):
+        checked(msz, f, g, xi)
+    verts = sum(f.numel() for f, _, _ in fields)
+    log(f"bench: merged C rounds {ms:.3f} ms/step ({verts / ms / 1e6:.3f} Gv/s), plain {plain_ms:.3f} ms/step")
+    return {"workload": "the ocean2d pair (3600x2400 at xi = 1e-4 and 1e-3), merged C rounds",
+            "ms_per_step": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
+            "steps": steps, "speedup_vs_plain": round(plain_ms / ms, 3),
+            "rounds": [{"xi": p[2], "rounds": st["rounds"], "rounds_r": st["rounds_r"],
+                        "outer_iters": st["outer_iters"], "n_edited": st["n_edited"]}
+                       for p, st in zip(fields, sts)]}
+
+
 def bench_edits(msz, torch, edits, pairs, reps=3):
     """Lossless encoding of the plain loop's edits on the ocean2d pair (Sec. 6.3):
     sizes, the edit ratio, and encode / decode times, each decode checked bit
@@ -350,7 +387,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="plain,edits,batched,learned")
+    ap.add_argument("--forms", default="plain,edits,merged,batched,learned")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-cpu-baseline", action="store_true",
@@ -383,6 +420,8 @@ def main():
     extra = {}
     if "edits" in forms:
         extra["edits"] = bench_edits(msz, torch, edits, pairs)
+    if "merged" in forms:
+        extra["merged"] = bench_merged(msz, torch, dev, pairs, args.form_steps, ms_per_step)
     if "batched" in forms:
         extra["batched"] = bench_batched(msz, torch, dev, args.form_steps, args.batch_cpu_baseline)
     if "learned" in forms:

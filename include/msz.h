@@ -84,6 +84,15 @@ enum {
 
 /* msz_options.flags bits. */
 #define MSZ_FLAG_TIMING 1 /* time every step (single-field calls; adds a little overhead) */
+/* Merged C rounds (the parallel C-loop of Sec. 6.1): each C round finds the
+ * false critical points of all four types on one snapshot of g and halves the
+ * union of their targets once, instead of running the FPmax, FPmin, FNmax and
+ * FNmin sub-loops in turn.  Deterministic; the result is bit-identical to the
+ * oracle's merged schedule (not to the default one) and still has zero
+ * segmentation error within xi.  stats.rounds[t] then counts the C rounds in
+ * which type t had a case.  Accepted by msz_fix, msz_fix_batch and
+ * msz_fix_learned. */
+#define MSZ_FLAG_MERGED_C 2
 
 typedef struct {
     int32_t ndim;        /* 2 or 3 */
@@ -123,7 +132,7 @@ typedef struct {
     void* workspace;          /* DEVICE scratch of >= msz_workspace_bytes(dims), or NULL */
     size_t workspace_bytes;   /* size of `workspace` */
     int32_t tile_override;    /* 0: autotuned/default tile; k > 0: tile variant k (see msz_tile_variants) */
-    int32_t flags;            /* 0 or MSZ_FLAG_TIMING */
+    int32_t flags;            /* MSZ_FLAG_* bits */
 } msz_options;
 
 /*
@@ -201,7 +210,8 @@ typedef struct {
  * is active.  opt->workspace (if given) must hold
  * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
  * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);
- * opt->max_rounds applies to every field (MSZ_FLAG_TIMING is ignored).
+ * opt->max_rounds and MSZ_FLAG_MERGED_C apply to every field (MSZ_FLAG_TIMING is
+ * ignored).
  * Returns MSZ_OK when every field converged, else the first failing field's
  * code (see each stats; per-phase timings are not filled).
  */

@@ -26,6 +26,7 @@ NET_PARAMS = 14289
 NET_FEATURES = 16
 N_PHASES = len(PHASES)
 FLAG_TIMING = 1
+FLAG_MERGED_C = 2  # merged C rounds (all four case types per round)
 
 
 class Dims(ctypes.Structure):
@@ -173,7 +174,7 @@ def tile_variants(ndim: int) -> int:
 
 def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: bool = True,
         workspace=None, tile: int = 0, edits_out=None, g_out=None, timing: bool = False,
-        stream=None):
+        merged: bool = False, stream=None):
     """Runs the correction loop on the GPU.
 
     Returns ``(status, delta, g, stats)``: ``delta`` with fl(fhat + delta) == g,
@@ -198,7 +199,7 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: boo
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
     opt.tile_override = int(tile)
-    opt.flags = FLAG_TIMING if timing else 0
+    opt.flags = (FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0)
     st = Stats()
     rc = lib().msz_fix(f.data_ptr(), fhat.data_ptr(), d, float(xi), edits.data_ptr(),
                        ctypes.byref(opt), ctypes.byref(st), _stream(stream))
@@ -275,7 +276,7 @@ def decode_edits(blob, shape, out=None, stream=None):
 
 
 def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles="auto", outs=None,
-              stream=None):
+              merged: bool = False, stream=None):
     """Corrects a list of (f, fhat, xi) together in one device-scheduled run (msz_fix_batch).
 
     ``tiles``: each field's direction tile variant, "auto" (the autotuner's
@@ -311,6 +312,7 @@ def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=Non
         pairs.append((e, g))
     opt = Options()
     opt.max_rounds = int(max_rounds)
+    opt.flags = FLAG_MERGED_C if merged else 0
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -410,7 +412,8 @@ def net_adam(params, grad, m, v, step: int, lr: float, stream=None):
 
 
 def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: int = 0, want_g: bool = True,
-                workspace=None, edits_out=None, g_out=None, timing: bool = False, stream=None):
+                workspace=None, edits_out=None, g_out=None, timing: bool = False, merged: bool = False,
+                stream=None):
     """msz_fix warm-started by the network; same return value as fix()."""
     import torch
     _check_field(f, "f")
@@ -423,7 +426,7 @@ def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: i
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
-    opt.flags = FLAG_TIMING if timing else 0
+    opt.flags = (FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0)
     st = Stats()
     rc = lib().msz_fix_learned(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), params.data_ptr(),
                                float(p_min), edits.data_ptr(), ctypes.byref(opt), ctypes.byref(st),

@@ -573,7 +573,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     if (!aligned16(f) || !aligned16(fhat) || !aligned16(edits_out) || !aligned16(o.warm_start) ||
         !aligned16(o.g_out) || !aligned16(o.workspace))
         return done(MSZ_EINVAL);
-    if ((o.flags & ~MSZ_FLAG_TIMING) != 0 || o.tile_override < 0 ||
+    if ((o.flags & ~(MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C)) != 0 || o.tile_override < 0 ||
         o.tile_override > tile_variant_count(d.ndim))
         return done(MSZ_EINVAL);
     if (int rc = check_xi(xi)) return done(rc);
@@ -586,6 +586,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     F = EngField{};
     F.gr = gr;
     F.variant = o.tile_override;
+    F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
     F.xi = xi;
     F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
     F.f = f;
@@ -630,7 +631,7 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
     if (!jobs || n_jobs <= 0 || n_jobs > kEngMaxFields) return MSZ_EINVAL;
     msz_options o{};
     if (opt) o = *opt;
-    if (o.warm_start || o.g_out || (o.flags & ~MSZ_FLAG_TIMING) || o.tile_override || !aligned16(o.workspace))
+    if (o.warm_start || o.g_out || (o.flags & ~(MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C)) || o.tile_override || !aligned16(o.workspace))
         return MSZ_EINVAL;
     for (int j = 0; j < n_jobs; ++j) {
         Grid gr;
@@ -660,6 +661,7 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
         F = EngField{};
         make_grid(J.d, F.gr);
         F.variant = J.tile;
+        F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
         F.xi = J.xi;
         F.cap = cap;
         F.f = J.f;

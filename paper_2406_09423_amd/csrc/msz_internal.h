@@ -155,9 +155,14 @@ enum EngOp : int {
     kOpStart       // before the first step (its successor is kOpPreA)
 };
 
+// EngState.type of a merged C round (all four case types at once); 0..3 are
+// the sub-loop types FPmax, FPmin, FNmax, FNmin.
+constexpr int kTypeMerged = 4;
+
 struct EngField {
     Grid gr;
     int variant;
+    int merged;  // 1: merged C rounds
     float xi;
     long long cap;
     const float *f, *fhat, *warm;

@@ -1545,6 +1545,25 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             unsigned changed = 0;
             int* list = reinterpret_cast<int*>(smem);
             const int type = st.type;
+            if (type == kTypeMerged) {
+                // every case of every type; all targets claimed, so a vertex
+                // proposed by several cases is edited once
+                for_flagged(
+                    F.cases, gr.n, lo, hi, 0x0F0F0F0Fu, list, list + kEngChunk,
+                    [&](int i) {
+                        const unsigned b = F.cases[i];
+                        if (b & 9u) claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, i, changed);
+                        if (b & 2u) claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_f[i] & 15u],
+                                                     changed);
+                        if (b & 4u) claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_g[i] >> 4],
+                                                     changed);
+                    },
+                    [](int) {});
+                unsigned v[1] = {changed};
+                const int idx[1] = {kCntChanged};
+                block_add<1>(v, cnt, idx);
+                break;
+            }
             for_flagged(
                 F.cases, gr.n, lo, hi, 0x01010101u << type, list, list + kEngChunk,
                 [&](int i) {
@@ -1743,6 +1762,12 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
     // C loop: the current type while it has cases, then the next types in
     // turn, back to FPmax while any of the first three has cases; then labels.
     auto c_decide = [&]() {
+        if (F.merged) {  // one type: all of them
+            st.type = kTypeMerged;
+            if (S->cases[0] + S->cases[1] + S->cases[2] + S->cases[3] > 0)
+                return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
+            return go(kOpRTile);
+        }
         for (int guard = 0; guard < 8; ++guard) {
             if (cases_of(st.type) > 0) return S->rounds_total >= F.cap ? finish(MSZ_ENOCONV) : go(kOpApplyC);
             if (st.type < 3) {
@@ -1793,7 +1818,9 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
         case kOpApplyC:
             if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
             S->rounds_total += 1;
-            if (st.type == 0) S->rounds[0] += 1;
+            if (st.type == kTypeMerged) {  // the types that had cases in this round
+                for (int t = 0; t < 4; ++t) S->rounds[t] += S->cases[t] > 0 ? 1 : 0;
+            } else if (st.type == 0) S->rounds[0] += 1;
             else if (st.type == 1) S->rounds[1] += 1;
             else if (st.type == 2) S->rounds[2] += 1;
             else S->rounds[3] += 1;

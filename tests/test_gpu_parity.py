@@ -42,7 +42,8 @@ def _bits(a):
 
 
 def assert_fix_parity(msz, f, fh, xi, **kw):
-    rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi, **{k: v for k, v in kw.items() if k != "tile"})
+    okw = {("merged_c" if k == "merged" else k): v for k, v in kw.items() if k != "tile"}
+    rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi, **okw)
     ws = kw.pop("warm_start", None)
     tile = kw.pop("tile", 0)
     rc, d, g, st = msz.fix(dev(f), dev(fh), xi, warm_start=None if ws is None else dev(ws), tile=tile, **kw)
@@ -374,3 +375,59 @@ def test_full_turb512_learned_properties(msz):
     assert all(v == 0 for v in cnt.values()), cnt
     rounds = lambda st: sum(st["rounds"]) + st["rounds_r"]
     assert rounds(st_l) < rounds(st_p), (rounds(st_l), rounds(st_p))
+
+
+# ------------------------------------------------------- merged C rounds ---
+
+def _merged_case(name):
+    rng = np.random.default_rng(31)
+    if name == "bumps128":
+        return [synth.bumps128()[0]]
+    if name == "ocean":
+        f = synth.gaussian_random_field((240, 360), 3.0, rng).astype(np.float32)
+        f = ((f - f.min()) / (f.max() - f.min())).astype(np.float32)
+        return [(f, synth.quantize(f, np.float32(x)), np.float32(x)) for x in (1e-4, 1e-3)]
+    if name == "turb":
+        f = synth.gaussian_random_field((37, 70, 95), 11.0 / 3.0, rng).astype(np.float32)
+        xi = synth.xi_for(f, 1e-3)
+        return [(f, synth.quantize(f, xi), xi)]
+    shape = (90, 120) if name == "checker2d" else (20, 22, 24)
+    parity = np.indices(shape).sum(axis=0) % 2
+    f = (0.5 + 1e-3 * parity + 1e-4 * rng.uniform(0, 1, size=shape)).astype(np.float32)
+    xi = np.float32(1e-2)
+    return [(f, synth.quantize(f, xi), xi)]
+
+
+@pytest.mark.parametrize("name", ["bumps128", "ocean", "checker2d", "checker3d", "turb"])
+def test_merged_c_bit_exact(msz, name):
+    """Merged C rounds (all four case types per round, Sec. 6.1): edited
+    values, deltas and statistics bit-identical to the oracle's merged
+    schedule, and zero segmentation error.  The checkerboards start with dense
+    rounds (full passes over g), the others are sparse."""
+    for f, fh, xi in _merged_case(name):
+        _say("merged C rounds", name, f.shape, float(xi))
+        rc, st = assert_fix_parity(msz, f, fh, xi, merged=True)
+        assert rc == msz.OK
+        rc_p, _, _, st_p = msz.fix(dev(f), dev(fh), xi)
+        assert rc_p == msz.OK
+        _say("  rounds merged", st["rounds"], st["rounds_r"], "plain", st_p["rounds"], st_p["rounds_r"])
+
+
+def test_merged_c_cap_and_batch(msz):
+    """The round cap ends a merged C phase like the oracle's, and a batch with
+    merged rounds gives every field its single-call result."""
+    f, fh, xi = synth.bumps128()[0]
+    _say("merged C rounds, cap 3")
+    rc, st = assert_fix_parity(msz, f, fh, xi, merged=True, max_rounds=3)
+    assert rc == msz.ENOCONV
+    fields = _batch_case(24)[:6]
+    _say("merged batch of", len(fields))
+    rcb, res = msz.fix_batch([(dev(a), dev(b), x) for a, b, x in fields], merged=True)
+    assert rcb == msz.OK
+    for j, (a, b, x) in enumerate(fields):
+        rc_s, d_s, g_s, s_s = msz.fix(dev(a), dev(b), x, merged=True)
+        st_b, d_b, g_b, s_b = res[j]
+        assert st_b == rc_s == msz.OK, (j, st_b, rc_s)
+        assert (_bits(host(g_b)) == _bits(host(g_s))).all(), j
+        assert (_bits(host(d_b)) == _bits(host(d_s))).all(), j
+        assert s_b == s_s, (j, s_b, s_s)
