@@ -207,8 +207,8 @@ def bench_batched(msz, torch, dev, steps, cpu_all_cores=False):
     outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
     ws = torch.empty(msz.batch_workspace_bytes(shapes), dtype=torch.uint8, device=dev)
 
-    def run():
-        rc, res = msz.fix_batch(fields, workspace=ws, tiles=tiles, outs=outs)
+    def run(merged=False):
+        rc, res = msz.fix_batch(fields, workspace=ws, tiles=tiles, outs=outs, merged=merged)
         if rc != msz.OK:
             raise RuntimeError(f"msz_fix_batch failed: {msz.strerror(rc)}")
         return res
@@ -234,6 +234,17 @@ def bench_batched(msz, torch, dev, steps, cpu_all_cores=False):
     ms_seq = (time.perf_counter() - t0) * 1e3
     log(f"bench: batched {ms:.2f} ms ({verts / ms / 1e6:.3f} Gv/s), one by one {ms_seq:.2f} ms")
     rounds = [sum(st["rounds"]) + st["rounds_r"] for _, _, _, st in res]
+    # the same batch with merged C rounds (all four case types per round)
+    run(merged=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res_m = run(merged=True)
+    torch.cuda.synchronize()
+    ms_m = (time.perf_counter() - t0) * 1e3 / steps
+    for (f, fh, xi), (_, _, g, _) in zip(fields, res_m):
+        checked(msz, f, g, xi)
+    log(f"bench: batched with merged C rounds {ms_m:.2f} ms ({verts / ms_m / 1e6:.3f} Gv/s)")
     cpu = None
     if cpu_all_cores:
         log("bench: oracle over the batch on all host cores")
@@ -245,6 +256,7 @@ def bench_batched(msz, torch, dev, steps, cpu_all_cores=False):
             "vertices": verts, "ms": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
             "steps": steps, "sequential_ms": round(ms_seq, 3),
             "speedup_vs_sequential": round(ms_seq / ms, 3), "max_rounds": max(rounds),
+            "merged_c_ms": round(ms_m, 3), "merged_c_value": round(verts / ms_m / 1e6, 4),
             "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}, "cpu_all_cores": cpu}
 
 
