@@ -72,11 +72,11 @@ enum {
     MSZ_PHASE_DIRS = 1,         /* steepest directions of f */
     MSZ_PHASE_DIRS_DETECT = 2,  /* directions and case bytes of every vertex of g */
     MSZ_PHASE_REFRESH = 3,      /* directions and case bytes around the last edits */
-    MSZ_PHASE_APPLY = 4,        /* halving of the round's targets (from case bytes or marks) */
+    MSZ_PHASE_APPLY = 4,        /* halving of a C round's targets (from the case bytes) */
     MSZ_PHASE_LABEL_TILE = 5,   /* in-LDS pointer jumping per tile */
     MSZ_PHASE_LABEL_JUMP = 6,   /* pointer compression of tile-face vertices */
     MSZ_PHASE_LABEL_FINAL = 7,  /* labels of f */
-    MSZ_PHASE_DETECT_R = 8,     /* troublemaker detection */
+    MSZ_PHASE_DETECT_R = 8,     /* troublemaker detection and the halving of their targets */
     MSZ_PHASE_DELTA = 9,        /* output deltas */
     MSZ_PHASE_NET = 10,         /* learned warm start: features, 3 conv layers, g0 */
     MSZ_N_PHASES = 11

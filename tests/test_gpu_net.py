@@ -217,10 +217,11 @@ def test_halvings_match_oracle(msz):
     assert want[1, 1, 1] == -1
 
 
-@pytest.mark.parametrize("p_min", [0.5, 0.25, 1.5])
-def test_fix_learned_bit_exact_with_oracle(msz, p_min):
+@pytest.mark.parametrize("p_min,merged", [(0.5, False), (0.25, False), (1.5, False), (0.5, True)])
+def test_fix_learned_bit_exact_with_oracle(msz, p_min, merged):
     """The warm start from the GPU's own prediction p, recomputed by the oracle,
-    then the oracle's loop from it: edits, g and round counts bit-identical."""
+    then the oracle's loop from it (with merged C rounds too): edits, g and
+    round counts bit-identical."""
     import synth
     f, fh, xi = synth.turb3d(n=32, nblobs=4)[0]
     params = random_params(12)
@@ -231,8 +232,8 @@ def test_fix_learned_bit_exact_with_oracle(msz, p_min):
     L = oracle.lower_bound(f, xi)
     g0 = nr.warm_start(p, fh, L, p_min)
     assert (g0 != fh).any()
-    rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi, warm_start=g0)
-    rc, d, g, st = msz.fix_learned(fd, fhd, xi, flat, p_min=p_min)
+    rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi, warm_start=g0, merged_c=merged)
+    rc, d, g, st = msz.fix_learned(fd, fhd, xi, flat, p_min=p_min, merged=merged)
     assert rc == rc_o == msz.OK
     assert np.array_equal(d.cpu().numpy().view(np.uint32), d_o.view(np.uint32))
     assert np.array_equal(g.cpu().numpy().view(np.uint32), g_o.view(np.uint32))

@@ -4,6 +4,7 @@ Labels, directions-derived counts, edited values, deltas and round statistics
 must be identical (the plain loop is deterministic: integer decisions and
 single IEEE float operations in both implementations).
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -216,6 +217,15 @@ def test_error_paths(msz):
     assert msz.fix(big_f, dev(fh), xi)[0] == msz.EINVAL
     with pytest.raises(msz.MszError):
         msz.labels(dev(nan))
+    # an unknown option flag is rejected before any work
+    fd, fhd = dev(f), dev(fh)
+    e = torch.empty_like(fd)
+    opt = msz.Options()
+    opt.flags = 4
+    st = msz.Stats()
+    rc = msz.lib().msz_fix(fd.data_ptr(), fhd.data_ptr(), msz.dims_of(f.shape), float(xi), e.data_ptr(),
+                           ctypes.byref(opt), ctypes.byref(st), msz._stream())
+    assert rc == msz.EINVAL
 
 
 def test_floor_collision_stalls(msz):
