@@ -259,7 +259,9 @@ struct EngineCtx {
         if (hipGraphCreate(&graph, 0) != hipSuccess) return MSZ_EDEVICE;
         hipGraphNode_t last = nullptr;
         auto chain = [&](hipGraphNode_t n) { last = n; };
-        auto add_kernel = [&](const void* fn, dim3 g, dim3 b, void** args) -> bool {
+        // a kernel node after the nodes deps[0 .. nd)
+        auto add_kernel_after = [&](const void* fn, dim3 g, dim3 b, void** args, const hipGraphNode_t* deps,
+                                    int nd) -> bool {
             hipKernelNodeParams p{};
             p.func = const_cast<void*>(fn);
             p.gridDim = g;
@@ -267,9 +269,13 @@ struct EngineCtx {
             p.sharedMemBytes = 0;
             p.kernelParams = args;
             hipGraphNode_t n = nullptr;
-            if (hipGraphAddKernelNode(&n, graph, last ? &last : nullptr, last ? 1 : 0, &p) != hipSuccess) return false;
+            if (hipGraphAddKernelNode(&n, graph, nd ? deps : nullptr, nd, &p) != hipSuccess) return false;
             chain(n);
             return true;
+        };
+        // a kernel node after the last one added
+        auto add_kernel = [&](const void* fn, dim3 g, dim3 b, void** args) -> bool {
+            return add_kernel_after(fn, g, b, args, last ? &last : nullptr, last ? 1 : 0);
         };
         if (nf == 1) {  // one field: one step kernel per step, deciding for itself
             const void* fn = eng_step1_kernel(has3 ? 3 : 2);
@@ -287,18 +293,27 @@ struct EngineCtx {
             EngState* cur = states + par * nf;
             EngState* nxt = states + (par ^ 1) * nf;
             unsigned long long* ts = timing ? tstamp + st * kEngStampWords : nullptr;
+            // the 2D and the 3D step kernels work on disjoint fields: both
+            // follow the last step's scan and may run side by side; the
+            // decision follows both
+            hipGraphNode_t prev = last, dep[2];
+            int nd = 0;
             if (has2) {
+                last = prev;
                 void* a[] = {&fields, &cur, &pre2, &nf, &ts};
                 if (!add_kernel(eng_step_kernel(2), dim3(grid2), dim3(256), a)) return MSZ_EDEVICE;
+                dep[nd++] = last;
             }
             if (has3) {
+                last = prev;
                 void* a[] = {&fields, &cur, &pre3, &nf, &ts};
                 if (!add_kernel(eng_step_kernel(3), dim3(grid3), dim3(256), a)) return MSZ_EDEVICE;
+                dep[nd++] = last;
             }
             int* log = timing ? oplog : nullptr;
             int stp = st;
             void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp, &counters};
-            if (!add_kernel(eng_decide_kernel(), dim3(nf), dim3(256), d)) return MSZ_EDEVICE;
+            if (!add_kernel_after(eng_decide_kernel(), dim3(nf), dim3(256), d, dep, nd)) return MSZ_EDEVICE;
             if (nf > 1) {
                 void* c[] = {&fields, &nxt, &nf, &pre2, &pre3, &ctl, &hflag_dev};
                 if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
