@@ -13,7 +13,7 @@
  *    ndim == 2 (nz must be 1): every quad is split along its (0,0)-(1,1)
  *    diagonal, so interior vertices have 6 neighbours.  ndim == 3: Freudenthal
  *    split of every cube along (0,0,0)-(1,1,1), 14 neighbours (Sec. 3, the PL
- *    setting).  No periodic wrap.  nx, ny, nz >= 1 and nx*ny*nz < 2^31.
+ *    setting).  No periodic wrap.  nx, ny, nz >= 1 and nx*ny*nz <= 2^31 - 2^16.
  *  - Order (Sec. 4, simulation of simplicity): vertex a is above b iff
  *    h_a > h_b, or h_a == h_b and a > b.  -0 and +0 compare equal.
  *  - Arrays: float32 / int32, DEVICE pointers, owned by the caller, at least

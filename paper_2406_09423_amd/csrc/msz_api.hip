@@ -21,12 +21,16 @@
 
 namespace msz {
 
+constexpr int64_t kMaxVertices = (int64_t(1) << 31) - (int64_t(1) << 16);
+
 bool make_grid(const msz_dims& d, Grid& gr) {
     if (d.ndim != 2 && d.ndim != 3) return false;
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) return false;
     if (d.ndim == 2 && d.nz != 1) return false;
     const int64_t n = static_cast<int64_t>(d.nx) * d.ny * d.nz;
-    if (n >= (int64_t(1) << 31)) return false;
+    // headroom below 2^31: vertex counts rounded up to whole work chunks,
+    // flag words and tiles are formed in 32-bit arithmetic
+    if (n > kMaxVertices) return false;
     gr.ndim = d.ndim;
     gr.nx = d.nx;
     gr.ny = d.ny;

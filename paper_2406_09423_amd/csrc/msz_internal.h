@@ -108,7 +108,7 @@ int tile_variant_count(int ndim);
 }  // namespace msz
 #include "../../include/msz.h"
 namespace msz {
-// Validates dims (ndim 2 or 3, nz == 1 in 2D, positive sides, n < 2^31) and fills gr.
+// Validates dims (ndim 2 or 3, nz == 1 in 2D, positive sides, n <= 2^31 - 2^16) and fills gr.
 bool make_grid(const msz_dims& d, Grid& gr);
 
 void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s);

@@ -45,6 +45,11 @@ def test_host_only_entry_points():
     assert msz.workspace_bytes((1, 1)) > 0
     assert msz.lib().msz_workspace_bytes(msz.Dims(2, 4, 4, 2)) == 0      # 2D with nz != 1
     assert msz.lib().msz_workspace_bytes(msz.Dims(3, 0, 4, 4)) == 0
+    # vertex counts up to 2^31 - 2^16 (sizes rounded up to whole chunks stay in 32 bits)
+    assert msz.lib().msz_workspace_bytes(msz.Dims(2, 2 ** 15 - 1, 2 ** 16, 1)) > 0   # exactly the limit
+    assert msz.lib().msz_workspace_bytes(msz.Dims(2, 2 ** 15, 2 ** 16 - 1, 1)) == 0  # 2^15 above it
+    assert msz.lib().msz_workspace_bytes(msz.Dims(2, 2 ** 31 - 1, 1, 1)) == 0
+    assert msz.lib().msz_workspace_bytes(msz.Dims(3, 1291, 1291, 1291)) == 0
     assert msz.lib().msz_workspace_bytes(msz.Dims(3, 2048, 2048, 512)) == 0   # n >= 2^31
     assert msz.tile_variants(2) >= 1 and msz.tile_variants(3) >= 1
     both = msz.workspace_bytes((64, 80)) + msz.workspace_bytes((16, 16, 16))
