@@ -557,13 +557,13 @@ __device__ __forceinline__ bool slot_in_grid(const Grid& gr, int x, int y, int z
     return NDIM == 2 ? in2 : in2 && z + dz >= 0 && z + dz < gr.nz;
 }
 
-// Halves g[t] once; flags t (so the refresh clears its mark) and, if the
-// value changed, its neighbours.
+// Halves g[t] once, from its value old and floor lt as read by the caller;
+// flags t (so the refresh clears its mark) and, if the value changed, its
+// neighbours.
 template <int NDIM>
-__device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* __restrict__ L,
-                                            uint8_t* __restrict__ dirty, const Grid& gr, int t, unsigned& changed) {
-    const float old = g[t];
-    const float nv = halve(old, L[t]);
+__device__ __forceinline__ void edit_value(float* __restrict__ g, uint8_t* __restrict__ dirty, const Grid& gr,
+                                           int t, float old, float lt, unsigned& changed) {
+    const float nv = halve(old, lt);
     dirty[t] = 1;
     if (nv == old) return;
     g[t] = nv;
@@ -575,16 +575,29 @@ __device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* 
         if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
 }
 
+template <int NDIM>
+__device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* __restrict__ L,
+                                            uint8_t* __restrict__ dirty, const Grid& gr, int t, unsigned& changed) {
+    edit_value<NDIM>(g, dirty, gr, t, g[t], L[t], changed);
+}
+
 // Edits target t unless another case of the same step already has: the first
 // to set t's mark (an atomic OR on its word) edits it.  The mark is cleared by
-// the refresh that follows (t is flagged by the edit).
+// the refresh that follows (t is flagged by the edit).  g[t] and L[t] are read
+// alongside the atomic (one memory round trip, not two): within a step only
+// the winner writes g[t], so the value read is the round's.
 template <int NDIM>
 __device__ __forceinline__ void claim_edit(uint8_t* __restrict__ marks, float* __restrict__ g,
                                            const float* __restrict__ L, uint8_t* __restrict__ dirty,
                                            const Grid& gr, int t, unsigned& changed) {
     const unsigned bit = 1u << (8 * (t & 3));
+    // relaxed workgroup-scope atomic loads: plain cached loads that the
+    // compiler keeps ahead of the atomic instead of sinking them into the
+    // winner's branch
+    const float old = __hip_atomic_load(g + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const float lt = __hip_atomic_load(L + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if ((atomicOr(reinterpret_cast<unsigned*>(marks + (t & ~3)), bit) & bit) == 0u)
-        edit_vertex<NDIM>(g, L, dirty, gr, t, changed);
+        edit_value<NDIM>(g, dirty, gr, t, old, lt, changed);
 }
 
 // --------------------------------------------------------------- labels ---
