@@ -5,9 +5,11 @@
 // the next operation of each field follows from its counters (decided inside
 // the step kernel for one field, by a decide kernel for a batch) --
 //   C phase  sub-loops FPmax, FPmin, FNmax, FNmin, each until it finds no case
-//            of its type; repeated until no false critical point remains;
-//   R phase  labels of g, troublemaker detection, one apply; back to the C
-//            phase whenever the apply created a false critical point.
+//            of its type, repeated until no false critical point remains (or,
+//            with MSZ_FLAG_MERGED_C, rounds over all four types at once);
+//   R phase  labels of g, then troublemaker detection, which also edits the
+//            troublemakers' targets; back to the C phase whenever those edits
+//            created a false critical point.
 // The host captures kGraphSteps steps in a HIP graph and relaunches it until
 // the device clears a done word in pinned host memory.
 // msz_fix runs the same schedule for one field.
