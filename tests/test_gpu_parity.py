@@ -189,6 +189,22 @@ def test_fix_warm_start(msz):
     assert_fix_parity(msz, f, fh, xi, warm_start=mid)
 
 
+@pytest.mark.parametrize("merged", [False, True])
+def test_fix_degenerate_shapes(msz, merged):
+    """One vertex, single rows and columns, 3D slabs one vertex thick, and
+    xi = 0 (every floor equals f, so fhat == f is the only valid input and no
+    edit is possible): bit-identical to the oracle under both schedules."""
+    rng = np.random.default_rng(20)
+    for shape in [(1, 1), (1, 9), (9, 1), (1, 1, 1), (1, 1, 9), (9, 1, 1), (1, 9, 1), (2, 1, 5), (1, 6, 6)]:
+        for levels in (0, 3):
+            f, fh, xi = synth.random_small(rng, shape, xi=0.2, levels=levels)
+            _say("fix degenerate", shape, levels, "merged" if merged else "")
+            assert_fix_parity(msz, f, fh, xi, merged=merged)
+    f = rng.uniform(0, 1, size=(7, 9)).astype(np.float32)
+    rc, st = assert_fix_parity(msz, f, f, np.float32(0.0), merged=merged)
+    assert rc == msz.OK and st["n_edited"] == 0
+
+
 def test_fix_identity(msz):
     rng = np.random.default_rng(18)
     f = rng.uniform(0, 1, size=(50, 60)).astype(np.float32)
