@@ -393,7 +393,7 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     EngineCtx& E = engine_ctx();
     if (int rc = E.init(dev)) return rc;
     const bool single = nf == 1;
-    const int grid2 = step_grid(dev, 2, single), grid3 = step_grid(dev, 3, single);
+    int grid2 = step_grid(dev, 2, single), grid3 = step_grid(dev, 3, single);
     if (grid2 < 1 || grid3 < 1) return MSZ_EDEVICE;
     bool has2 = false, has3 = false;
     std::vector<EngState> hs(2 * nf);
@@ -407,6 +407,16 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         has3 = has3 || three;
         p2[j + 1] = p2[j] + (three ? 0 : items);
         p3[j + 1] = p3[j] + (three ? items : 0);
+    }
+    if (!single) {
+        // batch step kernels: twice as many blocks as fit on the device at
+        // once, so the 2D and 3D kernels running side by side keep each
+        // other's idle slots filled (the 96-field batch: 61.9 ms against 68.1
+        // with one resident grid each, 89.7 with half).  The single-field
+        // kernel stays at one resident grid: each of its blocks takes the
+        // schedule decision itself, and twice as many cost 38% more.
+        grid2 *= 2;
+        grid3 *= 2;
     }
     timing = timing && nf == 1;
     if (timing) last_schedule().clear();
