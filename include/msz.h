@@ -204,9 +204,9 @@ typedef struct {
  * msz_fix_batch -- corrects n_jobs (<= 1024) independent fields of uneven
  * sizes together: every device step advances each unfinished field by one
  * operation of the schedule msz_fix follows (one step kernel per dimension
- * runs the work items of all fields as one index space; a decide kernel picks
- * each field's next operation), so each field's result is bit-identical to
- * its own msz_fix.  The steps run from a HIP graph relaunched until no field
+ * runs the work items of all its fields as one index space, the 2D and 3D
+ * kernels side by side; a decide kernel picks each field's next operation),
+ * so each field's result is bit-identical to its own msz_fix.  The steps run from a HIP graph relaunched until no field
  * is active.  opt->workspace (if given) must hold
  * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
  * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);
