@@ -241,43 +241,88 @@ struct DecTables {
     DecTable gap, val;
 };
 
-// Reads the bits of a chunk through a 64-bit register buffer (the next bit
-// in bit 0), a word at a time; past the chunk's end it reads zeros and sets
-// `over`.
+// Reads one chunk's bits in stream order (bit j of the chunk is bit j % 32 of
+// its word j / 32).  Words arrive eight at a time through a register queue
+// (eight independent loads per memory round trip instead of one dependent
+// load per word); 33 to 64 bits wait in buf, so a field of up to 30 bits or a
+// code of up to 20 is taken with shifts and one bit reversal (fields are
+// emitted most significant bit first).  Bits past the chunk's last word read
+// as zeros and mark the read as over.
 struct BitReader {
     const unsigned* w;
-    unsigned next, end;  // next word to load, end of the chunk's words
-    unsigned long long buf;
+    unsigned next, end;      // next word to load, end of the chunk's words
+    unsigned long long buf;  // the next `have` bits, the next one in bit 0
     int have;
+    unsigned q0, q1, q2, q3, q4, q5, q6, q7;  // loaded words, q0 first
+    int qn;
+    long long used, limit;   // bits taken, bits in the chunk
     bool over;
-    __device__ __forceinline__ unsigned bit() {
-        if (have == 0) {
-            if (next >= end) {
-                over = true;
-                return 0u;
-            }
-            buf = w[next++];
-            have = 32;
-        }
-        const unsigned b = static_cast<unsigned>(buf & 1ull);
-        buf >>= 1;
-        --have;
-        return b;
+    __device__ __forceinline__ void init(const unsigned* words, unsigned w0, unsigned wend) {
+        w = words;
+        next = w0;
+        end = wend;
+        buf = 0ull;
+        have = 0;
+        q0 = q1 = q2 = q3 = q4 = q5 = q6 = q7 = 0u;
+        qn = 0;
+        used = 0;
+        limit = 32ll * (wend - w0);
+        over = false;
     }
+    __device__ __forceinline__ void fetch() {
+        const unsigned left = end > next ? end - next : 0u;
+        const int k = left < 8u ? static_cast<int>(left) : 8;
+        q0 = k > 0 ? w[next] : 0u;
+        q1 = k > 1 ? w[next + 1] : 0u;
+        q2 = k > 2 ? w[next + 2] : 0u;
+        q3 = k > 3 ? w[next + 3] : 0u;
+        q4 = k > 4 ? w[next + 4] : 0u;
+        q5 = k > 5 ? w[next + 5] : 0u;
+        q6 = k > 6 ? w[next + 6] : 0u;
+        q7 = k > 7 ? w[next + 7] : 0u;
+        qn = k;
+        next += static_cast<unsigned>(k);
+    }
+    __device__ __forceinline__ unsigned pop() {
+        if (qn == 0) fetch();
+        if (qn == 0) return 0u;  // past the chunk
+        const unsigned v = q0;
+        q0 = q1, q1 = q2, q2 = q3, q3 = q4, q4 = q5, q5 = q6, q6 = q7, q7 = 0u;
+        --qn;
+        return v;
+    }
+    __device__ __forceinline__ void fill() {
+        while (have <= 32) {
+            buf |= static_cast<unsigned long long>(pop()) << have;
+            have += 32;
+        }
+    }
+    __device__ __forceinline__ void skip(int n) {
+        buf >>= n;
+        have -= n;
+        used += n;
+        if (used > limit) over = true;
+    }
+    // the next n <= 30 bits as a number (first bit most significant)
     __device__ __forceinline__ unsigned bits(int n) {
-        unsigned v = 0;
-        for (int i = 0; i < n; ++i) v = (v << 1) | bit();
+        if (n == 0) return 0u;
+        fill();
+        const unsigned v = __brev(static_cast<unsigned>(buf)) >> (32 - n);
+        skip(n);
         return v;
     }
 };
 
 // -1 on a malformed stream.
 __device__ __forceinline__ int decode_symbol(const DecTable& t, BitReader& r) {
-    int code = 0;
+    r.fill();
+    const unsigned peek = __brev(static_cast<unsigned>(r.buf));  // the next 32 bits, first one on top
     for (int len = 1; len <= kEncMaxLen; ++len) {
-        code = (code << 1) | static_cast<int>(r.bit());
-        const int rel = code - t.first[len];
-        if (rel >= 0 && rel < t.count[len]) return t.sym[t.offset[len] + rel];
+        const int rel = static_cast<int>(peek >> (32 - len)) - t.first[len];
+        if (rel >= 0 && rel < t.count[len]) {
+            r.skip(len);
+            return t.sym[t.offset[len] + rel];
+        }
     }
     return -1;
 }
@@ -303,7 +348,8 @@ __global__ void __launch_bounds__(64) k_dec_chunks(const DecTables* __restrict__
         atomicOr(bad, 1u);
         return;
     }
-    BitReader r{stream, w0, wend, 0ull, 0, false};
+    BitReader r;
+    r.init(stream, w0, wend);
     const int k_end = min(m, (c + 1) * kEncChunk);
     long long i = static_cast<int>(table[2 * c + 1]);
     for (int k = c * kEncChunk; k < k_end; ++k) {
