@@ -439,6 +439,26 @@ def test_merged_c_bit_exact(msz, name):
         _say("  rounds merged", st["rounds"], st["rounds_r"], "plain", st_p["rounds"], st_p["rounds_r"])
 
 
+def test_merged_c_full_sizes(msz):
+    """Merged C rounds at the workloads' full sizes: the 3600x2400 field at
+    xi = 1e-4 against the whole oracle run (merged schedule, about 20 s of
+    CPU), and the 256^3 turbulence field by its invariants, with the oracle's
+    labels of the GPU result equal to those of f."""
+    f, fh, xi = synth.ocean2d(rels=(1e-4,))[0]
+    _say("merged C rounds, full 3600x2400 xi=1e-4")
+    rc, st = assert_fix_parity(msz, f, fh, xi, merged=True)
+    assert rc == msz.OK
+    f, fh, xi = synth.turb3d()[0]
+    _say("merged C rounds, full 256^3")
+    rc, d, g, st = msz.fix(dev(f), dev(fh), xi, merged=True)
+    assert rc == msz.OK
+    g, d = host(g), host(d)
+    _full_invariants(msz, f, fh, xi, g, d, st)
+    Mg, mg = oracle.labels(g)
+    Mf, mf = oracle.labels(f)
+    assert (Mg == Mf).all() and (mg == mf).all()
+
+
 def test_merged_c_cap_and_batch(msz):
     """The round cap ends a merged C phase like the oracle's, and a batch with
     merged rounds gives every field its single-call result."""
