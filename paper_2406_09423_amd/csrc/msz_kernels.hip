@@ -7,8 +7,15 @@
 //   marks          uint8[n]   claims of the targets edited in the current round (an
 //                             edit shared by several cases is made once; padded to 16 B)
 //   dirty          uint8[n]   directions to recompute after an apply (padded to 16 B)
+//   target         uint8[n]   face-layer vertices that some tile pass of g made an exit
+//   M_f, m_f       int32[n]   labels of f (max, min)
 //   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests
 //   qf_up, qf_dn   int32      per label tile and face-layer vertex, its tile-pass pointer
+//   root_up/_dn    int32      per label tile and face-layer vertex, its roots at the last
+//                             compression
+//   tile_dirty, tile_lab, tile_wrong
+//                  uint8      per label tile: a direction of g changed; its labels may
+//                             have changed; its last troublemaker pass found a wrong label
 //   cnt            uint32[kSlots][kSlotStride] round counters; block b adds into slot
 //                  b % kSlots so that no cache line takes more than a few hundred
 //                  atomics per launch
