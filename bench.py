@@ -411,9 +411,8 @@ def main():
                          "(to attribute the step kernels of a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: one field's "
-              "correction loop runs on one GPU (DESIGN.md describes how the work would shard)",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: each field's "
+              "correction loop runs on a single GPU", file=sys.stderr)
         sys.exit(2)
     forms = [x for x in args.forms.split(",") if x]
 
