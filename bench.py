@@ -309,6 +309,26 @@ def bench_learned(msz, torch, dev, steps):
         log(f"bench: {name} 512^3 {ms:.2f} ms, rounds {out[name]['rounds']}")
     out["speedup"] = round(out["plain"]["ms"] / out["learned"]["ms"], 4)
     out["unit"] = "Gvertices/s"
+    # the same two with merged C rounds (all four case types per round)
+    for name, fn in (("plain_merged", lambda: msz.fix(fd, fhd, xi, workspace=ws, edits_out=e, g_out=g, merged=True)),
+                     ("learned_merged", lambda: msz.fix_learned(fd, fhd, xi, params, p_min=p_min, workspace=ws,
+                                                                edits_out=e, g_out=g, merged=True))):
+        try:
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                rc, _, _, st = fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            if rc != msz.OK:
+                raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
+            checked(msz, fd, g, xi)
+            out[name] = {"ms": round(ms, 3), "value": round(fd.numel() / ms / 1e6, 4),
+                         "c_rounds_by_type": st["rounds"], "r_rounds": st["rounds_r"], "n_edited": st["n_edited"]}
+            log(f"bench: {name} 512^3 {ms:.2f} ms")
+        except RuntimeError as err:  # reported, not fatal: the default forms above are the measured ones
+            out[name] = {"failed": str(err)}
     return out
 
 
