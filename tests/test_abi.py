@@ -54,3 +54,13 @@ def test_host_only_entry_points():
     assert msz.tile_variants(2) >= 1 and msz.tile_variants(3) >= 1
     both = msz.workspace_bytes((64, 80)) + msz.workspace_bytes((16, 16, 16))
     assert msz.batch_workspace_bytes([(64, 80), (16, 16, 16)]) == both   # the fields' own workspaces
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus N > 1 exits with status 2 and says why
+    before touching a device."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
