@@ -30,7 +30,7 @@ CASE_NAMES = ("fp_max", "fp_min", "fn_max", "fn_min")
 def build() -> str:
     """Compile the oracle into ``oracle/libmsz_ref.so`` (always recompiles)."""
     tmp = _SO + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _SO)
@@ -40,13 +40,14 @@ def build() -> str:
 class _Options(ctypes.Structure):
     _fields_ = [("max_rounds", ctypes.c_int64), ("warm_start", ctypes.c_void_p),
                 ("g_out", ctypes.c_void_p), ("fpmin_literal", ctypes.c_int32),
-                ("merged_c", ctypes.c_int32)]
+                ("merged_c", ctypes.c_int32), ("threads", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64 * 4), ("rounds_r", ctypes.c_int64),
                 ("outer_iters", ctypes.c_int64), ("n_edited", ctypes.c_int64),
-                ("false_init", ctypes.c_int64 * 4), ("n_inexact", ctypes.c_int64),
+                ("false_init", ctypes.c_int64 * 4), ("mislabel_init", ctypes.c_int64),
+                ("n_inexact", ctypes.c_int64),
                 ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
@@ -168,14 +169,17 @@ def stats_dict(st: _Stats) -> dict:
         "outer_iters": int(st.outer_iters),
         "n_edited": int(st.n_edited),
         "false_init": [int(x) for x in st.false_init],
+        "mislabel_init": int(st.mislabel_init),
         "n_inexact": int(st.n_inexact),
         "status": int(st.status),
     }
 
 
 def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, fpmin_literal: bool = False,
-        merged_c: bool = False):
-    """Run the correction loop.  Returns (status, delta, g, stats)."""
+        merged_c: bool = False, threads: int = 1):
+    """Run the correction loop.  Returns (status, delta, g, stats).  ``threads``
+    splits the per-vertex direction loop over that many threads (the result
+    does not depend on it); everything else runs serially."""
     f, fhat = _f32(f), _f32(fhat)
     assert f.shape == fhat.shape
     edits = np.zeros(f.shape, np.float32)
@@ -190,6 +194,7 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, fpmin_liter
     opt.g_out = _ptr(g)
     opt.fpmin_literal = 1 if fpmin_literal else 0
     opt.merged_c = 1 if merged_c else 0
+    opt.threads = int(threads)
     st = _Stats()
     rc = lib().msz_ref_fix(_ptr(f), _ptr(fhat), *grid_args(f.shape), np.float32(xi), _ptr(edits),
                            ctypes.byref(opt), ctypes.byref(st))

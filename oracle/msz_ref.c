@@ -4,11 +4,15 @@
  * TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked against.
  * It is deliberately plain and slow: naive neighbour loops, a memoised walk
  * for the labels, one full pass over the grid per detection.  No blocking,
- * fusion or reordering beyond what the definitions state.
+ * fusion or reordering beyond what the definitions state.  The one loop that
+ * may run on several threads (option `threads`) is the per-vertex direction
+ * loop of the correction loop: every vertex's directions depend only on the
+ * field, so the split changes no result; everything else runs serially.
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no fast-math: the
- * halving chain runs through subnormals, and every float operation must be a
- * single IEEE binary32/binary64 operation with round-to-nearest-even).
+ * Build: gcc -O2 -std=c11 -fopenmp -ffp-contract=off -fPIC -shared (no
+ * fast-math: the halving chain runs through subnormals, and every float
+ * operation must be a single IEEE binary32/binary64 operation with
+ * round-to-nearest-even).
  *
  * Readings of the paper that this file fixes (the paper is silent or
  * ambiguous on them) are marked "Reading:".
@@ -146,15 +150,12 @@ float msz_ref_halve(float g, float L) {
 /* value (the order above), not the slope; a vertex is its own ascent       */
 /* (descent) target when it is a maximum (minimum).                          */
 /* ------------------------------------------------------------------------ */
-int msz_ref_dirs(const float* h, int ndim, int nx, int ny, int nz, int32_t* up, int32_t* dn) {
-    grid_t gr;
-    int rc = make_grid(ndim, nx, ny, nz, &gr);
-    if (rc) return rc;
-    if (!h || !up || !dn) return MSZ_REF_EINVAL;
-    int64_t nb[14];
-    for (int64_t i = 0; i < gr.n; ++i) {
+static void dirs_of(const float* h, const grid_t* gr, int32_t* up, int32_t* dn, int threads) {
+#pragma omp parallel for num_threads(threads > 1 ? threads : 1) schedule(static)
+    for (int64_t i = 0; i < gr->n; ++i) {
+        int64_t nb[14];
         int64_t u = i, d = i;
-        int cnt = neighbours(&gr, i, nb);
+        int cnt = neighbours(gr, i, nb);
         for (int k = 0; k < cnt; ++k) {
             if (above(h, nb[k], u)) u = nb[k];
             if (above(h, d, nb[k])) d = nb[k];
@@ -162,6 +163,14 @@ int msz_ref_dirs(const float* h, int ndim, int nx, int ny, int nz, int32_t* up, 
         up[i] = (int32_t)u;
         dn[i] = (int32_t)d;
     }
+}
+
+int msz_ref_dirs(const float* h, int ndim, int nx, int ny, int nz, int32_t* up, int32_t* dn) {
+    grid_t gr;
+    int rc = make_grid(ndim, nx, ny, nz, &gr);
+    if (rc) return rc;
+    if (!h || !up || !dn) return MSZ_REF_EINVAL;
+    dirs_of(h, &gr, up, dn, 1);
     return MSZ_REF_OK;
 }
 
@@ -359,11 +368,10 @@ typedef struct {
     float* g;
     int32_t *upf, *dnf, *upg, *dng, *Mf, *mf, *Mg, *mg, *path;
     uint8_t* mark;
+    int threads;
 } loop_t;
 
-static void refresh_dirs(loop_t* s) {
-    msz_ref_dirs(s->g, s->gr.ndim, s->gr.nx, s->gr.ny, s->gr.nz, s->upg, s->dng);
-}
+static void refresh_dirs(loop_t* s) { dirs_of(s->g, &s->gr, s->upg, s->dng, s->threads); }
 
 static int64_t mark_c_targets(loop_t* s, int type, int literal) {
     int64_t count = 0;
@@ -457,13 +465,18 @@ int msz_ref_fix(const float* f, const float* fhat, int ndim, int nx, int ny, int
     s.Mf = ia + 4 * n, s.mf = ia + 5 * n, s.Mg = ia + 6 * n, s.mg = ia + 7 * n;
     s.path = ia + 8 * n;
     s.mark = mark;
+    s.threads = o.threads;
 
-    msz_ref_dirs(f, ndim, nx, ny, nz, s.upf, s.dnf);
+    dirs_of(f, &gr, s.upf, s.dnf, s.threads);
     follow(s.upf, n, s.Mf, s.path);
     follow(s.dnf, n, s.mf, s.path);
     refresh_dirs(&s);
     for (int64_t i = 0; i < n; ++i)
         for (int t = 0; t < 4; ++t) stats->false_init[t] += is_case(t, i, s.upf, s.dnf, s.upg, s.dng);
+    /* Appendix B: vertices of the start field whose max or min label differs from f's */
+    follow(s.upg, n, s.Mg, s.path);
+    follow(s.dng, n, s.mg, s.path);
+    for (int64_t i = 0; i < n; ++i) stats->mislabel_init += s.Mg[i] != s.Mf[i] || s.mg[i] != s.mf[i];
 
     int64_t rounds = 0;
     for (;;) {

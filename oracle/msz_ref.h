@@ -43,6 +43,9 @@ typedef struct {
     float* g_out;              /* optional: receives the edited field g */
     int32_t fpmin_literal;     /* 1: FPmin lowers the highest neighbour (literal Eq. 3); test use */
     int32_t merged_c;          /* 1: each C round fixes the cases of all four types at once (Sec. 6.1) */
+    int32_t threads;           /* threads of the per-vertex direction loop (<= 1: serial); results
+                                  do not depend on it */
+    int32_t pad;
 } msz_ref_options;
 
 typedef struct {
@@ -52,6 +55,7 @@ typedef struct {
     int64_t outer_iters;    /* number of times the C phase was entered */
     int64_t n_edited;       /* vertices whose final g differs from fhat */
     int64_t false_init[4];  /* false critical points of each type in the start field */
+    int64_t mislabel_init;  /* vertices of the start field with a wrong max or min label */
     int64_t n_inexact;      /* vertices where no float delta reproduces g exactly */
     int32_t status;
     int32_t pad;
