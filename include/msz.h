@@ -93,6 +93,13 @@ enum {
  * which type t had a case.  Accepted by msz_fix, msz_fix_batch and
  * msz_fix_learned. */
 #define MSZ_FLAG_MERGED_C 2
+/* Count the mislabelled vertices of the start field (stats.mislabel_init:
+ * the N_f of the right-labelled ratio before any edit, Appendix B).  This
+ * costs one extra labelling of the start field (a label tile pass, the face
+ * compression and a comparison pass), so it is opt-in; without the flag
+ * stats.mislabel_init is -1.  Accepted by msz_fix, msz_fix_batch and
+ * msz_fix_learned (there the start field is the network's warm start). */
+#define MSZ_FLAG_COUNT_INIT 4
 
 typedef struct {
     int32_t ndim;        /* 2 or 3 */
@@ -107,6 +114,8 @@ typedef struct {
     int64_t outer_iters;   /* times the C phase was entered */
     int64_t n_edited;      /* vertices whose final g differs from fhat */
     int64_t false_init[4]; /* false critical points of each type in the start field */
+    int64_t mislabel_init; /* vertices of the start field with a wrong max or min label (N_f of
+                              Appendix B); -1 unless MSZ_FLAG_COUNT_INIT was set */
     int64_t n_inexact;     /* vertices where no float32 delta gives fl(fhat + delta) == g */
     int32_t status;        /* the return code of the call */
     int32_t pad;

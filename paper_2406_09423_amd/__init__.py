@@ -27,6 +27,7 @@ NET_FEATURES = 16
 N_PHASES = len(PHASES)
 FLAG_TIMING = 1
 FLAG_MERGED_C = 2  # merged C rounds (all four case types per round)
+FLAG_COUNT_INIT = 4  # count the start field's mislabelled vertices (stats["mislabel_init"], else -1)
 
 
 class Dims(ctypes.Structure):
@@ -37,8 +38,8 @@ class Dims(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64 * 4), ("rounds_r", ctypes.c_int64),
                 ("outer_iters", ctypes.c_int64), ("n_edited", ctypes.c_int64),
-                ("false_init", ctypes.c_int64 * 4), ("n_inexact", ctypes.c_int64),
-                ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("false_init", ctypes.c_int64 * 4), ("mislabel_init", ctypes.c_int64),
+                ("n_inexact", ctypes.c_int64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("phase_ms", ctypes.c_float * N_PHASES), ("phase_launches", ctypes.c_int32 * N_PHASES)]
 
     def timing(self) -> dict:
@@ -53,6 +54,7 @@ class Stats(ctypes.Structure):
             "outer_iters": int(self.outer_iters),
             "n_edited": int(self.n_edited),
             "false_init": [int(x) for x in self.false_init],
+            "mislabel_init": int(self.mislabel_init),
             "n_inexact": int(self.n_inexact),
             "status": int(self.status),
         }
@@ -150,6 +152,10 @@ def dims_of(shape) -> Dims:
     raise ValueError(f"fields are 2D (ny, nx) or 3D (nz, ny, nx), got shape {tuple(shape)}")
 
 
+def _flags(timing: bool, merged: bool, count_init: bool) -> int:
+    return (FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0) | (FLAG_COUNT_INIT if count_init else 0)
+
+
 def _stream(stream=None) -> int:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -174,12 +180,13 @@ def tile_variants(ndim: int) -> int:
 
 def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: bool = True,
         workspace=None, tile: int = 0, edits_out=None, g_out=None, timing: bool = False,
-        merged: bool = False, stream=None):
+        merged: bool = False, count_init: bool = False, stream=None):
     """Runs the correction loop on the GPU.
 
     Returns ``(status, delta, g, stats)``: ``delta`` with fl(fhat + delta) == g,
     ``g`` the edited field (None unless ``want_g``), ``stats`` a dict (with a
-    per-kernel ``"timing"`` entry when ``timing`` is set).
+    per-kernel ``"timing"`` entry when ``timing`` is set; ``mislabel_init`` is
+    -1 unless ``count_init``).
     """
     import torch
     _check_field(f, "f")
@@ -199,7 +206,7 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: boo
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
     opt.tile_override = int(tile)
-    opt.flags = (FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0)
+    opt.flags = _flags(timing, merged, count_init)
     st = Stats()
     rc = lib().msz_fix(f.data_ptr(), fhat.data_ptr(), d, float(xi), edits.data_ptr(),
                        ctypes.byref(opt), ctypes.byref(st), _stream(stream))
@@ -276,7 +283,7 @@ def decode_edits(blob, shape, out=None, stream=None):
 
 
 def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles="auto", outs=None,
-              merged: bool = False, stream=None):
+              merged: bool = False, count_init: bool = False, stream=None):
     """Corrects a list of (f, fhat, xi) together in one device-scheduled run (msz_fix_batch).
 
     ``tiles``: each field's direction tile variant, "auto" (the autotuner's
@@ -312,7 +319,7 @@ def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=Non
         pairs.append((e, g))
     opt = Options()
     opt.max_rounds = int(max_rounds)
-    opt.flags = FLAG_MERGED_C if merged else 0
+    opt.flags = _flags(False, merged, count_init)
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -413,7 +420,7 @@ def net_adam(params, grad, m, v, step: int, lr: float, stream=None):
 
 def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: int = 0, want_g: bool = True,
                 workspace=None, edits_out=None, g_out=None, timing: bool = False, merged: bool = False,
-                stream=None):
+                count_init: bool = False, stream=None):
     """msz_fix warm-started by the network; same return value as fix()."""
     import torch
     _check_field(f, "f")
@@ -426,7 +433,7 @@ def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: i
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
-    opt.flags = (FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0)
+    opt.flags = _flags(timing, merged, count_init)
     st = Stats()
     rc = lib().msz_fix_learned(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), params.data_ptr(),
                                float(p_min), edits.data_ptr(), ctypes.byref(opt), ctypes.byref(st),

@@ -4,6 +4,8 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -11,7 +13,7 @@ SO = os.path.join(HERE, "libmsz.so")
 SOURCES = ["msz_kernels.hip", "msz_api.hip", "msz_net.hip", "msz_encode.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # every float operation is one IEEE operation: no contraction into FMAs,
     # subnormals kept (edits run through them), no packed fp32 instructions
     "-ffp-contract=off", "-fno-gpu-flush-denormals-to-zero",
@@ -21,13 +23,24 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    """Compile libmsz.so (always recompiles) and return its path."""
+    """Compile libmsz.so (always recompiles; the sources in parallel) and return its path."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = SO + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
-    if verbose:
-        print(" ".join(cmd), file=sys.stderr)
-    subprocess.run(cmd, check=True)
+    with tempfile.TemporaryDirectory(prefix="msz_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+
+        def compile_one(k: int) -> None:
+            cmd = [hipcc, *HIPCC_FLAGS, "-c", "-o", objs[k], os.path.join(CSRC, SOURCES[k])]
+            if verbose:
+                print(" ".join(cmd), file=sys.stderr)
+            subprocess.run(cmd, check=True)
+
+        with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+            list(pool.map(compile_one, range(len(SOURCES))))
+        tmp = SO + ".tmp"
+        cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+        if verbose:
+            print(" ".join(cmd), file=sys.stderr)
+        subprocess.run(cmd, check=True)
     os.replace(tmp, SO)
     return SO
 

@@ -57,6 +57,9 @@ namespace {
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// Option flags accepted by the correction entry points.
+constexpr int32_t kFixFlags = MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C | MSZ_FLAG_COUNT_INIT;
+
 // The kernels move four vertices per dwordx4 access.
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -541,8 +544,9 @@ void bind_field(EngField& F, char* w) {
     F.qd = reinterpret_cast<int*>(w + l.qd);
 }
 
-void copy_stats(const EngStats& e, msz_stats* out) {
+void copy_stats(const EngStats& e, bool counted_init, msz_stats* out) {
     for (int t = 0; t < 4; ++t) out->rounds[t] = e.rounds[t], out->false_init[t] = e.false_init[t];
+    out->mislabel_init = counted_init ? e.mislabel_init : -1;
     out->rounds_r = e.rounds_r;
     out->outer_iters = e.outer_iters;
     out->n_edited = e.n_edited;
@@ -604,7 +608,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     if (!aligned16(f) || !aligned16(fhat) || !aligned16(edits_out) || !aligned16(o.warm_start) ||
         !aligned16(o.g_out) || !aligned16(o.workspace))
         return done(MSZ_EINVAL);
-    if ((o.flags & ~(MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C)) != 0 || o.tile_override < 0 ||
+    if ((o.flags & ~kFixFlags) != 0 || o.tile_override < 0 ||
         o.tile_override > tile_variant_count(d.ndim))
         return done(MSZ_EINVAL);
     if (int rc = check_xi(xi)) return done(rc);
@@ -618,6 +622,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     F.gr = gr;
     F.variant = o.tile_override;
     F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
+    F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
     F.xi = xi;
     F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
     F.f = f;
@@ -631,7 +636,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     int64_t launches[MSZ_N_PHASES] = {};
     std::vector<EngStats> st;
     if (int rc = run_engine(hf, st, timing, ms, launches, step_bound(F.cap), s)) return done(rc);
-    copy_stats(st[0], stats);
+    copy_stats(st[0], F.count_init != 0, stats);
     for (int k = 0; k < MSZ_N_PHASES; ++k) {
         stats->phase_ms[k] = static_cast<float>(ms[k]);
         stats->phase_launches[k] = static_cast<int32_t>(launches[k]);
@@ -662,7 +667,7 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
     if (!jobs || n_jobs <= 0 || n_jobs > kEngMaxFields) return MSZ_EINVAL;
     msz_options o{};
     if (opt) o = *opt;
-    if (o.warm_start || o.g_out || (o.flags & ~(MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C)) || o.tile_override || !aligned16(o.workspace))
+    if (o.warm_start || o.g_out || (o.flags & ~kFixFlags) || o.tile_override || !aligned16(o.workspace))
         return MSZ_EINVAL;
     for (int j = 0; j < n_jobs; ++j) {
         Grid gr;
@@ -693,6 +698,7 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
         make_grid(J.d, F.gr);
         F.variant = J.tile;
         F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
+        F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
         F.xi = J.xi;
         F.cap = cap;
         F.f = J.f;
@@ -708,7 +714,7 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
     int first = rc;
     for (int j = 0; j < n_jobs; ++j) {
         msz_stats* out = jobs[j].stats;
-        if (rc == MSZ_OK) copy_stats(st[j], out);
+        if (rc == MSZ_OK) copy_stats(st[j], (o.flags & MSZ_FLAG_COUNT_INIT) != 0, out);
         else out->status = rc;
         if (first == MSZ_OK && out->status != MSZ_OK) first = out->status;
     }

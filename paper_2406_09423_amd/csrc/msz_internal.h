@@ -162,7 +162,8 @@ constexpr int kTypeMerged = 4;
 struct EngField {
     Grid gr;
     int variant;
-    int merged;  // 1: merged C rounds
+    int merged;      // 1: merged C rounds
+    int count_init;  // 1: label the start field once and count its mislabelled vertices
     float xi;
     long long cap;
     const float *f, *fhat, *warm;
@@ -182,11 +183,12 @@ struct EngField {
 };
 
 struct EngState {
-    int op, type, items, pad;
+    int op, type, items;
+    int init;  // 1 while the start field's labels are computed and counted (MSZ_FLAG_COUNT_INIT)
 };
 
 struct EngStats {
-    long long rounds[4], rounds_r, outer_iters, n_edited, false_init[4], n_inexact, rounds_total;
+    long long rounds[4], rounds_r, outer_iters, n_edited, false_init[4], n_inexact, rounds_total, mislabel_init;
     int cases[4];  // current number of cases of each type (kept up to date by the refresh steps)
     int status, pad;
 };

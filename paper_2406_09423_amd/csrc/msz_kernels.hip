@@ -1830,6 +1830,10 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             for (int t = 0; t < 4; ++t) S->false_init[t] = c[kCntCase + t];
             S->outer_iters = 1;
             st.type = 0;
+            if (F.count_init) {  // labels of the start field, then their count (no edits)
+                st.init = 1;
+                return go(kOpRTile);
+            }
             return c_decide();
         case kOpRefreshC:
         case kOpFullC:
@@ -1849,9 +1853,16 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             return go(kOpRJump);
         case kOpRJump:
             if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
-            st.type = S->rounds_total >= F.cap ? 1 : 0;  // at the cap: detect without editing
+            // at the cap, and for the start field's count: detect without editing
+            st.type = (st.init || S->rounds_total >= F.cap) ? 1 : 0;
             return go(kOpRDetect);
         case kOpRDetect:
+            if (st.init) {  // the start field's count; the correction starts now
+                S->mislabel_init = c[kCntWrong];
+                st.init = 0;
+                st.type = 0;
+                return c_decide();
+            }
             if (c[kCntWrong] == 0) return finish(MSZ_OK);
             if (st.type != 0) return finish(MSZ_ENOCONV);
             if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);

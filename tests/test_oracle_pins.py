@@ -296,6 +296,7 @@ def test_literal_loop_bit_exact_small_grids():
     rng = np.random.default_rng(8)
     prng = random.Random(8)
     total_rounds = 0
+    mislabelled = 0
     cases = 0
     for shape in [(3, 3), (4, 4), (3, 5), (5, 4), (2, 2, 2), (2, 3, 3), (3, 3, 3)]:
         for levels in (0, 5):
@@ -307,11 +308,18 @@ def test_literal_loop_bit_exact_small_grids():
                 assert (g.view(np.uint32) == lg.view(np.uint32)).all()
                 assert st["rounds"] == lst["rounds"] and st["rounds_r"] == lst["rounds_r"]
                 assert st["outer_iters"] == lst["outer_iters"]
+                # Appendix B's N_f of the start field: brute-force traced labels of fhat against f's
+                mesh = lit.Mesh(shape)
+                Mh, mh = lit.labels(mesh, fh.ravel())
+                Mf, mf = lit.labels(mesh, f.ravel())
+                assert st["mislabel_init"] == sum(a != b or c != e for a, b, c, e in zip(Mh, Mf, mh, mf))
                 if rc == oracle.OK:
                     _check_invariants(f, fh, xi, rc, d, g, st)
                 total_rounds += sum(st["rounds"]) + st["rounds_r"]
+                mislabelled += st["mislabel_init"]
                 cases += 1
     assert total_rounds > cases  # the cases really exercise the loop
+    assert mislabelled > cases
 
 
 def test_merged_c_rounds_bit_exact_with_literal():
@@ -386,11 +394,15 @@ def test_identity_and_order_preserving_inputs():
     f = rng.uniform(0, 1, size=(20, 30)).astype(np.float32)
     rc, d, g, st = oracle.fix(f, f, np.float32(0.01))
     assert rc == 0 and st["n_edited"] == 0 and not d.any()
-    assert sum(st["rounds"]) + st["rounds_r"] == 0
+    assert sum(st["rounds"]) + st["rounds_r"] == 0 and st["mislabel_init"] == 0
     # same order as f (exact shift by a power of two fraction): nothing to fix
     fi = rng.permutation(600).astype(np.float32).reshape(20, 30)
     rc, d, g, st = oracle.fix(fi, fi + np.float32(0.25), np.float32(0.5))
-    assert rc == 0 and st["n_edited"] == 0 and sum(st["false_init"]) == 0
+    assert rc == 0 and st["n_edited"] == 0 and sum(st["false_init"]) == 0 and st["mislabel_init"] == 0
+    # reversed order: every vertex's labels are wrong except where both agree by chance (none here:
+    # the max of f is the min of -f)
+    rc, d, g, st = oracle.fix(fi, -fi, np.float32(1200.0))
+    assert st["mislabel_init"] == fi.size
 
 
 def test_warm_start_resume():
