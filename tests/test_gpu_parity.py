@@ -238,7 +238,7 @@ def test_error_paths(msz):
     fd, fhd = dev(f), dev(fh)
     e = torch.empty_like(fd)
     opt = msz.Options()
-    opt.flags = 4
+    opt.flags = 1 << 20
     st = msz.Stats()
     rc = msz.lib().msz_fix(fd.data_ptr(), fhd.data_ptr(), msz.dims_of(f.shape), float(xi), e.data_ptr(),
                            ctypes.byref(opt), ctypes.byref(st), msz._stream())
