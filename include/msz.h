@@ -32,7 +32,8 @@
  *    (about 9 MB: field table, step states, round counters, statistics, the
  *    cached graph) and 512 bytes of pinned, device-mapped host memory (the
  *    done word and the final statistics of one-field runs) per host thread
- *    and device for the life of the process.
+ *    and device for the life of the process.  msz_fix_noalloc allocates
+ *    nothing: it works in a static device array instead (see there).
  *  - Errors: the return code is the only error channel; no global state
  *    besides the control block above.  msz_strerror() names a code.  Inputs
  *    must be finite with magnitude at most 2^100 (so that no edit can
@@ -60,7 +61,8 @@ enum {
     MSZ_ESTALL = -4,     /* a round had targets but every target sat at its floor L */
     MSZ_ENOCONV = -5,    /* max_rounds productive rounds were not enough */
     MSZ_EDEVICE = -6,    /* a HIP runtime call failed */
-    MSZ_ENOMEM = -7      /* the library could not allocate scratch memory */
+    MSZ_ENOMEM = -7,     /* the library could not allocate scratch memory */
+    MSZ_ETOOBIG = -8     /* msz_fix_noalloc: the field's scratch exceeds MSZ_NOALLOC_SCRATCH_BYTES */
 };
 
 /* Steps timed under MSZ_FLAG_TIMING (indices of msz_stats.phase_ms).  The
@@ -169,6 +171,33 @@ typedef struct {
  */
 int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edits_out,
             const msz_options* opt, msz_stats* stats, void* stream);
+
+/*
+ * msz_fix_noalloc -- msz_fix for callers that cannot allocate memory: code
+ * running while a stream is being captured into a graph elsewhere, tight
+ * serving loops, harnesses that forbid allocation.  It calls no hipMalloc,
+ * hipFree, hipHostMalloc or graph instantiation: its workspace and control
+ * block live in one static device array of MSZ_NOALLOC_SCRATCH_BYTES bytes,
+ * which every device the library runs on holds from module load until the
+ * process ends, and it launches the step kernels directly.
+ *
+ * Arguments and results are those of msz_fix, and so is the result: g,
+ * edits_out and every statistic are bit-identical to msz_fix's.  Differences:
+ *  - opt->workspace must be NULL and opt->workspace_bytes 0, and
+ *    MSZ_FLAG_TIMING is not accepted (MSZ_EINVAL);
+ *  - a field whose workspace plus the control block exceeds the array
+ *    returns MSZ_ETOOBIG before any device work.  The limit admits, e.g., a
+ *    128^3 field or a 1700 x 1700 one (the workspace takes about 35 bytes
+ *    per vertex in 3D, 31 in 2D: msz_workspace_bytes);
+ *  - every call on a device shares that device's array, and a call leaves
+ *    its contents behind (each call clears what it needs cleared).  Calls
+ *    that overlap on one device, from several host threads or streams,
+ *    race on the array and give undefined results: serialise them.
+ * The call synchronises on the stream before returning, as msz_fix does.
+ */
+#define MSZ_NOALLOC_SCRATCH_BYTES (96u << 20)
+int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, float* edits_out,
+                    const msz_options* opt, msz_stats* stats, void* stream);
 
 /* Profiling aid: the step schedule of the calling host thread's last msz_fix
  * that ran with MSZ_FLAG_TIMING.  Every step of the device schedule runs one

@@ -18,7 +18,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmsz.so")
 
-OK, EINVAL, ENONFINITE, EBOUND, ESTALL, ENOCONV, EDEVICE, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENONFINITE, EBOUND, ESTALL, ENOCONV, EDEVICE, ENOMEM, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8
+NOALLOC_SCRATCH_BYTES = 96 << 20  # the static device scratch of msz_fix_noalloc
 CASE_NAMES = ("fp_max", "fp_min", "fn_max", "fn_min")
 PHASES = ("validate", "dirs", "dirs_detect", "refresh", "apply", "label_tile", "label_jump",
           "label_final", "detect_r", "delta", "net")
@@ -100,6 +101,7 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         P, F, I32 = ctypes.c_void_p, ctypes.c_float, ctypes.c_int32
         L.msz_fix.argtypes = [P, P, Dims, F, P, ctypes.POINTER(Options), ctypes.POINTER(Stats), P]
+        L.msz_fix_noalloc.argtypes = [P, P, Dims, F, P, ctypes.POINTER(Options), ctypes.POINTER(Stats), P]
         L.msz_labels.argtypes = [P, Dims, P, P, P]
         L.msz_count_false.argtypes = [P, P, Dims, ctypes.POINTER(FalseCounts), P]
         L.msz_fix_batch.argtypes = [ctypes.POINTER(Job), I32, ctypes.POINTER(Options), P]
@@ -129,7 +131,7 @@ def lib() -> ctypes.CDLL:
         L.msz_encode_edits.argtypes = [P, ctypes.c_int64, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t),
                                        ctypes.POINTER(EditStats), P]
         L.msz_decode_edits.argtypes = [P, ctypes.c_size_t, P, ctypes.c_int64, P]
-        for fn in (L.msz_fix, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants,
+        for fn in (L.msz_fix, L.msz_fix_noalloc, L.msz_labels, L.msz_count_false, L.msz_fix_batch, L.msz_tile_variants,
                    L.msz_net_features, L.msz_net_forward, L.msz_net_gradients, L.msz_net_adam,
                    L.msz_fix_learned, L.msz_net_halvings, L.msz_encode_edits, L.msz_decode_edits):
             fn.restype = ctypes.c_int
@@ -214,6 +216,32 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: boo
     if timing:
         out["timing"] = st.timing()
     return int(rc), edits, g, out
+
+
+def fix_noalloc(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, edits_out=None, g_out=None,
+                tile: int = 0, merged: bool = False, count_init: bool = False, stream=None):
+    """msz_fix_noalloc: the correction loop with all scratch in the library's
+    static device array (no allocation inside the call).  ``edits_out`` and
+    ``g_out`` (optional) are caller-owned outputs; returns ``(status, delta,
+    g, stats)`` like :func:`fix`."""
+    import torch
+    _check_field(f, "f")
+    _check_field(fhat, "fhat")
+    if f.shape != fhat.shape:
+        raise ValueError("f and fhat differ in shape")
+    edits = edits_out if edits_out is not None else torch.empty_like(f)
+    opt = Options()
+    opt.max_rounds = int(max_rounds)
+    if warm_start is not None:
+        _check_field(warm_start, "warm_start")
+        opt.warm_start = warm_start.data_ptr()
+    opt.g_out = g_out.data_ptr() if g_out is not None else None
+    opt.tile_override = int(tile)
+    opt.flags = _flags(False, merged, count_init)
+    st = Stats()
+    rc = lib().msz_fix_noalloc(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), edits.data_ptr(),
+                               ctypes.byref(opt), ctypes.byref(st), _stream(stream))
+    return int(rc), edits, g_out, st.as_dict()
 
 
 def last_schedule() -> list:

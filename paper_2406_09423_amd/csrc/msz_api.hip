@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/msz.h"
@@ -439,7 +440,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         EngStats* tp = E.stats;
         unsigned* cp = E.counters;
         int* lp = E.ctl;
-        void* a[] = {&F, &fp, &sp, &tp, &cp, &lp};
+        int* no_word = nullptr;  // the done word is in pinned host memory, raised above
+        void* a[] = {&F, &fp, &sp, &tp, &cp, &lp, &no_word};
         const int nw = (F.gr.n + 15) >> 4;
         MSZ_HIP(hipLaunchKernel(eng_setup1_kernel(), dim3(std::max(1, std::min(2048, (nw + 255) / 256))), dim3(256),
                                 a, 0, s));
@@ -561,6 +563,104 @@ int64_t step_bound(int64_t cap) {
     return std::min<int64_t>(b, int64_t(1) << 26);
 }
 
+// ------------------------------------------------ no-allocation variant ---
+// msz_fix_noalloc keeps everything beyond its inputs and outputs in `scratch`:
+// a one-field control block (field entry, the two step states, three
+// statistics records, the active word, three round-counter sets, and the
+// done word with the final statistics) and, after it, the field's workspace.
+// In host code `scratch` names a host-side stand-in; its device address comes
+// from hipGetSymbolAddress, once per device.
+
+struct NoAllocCtl {
+    size_t fields, states, stats, ctl, cnt3, words, work;  // byte offsets; work = start of the workspace
+};
+
+NoAllocCtl noalloc_ctl() {
+    NoAllocCtl c{};
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        const size_t r = o;
+        o += align256(b);
+        return r;
+    };
+    c.fields = take(sizeof(EngField));
+    c.states = take(sizeof(EngState) * 2);
+    c.stats = take(sizeof(EngStats) * 3);
+    c.ctl = take(sizeof(int) * 4);
+    c.cnt3 = take(sizeof(unsigned) * 3 * kCntBlockWords);
+    c.words = take(512);
+    c.work = o;
+    return c;
+}
+
+}  // namespace
+}  // namespace msz
+
+static __device__ __align__(256) char scratch[MSZ_NOALLOC_SCRATCH_BYTES];
+
+namespace msz {
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device; nullptr if the lookup failed.
+char* scratch_base(int dev) {
+    static std::mutex mu;
+    static char* base[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!base[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        base[dev] = static_cast<char*>(p);
+    }
+    return base[dev];
+}
+
+// The one-field schedule on the control block at `base`: the setup kernel,
+// then the step kernel launched kGraphSteps times between checks of the done
+// word (copied back into host stack memory), until the device lowers it.
+int run_noalloc(EngField F, char* base, int64_t max_steps, EngStats& out, hipStream_t s) {
+    int dev = 0;
+    MSZ_HIP(hipGetDevice(&dev));
+    const NoAllocCtl c = noalloc_ctl();
+    EngField* fp = reinterpret_cast<EngField*>(base + c.fields);
+    EngState* sp = reinterpret_cast<EngState*>(base + c.states);
+    EngStats* tp = reinterpret_cast<EngStats*>(base + c.stats);
+    int* lp = reinterpret_cast<int*>(base + c.ctl);
+    unsigned* cp = reinterpret_cast<unsigned*>(base + c.cnt3);
+    int* wp = reinterpret_cast<int*>(base + c.words);
+    const int grid = step_grid(dev, F.gr.ndim, true);
+    if (grid < 1) return MSZ_EDEVICE;
+    F.cnt = cp;
+    {
+        void* a[] = {&F, &fp, &sp, &tp, &cp, &lp, &wp};
+        const int nw = (F.gr.n + 15) >> 4;
+        MSZ_HIP(hipLaunchKernel(eng_setup1_kernel(), dim3(std::max(1, std::min(2048, (nw + 255) / 256))), dim3(256),
+                                a, 0, s));
+    }
+    const void* fn = eng_step1_kernel(F.gr.ndim);
+    int* no_log = nullptr;
+    unsigned long long* no_stamps = nullptr;
+    int words[128];
+    static_assert(sizeof(words) == 512, "the done word block");
+    for (int64_t steps = 0;;) {
+        for (int k = 0; k < kGraphSteps; ++k) {
+            int kk = k;
+            void* a[] = {&fp, &sp, &sp, &tp, &cp, &lp, &wp, &no_log, &kk, &no_stamps};
+            MSZ_HIP(hipLaunchKernel(fn, dim3(grid), dim3(256), a, 0, s));
+        }
+        MSZ_HIP(hipMemcpyAsync(words, wp, sizeof(words), hipMemcpyDeviceToHost, s));
+        MSZ_HIP(hipStreamSynchronize(s));
+        steps += kGraphSteps;
+        if (words[0] == 0) break;
+        if (steps > max_steps) return MSZ_EDEVICE;
+    }
+    std::memcpy(&out, words + kHostStatsWord, sizeof(EngStats));
+    return MSZ_OK;
+}
+
 }  // namespace
 }  // namespace msz
 
@@ -578,6 +678,7 @@ const char* msz_strerror(int code) {
         case MSZ_ENOCONV: return "round cap reached";
         case MSZ_EDEVICE: return "HIP runtime error";
         case MSZ_ENOMEM: return "out of device memory";
+        case MSZ_ETOOBIG: return "field too large for the static scratch of msz_fix_noalloc";
         default: return "unknown error";
     }
 }
@@ -641,6 +742,50 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
         stats->phase_ms[k] = static_cast<float>(ms[k]);
         stats->phase_launches[k] = static_cast<int32_t>(launches[k]);
     }
+    return stats->status;
+}
+
+int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, float* edits_out,
+                    const msz_options* opt, msz_stats* stats, void* stream) {
+    if (!stats) return MSZ_EINVAL;
+    std::memset(stats, 0, sizeof(*stats));
+    auto done = [&](int rc) {
+        stats->status = rc;
+        return rc;
+    };
+    Grid gr;
+    if (!make_grid(d, gr) || !f || !fhat || !edits_out) return done(MSZ_EINVAL);
+    msz_options o{};
+    if (opt) o = *opt;
+    if (!aligned16(f) || !aligned16(fhat) || !aligned16(edits_out) || !aligned16(o.warm_start) ||
+        !aligned16(o.g_out))
+        return done(MSZ_EINVAL);
+    if (o.workspace || o.workspace_bytes || (o.flags & ~(MSZ_FLAG_MERGED_C | MSZ_FLAG_COUNT_INIT)) != 0 ||
+        o.tile_override < 0 || o.tile_override > tile_variant_count(d.ndim))
+        return done(MSZ_EINVAL);
+    if (int rc = check_xi(xi)) return done(rc);
+    const NoAllocCtl c = noalloc_ctl();
+    if (c.work + layout_for(gr).total > MSZ_NOALLOC_SCRATCH_BYTES) return done(MSZ_ETOOBIG);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return done(MSZ_EDEVICE);
+    char* base = scratch_base(dev);
+    if (!base) return done(MSZ_EDEVICE);
+    EngField F{};
+    F.gr = gr;
+    F.variant = o.tile_override;
+    F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
+    F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
+    F.xi = xi;
+    F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
+    F.f = f;
+    F.fhat = fhat;
+    F.warm = o.warm_start;
+    F.edits = edits_out;
+    F.g_out = o.g_out;
+    bind_field(F, base + c.work);
+    EngStats st{};
+    if (int rc = run_noalloc(F, base, step_bound(F.cap), st, static_cast<hipStream_t>(stream))) return done(rc);
+    copy_stats(st, F.count_init != 0, stats);
     return stats->status;
 }
 

@@ -1953,7 +1953,9 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
 // (a step reads k - 1's and block 0 writes k's); counter sets by k % 3 (a step
 // reads set k - 1, adds into set k and clears set k + 1, which step k - 1
 // read and step k + 1 fills).  stats[2] receives the statistics once the
-// field is done, and hflag (pinned host memory, if set) is cleared then.  A
+// field is done; then the final statistics go to the done word block hflag
+// (pinned host memory, or device memory for the no-allocation entry point;
+// skipped when NULL) and its first word is cleared.  A
 // graph holds kEngTimeSlots (a multiple of 6) steps, so the parities continue
 // across launches.
 template <int NDIM>
@@ -2086,17 +2088,19 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
 
 // Start of a one-field run: the field table entry (passed by value), the
 // states of "step -1" (done) and step 0 (start), the three counter sets, the
-// statistics, the active word, and the field's marks, case bytes, dirty
-// flags and exit targets -- everything the host would otherwise upload or
-// clear one call at a time.
+// statistics, the active word, the done word (when it lives in device memory,
+// else NULL: the host raises its own) and the field's marks, case bytes,
+// dirty flags and exit targets -- everything the host would otherwise upload
+// or clear one call at a time.
 __global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* fields, EngState* states,
-                                                    EngStats* stats, unsigned* cnt3, int* ctl) {
+                                                    EngStats* stats, unsigned* cnt3, int* ctl, int* done_word) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     if (tid == 0) {
         fields[0] = F;
         states[0] = EngState{kOpDone, 0, 0, 0};
         states[1] = EngState{kOpStart, 0, 1, 0};
         ctl[0] = 1;
+        if (done_word) done_word[0] = 1;
     }
     for (int w = tid; w < 3 * kCntBlockWords; w += nthr) cnt3[w] = 0u;
     constexpr int SW = 3 * static_cast<int>(sizeof(EngStats) / 4);
