@@ -1,23 +1,29 @@
 """Benchmark of the MSz correction loop on one MI355X.
 
-A step corrects the 3600x2400 k^-3 Gaussian-random-field pair (xi = 1e-4 and
-1e-3 of the value range) to zero segmentation error with the plain loop; the
-fields are resident in HBM before the clock starts.  The same run also times
-the two other forms on their own workloads, and the encoding of the edits
-(reported under "forms"):
-  edits    the plain loop's edits on the pair, losslessly encoded on the GPU
-           (sorted index gaps and values, Huffman coded) and decoded back
-  merged   the same pair with merged C rounds (all four case types fixed in
-           one round, the parallel C-loop of Sec. 6.1)
-  batched  96 uneven k^-3 fields (64 2D with sides 64..2048, 32 3D cubes
-           32^3..192^3, xi in {1e-4, 1e-3, 1e-2} x range) in one launch
-  learned  a 512^3 k^-11/3 field at xi = 1e-3 x range: the warm-started loop
-           (features + network + loop) against the plain loop on that field.
-Every result is checked for zero segmentation error outside the clock.
+A step corrects the 96-field batch to zero segmentation error in one
+device-scheduled run (msz_fix_batch): 64 2D k^-3 Gaussian random fields with
+sides drawn from 64..2048 and 32 3D cubes of 32^3..192^3, each with its own
+bound xi in {1e-4, 1e-3, 1e-2} x range, about 1.35e8 vertices in all, the
+tile of each field from the autotuner's table.  The fields are resident in
+HBM before the clock starts.  The roofline comes from one instrumented run of
+the same step: every step-kernel launch reports its duration (GPU clock
+stamps) and the algorithmic bytes of the units its blocks visited.
+
+The same run times the other forms and configurations (reported under
+"forms"), each result checked for zero segmentation error outside the clock:
+  plain       the 3600x2400 k^-3 pair (xi = 1e-4 and 1e-3 x range), per-step
+              operation times and bytes, and the oracle on one pinned core
+  merged      the same pair with merged C rounds (Sec. 6.1 parallel C-loop)
+  preemptive  the same pair in the preemptive edit mode (Sec. 6.1)
+  bumps128    the 128x128 bumps field (median of 100 calls)
+  turb256     the 256^3 k^-11/3 field with 64 blobs
+  learned     the 512^3 k^-11/3 field: the warm-started loop against the plain one
+  edits       the plain loop's edits on the pair, encoded and decoded on the GPU
+  batch_modes the batch with merged C rounds and preemptive (opt-in)
 Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,edits,merged,batched,learned]
-                  [--no-cpu-baseline] [--batch-cpu-baseline] [--calib-copy] [--schedule-out FILE]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,merged,...]
+                  [--no-cpu-baseline] [--calib-copy]
 """
 from __future__ import annotations
 
@@ -25,6 +31,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -35,22 +42,9 @@ if ROOT not in sys.path:
 METRIC = "Gvertices/s corrected to zero MS-label error @xi; plain vs batched vs learned"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2406_09423_amd/csrc/msz_kernels.hip", "paper_2406_09423_amd/csrc/msz_internal.h")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_ocean2d.json")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "traffic_batch96.json")
 CALIB_BYTES = 1 << 30   # bytes read (and written) by the calibration copy
-
-# Algorithmic (compulsory) HBM bytes per vertex of each kernel kind, per launch.
-BYTES_PER_VERTEX = {
-    "dirs_detect": 4 + 1 + 1 + 1 + 2,  # read g, dirs_f; write dirs_g, case bytes; clear dirty flags and marks
-    "dirs": 4 + 1,              # read the field, write dirs
-    "refresh": 1,               # read the dirty flags (the refreshed vertices are sparse)
-    "apply": 1,                 # read the case bytes or marks (edited vertices are sparse)
-    "label_tile": 1 + 8,        # read dirs, write both pointer arrays
-    "label_jump": 0,            # touches only the tiles' face layers
-    "detect_r": 2 + 8 + 8 + 8,  # dirs x2, pointers x2, pointer-of-pointer x2, labels of f x2
-    "delta": 4 + 4 + 4 + 4,     # read g, fhat; write delta, g
-    "validate": 4 + 4 + 4 + 4,  # read f, fhat; write L, g
-    "label_final": 8 + 8 + 8,   # read q x2, gather q[q] x2, write labels x2
-}
+DEFAULT_FORMS = "plain,merged,preemptive,bumps128,turb256,learned,edits"
 
 
 def log(*a):
@@ -78,6 +72,24 @@ def stored_traffic(kernel: str):
     return int(k["bytes_per_launch"]) if k else None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cpus() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
 def checked(msz, f, g, xi):
     cnt = msz.count_false(f, g)
     if any(v != 0 for v in cnt.values()):
@@ -87,115 +99,51 @@ def checked(msz, f, g, xi):
         raise RuntimeError(f"bound broken: {err} > {xi}")
 
 
-def bench_plain(msz, torch, dev, args):
-    import synth
-    log("bench: generating the 3600x2400 pair")
-    pairs = synth.ocean2d()
-    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)) for f, fh, xi in pairs]
-    n_per = fields[0][0].numel()
-    ws = torch.empty(msz.workspace_bytes(fields[0][0].shape), dtype=torch.uint8, device=dev)
-    outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
+def by_kernel(launches):
+    """Launch records summed per step kernel."""
+    out = {}
+    for r in launches:
+        k = out.setdefault(r["kernel"], {"launches": 0, "us": 0.0, "bytes": 0})
+        k["launches"] += 1
+        k["us"] += r["us"]
+        k["bytes"] += r["bytes"]
+    return out
 
-    schedules = []  # with --schedule-out: every call timed, its step schedule kept
 
-    def step(timing=False):
-        res = []
-        for (f, fh, xi), (e, g) in zip(fields, outs):
-            rc, _, _, st = msz.fix(f, fh, xi, workspace=ws, edits_out=e, g_out=g,
-                                   timing=timing or args.schedule_out is not None)
-            if rc != msz.OK:
-                raise RuntimeError(f"msz_fix failed: {msz.strerror(rc)}")
-            if args.schedule_out is not None:
-                schedules.append({"xi": xi, "phases": msz.last_schedule()})
-            res.append(st)
-        return res
-
-    log(f"bench: warmup {args.warmup}")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sts = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    verts = n_per * len(fields)
-    log(f"bench: plain {ms_per_step:.3f} ms/step, {verts / ms_per_step / 1e6:.3f} Gvertices/s")
-    for (f, fh, xi), (e, g) in zip(fields, outs):
-        checked(msz, f, g, xi)
-    # the same steps again with every device step timed (the step kernel stamps
-    # its first block's start and its last block's end with the GPU's
-    # constant-rate clock): per-kernel durations for the roofline
-    log(f"bench: {args.steps} instrumented steps")
-    phase_ms, phase_n = {}, {}
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        for st in step(timing=True):
-            for name, v in st["timing"].items():
-                phase_ms[name] = phase_ms.get(name, 0.0) + v["ms"]
-                phase_n[name] = phase_n.get(name, 0) + v["launches"]
-    torch.cuda.synchronize()
-    ms_instrumented = (time.perf_counter() - t2) * 1e3 / args.steps
-
-    dominant = max((k for k in phase_ms if phase_n.get(k)), key=lambda k: phase_ms[k])
-    avg_ms = phase_ms[dominant] / phase_n[dominant]
-    bpl = BYTES_PER_VERTEX.get(dominant, 0) * n_per
-    achieved = bpl / (avg_ms * 1e-3) / 1e9 if bpl else None
-    traffic = stored_traffic(dominant)
-    roofline = {
-        "kernel": dominant,
-        "bound": "hbm",
-        "achieved": round(achieved, 1) if achieved else None,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": traffic,
-        "avg_launch_us": round(avg_ms * 1e3, 2),
-        "bytes_per_launch": bpl,
-        "launches_per_step": phase_n[dominant] / args.steps,
-        "timing": "GPU clock stamps of every step kernel in an instrumented pass of the same steps "
-                  f"({ms_instrumented:.3f} ms/step with the stamps)",
-    }
-    phases = {}
-    for k in phase_ms:
-        if not phase_n[k]:
+def by_phase(launches, calls: int = 1):
+    """Launch records of one-field runs summed per operation, per call."""
+    acc = {}
+    for r in launches:
+        if r["phase"] is None:
             continue
-        us = phase_ms[k] / phase_n[k] * 1e3
-        b = BYTES_PER_VERTEX.get(k)
-        phases[k] = {"ms_per_step": round(phase_ms[k] / args.steps, 4),
-                     "launches_per_step": phase_n[k] / args.steps, "avg_us": round(us, 2),
-                     "algorithmic_GBps": round(b * n_per / (us * 1e-6) / 1e9, 1) if b else None}
-    rounds = [{"xi": xi, "rounds": st["rounds"], "rounds_r": st["rounds_r"], "outer_iters": st["outer_iters"],
-               "n_edited": st["n_edited"]} for (_, _, xi), st in zip(fields, sts)]
-    if args.schedule_out is not None:
-        with open(args.schedule_out, "w") as fh:
-            json.dump({"phase_names": list(msz.PHASES), "calls": schedules}, fh)
-    return pairs, verts, ms_per_step, roofline, phases, rounds, [e for e, _ in outs]
+        k = acc.setdefault(r["phase"], {"launches": 0, "us": 0.0, "bytes": 0})
+        k["launches"] += 1
+        k["us"] += r["us"]
+        k["bytes"] += r["bytes"]
+    out = {}
+    for name, k in acc.items():
+        gbs = k["bytes"] / (k["us"] * 1e-6) / 1e9 if k["us"] > 0 else None
+        out[name] = {"launches_per_call": k["launches"] / calls, "ms_per_call": round(k["us"] / calls / 1e3, 4),
+                     "avg_us": round(k["us"] / k["launches"], 2), "bytes_per_call": k["bytes"] // calls,
+                     "algorithmic_GBps": round(gbs, 1) if gbs else None,
+                     "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4) if gbs else None}
+    return out
 
 
-def batch_oracle_all_cores(host_fields):
-    """The serial C oracle over the whole batch, one field per task on a pool
-    of host threads (the oracle is a C library: ctypes releases the GIL)."""
-    import concurrent.futures
-
-    import oracle
-    oracle.build()
-    workers = max(1, min(16, os.cpu_count() or 1))
-    verts = sum(f.size for f, _, _ in host_fields)
-    # largest fields first, so the slowest one does not start last
-    order = sorted(host_fields, key=lambda t: -t[0].size)
+def timed(fn, steps: int, warmup: int, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
-        rcs = list(ex.map(lambda t: oracle.fix(*t)[0], order))
-    dt = time.perf_counter() - t0
-    assert all(rc == 0 for rc in rcs)
-    return {"value": round(verts / dt / 1e9, 6), "unit": "Gvertices/s", "cores": workers, "kind": "oracle",
-            "sample": "the whole 96-field batch, one field per task on a pool of host threads", "seconds": round(dt, 2)}
+    for _ in range(steps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, r
 
 
-def bench_batched(msz, torch, dev, steps, cpu_all_cores=False):
+# ------------------------------------------------------------ headline ---
+
+def bench_batch(msz, torch, dev, args):
     import synth
     from paper_2406_09423_amd import autotune
     log("bench: generating the 96-field batch")
@@ -207,62 +155,166 @@ def bench_batched(msz, torch, dev, steps, cpu_all_cores=False):
     outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
     ws = torch.empty(msz.batch_workspace_bytes(shapes), dtype=torch.uint8, device=dev)
 
-    def run(merged=False):
-        rc, res = msz.fix_batch(fields, workspace=ws, tiles=tiles, outs=outs, merged=merged)
+    def run(timing=False, **kw):
+        rc, res = msz.fix_batch(fields, workspace=ws, tiles=tiles, outs=outs, timing=timing, **kw)
         if rc != msz.OK:
             raise RuntimeError(f"msz_fix_batch failed: {msz.strerror(rc)}")
         return res
 
-    run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        res = run()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
+    log(f"bench: batch warmup {args.warmup}, timing {args.steps} steps")
+    ms, res = timed(run, args.steps, args.warmup, torch)
+    log(f"bench: batch {ms:.3f} ms/step, {verts / ms / 1e6:.3f} Gvertices/s")
     for (f, fh, xi), (_, _, g, _) in zip(fields, res):
         checked(msz, f, g, xi)
-    # the same fields one msz_fix call after another, for comparison
-    ws1 = torch.empty(max(msz.workspace_bytes(s) for s in shapes), dtype=torch.uint8, device=dev)
+    # one instrumented run of the same step: every step-kernel launch
+    run(timing=True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for (f, fh, xi), (e, g), tl in zip(fields, outs, tiles):
-        rc, _, _, _ = msz.fix(f, fh, xi, workspace=ws1, edits_out=e, g_out=g, tile=tl)
-        if rc != msz.OK:
-            raise RuntimeError(f"msz_fix failed: {msz.strerror(rc)}")
-    torch.cuda.synchronize()
-    ms_seq = (time.perf_counter() - t0) * 1e3
-    log(f"bench: batched {ms:.2f} ms ({verts / ms / 1e6:.3f} Gv/s), one by one {ms_seq:.2f} ms")
+    kern = by_kernel(msz.last_launches())
+    dominant = max(kern, key=lambda k: kern[k]["us"])
+    d = kern[dominant]
+    avg_us = d["us"] / d["launches"]
+    bpl = d["bytes"] / d["launches"]
+    achieved = bpl / (avg_us * 1e-6) / 1e9
+    sym = msz.KERNEL_SYMBOLS[msz.KERNELS.index(dominant)]
+    roofline = {
+        "kernel": sym,
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": stored_traffic(sym),
+        "avg_launch_us": round(avg_us, 2),
+        "bytes_per_launch": int(bpl),
+        "launches_per_step": d["launches"],
+        "timing": "GPU clock stamps (first block's start to last block's end) of every launch of the kernel in "
+                  "an instrumented run of the step; bytes: the algorithmic bytes of the units its blocks visited",
+    }
+    kernels = {msz.KERNEL_SYMBOLS[msz.KERNELS.index(k)]: {
+        "launches": v["launches"], "ms": round(v["us"] / 1e3, 3), "avg_us": round(v["us"] / v["launches"], 2),
+        "bytes": v["bytes"], "algorithmic_GBps": round(v["bytes"] / (v["us"] * 1e-6) / 1e9, 1) if v["us"] else None}
+        for k, v in kern.items()}
     rounds = [sum(st["rounds"]) + st["rounds_r"] for _, _, _, st in res]
-    # the same batch with merged C rounds (all four case types per round)
-    run(merged=True)
-    torch.cuda.synchronize()
+    info = {"kernels": kernels, "max_rounds": max(rounds), "total_rounds": sum(rounds),
+            "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}}
+    extra = {}
+    if "batch_modes" in args.forms:
+        for name, kw in (("merged", {"merged": True}), ("preemptive", {"preemptive": True})):
+            ms_m, res_m = timed(lambda: run(**kw), args.form_steps, 1, torch)
+            for (f, fh, xi), (_, _, g, _) in zip(fields, res_m):
+                checked(msz, f, g, xi)
+            extra[name] = {"ms": round(ms_m, 3), "value": round(verts / ms_m / 1e6, 4),
+                           "total_rounds": sum(sum(st["rounds"]) + st["rounds_r"] for _, _, _, st in res_m)}
+            log(f"bench: batch {name} {ms_m:.3f} ms")
+    del fields, outs, ws
+    return host_fields, verts, ms, roofline, info, extra
+
+
+def oracle_batch_all_cores(host_fields):
+    """The serial C oracle over the whole batch, one field per task on a pool
+    of host threads (ctypes releases the GIL), largest fields first."""
+    import concurrent.futures
+
+    import oracle
+    oracle.build()
+    workers = max(1, min(16, host_cpus()))
+    verts = sum(f.size for f, _, _ in host_fields)
+    order = sorted(host_fields, key=lambda t: -t[0].size)
+    log(f"bench: oracle over the batch on {workers} host threads")
     t0 = time.perf_counter()
-    for _ in range(steps):
-        res_m = run(merged=True)
-    torch.cuda.synchronize()
-    ms_m = (time.perf_counter() - t0) * 1e3 / steps
-    for (f, fh, xi), (_, _, g, _) in zip(fields, res_m):
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        rcs = list(ex.map(lambda t: oracle.fix(*t)[0], order))
+    dt = time.perf_counter() - t0
+    if not all(rc == 0 for rc in rcs):
+        raise RuntimeError("oracle failed on a batch field")
+    log(f"bench: oracle batch {dt:.1f} s")
+    return {"value": round(verts / dt / 1e9, 6), "unit": "Gvertices/s", "cores": workers, "kind": "oracle",
+            "sample": "the whole 96-field batch (the headline workload), the serial C oracle once per field, "
+                      f"fields spread over {workers} host threads, largest first",
+            "seconds": round(dt, 2), "host_cpus": host_cpus(), "os_cpu_count": os.cpu_count(),
+            "cpu_model": cpu_model()}
+
+
+# --------------------------------------------------------------- forms ---
+
+def single_form(msz, torch, dev, pairs, steps, label, **kw):
+    """The fields of `pairs` one msz_fix call after another per step: time per
+    step, then one instrumented step for per-operation times and bytes."""
+    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)) for f, fh, xi in pairs]
+    ws = torch.empty(max(msz.workspace_bytes(f.shape) for f, _, _ in fields), dtype=torch.uint8, device=dev)
+    outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
+
+    def step(timing=False):
+        sts, launches = [], []
+        for (f, fh, xi), (e, g) in zip(fields, outs):
+            rc, _, _, st = msz.fix(f, fh, xi, workspace=ws, edits_out=e, g_out=g, timing=timing, **kw)
+            if rc != msz.OK:
+                raise RuntimeError(f"msz_fix ({label}) failed: {msz.strerror(rc)}")
+            sts.append(st)
+            if timing:
+                launches += msz.last_launches()
+        return sts, launches
+
+    ms, (sts, _) = timed(step, steps, 1, torch)
+    for (f, fh, xi), (e, g) in zip(fields, outs):
         checked(msz, f, g, xi)
-    log(f"bench: batched with merged C rounds {ms_m:.2f} ms ({verts / ms_m / 1e6:.3f} Gv/s)")
-    cpu = None
-    if cpu_all_cores:
-        log("bench: oracle over the batch on all host cores")
-        cpu = batch_oracle_all_cores(host_fields)
-        log(f"bench: oracle batch {cpu['seconds']} s on {cpu['cores']} threads")
-    del host_fields
-    return {"workload": "96 uneven k^-3 fields: 64 2D (sides U{64..2048}), 32 3D (U{32..192}^3), "
-                        "xi in {1e-4,1e-3,1e-2} x range; one device-scheduled run",
-            "vertices": verts, "ms": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
-            "steps": steps, "sequential_ms": round(ms_seq, 3),
-            "speedup_vs_sequential": round(ms_seq / ms, 3), "max_rounds": max(rounds),
-            "merged_c_ms": round(ms_m, 3), "merged_c_value": round(verts / ms_m / 1e6, 4),
-            "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}, "cpu_all_cores": cpu}
+    _, launches = step(timing=True)
+    verts = sum(f.numel() for f, _, _ in fields)
+    log(f"bench: {label} {ms:.3f} ms/step ({verts / ms / 1e6:.3f} Gv/s)")
+    out = {"ms_per_step": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
+           "vertices_per_step": verts, "steps": steps, "phases": by_phase(launches),
+           "rounds": [{"xi": xi, "rounds": st["rounds"], "rounds_r": st["rounds_r"],
+                       "outer_iters": st["outer_iters"], "n_edited": st["n_edited"]}
+                      for (_, _, xi), st in zip(fields, sts)]}
+    return out, [e for e, _ in outs]
+
+
+def oracle_one_core(pairs):
+    """The serial C oracle on each field of `pairs`, this process pinned to one core."""
+    import oracle
+    oracle.build()
+    cpus = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {cpus[0]})
+    try:
+        t0 = time.perf_counter()
+        for f, fh, xi in pairs:
+            rc, _, _, _ = oracle.fix(f, fh, xi)
+            if rc != 0:
+                raise RuntimeError("oracle failed")
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, set(cpus))
+    verts = sum(f.size for f, _, _ in pairs)
+    return {"value": round(verts / dt / 1e9, 6), "unit": "Gvertices/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 2), "pinned_cpu": cpus[0], "cpu_model": cpu_model(), "host_cpus": len(cpus)}
+
+
+def bench_bumps128(msz, torch, dev, reps=100):
+    import synth
+    f, fh, xi = synth.bumps128()[0]
+    fd, fhd = torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev)
+    ws = torch.empty(msz.workspace_bytes(fd.shape), dtype=torch.uint8, device=dev)
+    e, g = torch.empty_like(fd), torch.empty_like(fd)
+    for _ in range(3):
+        msz.fix(fd, fhd, float(xi), workspace=ws, edits_out=e, g_out=g)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, _, _, st = msz.fix(fd, fhd, float(xi), workspace=ws, edits_out=e, g_out=g)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        if rc != msz.OK:
+            raise RuntimeError(msz.strerror(rc))
+    checked(msz, fd, g, float(xi))
+    med = statistics.median(times)
+    log(f"bench: bumps128 median {med:.3f} ms")
+    return {"workload": "128x128 sum of 32 Gaussian bumps + noise, xi = 1e-3 x range", "median_ms": round(med, 4),
+            "min_ms": round(min(times), 4), "calls": reps, "value": round(fd.numel() / med / 1e6, 5),
+            "unit": "Gvertices/s", "rounds": sum(st["rounds"]) + st["rounds_r"]}
 
 
 def bench_learned(msz, torch, dev, steps):
-    import numpy as np
-
     import synth
     from paper_2406_09423_amd import train_net
     if not os.path.exists(train_net.WEIGHTS_PATH):
@@ -276,95 +328,35 @@ def bench_learned(msz, torch, dev, steps):
     xi = float(xi)
     ws = torch.empty(msz.learned_workspace_bytes(fd.shape), dtype=torch.uint8, device=dev)
     e, g = torch.empty_like(fd), torch.empty_like(fd)
-    out = {"workload": "512^3 k^-11/3 Gaussian random field, xi = 1e-3 x range", "vertices": fd.numel(),
+    n = fd.numel()
+    out = {"workload": "512^3 k^-11/3 Gaussian random field, xi = 1e-3 x range", "vertices": n,
            "p_min": p_min, "steps": steps}
     for name, fn in (("plain", lambda t: msz.fix(fd, fhd, xi, workspace=ws, edits_out=e, g_out=g, timing=t)),
                      ("learned", lambda t: msz.fix_learned(fd, fhd, xi, params, p_min=p_min, workspace=ws,
                                                            edits_out=e, g_out=g, timing=t))):
-        fn(False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            rc, _, _, st = fn(False)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ms, (rc, _, _, st) = timed(lambda: fn(False), steps, 1, torch)
         if rc != msz.OK:
             raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
         checked(msz, fd, g, xi)
         _, _, _, stt = fn(True)
-        n = fd.numel()
-        phases = {}
-        for k, v in stt["timing"].items():  # one timed call: per-operation step times on 512^3
-            if not v["launches"] or k == "net":
-                continue
-            us = v["ms"] / v["launches"] * 1e3
-            b = BYTES_PER_VERTEX.get(k)
-            phases[k] = {"launches": v["launches"], "avg_us": round(us, 2),
-                         "algorithmic_GBps": round(b * n / (us * 1e-6) / 1e9, 1) if b else None,
-                         "frac_of_hbm_peak": round(b * n / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if b else None}
         out[name] = {"ms": round(ms, 3), "value": round(n / ms / 1e6, 4),
                      "rounds": sum(st["rounds"]) + st["rounds_r"], "outer_iters": st["outer_iters"],
                      "n_edited": st["n_edited"], "net_ms": round(stt["timing"]["net"]["ms"], 3),
-                     "phases": phases}
+                     "phases": by_phase(msz.last_launches())}
         log(f"bench: {name} 512^3 {ms:.2f} ms, rounds {out[name]['rounds']}")
     out["speedup"] = round(out["plain"]["ms"] / out["learned"]["ms"], 4)
     out["unit"] = "Gvertices/s"
-    # the same two with merged C rounds (all four case types per round)
     for name, fn in (("plain_merged", lambda: msz.fix(fd, fhd, xi, workspace=ws, edits_out=e, g_out=g, merged=True)),
                      ("learned_merged", lambda: msz.fix_learned(fd, fhd, xi, params, p_min=p_min, workspace=ws,
                                                                 edits_out=e, g_out=g, merged=True))):
-        try:
-            fn()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                rc, _, _, st = fn()
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / steps
-            if rc != msz.OK:
-                raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
-            checked(msz, fd, g, xi)
-            out[name] = {"ms": round(ms, 3), "value": round(fd.numel() / ms / 1e6, 4),
-                         "c_rounds_by_type": st["rounds"], "r_rounds": st["rounds_r"], "n_edited": st["n_edited"]}
-            log(f"bench: {name} 512^3 {ms:.2f} ms")
-        except RuntimeError as err:  # reported, not fatal: the default forms above are the measured ones
-            out[name] = {"failed": str(err)}
+        ms, (rc, _, _, st) = timed(fn, steps, 1, torch)
+        if rc != msz.OK:
+            raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
+        checked(msz, fd, g, xi)
+        out[name] = {"ms": round(ms, 3), "value": round(n / ms / 1e6, 4),
+                     "c_rounds_by_type": st["rounds"], "r_rounds": st["rounds_r"], "n_edited": st["n_edited"]}
+        log(f"bench: {name} 512^3 {ms:.2f} ms")
     return out
-
-
-def bench_merged(msz, torch, dev, pairs, steps, plain_ms):
-    """The ocean2d pair with merged C rounds (all four case types per round,
-    the parallel C-loop of Sec. 6.1): time per step, rounds, zero error."""
-    fields = [(torch.from_numpy(f).to(dev), torch.from_numpy(fh).to(dev), float(xi)) for f, fh, xi in pairs]
-    ws = torch.empty(msz.workspace_bytes(fields[0][0].shape), dtype=torch.uint8, device=dev)
-    outs = [(torch.empty_like(f), torch.empty_like(f)) for f, _, _ in fields]
-
-    def step(timing=False):
-        res = []
-        for (f, fh, xi), (e, g) in zip(fields, outs):
-            rc, _, _, st = msz.fix(f, fh, xi, workspace=ws, edits_out=e, g_out=g, merged=True, timing=timing)
-            if rc != msz.OK:
-                raise RuntimeError(f"msz_fix (merged C rounds) failed: {msz.strerror(rc)}")
-            res.append(st)
-        return res
-
-    step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        sts = step()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    for (f, fh, xi), (e, g) in zip(fields, outs):
-        checked(msz, f, g, xi)
-    verts = sum(f.numel() for f, _, _ in fields)
-    log(f"bench: merged C rounds {ms:.3f} ms/step ({verts / ms / 1e6:.3f} Gv/s), plain {plain_ms:.3f} ms/step")
-    return {"workload": "the ocean2d pair (3600x2400 at xi = 1e-4 and 1e-3), merged C rounds",
-            "ms_per_step": round(ms, 3), "value": round(verts / ms / 1e6, 4), "unit": "Gvertices/s",
-            "steps": steps, "speedup_vs_plain": round(plain_ms / ms, 3),
-            "rounds": [{"xi": p[2], "rounds": st["rounds"], "rounds_r": st["rounds_r"],
-                        "outer_iters": st["outer_iters"], "n_edited": st["n_edited"]}
-                       for p, st in zip(fields, sts)]}
 
 
 def bench_edits(msz, torch, edits, pairs, reps=3):
@@ -376,20 +368,10 @@ def bench_edits(msz, torch, edits, pairs, reps=3):
         n = e.numel()
         buf = torch.empty(msz.edits_bound(n), dtype=torch.uint8, device=e.device)
         dec = torch.empty_like(e)
-        msz.encode_edits(e, out=buf)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            rc, blob, st = msz.encode_edits(e, out=buf)
-        torch.cuda.synchronize()
-        t_enc = (time.perf_counter() - t0) * 1e3 / reps
+        t_enc, (rc, blob, st) = timed(lambda: msz.encode_edits(e, out=buf), reps, 1, torch)
         if rc != msz.OK:
             raise RuntimeError(f"msz_encode_edits: {msz.strerror(rc)}")
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            rc, _ = msz.decode_edits(blob, e.shape, out=dec)
-        torch.cuda.synchronize()
-        t_dec = (time.perf_counter() - t0) * 1e3 / reps
+        t_dec, (rc, _) = timed(lambda: msz.decode_edits(blob, e.shape, out=dec), reps, 0, torch)
         if rc != msz.OK or not torch.equal(dec.view(torch.int32), e.view(torch.int32)):
             raise RuntimeError("decoded edits differ")
         m = st["n_edits"]
@@ -399,8 +381,8 @@ def bench_edits(msz, torch, edits, pairs, reps=3):
                     "value_bits_per_edit": round(st["value_bits"] / max(m, 1), 3),
                     "bits_per_vertex": round(8 * st["bytes"] / n, 5),
                     "encode_ms": round(t_enc, 3), "decode_ms": round(t_dec, 3)})
-        log(f"bench: edits xi={float(xi):g}: {m} edits, {st['bytes']} bytes "
-            f"({8 * st['bytes'] / max(m, 1):.2f} bits/edit), encode {t_enc:.2f} ms, decode {t_dec:.2f} ms")
+        log(f"bench: edits xi={float(xi):g}: {m} edits, {st['bytes']} bytes, encode {t_enc:.2f} ms, "
+            f"decode {t_dec:.2f} ms")
     return {"workload": "edits of the plain loop on the ocean2d pair, encoded on the GPU and decoded back",
             "fields": out}
 
@@ -419,22 +401,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="plain,edits,merged,batched,learned")
+    ap.add_argument("--forms", default=DEFAULT_FORMS,
+                    help=f"comma list of extra forms (default {DEFAULT_FORMS}; also batch_modes; none)")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-cpu-baseline", action="store_true",
-                    help="also time the oracle over the whole batch on all host cores (minutes)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a 1 GiB device copy first (calibrates HBM byte counters)")
-    ap.add_argument("--schedule-out", default=None,
-                    help="time every plain-form call and write each call's step schedule to this JSON file "
-                         "(to attribute the step kernels of a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: each field's "
               "correction loop runs on a single GPU", file=sys.stderr)
         sys.exit(2)
-    forms = [x for x in args.forms.split(",") if x]
+    args.forms = [x for x in args.forms.split(",") if x and x != "none"]
 
     import torch
 
@@ -445,54 +423,70 @@ def main():
     msz.lib()
     if args.calib_copy:
         calibration_copy(torch, dev)
-    pairs, verts, ms_per_step, roofline, phases, rounds, edits = bench_plain(msz, torch, dev, args)
-    value = verts / (ms_per_step * 1e-3) / 1e9
+    host_fields, verts, ms, roofline, batch_info, batch_modes = bench_batch(msz, torch, dev, args)
 
-    extra = {}
-    if "edits" in forms:
-        extra["edits"] = bench_edits(msz, torch, edits, pairs)
-    if "merged" in forms:
-        extra["merged"] = bench_merged(msz, torch, dev, pairs, args.form_steps, ms_per_step)
-    if "batched" in forms:
-        extra["batched"] = bench_batched(msz, torch, dev, args.form_steps, args.batch_cpu_baseline)
-    if "learned" in forms:
-        extra["learned"] = bench_learned(msz, torch, dev, args.form_steps)
+    forms = {"batch": batch_info}
+    if batch_modes:
+        forms["batch_modes"] = batch_modes
+    pairs = None
+    if any(k in args.forms for k in ("plain", "merged", "preemptive", "edits")):
+        import synth
+        log("bench: generating the 3600x2400 pair")
+        pairs = synth.ocean2d()
+    wl2 = "3600x2400 k^-3 Gaussian random field pair, xi = 1e-4 and 1e-3 x range"
+    if "plain" in args.forms or "edits" in args.forms:
+        res, edits = single_form(msz, torch, dev, pairs, args.form_steps, "plain 3600x2400 pair")
+        res["workload"] = wl2 + ", plain loop"
+        if "plain" in args.forms:
+            forms["plain"] = res
+        if "edits" in args.forms:
+            forms["edits"] = bench_edits(msz, torch, edits, pairs)
+        del edits
+    if "merged" in args.forms:
+        forms["merged"], _ = single_form(msz, torch, dev, pairs, args.form_steps, "merged C rounds", merged=True)
+        forms["merged"]["workload"] = wl2 + ", merged C rounds"
+    if "preemptive" in args.forms:
+        forms["preemptive"], _ = single_form(msz, torch, dev, pairs, args.form_steps, "preemptive",
+                                             preemptive=True)
+        forms["preemptive"]["workload"] = wl2 + ", preemptive edit mode (not deterministic)"
+    if "bumps128" in args.forms:
+        forms["bumps128"] = bench_bumps128(msz, torch, dev)
+    if "turb256" in args.forms:
+        import synth
+        log("bench: generating the 256^3 field")
+        forms["turb256"], _ = single_form(msz, torch, dev, synth.turb3d(), args.form_steps, "turb256")
+        forms["turb256"]["workload"] = "256^3 k^-11/3 Gaussian random field + 64 blobs, xi = 1e-3 x range"
+    if "learned" in args.forms:
+        forms["learned"] = bench_learned(msz, torch, dev, args.form_steps)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build()
-        f, fh, xi = pairs[0]
-        log("bench: oracle on the xi = 1e-4 field (serial C, one core)")
-        tc = time.perf_counter()
-        rc, _, _, _ = oracle.fix(f, fh, xi)
-        dt = time.perf_counter() - tc
-        assert rc == 0
-        cpu = {"value": round(f.size / dt / 1e9, 6), "unit": "Gvertices/s", "cores": 1, "kind": "oracle",
-               "sample": "half a step: the xi = 1e-4 field of the 3600x2400 pair (8.64 M vertices), "
-                         "serial C oracle on one core", "seconds": round(dt, 2)}
+        cpu = oracle_batch_all_cores(host_fields)
+        if pairs is not None and "plain" in forms:
+            log("bench: oracle on the 3600x2400 pair, one pinned core")
+            forms["plain"]["cpu_oracle_one_core"] = oracle_one_core(pairs)
+            log(f"bench: oracle pair {forms['plain']['cpu_oracle_one_core']['seconds']} s")
 
     out = {
         "metric": METRIC,
-        "value": round(value, 4),
+        "value": round(verts / ms / 1e6, 4),
         "unit": "Gvertices/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(ms, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "ocean2d: 3600x2400 k^-3 Gaussian random field in [0,1], quantised at "
-                               "xi = 1e-4 and 1e-3; plain loop, both fields per step",
-                   "vertices_per_step": verts, "form": "plain"},
+        "config": {"workload": "batch96: 96 uneven k^-3 Gaussian random fields (64 2D, sides U{64..2048}; "
+                               "32 3D cubes, U{32..192}^3), xi in {1e-4,1e-3,1e-2} x range, corrected together "
+                               "by msz_fix_batch",
+                   "vertices_per_step": verts, "form": "batched"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "phases": phases,
-        "rounds": rounds,
-        "forms": extra,
+        "forms": forms,
         "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)

@@ -85,7 +85,7 @@ enum {
 };
 
 /* msz_options.flags bits. */
-#define MSZ_FLAG_TIMING 1 /* time every step (single-field calls; adds a little overhead) */
+#define MSZ_FLAG_TIMING 1 /* time every step kernel (adds a little overhead): msz_stats.phase_ms, msz_last_launches */
 /* Merged C rounds (the parallel C-loop of Sec. 6.1): each C round finds the
  * false critical points of all four types on one snapshot of g and halves the
  * union of their targets once, instead of running the FPmax, FPmin, FNmax and
@@ -102,6 +102,17 @@ enum {
  * stats.mislabel_init is -1.  Accepted by msz_fix, msz_fix_batch and
  * msz_fix_learned (there the start field is the network's warm start). */
 #define MSZ_FLAG_COUNT_INIT 4
+/* Preemptive mode (Sec. 6.1): merged C rounds (implied) in which a target
+ * proposed by several cases -- a C round's or an R round's -- is edited by
+ * each of them without a claim, so they race: cases that read the same value
+ * write the same halving (one edit survives and the lost ones are found again
+ * in a later round), and a case that reads another's result halves it once
+ * more.  The result is not deterministic; every run still ends with zero
+ * segmentation error, |f - g| <= xi and g <= fhat (every value written is a
+ * halving of a value no larger than the round's snapshot, so each round
+ * lowers what it changes and the loop ends as the synchronous one does).
+ * Accepted by msz_fix, msz_fix_batch, msz_fix_learned and msz_fix_noalloc. */
+#define MSZ_FLAG_PREEMPTIVE 8
 
 typedef struct {
     int32_t ndim;        /* 2 or 3 */
@@ -199,13 +210,38 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
 int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, float* edits_out,
                     const msz_options* opt, msz_stats* stats, void* stream);
 
+/* Profiling aid: every step-kernel launch of the calling host thread's last
+ * msz_fix or msz_fix_batch call that ran with MSZ_FLAG_TIMING, in launch
+ * order.  A step kernel records, from the GPU's constant-rate clock, its first
+ * block's start and its last block's end, and the algorithmic bytes of the
+ * units its blocks visited: per operation, the compulsory reads and writes of
+ * each vertex of a visited direction or label tile, each scanned flag byte,
+ * edit attempt, recomputed vertex, face-layer pointer, and each pointer load
+ * or store of the compression walks (halo and cache re-reads not counted). */
+enum {
+    MSZ_KERNEL_STEP1_2D = 0, /* one field: the step kernel of a 2D field (decides and runs) */
+    MSZ_KERNEL_STEP1_3D = 1,
+    MSZ_KERNEL_BATCH_2D = 2, /* a batch: the step kernel of the 2D fields */
+    MSZ_KERNEL_BATCH_3D = 3
+};
+typedef struct {
+    int32_t kernel;  /* MSZ_KERNEL_* */
+    int32_t phase;   /* MSZ_PHASE_* of a one-field step; -1 for a batch step (mixed) or an idle step */
+    double us;       /* first block's start to last block's end, microseconds (0 if no block ran) */
+    int64_t bytes;   /* algorithmic bytes of the units the launch visited */
+} msz_launch;
+/* Writes at most max records (out may be NULL); returns the number recorded. */
+int32_t msz_last_launches(msz_launch* out, int32_t max);
+
 /* Profiling aid: the step schedule of the calling host thread's last msz_fix
- * that ran with MSZ_FLAG_TIMING.  Every step of the device schedule runs one
- * operation; step k is phases_out[k] (an MSZ_PHASE_* index, or -1 for the
- * idle steps that end the last graph launch).  Writes at most max entries
- * (phases_out may be NULL) and returns the number of steps recorded.  The
- * entries line up one to one with the step-kernel dispatches of that call
- * in a kernel trace. */
+ * or msz_fix_batch that ran with MSZ_FLAG_TIMING.  Every step of the device
+ * schedule runs one operation per field; for one field, step k is
+ * phases_out[k] (an MSZ_PHASE_* index, or -1 for the idle steps that end the
+ * last graph launch), and the entries line up one to one with the step-kernel
+ * dispatches of that call in a kernel trace; for a batch of n_jobs fields,
+ * phases_out[k * n_jobs + j] is field j's operation in step k (-1 once it is
+ * done).  Writes at most max entries (phases_out may be NULL) and returns the
+ * number of entries recorded. */
 int32_t msz_last_schedule(int32_t* phases_out, int32_t max);
 
 /*
@@ -248,8 +284,9 @@ typedef struct {
  * is active.  opt->workspace (if given) must hold
  * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
  * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);
- * opt->max_rounds and MSZ_FLAG_MERGED_C apply to every field (MSZ_FLAG_TIMING is
- * ignored).
+ * opt->max_rounds, MSZ_FLAG_MERGED_C and MSZ_FLAG_PREEMPTIVE apply to every field
+ * (MSZ_FLAG_TIMING records the step-kernel launches for msz_last_launches and
+ * fills no per-field timings).
  * Returns MSZ_OK when every field converged, else the first failing field's
  * code (see each stats; per-phase timings are not filled).
  */

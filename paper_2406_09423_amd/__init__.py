@@ -29,6 +29,7 @@ N_PHASES = len(PHASES)
 FLAG_TIMING = 1
 FLAG_MERGED_C = 2  # merged C rounds (all four case types per round)
 FLAG_COUNT_INIT = 4  # count the start field's mislabelled vertices (stats["mislabel_init"], else -1)
+FLAG_PREEMPTIVE = 8  # merged C rounds whose shared targets are edited without claims (not deterministic)
 
 
 class Dims(ctypes.Structure):
@@ -83,6 +84,15 @@ class EditStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_edits", "bytes", "index_bits", "value_bits")]
 
 
+class Launch(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("phase", ctypes.c_int32), ("us", ctypes.c_double),
+                ("bytes", ctypes.c_int64)]
+
+
+KERNELS = ("step1_2d", "step1_3d", "batch_2d", "batch_3d")  # MSZ_KERNEL_*: device names below
+KERNEL_SYMBOLS = ("k_eng_step1<2>", "k_eng_step1<3>", "k_eng_step<2>", "k_eng_step<3>")
+
+
 class MszError(RuntimeError):
     def __init__(self, code: int, what: str):
         super().__init__(f"{what}: {strerror(code)} ({code})")
@@ -110,6 +120,8 @@ def lib() -> ctypes.CDLL:
         L.msz_batch_workspace_bytes.argtypes = [ctypes.POINTER(Job), I32]
         L.msz_batch_workspace_bytes.restype = ctypes.c_size_t
         L.msz_tile_variants.argtypes = [I32]
+        L.msz_last_launches.argtypes = [P, I32]
+        L.msz_last_launches.restype = I32
         L.msz_last_schedule.argtypes = [P, I32]
         L.msz_last_schedule.restype = I32
         L.msz_strerror.argtypes = [ctypes.c_int]
@@ -154,8 +166,9 @@ def dims_of(shape) -> Dims:
     raise ValueError(f"fields are 2D (ny, nx) or 3D (nz, ny, nx), got shape {tuple(shape)}")
 
 
-def _flags(timing: bool, merged: bool, count_init: bool) -> int:
-    return (FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0) | (FLAG_COUNT_INIT if count_init else 0)
+def _flags(timing: bool, merged: bool, count_init: bool, preemptive: bool = False) -> int:
+    return ((FLAG_TIMING if timing else 0) | (FLAG_MERGED_C if merged else 0) | (FLAG_COUNT_INIT if count_init else 0)
+            | (FLAG_PREEMPTIVE if preemptive else 0))
 
 
 def _stream(stream=None) -> int:
@@ -182,7 +195,7 @@ def tile_variants(ndim: int) -> int:
 
 def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: bool = True,
         workspace=None, tile: int = 0, edits_out=None, g_out=None, timing: bool = False,
-        merged: bool = False, count_init: bool = False, stream=None):
+        merged: bool = False, count_init: bool = False, preemptive: bool = False, stream=None):
     """Runs the correction loop on the GPU.
 
     Returns ``(status, delta, g, stats)``: ``delta`` with fl(fhat + delta) == g,
@@ -208,7 +221,7 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: boo
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
     opt.tile_override = int(tile)
-    opt.flags = _flags(timing, merged, count_init)
+    opt.flags = _flags(timing, merged, count_init, preemptive)
     st = Stats()
     rc = lib().msz_fix(f.data_ptr(), fhat.data_ptr(), d, float(xi), edits.data_ptr(),
                        ctypes.byref(opt), ctypes.byref(st), _stream(stream))
@@ -219,7 +232,7 @@ def fix(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, want_g: boo
 
 
 def fix_noalloc(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, edits_out=None, g_out=None,
-                tile: int = 0, merged: bool = False, count_init: bool = False, stream=None):
+                tile: int = 0, merged: bool = False, count_init: bool = False, preemptive: bool = False, stream=None):
     """msz_fix_noalloc: the correction loop with all scratch in the library's
     static device array (no allocation inside the call).  ``edits_out`` and
     ``g_out`` (optional) are caller-owned outputs; returns ``(status, delta,
@@ -237,11 +250,22 @@ def fix_noalloc(f, fhat, xi: float, *, max_rounds: int = 0, warm_start=None, edi
         opt.warm_start = warm_start.data_ptr()
     opt.g_out = g_out.data_ptr() if g_out is not None else None
     opt.tile_override = int(tile)
-    opt.flags = _flags(False, merged, count_init)
+    opt.flags = _flags(False, merged, count_init, preemptive)
     st = Stats()
     rc = lib().msz_fix_noalloc(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), edits.data_ptr(),
                                ctypes.byref(opt), ctypes.byref(st), _stream(stream))
     return int(rc), edits, g_out, st.as_dict()
+
+
+def last_launches() -> list:
+    """Every step-kernel launch of this thread's last timed fix / fix_batch:
+    dicts with the kernel name, phase (None for batch or idle steps), duration
+    (us, GPU clock stamps) and the algorithmic bytes its blocks visited."""
+    n = int(lib().msz_last_launches(None, 0))
+    buf = (Launch * max(n, 1))()
+    lib().msz_last_launches(ctypes.cast(buf, ctypes.c_void_p), n)
+    return [{"kernel": KERNELS[buf[k].kernel], "phase": PHASES[buf[k].phase] if buf[k].phase >= 0 else None,
+             "us": float(buf[k].us), "bytes": int(buf[k].bytes)} for k in range(n)]
 
 
 def last_schedule() -> list:
@@ -311,8 +335,11 @@ def decode_edits(blob, shape, out=None, stream=None):
 
 
 def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=None, tiles="auto", outs=None,
-              merged: bool = False, count_init: bool = False, stream=None):
+              merged: bool = False, count_init: bool = False, preemptive: bool = False, timing: bool = False,
+              stream=None):
     """Corrects a list of (f, fhat, xi) together in one device-scheduled run (msz_fix_batch).
+
+    With ``timing`` every step-kernel launch is recorded (see :func:`last_launches`).
 
     ``tiles``: each field's direction tile variant, "auto" (the autotuner's
     table, autotune.py) or None (the default tile).  ``outs`` optionally gives
@@ -347,7 +374,7 @@ def fix_batch(fields, *, max_rounds: int = 0, want_g: bool = True, workspace=Non
         pairs.append((e, g))
     opt = Options()
     opt.max_rounds = int(max_rounds)
-    opt.flags = _flags(False, merged, count_init)
+    opt.flags = _flags(timing, merged, count_init, preemptive)
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -448,7 +475,7 @@ def net_adam(params, grad, m, v, step: int, lr: float, stream=None):
 
 def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: int = 0, want_g: bool = True,
                 workspace=None, edits_out=None, g_out=None, timing: bool = False, merged: bool = False,
-                count_init: bool = False, stream=None):
+                count_init: bool = False, preemptive: bool = False, stream=None):
     """msz_fix warm-started by the network; same return value as fix()."""
     import torch
     _check_field(f, "f")
@@ -461,7 +488,7 @@ def fix_learned(f, fhat, xi: float, params, *, p_min: float = 0.5, max_rounds: i
     if workspace is not None:
         opt.workspace = workspace.data_ptr()
         opt.workspace_bytes = workspace.numel() * workspace.element_size()
-    opt.flags = _flags(timing, merged, count_init)
+    opt.flags = _flags(timing, merged, count_init, preemptive)
     st = Stats()
     rc = lib().msz_fix_learned(f.data_ptr(), fhat.data_ptr(), dims_of(f.shape), float(xi), params.data_ptr(),
                                float(p_min), edits.data_ptr(), ctypes.byref(opt), ctypes.byref(st),

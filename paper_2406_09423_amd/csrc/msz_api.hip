@@ -59,7 +59,7 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Option flags accepted by the correction entry points.
-constexpr int32_t kFixFlags = MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C | MSZ_FLAG_COUNT_INIT;
+constexpr int32_t kFixFlags = MSZ_FLAG_TIMING | MSZ_FLAG_MERGED_C | MSZ_FLAG_COUNT_INIT | MSZ_FLAG_PREEMPTIVE;
 
 // The kernels move four vertices per dwordx4 access.
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -204,7 +204,9 @@ struct EngineCtx {
     // with the process.
 
     static size_t host_bytes() { return 256 + stamp_bytes(); }
-    static size_t stamp_bytes() { return sizeof(unsigned long long) * kEngStampWords * kGraphSteps; }
+    // per step, a stamp block for each of the two step kernels (a batch's 2D
+    // and 3D kernels; a single field uses the first)
+    static size_t stamp_bytes() { return sizeof(unsigned long long) * kEngStampWords * 2 * kGraphSteps; }
     unsigned long long* host_stamps() const { return reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(host) + 256); }
 
     int init(int dev) {
@@ -224,7 +226,7 @@ struct EngineCtx {
         const size_t op2 = take(sizeof(int) * (kEngMaxFields + 1));
         const size_t op3 = take(sizeof(int) * (kEngMaxFields + 1));
         const size_t oc = take(sizeof(int) * 4);
-        const size_t ol = take(sizeof(int) * kGraphSteps);
+        const size_t ol = take(sizeof(int) * kGraphSteps * kEngMaxFields);
         const size_t ot = take(stamp_bytes());
         const size_t oc2 = take(sizeof(unsigned) * kCntBlockWords * kEngMaxFields);
         void* p = nullptr;
@@ -291,7 +293,7 @@ struct EngineCtx {
             const void* fn = eng_step1_kernel(has3 ? 3 : 2);
             const int grid = has3 ? grid3 : grid2;
             for (int st = 0; st < kGraphSteps; ++st) {
-                unsigned long long* ts = timing ? tstamp + st * kEngStampWords : nullptr;
+                unsigned long long* ts = timing ? tstamp + 2 * st * kEngStampWords : nullptr;
                 int* log = timing ? oplog : nullptr;
                 int stp = st;
                 void* a[] = {&fields, &states, &states, &stats, &counters, &ctl, &hflag_dev, &log, &stp, &ts};
@@ -302,7 +304,8 @@ struct EngineCtx {
             const int par = st & 1;
             EngState* cur = states + par * nf;
             EngState* nxt = states + (par ^ 1) * nf;
-            unsigned long long* ts = timing ? tstamp + st * kEngStampWords : nullptr;
+            unsigned long long* ts2 = timing ? tstamp + 2 * st * kEngStampWords : nullptr;
+            unsigned long long* ts3 = timing ? tstamp + (2 * st + 1) * kEngStampWords : nullptr;
             // the 2D and the 3D step kernels work on disjoint fields: both
             // follow the last step's scan and may run side by side; the
             // decision follows both
@@ -310,13 +313,13 @@ struct EngineCtx {
             int nd = 0;
             if (has2) {
                 last = prev;
-                void* a[] = {&fields, &cur, &pre2, &nf, &ts};
+                void* a[] = {&fields, &cur, &pre2, &nf, &ts2};
                 if (!add_kernel(eng_step_kernel(2), dim3(grid2), dim3(256), a)) return MSZ_EDEVICE;
                 dep[nd++] = last;
             }
             if (has3) {
                 last = prev;
-                void* a[] = {&fields, &cur, &pre3, &nf, &ts};
+                void* a[] = {&fields, &cur, &pre3, &nf, &ts3};
                 if (!add_kernel(eng_step_kernel(3), dim3(grid3), dim3(256), a)) return MSZ_EDEVICE;
                 dep[nd++] = last;
             }
@@ -386,9 +389,17 @@ std::vector<int32_t>& last_schedule() {
     return v;
 }
 
+// Every step-kernel launch of the calling thread's last timed run.
+std::vector<msz_launch>& last_launches() {
+    thread_local std::vector<msz_launch> v;
+    return v;
+}
+
 // One engine run over hf.size() fields whose workspaces are already bound.
-// Fills st[] (one per field); with timing (one field only) adds the per-step
-// durations to ms[] / launches[] by phase.
+// Fills st[] (one per field).  With timing, every step-kernel launch is
+// recorded (last_launches: duration from its clock stamps, algorithmic bytes)
+// and, for one field, the per-step durations are added to ms[] / launches[]
+// by phase.
 int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing, double* ms, int64_t* launches,
                int64_t max_steps, hipStream_t s) {
     const int nf = static_cast<int>(hf.size());
@@ -422,8 +433,10 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         grid2 *= 2;
         grid3 *= 2;
     }
-    timing = timing && nf == 1;
-    if (timing) last_schedule().clear();
+    if (timing) {
+        last_schedule().clear();
+        last_launches().clear();
+    }
     for (int j = 0; j < nf; ++j) hf[j].cnt = E.counters + static_cast<size_t>(j) * kCntBlockWords;
     if (int rc = E.graph_for(nf, has2, has3, timing, grid2, grid3)) {
         E.drop_graph();
@@ -480,6 +493,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
             if (steps > max_steps) { rc = MSZ_EDEVICE; break; }
         }
     }
+    std::vector<int> batch_log;  // timed batch: the operation of every field in every step of a launch
+    if (timing && !single) batch_log.resize(static_cast<size_t>(kGraphSteps) * nf);
     while (timing) {  // one launch at a time, with the schedule and clock stamps of each step read back
         if (hipMemsetAsync(E.tstamp, 0, EngineCtx::stamp_bytes(), s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         if (hipGraphLaunch(E.exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
@@ -490,16 +505,33 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
             rc = MSZ_EDEVICE;
             break;
         }
+        if (!single && hipMemcpyAsync(batch_log.data(), E.oplog, sizeof(int) * batch_log.size(),
+                                      hipMemcpyDeviceToHost, s) != hipSuccess) {
+            rc = MSZ_EDEVICE;
+            break;
+        }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
         for (int k = 0; k < kGraphSteps; ++k) {
-            const int ph = phase_of_op(E.host[1 + k]);
-            last_schedule().push_back(ph);
-            const unsigned long long* t = E.host_stamps() + k * kEngStampWords;
-            unsigned long long end = 0;
-            for (int w = 1; w < kEngStampWords; ++w) end = std::max(end, t[w]);
-            if (ph >= 0 && end >= t[0]) {
-                ms[ph] += static_cast<double>(end - t[0]) / wall_khz;
-                launches[ph] += 1;
+            const int ph = single ? phase_of_op(E.host[1 + k]) : -1;
+            if (single) last_schedule().push_back(ph);
+            for (int j = 0; !single && j < nf; ++j) last_schedule().push_back(phase_of_op(batch_log[k * nf + j]));
+            for (int d = 0; d < 2; ++d) {
+                if (single ? d != 0 : !(d == 0 ? has2 : has3)) continue;
+                const unsigned long long* t = E.host_stamps() + (2 * k + d) * kEngStampWords;
+                unsigned long long end = 0;
+                for (int w = 1; w <= kEngEndSlots; ++w) end = std::max(end, t[w]);
+                const double dms = end >= t[0] ? static_cast<double>(end - t[0]) / wall_khz : 0.0;
+                msz_launch rec{};
+                rec.kernel = single ? (has3 ? MSZ_KERNEL_STEP1_3D : MSZ_KERNEL_STEP1_2D)
+                                    : (d == 0 ? MSZ_KERNEL_BATCH_2D : MSZ_KERNEL_BATCH_3D);
+                rec.phase = ph;
+                rec.us = dms * 1e3;
+                rec.bytes = static_cast<int64_t>(t[kEngBytesWord]);
+                last_launches().push_back(rec);
+                if (single && ph >= 0 && end >= t[0]) {
+                    ms[ph] += dms;
+                    launches[ph] += 1;
+                }
             }
         }
         steps += kGraphSteps;
@@ -722,7 +754,8 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     F = EngField{};
     F.gr = gr;
     F.variant = o.tile_override;
-    F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
+    F.preempt = (o.flags & MSZ_FLAG_PREEMPTIVE) != 0;
+    F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0 || F.preempt;
     F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
     F.xi = xi;
     F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
@@ -760,7 +793,7 @@ int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, flo
     if (!aligned16(f) || !aligned16(fhat) || !aligned16(edits_out) || !aligned16(o.warm_start) ||
         !aligned16(o.g_out))
         return done(MSZ_EINVAL);
-    if (o.workspace || o.workspace_bytes || (o.flags & ~(MSZ_FLAG_MERGED_C | MSZ_FLAG_COUNT_INIT)) != 0 ||
+    if (o.workspace || o.workspace_bytes || (o.flags & ~(kFixFlags & ~MSZ_FLAG_TIMING)) != 0 ||
         o.tile_override < 0 || o.tile_override > tile_variant_count(d.ndim))
         return done(MSZ_EINVAL);
     if (int rc = check_xi(xi)) return done(rc);
@@ -773,7 +806,8 @@ int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, flo
     EngField F{};
     F.gr = gr;
     F.variant = o.tile_override;
-    F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
+    F.preempt = (o.flags & MSZ_FLAG_PREEMPTIVE) != 0;
+    F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0 || F.preempt;
     F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
     F.xi = xi;
     F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
@@ -787,6 +821,14 @@ int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, flo
     if (int rc = run_noalloc(F, base, step_bound(F.cap), st, static_cast<hipStream_t>(stream))) return done(rc);
     copy_stats(st, F.count_init != 0, stats);
     return stats->status;
+}
+
+int32_t msz_last_launches(msz_launch* out, int32_t max) {
+    const std::vector<msz_launch>& v = last_launches();
+    const int32_t n = static_cast<int32_t>(v.size());
+    if (out)
+        for (int32_t k = 0; k < n && k < max; ++k) out[k] = v[k];
+    return n;
 }
 
 int32_t msz_last_schedule(int32_t* phases_out, int32_t max) {
@@ -842,7 +884,8 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
         F = EngField{};
         make_grid(J.d, F.gr);
         F.variant = J.tile;
-        F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0;
+        F.preempt = (o.flags & MSZ_FLAG_PREEMPTIVE) != 0;
+        F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0 || F.preempt;
         F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
         F.xi = J.xi;
         F.cap = cap;
@@ -855,7 +898,9 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
         w += layout_for(F.gr).total;
     }
     std::vector<EngStats> st;
-    int rc = run_engine(hf, st, false, nullptr, nullptr, step_bound(cap), s);
+    double ms[MSZ_N_PHASES] = {};
+    int64_t launches[MSZ_N_PHASES] = {};
+    int rc = run_engine(hf, st, (o.flags & MSZ_FLAG_TIMING) != 0, ms, launches, step_bound(cap), s);
     int first = rc;
     for (int j = 0; j < n_jobs; ++j) {
         msz_stats* out = jobs[j].stats;

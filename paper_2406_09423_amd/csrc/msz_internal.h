@@ -131,7 +131,9 @@ namespace msz {
 // k_eng_scan sums the next step's items (see the engine in msz_kernels.hip).
 constexpr int kEngMaxFields = 1024;
 constexpr int kEngTimeSlots = 48;                   // steps per graph launch (a multiple of 2 and 3)
-constexpr int kEngStampWords = 65;                  // per timed step: start, then 64 slots of block ends
+constexpr int kEngEndSlots = 64;                    // per timed step: start, 64 slots of block ends,
+constexpr int kEngBytesWord = 1 + kEngEndSlots;     // then the algorithmic bytes the step's blocks visited
+constexpr int kEngStampWords = 2 + kEngEndSlots;
 constexpr int kEngChunk = 4096;                     // vertices per flat work item
 constexpr int kHostStatsWord = 32;                  // final statistics in the host word block, from word 32
 
@@ -163,6 +165,7 @@ struct EngField {
     Grid gr;
     int variant;
     int merged;      // 1: merged C rounds
+    int preempt;     // 1: shared targets edited without claims (preemptive mode; implies merged)
     int count_init;  // 1: label the start field once and count its mislabelled vertices
     float xi;
     long long cap;

@@ -607,6 +607,38 @@ __device__ __forceinline__ void claim_edit(uint8_t* __restrict__ marks, float* _
         edit_value<NDIM>(g, dirty, gr, t, old, lt, changed);
 }
 
+// Preemptive edit (the preemptive mode of Sec. 6.1): halves g[t] from
+// whatever value it holds when read, with no claim.  Cases that share a
+// target race: those that read the same value write the same result (one
+// edit survives; the lost ones come back as cases in a later round), and one
+// that reads another's result halves it again.  Every value written is a
+// halving of a value no larger than the round's snapshot, so a round still
+// lowers each target it changes and the loop ends as the synchronous one does.
+template <int NDIM>
+__device__ __forceinline__ void preempt_edit(float* __restrict__ g, const float* __restrict__ L,
+                                             uint8_t* __restrict__ dirty, const Grid& gr, int t, unsigned& changed) {
+    const float old = __hip_atomic_load(g + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const float nv = halve(old, L[t]);
+    dirty[t] = 1;
+    if (nv == old) return;
+    __hip_atomic_store(g + t, nv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ++changed;
+    const int x = t % gr.nx, y = (t / gr.nx) % gr.ny, z = NDIM == 3 ? t / gr.nxy : 0;
+    constexpr int NS = NDIM == 3 ? 14 : 6;
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
+}
+
+// A shared target's edit: claimed (synchronous rounds) or preemptive.
+template <int NDIM>
+__device__ __forceinline__ void target_edit(bool preempt, uint8_t* __restrict__ marks, float* __restrict__ g,
+                                            const float* __restrict__ L, uint8_t* __restrict__ dirty,
+                                            const Grid& gr, int t, unsigned& changed) {
+    if (preempt) preempt_edit<NDIM>(g, L, dirty, gr, t, changed);
+    else claim_edit<NDIM>(marks, g, L, dirty, gr, t, changed);
+}
+
 // --------------------------------------------------------------- labels ---
 //
 // Pointer jumping along the forests of steepest ascent and descent (Sec. 6.2).
@@ -848,7 +880,7 @@ __device__ __forceinline__ int tile_of_vertex(const Grid& gr, int i) {
 // the flagged vertices are all the compression of g has to resolve.
 template <int NDIM>
 __device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* su, const int* sd, int* qf_up,
-                                           int* qf_dn, uint8_t* target) {
+                                           int* qf_dn, uint8_t* target, unsigned& nface) {
     using T = LabelTile<NDIM>;
     constexpr int FC = face_count<NDIM>();
     const int3 o = tile_origin<NDIM>(gr, tile);
@@ -864,6 +896,7 @@ __device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* 
         qf_dn[tile * FC + b] = td;
         target[tu] = 1;
         target[td] = 1;
+        ++nface;
     }
 }
 
@@ -872,7 +905,7 @@ __device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* 
 // the face-layer pointers are put back.
 template <int NDIM>
 __device__ __forceinline__ void restore_faces(const Grid& gr, int tile, int* q_up, int* q_dn, const int* qf_up,
-                                              const int* qf_dn) {
+                                              const int* qf_dn, unsigned& nface) {
     constexpr int FC = face_count<NDIM>();
     const int3 o = tile_origin<NDIM>(gr, tile);
     for (int b = threadIdx.x; b < FC; b += blockDim.x) {
@@ -882,6 +915,7 @@ __device__ __forceinline__ void restore_faces(const Grid& gr, int tile, int* q_u
         const int i = x + gr.nx * y + gr.nxy * z;
         q_up[i] = qf_up[tile * FC + b];
         q_dn[i] = qf_dn[tile * FC + b];
+        ++nface;
     }
 }
 
@@ -903,22 +937,25 @@ __device__ __forceinline__ void store_relaxed(int* p, int v) {
 // forests are acyclic (every pointer goes strictly up, resp. down, the total
 // order), so the walks end; the step cap only guards against corrupted input
 // and is reported as an error.
+// acc counts the pointer loads and stores (4 bytes each).
 constexpr int kMaxWalk = 1 << 22;
-__device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, int& rd) {
+__device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, int& rd, unsigned& acc) {
     int yu = load_relaxed(qu + x), yd = load_relaxed(qd + x);
     ru = yu;
     rd = yd;
+    acc += 2;
     bool du = false, dd = false;
     for (int it = 0; it < kMaxWalk; ++it) {
         const int zu = du ? yu : load_relaxed(qu + yu);
         const int zd = dd ? yd : load_relaxed(qd + yd);
+        acc += (du ? 0u : 1u) + (dd ? 0u : 1u);
         if (!du) {
             if (zu == yu) du = true;  // only roots point at themselves
-            else store_relaxed(qu + x, zu), yu = zu;
+            else store_relaxed(qu + x, zu), yu = zu, ++acc;
         }
         if (!dd) {
             if (zd == yd) dd = true;
-            else store_relaxed(qd + x, zd), yd = zd;
+            else store_relaxed(qd + x, zd), yd = zd, ++acc;
         }
         if (du && dd) {
             ru = yu;
@@ -937,9 +974,10 @@ __device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, 
 // the labels of the tile and of every tile holding a mesh neighbour of the
 // vertex (the only tiles whose exits can land on it) may have changed, and
 // tile_lab flags them.
+// acc counts the 4-byte words the walks and the root records move.
 template <int NDIM>
 __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __restrict__ q_up,
-                                              int* __restrict__ q_dn, int* root_up = nullptr,
+                                              int* __restrict__ q_dn, unsigned& acc, int* root_up = nullptr,
                                               int* root_dn = nullptr, uint8_t* tile_lab = nullptr,
                                               const uint8_t* target = nullptr) {
     using T = LabelTile<NDIM>;
@@ -956,12 +994,14 @@ __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __r
         const int i = x + gr.nx * y + gr.nxy * z;
         if (target && !target[i]) continue;
         int ru, rd;
-        ok = compress_both(q_up, q_dn, i, ru, rd) && ok;
+        ok = compress_both(q_up, q_dn, i, ru, rd, acc) && ok;
         if (!root_up) continue;
         const long e = static_cast<long>(tile) * FC + b;
+        acc += 2;
         if (root_up[e] == ru && root_dn[e] == rd) continue;
         root_up[e] = ru;
         root_dn[e] = rd;
+        acc += 2;
         // tiles across the faces this vertex lies on, and the tile itself
         const int ex0 = l.x == 0 ? -1 : 0, ex1 = l.x == T::X - 1 ? 1 : 0;
         const int ey0 = l.y == 0 ? -1 : 0, ey1 = l.y == T::Y - 1 ? 1 : 0;
@@ -981,7 +1021,8 @@ template <int NDIM>
 __global__ void __launch_bounds__(256) k_label_compress(Grid gr, int* __restrict__ q_up,
                                                         int* __restrict__ q_dn,
                                                         unsigned* __restrict__ cnt) {
-    if (!compress_tile<NDIM>(gr, xcd_logical_block(blockIdx.x, gridDim.x), q_up, q_dn))
+    unsigned acc = 0;
+    if (!compress_tile<NDIM>(gr, xcd_logical_block(blockIdx.x, gridDim.x), q_up, q_dn, acc))
         atomicOr(cnt + kCntErr, kErrWalk);
 }
 
@@ -1069,10 +1110,11 @@ struct TargetList {
     float* g;
     const float* L;
     uint8_t* dirty;
+    bool preempt;  // edits without claims (preemptive mode)
     template <int NDIM>
     __device__ __forceinline__ void put(const Grid& gr, unsigned k, int t, unsigned& changed) const {
         if (k < static_cast<unsigned>(kCap)) list[k] = t;
-        else claim_edit<NDIM>(marks, g, L, dirty, gr, t, changed);
+        else target_edit<NDIM>(preempt, marks, g, L, dirty, gr, t, changed);
     }
     // Appends each lane's targets (-1: none; nloc of them): one LDS atomic per
     // wave, positions from a prefix sum over the wave.
@@ -1498,9 +1540,55 @@ __device__ __forceinline__ void refresh_vertex(const EngField& F, int j, unsigne
     for (int t = 0; t < 4; ++t) c[t] += ((now >> t) & 1u) - ((was >> t) & 1u);
 }
 
+// ----------------------------------------------------- byte accounting ---
+// With profiling on, every step reports the algorithmic bytes of the units
+// its blocks visited (per unit, the compulsory reads and writes of the
+// operation; halo and cache re-reads are not counted):
+//   validate 16 B per vertex (20 with a warm start), directions of f 5,
+//   full direction and case pass over g 9, label tile 9 per vertex of a
+//   relabelled tile plus 10 per saved face vertex (16 per restored one of an
+//   unchanged tile), labels of f 24, troublemakers 26 per vertex of a visited
+//   tile, deltas 16; an apply or refresh 1 per scanned flag byte, plus 16 per
+//   edit attempt and 1 per neighbour flagged after a change (apply) or 9 per
+//   recomputed vertex and 32 per cleared flag word (refresh); the compression
+//   4 per pointer load or store of its walks and root records.
+
+// Vertices of the direction work items [lo, hi) of F.
+template <int NDIM>
+__device__ __forceinline__ long long dirs_vertices(const EngField& F, int lo, int hi) {
+    const DirsVariant v = variant_of(NDIM, F.variant);
+    const Grid& gr = F.gr;
+    const int tx = (gr.nx + kTileX - 1) / kTileX, ty = (gr.ny + v.ty - 1) / v.ty;
+    const int zc = NDIM == 3 ? v.zc : 1;
+    long long n = 0;
+    for (int it = lo; it < hi; ++it) {
+        const int x0 = (it % tx) * kTileX, y0 = ((it / tx) % ty) * v.ty, z0 = NDIM == 3 ? (it / (tx * ty)) * zc : 0;
+        n += static_cast<long long>(min(kTileX, gr.nx - x0)) * min(v.ty, gr.ny - y0) * (NDIM == 3 ? min(zc, gr.nz - z0) : 1);
+    }
+    return n;
+}
+
+// Vertices of label tile t.
+template <int NDIM>
+__device__ __forceinline__ long long tile_vertices(const Grid& gr, int t) {
+    using T = LabelTile<NDIM>;
+    const int3 o = tile_origin<NDIM>(gr, t);
+    return static_cast<long long>(min(T::X, gr.nx - o.x)) * min(T::Y, gr.ny - o.y) * min(T::Z, gr.nz - o.z);
+}
+
+// Vertices of the chunks [lo, hi).
+__device__ __forceinline__ long long chunk_vertices(const Grid& gr, int lo, int hi) {
+    const long long a = static_cast<long long>(lo) * kEngChunk;
+    const long long b = min(static_cast<long long>(hi) * kEngChunk, static_cast<long long>(gr.n));
+    return b > a ? b - a : 0;
+}
+
+// acct: this thread's share of the algorithmic bytes of the range (see above).
 template <int NDIM>
 __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem,
-                                              unsigned* cnt) {
+                                              unsigned* cnt, unsigned long long& acct) {
+    constexpr int NS = NDIM == 3 ? 14 : 6;
+    const bool lead = threadIdx.x == 0;  // adds the bytes that are fixed per range
     const Grid& gr = F.gr;
     int* su = reinterpret_cast<int*>(smem);
     int* sd = su + 4096;
@@ -1516,33 +1604,40 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                     if (w < ng) validate_group(F.f, F.fhat, F.warm, F.xi, gr.n, F.L, F.g, w, bad);
                 }
             if (bad) atomicOr(cnt + kCntErr, bad);
+            if (lead) acct += (F.warm ? 20 : 16) * chunk_vertices(gr, lo, hi);
             break;
         }
         case kOpPreA2: {
             unsigned c[4] = {0u, 0u, 0u, 0u};
             eng_dirs<NDIM, 0>(F, F.f, F.dirs_f, lo, hi, sm, c);
+            if (lead) acct += 5 * dirs_vertices<NDIM>(F, lo, hi);
             break;
         }
         case kOpPreB:
             for (int item = lo; item < hi; ++item) {
                 label_tile_body<NDIM>(F.dirs_f, gr, item, F.qu, F.qd, su, sd);
                 __syncthreads();
+                if (lead) acct += 9 * tile_vertices<NDIM>(gr, item);
             }
             break;
         case kOpRTile:
             // only tiles with a changed direction are redone; the others get
             // their face-layer pointers back
             for (int item = lo; item < hi; ++item) {
+                unsigned nface = 0;
                 if (F.tile_dirty[item]) {
                     label_tile_body<NDIM>(F.dirs_g, gr, item, F.qu, F.qd, su, sd);
                     __syncthreads();
-                    save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn, F.target);
+                    save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn, F.target, nface);
                     if (threadIdx.x == 0) {
                         F.tile_dirty[item] = 0;
                         F.tile_lab[item] = 1;  // its own pointers changed
+                        acct += 9 * tile_vertices<NDIM>(gr, item);
                     }
+                    acct += 10ull * nface;
                 } else {
-                    restore_faces<NDIM>(gr, item, F.qu, F.qd, F.qf_up, F.qf_dn);
+                    restore_faces<NDIM>(gr, item, F.qu, F.qd, F.qf_up, F.qf_dn, nface);
+                    acct += 16ull * nface;
                 }
                 __syncthreads();
             }
@@ -1550,35 +1645,47 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
         case kOpPreC:
         case kOpRJump: {
             bool ok = true;
+            unsigned words = 0;
             const bool g_pass = st.op == kOpRJump;  // the forests of g: track root changes
             for (int item = lo; item < hi; ++item)
-                ok = compress_tile<NDIM>(gr, item, F.qu, F.qd, g_pass ? F.root_up : nullptr,
+                ok = compress_tile<NDIM>(gr, item, F.qu, F.qd, words, g_pass ? F.root_up : nullptr,
                                          g_pass ? F.root_dn : nullptr, F.tile_lab, g_pass ? F.target : nullptr) && ok;
             if (!ok) atomicOr(cnt + kCntErr, kErrWalk);
+            acct += 4ull * words;
             break;
         }
         case kOpPreD:
-            for (int item = lo; item < hi; ++item) label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf);
+            for (int item = lo; item < hi; ++item) {
+                label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf);
+                if (lead) acct += 24 * tile_vertices<NDIM>(gr, item);
+            }
             break;
         case kOpApplyC: {
             // the targets of the cases of the current type
-            unsigned changed = 0;
+            unsigned changed = 0, tries = 0;
             int* list = reinterpret_cast<int*>(smem);
             const int type = st.type;
+            if (lead) acct += chunk_vertices(gr, lo, hi);  // the case bytes scanned
             if (type == kTypeMerged) {
                 // every case of every type; all targets claimed, so a vertex
-                // proposed by several cases is edited once
+                // proposed by several cases is edited once (or, preemptive,
+                // edited by each case that gets there, racing)
+                const bool pre = F.preempt != 0;
                 for_flagged(
                     F.cases, gr.n, lo, hi, 0x0F0F0F0Fu, list, list + kEngChunk,
                     [&](int i) {
                         const unsigned b = F.cases[i];
-                        if (b & 9u) claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, i, changed);
-                        if (b & 2u) claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_f[i] & 15u],
-                                                     changed);
-                        if (b & 4u) claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_g[i] >> 4],
-                                                     changed);
+                        tries += __popc(b & 0xFu);
+                        if (b & 9u) target_edit<NDIM>(pre, F.marks, F.g, F.L, F.dirty, gr, i, changed);
+                        if (b & 2u)
+                            target_edit<NDIM>(pre, F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_f[i] & 15u],
+                                              changed);
+                        if (b & 4u)
+                            target_edit<NDIM>(pre, F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_g[i] >> 4],
+                                              changed);
                     },
                     [](int) {});
+                acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed;
                 unsigned v[1] = {changed};
                 const int idx[1] = {kCntChanged};
                 block_add<1>(v, cnt, idx);
@@ -1587,6 +1694,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             for_flagged(
                 F.cases, gr.n, lo, hi, 0x01010101u << type, list, list + kEngChunk,
                 [&](int i) {
+                    ++tries;
                     if (type == 0 || type == 3) {
                         edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, i, changed);
                         return;
@@ -1596,6 +1704,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                     claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, t, changed);
                 },
                 [](int) {});
+            acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed;
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
             block_add<1>(v, cnt, idx);
@@ -1607,6 +1716,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             unsigned c[4] = {0u, 0u, 0u, 0u};
             eng_dirs<NDIM, 1>(F, F.g, F.dirs_g, lo, hi, sm, c);
             block_add<4>(c, cnt, cidx);
+            if (lead) acct += 9 * dirs_vertices<NDIM>(F, lo, hi);
             // every label tile is redone next time: this range's share of the flags
             const long long nt = label_tiles_of(gr), items = eng_items(F, st.op);
             for (long long t = lo * nt / items + threadIdx.x; t < hi * nt / items; t += blockDim.x) F.tile_dirty[t] = 1;
@@ -1617,15 +1727,22 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             // directions and cases of the flagged vertices; their flags and
             // marks are cleared
             unsigned c[4] = {0u, 0u, 0u, 0u};
+            unsigned nv = 0, nw = 0;
             int* list = reinterpret_cast<int*>(smem);
             for_flagged(
                 F.dirty, gr.n, lo, hi, 0xFFFFFFFFu, list, list + kEngChunk,
-                [&](int j) { refresh_vertex<NDIM>(F, j, c); },
+                [&](int j) {
+                    refresh_vertex<NDIM>(F, j, c);
+                    ++nv;
+                },
                 [&](int w) {
                     reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
                     reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
+                    ++nw;
                 });
             block_add<4>(c, cnt, cidx);
+            acct += 9ull * nv + 32ull * nw;
+            if (lead) acct += chunk_vertices(gr, lo, hi);
             break;
         }
         case kOpRDetect: {
@@ -1638,12 +1755,15 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             __shared__ unsigned s_targets;
             unsigned wrong = 0, cases = 0, changed = 0;
             const TargetList tl{st.type == 0 ? reinterpret_cast<int*>(smem) : nullptr, &s_targets, F.marks, F.g,
-                                F.L, F.dirty};
+                                F.L, F.dirty, F.preempt != 0};
             // the listed targets, edited by all threads; ends with a barrier
+            unsigned tries = 0;
             auto edit_targets = [&]() {
                 const int nt = min(static_cast<int>(s_targets), TargetList::kCap);
-                for (int e = threadIdx.x; e < nt; e += blockDim.x)
-                    claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, tl.list[e], changed);
+                for (int e = threadIdx.x; e < nt; e += blockDim.x) {
+                    target_edit<NDIM>(tl.preempt, F.marks, F.g, F.L, F.dirty, gr, tl.list[e], changed);
+                    ++tries;
+                }
                 __syncthreads();
             };
             if (threadIdx.x == 0) s_targets = 0;
@@ -1653,6 +1773,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 const unsigned before = wrong;
                 detect_r_tile<NDIM, 1>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, tl, wrong, cases,
                                        changed);
+                if (lead) acct += 26 * tile_vertices<NDIM>(gr, item);
                 const int any = __syncthreads_or(wrong != before);
                 if (threadIdx.x == 0) {
                     F.tile_wrong[item] = any ? 1 : 0;
@@ -1669,6 +1790,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 __syncthreads();
                 edit_targets();
             }
+            acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed;
             unsigned v[3] = {wrong, cases, changed};
             const int idx[3] = {kCntWrong, kCntRCases, kCntChanged};
             block_add<3>(v, cnt, idx);
@@ -1682,6 +1804,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                     const int w = item * (kEngChunk / 4) + threadIdx.x + 256 * k;
                     if (w < ng) delta_group(F.g, F.fhat, gr.n, F.edits, F.g_out, w, edited, inexact);
                 }
+            if (lead) acct += 16 * chunk_vertices(gr, lo, hi);
             unsigned v[2] = {edited, inexact};
             const int idx[2] = {kCntEdited, kCntInexact};
             block_add<2>(v, cnt, idx);
@@ -1697,7 +1820,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
 // of the fields' items in this step (fields of the other dimension count 0).
 template <int NDIM>
 __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
-                                              int nf, char* smem) {
+                                              int nf, char* smem, unsigned long long& acct) {
     // The tables were written by the previous kernel of the stream, so plain
     // loads see them; one field needs no search.
     if (nf == 1) {
@@ -1707,7 +1830,7 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
         const int per = (total + nb - 1) / nb;
         const int lo = b * per, hi = min(total, lo + per);
-        if (lo < hi) eng_run_range<NDIM>(fields[0], st, lo, hi, smem, fields[0].cnt);
+        if (lo < hi) eng_run_range<NDIM>(fields[0], st, lo, hi, smem, fields[0].cnt, acct);
         return;
     }
     const int total = pre[nf];
@@ -1726,27 +1849,35 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         const int base = pre[a];
         const int end = min(hi, pre[a + 1]);
         const EngState st = cur[a];
-        eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem, fields[a].cnt);
+        eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem, fields[a].cnt, acct);
         lo = end;
     }
 }
 
-// ts (optional, profiling; kEngStampWords zeroed words): block 0 stores its
-// start in ts[0]; every block raises ts[1 + blockIdx % 64] to its end.  Both
-// come from the constant-rate GPU clock; 64 end slots keep the atomics from
-// queueing on one address.
+// Profiling record of a step (ts: kEngStampWords zeroed words, or NULL): block
+// 0 stores its start in ts[0]; every block raises ts[1 + blockIdx % 64] to its
+// end (64 slots keep the atomics from queueing on one address) and adds the
+// algorithmic bytes it visited to ts[kEngBytesWord] (one atomic per wave).
+// Times come from the constant-rate GPU clock.
+__device__ __forceinline__ void stamp_end(unsigned long long* ts, unsigned long long acct) {
+    unsigned long long b = acct;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(ts + kEngBytesWord, b);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(ts + 1 + blockIdx.x % kEngEndSlots, static_cast<unsigned long long>(wall_clock64()));
+}
+
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
                                                   const int* pre, int nf, unsigned long long* ts) {
     __shared__ __align__(16) char smem[kEngSmemBytes];
     static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
     if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = static_cast<unsigned long long>(wall_clock64());
-    eng_step_body<NDIM>(fields, cur, pre, nf, smem);
-    if (ts) {
-        __syncthreads();
-        if (threadIdx.x == 0)
-            atomicMax(ts + 1 + blockIdx.x % (kEngStampWords - 1), static_cast<unsigned long long>(wall_clock64()));
-    }
+    unsigned long long acct = 0;
+    eng_step_body<NDIM>(fields, cur, pre, nf, smem, acct);
+    if (ts) stamp_end(ts, acct);
 }
 
 // The schedule (the host loop of a single correction, step by step): the next
@@ -1891,8 +2022,9 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
 // (kSlots slots of kCntSlots counters, at cnt_all + f * kCntBlockWords), clear
 // it, and thread 0 writes the next state.  Every load (state, counters,
 // statistics) is issued before any is used, so a decision costs one memory
-// round trip.  With one field it also writes the next prefix sums, the
-// active count and, if oplog is set, the operation this step ran.
+// round trip.  With one field it also writes the next prefix sums and the
+// active count; if oplog is set, oplog[step * nf + f] receives the operation
+// field f ran in this step.
 __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__ fields, const EngState* cur,
                                                     EngState* nxt, EngStats* stats, int nf, int* pre2, int* pre3,
                                                     int* ctl, int* oplog, int step, unsigned* cnt_all) {
@@ -1909,7 +2041,7 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
     const EngState st = cur[f];
     EngStats S;
     if (threadIdx.x == 0) S = stats[f];
-    if (nf == 1 && oplog && threadIdx.x == 0) oplog[step] = st.items > 0 ? st.op : kOpDone;
+    if (oplog && threadIdx.x == 0) oplog[step * nf + f] = st.items > 0 ? st.op : kOpDone;
     EngState ns = st;
     if (st.items > 0) {
         unsigned acc = 0;
@@ -2038,17 +2170,14 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < kCntBlockWords; w += gridDim.x * blockDim.x) c_next[w] = 0u;
     __syncthreads();
     const EngState st = s_next;
+    unsigned long long acct = 0;
     if (st.items > 0) {
         const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
         const int per = (st.items + nb - 1) / nb;
         const int lo = b * per, hi = min(st.items, lo + per);
-        if (lo < hi) eng_run_range<NDIM>(F, st, lo, hi, smem, c_cur);
+        if (lo < hi) eng_run_range<NDIM>(F, st, lo, hi, smem, c_cur, acct);
     }
-    if (ts) {
-        __syncthreads();
-        if (threadIdx.x == 0)
-            atomicMax(ts + 1 + blockIdx.x % (kEngStampWords - 1), static_cast<unsigned long long>(wall_clock64()));
-    }
+    if (ts) stamp_end(ts, acct);
 }
 
 // Prefix sums of the next step's items per dimension, and the active count
