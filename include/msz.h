@@ -75,10 +75,10 @@ enum {
     MSZ_PHASE_DIRS_DETECT = 2,  /* directions and case bytes of every vertex of g */
     MSZ_PHASE_REFRESH = 3,      /* directions and case bytes around the last edits */
     MSZ_PHASE_APPLY = 4,        /* halving of a C round's targets (from the case bytes) */
-    MSZ_PHASE_LABEL_TILE = 5,   /* in-LDS pointer jumping per tile */
-    MSZ_PHASE_LABEL_JUMP = 6,   /* pointer compression of tile-face vertices */
+    MSZ_PHASE_LABEL_TILE = 5,   /* in-LDS pointer jumping per changed tile */
+    MSZ_PHASE_LABEL_JUMP = 6,   /* (unused: the loop's labels follow the tiles' exit chains) */
     MSZ_PHASE_LABEL_FINAL = 7,  /* labels of f */
-    MSZ_PHASE_DETECT_R = 8,     /* troublemaker detection and the halving of their targets */
+    MSZ_PHASE_DETECT_R = 8,     /* labels of g along the exit chains, troublemakers and the halving of their targets */
     MSZ_PHASE_DELTA = 9,        /* output deltas */
     MSZ_PHASE_NET = 10,         /* learned warm start: features, 3 conv layers, g0 */
     MSZ_N_PHASES = 11
@@ -197,9 +197,9 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
  *  - opt->workspace must be NULL and opt->workspace_bytes 0, and
  *    MSZ_FLAG_TIMING is not accepted (MSZ_EINVAL);
  *  - a field whose workspace plus the control block exceeds the array
- *    returns MSZ_ETOOBIG before any device work.  The limit admits, e.g., a
- *    128^3 field or a 1700 x 1700 one (the workspace takes about 35 bytes
- *    per vertex in 3D, 31 in 2D: msz_workspace_bytes);
+ *    returns MSZ_ETOOBIG before any device work.  The limit admits fields of
+ *    up to about 3.4e6 vertices, e.g. 150^3 or 1850 x 1850 (the workspace
+ *    takes 29 bytes per vertex: msz_workspace_bytes);
  *  - every call on a device shares that device's array, and a call leaves
  *    its contents behind (each call clears what it needs cleared).  Calls
  *    that overlap on one device, from several host threads or streams,

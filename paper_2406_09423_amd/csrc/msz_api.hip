@@ -66,13 +66,11 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, target, tile_dirty, tile_lab, tile_wrong, Mf, mf, qu, qd, qf_up, qf_dn,
-        root_up, root_dn, total;
+    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, tile_dirty, Mf, mf, qu, qd, total;
 };
 
 Layout layout_for(const Grid& gr) {
     const int64_t n = gr.n;
-    const int64_t faces = label_face_words(gr);
     Layout l{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -87,18 +85,11 @@ Layout layout_for(const Grid& gr) {
     l.marks = take((n + 15) & ~int64_t(15));
     l.cases = take((n + 15) & ~int64_t(15));
     l.dirty = take((n + 15) & ~int64_t(15));
-    l.target = take((n + 15) & ~int64_t(15));
     l.tile_dirty = take(label_tile_count(gr));
-    l.tile_lab = take(label_tile_count(gr));
-    l.tile_wrong = take(label_tile_count(gr));
     l.Mf = take(n * 4);
     l.mf = take(n * 4);
     l.qu = take(n * 4);
     l.qd = take(n * 4);
-    l.qf_up = take(faces * 4);
-    l.qf_dn = take(faces * 4);
-    l.root_up = take(faces * 4);
-    l.root_dn = take(faces * 4);
     l.total = o;
     return l;
 }
@@ -353,7 +344,6 @@ int phase_of_op(int op) {
         case kOpPreA: return MSZ_PHASE_VALIDATE;
         case kOpPreA2: return MSZ_PHASE_DIRS;
         case kOpPreB: case kOpRTile: return MSZ_PHASE_LABEL_TILE;
-        case kOpPreC: case kOpRJump: return MSZ_PHASE_LABEL_JUMP;
         case kOpPreD: return MSZ_PHASE_LABEL_FINAL;
         case kOpApplyC: return MSZ_PHASE_APPLY;
         case kOpPreE: case kOpFullC: case kOpFullR: return MSZ_PHASE_DIRS_DETECT;
@@ -565,13 +555,6 @@ void bind_field(EngField& F, char* w) {
     F.cases = reinterpret_cast<uint8_t*>(w + l.cases);
     F.dirty = reinterpret_cast<uint8_t*>(w + l.dirty);
     F.tile_dirty = reinterpret_cast<uint8_t*>(w + l.tile_dirty);
-    F.qf_up = reinterpret_cast<int*>(w + l.qf_up);
-    F.qf_dn = reinterpret_cast<int*>(w + l.qf_dn);
-    F.root_up = reinterpret_cast<int*>(w + l.root_up);
-    F.root_dn = reinterpret_cast<int*>(w + l.root_dn);
-    F.tile_lab = reinterpret_cast<uint8_t*>(w + l.tile_lab);
-    F.tile_wrong = reinterpret_cast<uint8_t*>(w + l.tile_wrong);
-    F.target = reinterpret_cast<uint8_t*>(w + l.target);
     F.Mf = reinterpret_cast<int*>(w + l.Mf);
     F.mf = reinterpret_cast<int*>(w + l.mf);
     F.qu = reinterpret_cast<int*>(w + l.qu);
@@ -927,7 +910,7 @@ int msz_labels(const float* field, msz_dims d, int32_t* max_label, int32_t* min_
     launch_check_finite(field, gr.n, cnt, s);
     launch_dirs(field, gr, 0, dirs, s);
     launch_label_forests(dirs, gr, max_label, min_label, cnt, s);
-    launch_label_final(max_label, min_label, gr, max_label, min_label, s);
+    launch_label_final(max_label, min_label, gr, max_label, min_label, cnt, s);
     if (int rc = read_counters(cnt, hc, s)) return rc;
     if (hc[kCntErr] & kErrWalk) return MSZ_EDEVICE;
     return hc[kCntErr] ? MSZ_ENONFINITE : MSZ_OK;

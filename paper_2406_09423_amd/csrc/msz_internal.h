@@ -117,7 +117,8 @@ void launch_label_tile(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn
 void launch_label_compress(const Grid& gr, int* q_up, int* q_dn, unsigned* cnt, hipStream_t s);
 void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q_dn, unsigned* cnt,
                           hipStream_t s);
-void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, hipStream_t s);
+void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, unsigned* cnt,
+                        hipStream_t s);
 void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu, const int* qfd,
                     const int* qgu, const int* qgd, int n, unsigned* cnt, hipStream_t s);
 
@@ -141,15 +142,13 @@ enum EngOp : int {
     kOpPreA = 0,   // validation, floors, start field
     kOpPreA2,      // directions of f
     kOpPreB,       // label tiles of f
-    kOpPreC,       // compression of f's tile faces
-    kOpPreD,       // labels of f
+    kOpPreD,       // labels of f (following the exit chains)
     kOpPreE,       // directions of g and the case bytes of every vertex
     kOpApplyC,     // C-loop apply: the targets of every case of the current type
     kOpRefreshC,   // directions and cases of the vertices around the last C edits
     kOpFullC,      // the same for every vertex (after an apply that changed many)
-    kOpRTile,      // label tiles of g
-    kOpRJump,      // compression of g's tile faces
-    kOpRDetect,    // troublemakers, and the edits of their targets
+    kOpRTile,      // label tiles of g (the changed ones)
+    kOpRDetect,    // troublemakers (labels by following the exit chains), and the edits of their targets
     kOpRefreshR,   // directions and cases of the vertices around the last R edits
     kOpFullR,      // the same for every vertex
     kOpDelta,      // output
@@ -177,11 +176,6 @@ struct EngField {
     uint8_t *dirty;  // per vertex: its directions in g must be recomputed (it or a neighbour was edited)
     uint8_t *tile_dirty;  // per label tile: a direction of g in it changed since its last tile pass
     int *Mf, *mf, *qu, *qd;
-    int *qf_up, *qf_dn;   // per label tile and face-layer vertex: the tile pass's pointer (before compression)
-    int *root_up, *root_dn;  // per label tile and face-layer vertex: its roots after the last compression
-    uint8_t *tile_lab;    // per label tile: labels of g in it may have changed since its last troublemaker pass
-    uint8_t *tile_wrong;  // per label tile: its last troublemaker pass found a mislabelled vertex
-    uint8_t *target;      // per vertex: some tile pass of g made it a tile's exit (or extremum)
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
 
@@ -199,7 +193,6 @@ struct EngStats {
 // Number of work items of operation op for one field (device and host).
 int eng_items_host(const EngField& F, int op);
 int label_tile_count(const Grid& gr);   // label tiles of the grid
-int label_face_words(const Grid& gr);   // label tiles x face-layer vertices of a full tile
 const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)
 const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre2, pre3, ctl, hflag)

@@ -7,15 +7,12 @@
 //   marks          uint8[n]   claims of the targets edited in the current round (an
 //                             edit shared by several cases is made once; padded to 16 B)
 //   dirty          uint8[n]   directions to recompute after an apply (padded to 16 B)
-//   target         uint8[n]   face-layer vertices that some tile pass of g made an exit
 //   M_f, m_f       int32[n]   labels of f (max, min)
-//   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests
-//   qf_up, qf_dn   int32      per label tile and face-layer vertex, its tile-pass pointer
-//   root_up/_dn    int32      per label tile and face-layer vertex, its roots at the last
-//                             compression
-//   tile_dirty, tile_lab, tile_wrong
-//                  uint8      per label tile: a direction of g changed; its labels may
-//                             have changed; its last troublemaker pass found a wrong label
+//   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests: a
+//                             root (extremum) id as itself (>= 0), an exit of the vertex's
+//                             label tile, a vertex e of the next tile on its line, as -e-1
+//   tile_dirty     uint8      per label tile: a direction of g in it changed since its
+//                             last tile pass
 //   cnt            uint32[kSlots][kSlotStride] round counters; block b adds into slot
 //                  b % kSlots so that no cache line takes more than a few hundred
 //                  atomics per launch
@@ -643,12 +640,16 @@ __device__ __forceinline__ void target_edit(bool preempt, uint8_t* __restrict__ 
 //
 // Pointer jumping along the forests of steepest ascent and descent (Sec. 6.2).
 // Stage 1 resolves each 4096-vertex tile inside LDS: every vertex ends up
-// pointing at either the extremum it reaches inside its tile or the first
-// vertex outside the tile on its integral line.  Such exit targets lie on the
-// face layer of their own tile, so stage 2 only has to compress pointers of
-// face-layer vertices (each thread walks its own chain, writing back every
-// step; any value read is an ancestor, so no barrier is needed and each walk
-// strictly advances).  Afterwards label(i) = q[q[i]].
+// pointing at either the extremum it reaches inside its tile (stored as its
+// id) or the first vertex e outside the tile on its integral line (stored as
+// -e-1).  Such exit targets lie on the face layer of their own tile.  A label
+// is then the end of a short chain of exits (on the fields here a tile exit
+// leads on through another tile a quarter of the time): follow_root walks it.
+// The correction loop follows the chains where it needs labels (a few
+// gathers per hundred vertices).  msz_labels and msz_count_false first
+// compress the exit targets' pointers to their roots (each thread walks its
+// own chain, writing back every step; any value read is an ancestor, so no
+// barrier is needed and each walk strictly advances).
 
 template <int NDIM>
 struct LabelTile;
@@ -670,12 +671,60 @@ __host__ __device__ __forceinline__ int label_tiles_of(const Grid& gr) {
     return ((gr.nx + T::X - 1) / T::X) * ((gr.ny + T::Y - 1) / T::Y) * ((gr.nz + T::Z - 1) / T::Z);
 }
 
+// The stored pointer of a tile-pass terminal a (tile origin X0, Y0, Z0): an
+// exit code -e-1 as it is, an extremum's local code as its global id.  (A
+// non-negative a, a local index, cannot remain after the jumping; it would
+// name an in-tile ancestor.)
+template <int NDIM>
+__device__ __forceinline__ int tile_term_global(const Grid& gr, int X0, int Y0, int Z0, int a) {
+    using T = LabelTile<NDIM>;
+    if (a < 0 && a >= -gr.n) return a;
+    const int l = a < 0 ? -a - 1 - gr.n : a;
+    return X0 + l % T::X + gr.nx * (Y0 + (l / T::X) % T::Y) + gr.nxy * (Z0 + l / (T::X * T::Y));
+}
+
+// Follows K chains of exits from stored pointers y[k] to their roots, one
+// level per pass, so that the gathers of a pass are in flight together (y[k]
+// in q_up when k is even, in q_dn when odd; entries already >= 0 stay).
+// Every chain of the forest ends at an extremum within finitely many tiles.
+// hops counts the gathers; the pass cap only guards against corrupted input
+// and sets bad.
+constexpr int kMaxChain = 1 << 20;
+
+template <int K>
+__device__ __forceinline__ void follow_roots(const int* q_up, const int* q_dn, int (&y)[K], unsigned& bad,
+                                             unsigned& hops) {
+    for (int pass = 0;; ++pass) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) any |= y[k] < 0;
+        if (!any) return;
+        if (pass == kMaxChain) {
+            bad = kErrWalk;
+#pragma unroll
+            for (int k = 0; k < K; ++k) y[k] = max(y[k], 0);
+            return;
+        }
+        // unconditional loads (a finished chain reads entry 0, one line for
+        // the whole wave), so that all K are issued before the first wait
+        int z[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) z[k] = ((k & 1) ? q_dn : q_up)[y[k] < 0 ? -y[k] - 1 : 0];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            hops += y[k] < 0;
+            y[k] = y[k] < 0 ? z[k] : y[k];
+        }
+    }
+}
+
 // One label tile; su, sd: LDS arrays of the tile's vertex count.  The caller
 // separates consecutive tiles of one block with a barrier.
 //
 // Thread t owns the 4-vertex row groups starting at l = 4 t + 1024 k and
 // keeps their pointers in registers; the LDS copy is what other threads read.
-// Terminal pointers are stored as -(global id) - 1.
+// Terminal pointers are negative: an exit e as -e-1 (in -n .. -1), an in-tile
+// extremum with local index l as -(n + l) - 1 (below -n; n + 4096 < 2^31).
 template <int NDIM>
 __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs, const Grid& gr, int tile,
                                                 int* __restrict__ q_up, int* __restrict__ q_dn, int* su, int* sd) {
@@ -727,7 +776,7 @@ __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs
                 for (int w = 0; w < 2; ++w) {
                     const unsigned s = s2[w];
                     if (s == kSelf) {
-                        p[w] = -i - 1;
+                        p[w] = -(gr.n + lx + T::X * (ly + T::Y * lz)) - 1;
                     } else {
                         int dx, dy, dz;
                         slot_delta(s, dx, dy, dz);
@@ -782,11 +831,8 @@ __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs
         if (!pending) break;
     }
     // Every in-tile path is shorter than the tile, so all pointers are terminal
-    // here; a non-terminal one would still name an in-grid ancestor.
-    auto global_of = [&](int a) {
-        return a < 0 ? -a - 1
-                     : X0 + a % T::X + gr.nx * (Y0 + (a / T::X) % T::Y) + gr.nxy * (Z0 + a / (T::X * T::Y));
-    };
+    // here: an exit keeps its code, an extremum becomes its id.
+    auto global_of = [&](int a) { return tile_term_global<NDIM>(gr, X0, Y0, Z0, a); };
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         const int l0 = 4 * threadIdx.x + 1024 * k;
@@ -852,7 +898,6 @@ __device__ __forceinline__ int3 face_vertex(int b) {
 }
 
 int label_tile_count(const Grid& gr) { return label_tiles_of(gr); }
-int label_face_words(const Grid& gr) { return label_tiles_of(gr) * (gr.ndim == 3 ? face_count<3>() : face_count<2>()); }
 
 // Origin of a label tile.
 template <int NDIM>
@@ -869,54 +914,6 @@ __device__ __forceinline__ int tile_of_vertex(const Grid& gr, int i) {
     const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y;
     const int x = i % gr.nx, y = (i / gr.nx) % gr.ny, z = NDIM == 3 ? i / gr.nxy : 0;
     return x / T::X + tx_n * (y / T::Y + ty_n * (z / T::Z));
-}
-
-// After a tile pass of g (su, sd still hold the tile's final local pointers,
-// after a barrier): keeps the face-layer vertices' pointers, which the
-// compression then overwrites, so that a later pass over an unchanged tile
-// only has to put them back, and flags their targets.  Every exit of the tile
-// (the first vertex outside it on some integral line) is the target of one of
-// its face-layer vertices (the last vertex of that line inside the tile), so
-// the flagged vertices are all the compression of g has to resolve.
-template <int NDIM>
-__device__ __forceinline__ void save_faces(const Grid& gr, int tile, const int* su, const int* sd, int* qf_up,
-                                           int* qf_dn, uint8_t* target, unsigned& nface) {
-    using T = LabelTile<NDIM>;
-    constexpr int FC = face_count<NDIM>();
-    const int3 o = tile_origin<NDIM>(gr, tile);
-    auto global_of = [&](int a) {
-        return a < 0 ? -a - 1 : o.x + a % T::X + gr.nx * (o.y + (a / T::X) % T::Y) + gr.nxy * (o.z + a / (T::X * T::Y));
-    };
-    for (int b = threadIdx.x; b < FC; b += blockDim.x) {
-        const int3 l = face_vertex<NDIM>(b);
-        if (o.x + l.x >= gr.nx || o.y + l.y >= gr.ny || o.z + l.z >= gr.nz) continue;
-        const int a = l.x + T::X * (l.y + T::Y * l.z);
-        const int tu = global_of(su[a]), td = global_of(sd[a]);
-        qf_up[tile * FC + b] = tu;
-        qf_dn[tile * FC + b] = td;
-        target[tu] = 1;
-        target[td] = 1;
-        ++nface;
-    }
-}
-
-// The tile pass of an unchanged tile: its interior pointers are still those
-// of its last pass (the compression only writes face-layer vertices), so only
-// the face-layer pointers are put back.
-template <int NDIM>
-__device__ __forceinline__ void restore_faces(const Grid& gr, int tile, int* q_up, int* q_dn, const int* qf_up,
-                                              const int* qf_dn, unsigned& nface) {
-    constexpr int FC = face_count<NDIM>();
-    const int3 o = tile_origin<NDIM>(gr, tile);
-    for (int b = threadIdx.x; b < FC; b += blockDim.x) {
-        const int3 l = face_vertex<NDIM>(b);
-        const int x = o.x + l.x, y = o.y + l.y, z = o.z + l.z;
-        if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
-        const int i = x + gr.nx * y + gr.nxy * z;
-        q_up[i] = qf_up[tile * FC + b];
-        q_dn[i] = qf_dn[tile * FC + b];
-        ++nface;
-    }
 }
 
 // Pointer loads and stores of the compression walks.  Every value a walk can
@@ -941,78 +938,37 @@ __device__ __forceinline__ void store_relaxed(int* p, int v) {
 constexpr int kMaxWalk = 1 << 22;
 __device__ __forceinline__ bool compress_both(int* qu, int* qd, int x, int& ru, int& rd, unsigned& acc) {
     int yu = load_relaxed(qu + x), yd = load_relaxed(qd + x);
-    ru = yu;
-    rd = yd;
     acc += 2;
-    bool du = false, dd = false;
     for (int it = 0; it < kMaxWalk; ++it) {
-        const int zu = du ? yu : load_relaxed(qu + yu);
-        const int zd = dd ? yd : load_relaxed(qd + yd);
-        acc += (du ? 0u : 1u) + (dd ? 0u : 1u);
-        if (!du) {
-            if (zu == yu) du = true;  // only roots point at themselves
-            else store_relaxed(qu + x, zu), yu = zu, ++acc;
-        }
-        if (!dd) {
-            if (zd == yd) dd = true;
-            else store_relaxed(qd + x, zd), yd = zd, ++acc;
-        }
-        if (du && dd) {
+        if (yu >= 0 && yd >= 0) {  // both roots
             ru = yu;
             rd = yd;
             return true;
         }
+        const int zu = yu >= 0 ? yu : load_relaxed(qu - yu - 1);
+        const int zd = yd >= 0 ? yd : load_relaxed(qd - yd - 1);
+        acc += (yu < 0 ? 2u : 0u) + (yd < 0 ? 2u : 0u);
+        if (yu < 0) store_relaxed(qu + x, zu), yu = zu;
+        if (yd < 0) store_relaxed(qd + x, zd), yd = zd;
     }
     return false;
 }
 
-// Compresses the pointers of one tile's face-layer vertices (with target set,
-// only the flagged ones: a label is q[q[i]], so only the vertices some
-// pointer can name need their roots); false if a walk hit its cap.  With
-// root_up set (the tile passes of g), each compressed face vertex's
-// roots are compared with those of the last compression: if either changed,
-// the labels of the tile and of every tile holding a mesh neighbour of the
-// vertex (the only tiles whose exits can land on it) may have changed, and
-// tile_lab flags them.
-// acc counts the 4-byte words the walks and the root records move.
+// Compresses the pointers of one tile's face-layer vertices to their roots
+// (every exit target is one of them); false if a walk hit its cap.
+// acc counts the 4-byte words the walks move.
 template <int NDIM>
 __device__ __forceinline__ bool compress_tile(const Grid& gr, int tile, int* __restrict__ q_up,
-                                              int* __restrict__ q_dn, unsigned& acc, int* root_up = nullptr,
-                                              int* root_dn = nullptr, uint8_t* tile_lab = nullptr,
-                                              const uint8_t* target = nullptr) {
-    using T = LabelTile<NDIM>;
+                                              int* __restrict__ q_dn, unsigned& acc) {
     constexpr int FC = face_count<NDIM>();
-    const int tx_n = (gr.nx + T::X - 1) / T::X;
-    const int ty_n = (gr.ny + T::Y - 1) / T::Y;
-    const int tz_n = (gr.nz + T::Z - 1) / T::Z;
-    const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
+    const int3 o = tile_origin<NDIM>(gr, tile);
     bool ok = true;
     for (int b = threadIdx.x; b < FC; b += blockDim.x) {
         const int3 l = face_vertex<NDIM>(b);
-        const int x = bx * T::X + l.x, y = by * T::Y + l.y, z = bz * T::Z + l.z;
+        const int x = o.x + l.x, y = o.y + l.y, z = o.z + l.z;
         if (x >= gr.nx || y >= gr.ny || z >= gr.nz) continue;
-        const int i = x + gr.nx * y + gr.nxy * z;
-        if (target && !target[i]) continue;
         int ru, rd;
-        ok = compress_both(q_up, q_dn, i, ru, rd, acc) && ok;
-        if (!root_up) continue;
-        const long e = static_cast<long>(tile) * FC + b;
-        acc += 2;
-        if (root_up[e] == ru && root_dn[e] == rd) continue;
-        root_up[e] = ru;
-        root_dn[e] = rd;
-        acc += 2;
-        // tiles across the faces this vertex lies on, and the tile itself
-        const int ex0 = l.x == 0 ? -1 : 0, ex1 = l.x == T::X - 1 ? 1 : 0;
-        const int ey0 = l.y == 0 ? -1 : 0, ey1 = l.y == T::Y - 1 ? 1 : 0;
-        const int ez0 = NDIM == 3 && l.z == 0 ? -1 : 0, ez1 = NDIM == 3 && l.z == T::Z - 1 ? 1 : 0;
-        for (int dz = ez0; dz <= ez1; ++dz)
-            for (int dy = ey0; dy <= ey1; ++dy)
-                for (int dx = ex0; dx <= ex1; ++dx) {
-                    const int tx = bx + dx, ty = by + dy, tz = bz + dz;
-                    if (tx < 0 || tx >= tx_n || ty < 0 || ty >= ty_n || tz < 0 || tz >= tz_n) continue;
-                    tile_lab[tx + tx_n * (ty + ty_n * tz)] = 1;
-                }
+        ok = compress_both(q_up, q_dn, x + gr.nx * y + gr.nxy * z, ru, rd, acc) && ok;
     }
     return ok;
 }
@@ -1050,11 +1006,13 @@ __device__ __forceinline__ TileGroup<NDIM> tile_group(const Grid& gr, int tile, 
     return g;
 }
 
-// Writes the final labels label(i) = q[q[i]], tile by tile.  May run in place
-// (M == q_up, m == q_dn): the values it reads are fixed points.
+// Writes the final labels (the root at the end of each vertex's chain), tile
+// by tile; returns kErrWalk if a chain hit the step cap.  May run in place
+// (M == q_up, m == q_dn): a value read is then a pointer along the chain or,
+// once written, its root.
 template <int NDIM>
-__device__ __forceinline__ void label_final_tile(const int* q_up, const int* q_dn, const Grid& gr, int tile, int* M,
-                                                 int* m) {
+__device__ __forceinline__ unsigned label_final_tile(const int* q_up, const int* q_dn, const Grid& gr, int tile,
+                                                     int* M, int* m, unsigned& hops) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
     int a[G][4], b[G][4];
     TileGroup<NDIM> tg[G];
@@ -1072,13 +1030,21 @@ __device__ __forceinline__ void label_final_tile(const int* q_up, const int* q_d
             for (int j = 0; j < tg[k].count; ++j) a[k][j] = q_up[tg[k].i0 + j], b[k][j] = q_dn[tg[k].i0 + j];
         }
     }
+    unsigned bad = 0;
 #pragma unroll
     for (int k = 0; k < G; ++k) {
+        int y[8];  // a group's up and down chains, walked together
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            y[2 * j] = j < tg[k].count ? a[k][j] : 0;
+            y[2 * j + 1] = j < tg[k].count ? b[k][j] : 0;
+        }
+        follow_roots<8>(q_up, q_dn, y, bad, hops);
         int ra[4], rb[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            ra[j] = j < tg[k].count ? q_up[a[k][j]] : 0;
-            rb[j] = j < tg[k].count ? q_dn[b[k][j]] : 0;
+            ra[j] = y[2 * j];
+            rb[j] = y[2 * j + 1];
         }
         if (tg[k].vec) {
             *reinterpret_cast<int4*>(M + tg[k].i0) = make_int4(ra[0], ra[1], ra[2], ra[3]);
@@ -1087,13 +1053,17 @@ __device__ __forceinline__ void label_final_tile(const int* q_up, const int* q_d
             for (int j = 0; j < tg[k].count; ++j) M[tg[k].i0 + j] = ra[j], m[tg[k].i0 + j] = rb[j];
         }
     }
+    return bad;
 }
 
 template <int NDIM>
 __global__ void __launch_bounds__(256) k_label_final(const int* q_up, const int* q_dn, Grid gr, int* M,
-                                                     int* m) {
+                                                     int* m, unsigned* __restrict__ cnt) {
     const ItemRange range = xcd_items(label_tiles_of(gr));
-    for (int tile = range.first; tile < range.hi; tile += range.stride) label_final_tile<NDIM>(q_up, q_dn, gr, tile, M, m);
+    unsigned bad = 0, hops = 0;
+    for (int tile = range.first; tile < range.hi; tile += range.stride)
+        bad |= label_final_tile<NDIM>(q_up, q_dn, gr, tile, M, m, hops);
+    if (bad) atomicOr(cnt + kCntErr, bad);
 }
 
 // LDS of a step kernel: two flag-gather lists of kEngChunk vertices, the
@@ -1148,7 +1118,7 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
                                               const int* __restrict__ Mf, const int* __restrict__ mf, const Grid& gr,
                                               int tile, const TargetList& tl, unsigned& wrong, unsigned& cases,
-                                              unsigned& changed) {
+                                              unsigned& changed, unsigned& bad, unsigned& hops) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
     static_assert(G % GB == 0, "whole batches of groups");
 #pragma unroll 1
@@ -1183,6 +1153,15 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
                 }
             }
         }
+        int y[8 * GB];  // the labels of the batch's vertices: their chains walked together
+#pragma unroll
+        for (int k = 0; k < GB; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                y[8 * k + 2 * j] = j < tg[k].count ? qu[k][j] : 0;
+                y[8 * k + 2 * j + 1] = j < tg[k].count ? qd[k][j] : 0;
+            }
+        follow_roots<8 * GB>(q_up, q_dn, y, bad, hops);
 #pragma unroll
         for (int k = 0; k < GB; ++k) {
             int tn[4], tx[4], nloc = 0;
@@ -1192,8 +1171,8 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
                 if (j >= tg[k].count) continue;
                 const int i = tg[k].i0 + j;
                 const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
-                const bool wM = q_up[qu[k][j]] != Mv[k][j];
-                const bool wm = q_dn[qd[k][j]] != mv[k][j];
+                const bool wM = y[8 * k + 2 * j] != Mv[k][j];
+                const bool wm = y[8 * k + 2 * j + 1] != mv[k][j];
                 wrong += wM || wm;
                 const bool rmin = wm && ((dg & 15u) != (df & 15u));
                 const bool rmax = wM && ((dg >> 4) != (df >> 4));
@@ -1216,20 +1195,25 @@ __global__ void __launch_bounds__(256) k_compare(const uint8_t* __restrict__ dir
                                                  const int* __restrict__ qgd, int n,
                                                  unsigned* __restrict__ cnt) {
     unsigned c[7] = {0, 0, 0, 0, 0, 0, 0};
+    unsigned bad = 0, hops = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const unsigned bits = case_bits(dirs_f[i], dirs_g[i]);
         c[0] += bits & 1u;
         c[1] += (bits >> 1) & 1u;
         c[2] += (bits >> 2) & 1u;
         c[3] += (bits >> 3) & 1u;
-        const bool wM = qgu[qgu[i]] != qfu[qfu[i]];
-        const bool wm = qgd[qgd[i]] != qfd[qfd[i]];
+        int yg[2] = {qgu[i], qgd[i]}, yf[2] = {qfu[i], qfd[i]};
+        follow_roots<2>(qgu, qgd, yg, bad, hops);
+        follow_roots<2>(qfu, qfd, yf, bad, hops);
+        const bool wM = yg[0] != yf[0];
+        const bool wm = yg[1] != yf[1];
         c[4] += wM;
         c[5] += wm;
         c[6] += wM || wm;
     }
     const int idx[7] = {kCntCase + 0, kCntCase + 1, kCntCase + 2, kCntCase + 3,
                         kCntWrongMax, kCntWrongMin, kCntWrong};
+    if (bad) atomicOr(cnt + kCntErr, bad);
     block_add<7>(c, cnt, idx);
 }
 
@@ -1348,11 +1332,12 @@ void launch_label_forests(const uint8_t* dirs, const Grid& gr, int* q_up, int* q
     launch_label_compress(gr, q_up, q_dn, cnt, s);
 }
 
-void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, hipStream_t s) {
+void launch_label_final(const int* q_up, const int* q_dn, const Grid& gr, int* M, int* m, unsigned* cnt,
+                        hipStream_t s) {
     const int nt = label_tiles_of(gr);
     const int nb = nt < kDirsBlocks ? nt : kDirsBlocks;
-    if (gr.ndim == 2) hipLaunchKernelGGL(k_label_final<2>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m);
-    else hipLaunchKernelGGL(k_label_final<3>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m);
+    if (gr.ndim == 2) hipLaunchKernelGGL(k_label_final<2>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m, cnt);
+    else hipLaunchKernelGGL(k_label_final<3>, dim3(nb), dim3(256), 0, s, q_up, q_dn, gr, M, m, cnt);
 }
 
 void launch_compare(const uint8_t* dirs_f, const uint8_t* dirs_g, const int* qfu, const int* qfd,
@@ -1396,7 +1381,7 @@ __host__ __device__ inline int eng_items(const EngField& F, int op) {
     switch (op) {
         case kOpPreA: case kOpApplyC: case kOpRefreshC: case kOpRefreshR: case kOpDelta:
             return chunks;
-        case kOpPreB: case kOpPreC: case kOpPreD: case kOpRTile: case kOpRJump: case kOpRDetect: return tiles;
+        case kOpPreB: case kOpPreD: case kOpRTile: case kOpRDetect: return tiles;
         case kOpPreA2: case kOpPreE: case kOpFullC: case kOpFullR: return dirs;
         default: return 0;
     }
@@ -1547,8 +1532,9 @@ __device__ __forceinline__ void refresh_vertex(const EngField& F, int j, unsigne
 //   validate 16 B per vertex (20 with a warm start), directions of f 5,
 //   full direction and case pass over g 9, label tile 9 per vertex of a
 //   relabelled tile plus 10 per saved face vertex (16 per restored one of an
-//   unchanged tile), labels of f 24, troublemakers 26 per vertex of a visited
-//   tile, deltas 16; an apply or refresh 1 per scanned flag byte, plus 16 per
+//   unchanged tile), labels of f 16 and troublemakers 18 per vertex of a
+//   visited tile, both plus 4 per gather along an exit chain, deltas 16; an
+//   apply or refresh 1 per scanned flag byte, plus 16 per
 //   edit attempt and 1 per neighbour flagged after a change (apply) or 9 per
 //   recomputed vertex and 32 per cleared flag word (refresh); the compression
 //   4 per pointer load or store of its walks and root records.
@@ -1584,7 +1570,10 @@ __device__ __forceinline__ long long chunk_vertices(const Grid& gr, int lo, int 
 }
 
 // acct: this thread's share of the algorithmic bytes of the range (see above).
-template <int NDIM>
+// RGB: 4-vertex groups per thread whose label chains the troublemaker pass
+// walks together (more overlap their gathers; the one-field kernel has the
+// registers for two, the batch kernel for one).
+template <int NDIM, int RGB = 1>
 __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem,
                                               unsigned* cnt, unsigned long long& acct) {
     constexpr int NS = NDIM == 3 ? 14 : 6;
@@ -1621,45 +1610,29 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             }
             break;
         case kOpRTile:
-            // only tiles with a changed direction are redone; the others get
-            // their face-layer pointers back
+            // only tiles with a changed direction are redone: the others'
+            // pointers are still those of their last pass
             for (int item = lo; item < hi; ++item) {
-                unsigned nface = 0;
-                if (F.tile_dirty[item]) {
-                    label_tile_body<NDIM>(F.dirs_g, gr, item, F.qu, F.qd, su, sd);
-                    __syncthreads();
-                    save_faces<NDIM>(gr, item, su, sd, F.qf_up, F.qf_dn, F.target, nface);
-                    if (threadIdx.x == 0) {
-                        F.tile_dirty[item] = 0;
-                        F.tile_lab[item] = 1;  // its own pointers changed
-                        acct += 9 * tile_vertices<NDIM>(gr, item);
-                    }
-                    acct += 10ull * nface;
-                } else {
-                    restore_faces<NDIM>(gr, item, F.qu, F.qd, F.qf_up, F.qf_dn, nface);
-                    acct += 16ull * nface;
-                }
+                if (!F.tile_dirty[item]) continue;
+                label_tile_body<NDIM>(F.dirs_g, gr, item, F.qu, F.qd, su, sd);
                 __syncthreads();
+                if (threadIdx.x == 0) {
+                    F.tile_dirty[item] = 0;
+                    acct += 9 * tile_vertices<NDIM>(gr, item);
+                }
             }
             break;
-        case kOpPreC:
-        case kOpRJump: {
-            bool ok = true;
-            unsigned words = 0;
-            const bool g_pass = st.op == kOpRJump;  // the forests of g: track root changes
-            for (int item = lo; item < hi; ++item)
-                ok = compress_tile<NDIM>(gr, item, F.qu, F.qd, words, g_pass ? F.root_up : nullptr,
-                                         g_pass ? F.root_dn : nullptr, F.tile_lab, g_pass ? F.target : nullptr) && ok;
-            if (!ok) atomicOr(cnt + kCntErr, kErrWalk);
-            acct += 4ull * words;
+        case kOpPreD:
+        {
+            unsigned bad = 0, hops = 0;
+            for (int item = lo; item < hi; ++item) {
+                bad |= label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf, hops);
+                if (lead) acct += 16 * tile_vertices<NDIM>(gr, item);
+            }
+            acct += 4ull * hops;
+            if (bad) atomicOr(cnt + kCntErr, bad);
             break;
         }
-        case kOpPreD:
-            for (int item = lo; item < hi; ++item) {
-                label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf);
-                if (lead) acct += 24 * tile_vertices<NDIM>(gr, item);
-            }
-            break;
         case kOpApplyC: {
             // the targets of the cases of the current type
             unsigned changed = 0, tries = 0;
@@ -1746,8 +1719,8 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             break;
         }
         case kOpRDetect: {
-            // A tile whose labels cannot have changed and that had no
-            // mislabelled vertex last time has none now: skipped.  The
+            // Every tile is visited (its labels follow the exit chains, which
+            // may run through any relabelled tile).  The
             // troublemakers' targets of the block's tiles go to an LDS list
             // and are edited together once it is half full and at the end
             // (type 0; type 1 only counts): detection reads directions and
@@ -1768,17 +1741,12 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             };
             if (threadIdx.x == 0) s_targets = 0;
             __syncthreads();
+            unsigned bad = 0, hops = 0;
             for (int item = lo; item < hi; ++item) {
-                if (!F.tile_lab[item] && !F.tile_wrong[item]) continue;
-                const unsigned before = wrong;
-                detect_r_tile<NDIM, 1>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, tl, wrong, cases,
-                                       changed);
-                if (lead) acct += 26 * tile_vertices<NDIM>(gr, item);
-                const int any = __syncthreads_or(wrong != before);
-                if (threadIdx.x == 0) {
-                    F.tile_wrong[item] = any ? 1 : 0;
-                    F.tile_lab[item] = 0;
-                }
+                detect_r_tile<NDIM, RGB>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, tl, wrong, cases,
+                                         changed, bad, hops);
+                if (lead) acct += 18 * tile_vertices<NDIM>(gr, item);
+                __syncthreads();  // every wave's additions to the list are in s_targets
                 // past half the list: edit what it holds and empty it
                 if (tl.list && s_targets > TargetList::kCap / 2) {
                     edit_targets();
@@ -1790,7 +1758,8 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 __syncthreads();
                 edit_targets();
             }
-            acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed;
+            acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed + 4ull * hops;
+            if (bad) atomicOr(cnt + kCntErr, bad);
             unsigned v[3] = {wrong, cases, changed};
             const int idx[3] = {kCntWrong, kCntRCases, kCntChanged};
             block_add<3>(v, cnt, idx);
@@ -1948,12 +1917,10 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             return go(kOpPreA2);
         case kOpPreA2:
             return go(kOpPreB);
-        case kOpPreB:
-            return go(kOpPreC);
-        case kOpPreC:
-            if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
+        case kOpPreB:  // the labels of f follow the exit chains: no compression
             return go(kOpPreD);
         case kOpPreD:
+            if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
             st.type = 0;
             return go(kOpPreE);
         case kOpPreE:
@@ -1981,13 +1948,11 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             else S->rounds[3] += 1;
             return after_apply(kOpRefreshC, kOpFullC);
         case kOpRTile:
-            return go(kOpRJump);
-        case kOpRJump:
-            if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
             // at the cap, and for the start field's count: detect without editing
             st.type = (st.init || S->rounds_total >= F.cap) ? 1 : 0;
             return go(kOpRDetect);
         case kOpRDetect:
+            if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
             if (st.init) {  // the start field's count; the correction starts now
                 S->mislabel_init = c[kCntWrong];
                 st.init = 0;
@@ -2175,7 +2140,7 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
         const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
         const int per = (st.items + nb - 1) / nb;
         const int lo = b * per, hi = min(st.items, lo + per);
-        if (lo < hi) eng_run_range<NDIM>(F, st, lo, hi, smem, c_cur, acct);
+        if (lo < hi) eng_run_range<NDIM, 2>(F, st, lo, hi, smem, c_cur, acct);
     }
     if (ts) stamp_end(ts, acct);
 }
@@ -2218,9 +2183,9 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
 // Start of a one-field run: the field table entry (passed by value), the
 // states of "step -1" (done) and step 0 (start), the three counter sets, the
 // statistics, the active word, the done word (when it lives in device memory,
-// else NULL: the host raises its own) and the field's marks, case bytes,
-// dirty flags and exit targets -- everything the host would otherwise upload
-// or clear one call at a time.
+// else NULL: the host raises its own) and the field's marks, case bytes and
+// dirty flags -- everything the host would otherwise upload or clear one
+// call at a time.
 __global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* fields, EngState* states,
                                                     EngStats* stats, unsigned* cnt3, int* ctl, int* done_word) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
@@ -2239,11 +2204,10 @@ __global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* 
         reinterpret_cast<uint4*>(F.marks)[w] = make_uint4(0u, 0u, 0u, 0u);
         reinterpret_cast<uint4*>(F.cases)[w] = make_uint4(0u, 0u, 0u, 0u);
         reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
-        reinterpret_cast<uint4*>(F.target)[w] = make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
-// Clears every field's marks, case bytes, dirty flags, exit targets and counter block.
+// Clears every field's marks, case bytes, dirty flags and counter block.
 __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ fields, int nf) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     for (int f = 0; f < nf; ++f) {
@@ -2251,13 +2215,11 @@ __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ f
         uint4* m = reinterpret_cast<uint4*>(F.marks);
         uint4* cs = reinterpret_cast<uint4*>(F.cases);
         uint4* dt = reinterpret_cast<uint4*>(F.dirty);
-        uint4* tg = reinterpret_cast<uint4*>(F.target);
         const int nw = (F.gr.n + 15) >> 4;
         for (int w = tid; w < nw; w += nthr) {
             m[w] = make_uint4(0u, 0u, 0u, 0u);
             cs[w] = make_uint4(0u, 0u, 0u, 0u);
             dt[w] = make_uint4(0u, 0u, 0u, 0u);
-            tg[w] = make_uint4(0u, 0u, 0u, 0u);
         }
         for (int w = tid; w < kCntBlockWords; w += nthr) F.cnt[w] = 0u;
     }

@@ -29,7 +29,7 @@ def _bits(t):
 
 
 # bytes per vertex of the operations that visit every vertex once per launch
-WHOLE_FIELD = {"validate": 16, "dirs": 5, "dirs_detect": 9, "label_final": 24, "delta": 16}
+WHOLE_FIELD = {"validate": 16, "dirs": 5, "dirs_detect": 9, "delta": 16}
 
 
 @pytest.mark.parametrize("shape", [(77, 130), (21, 40, 35)])
@@ -60,6 +60,10 @@ def test_single_field_records(msz, shape):
         if r["phase"] in WHOLE_FIELD:
             assert r["bytes"] == WHOLE_FIELD[r["phase"]] * n, r
             seen.add(r["phase"])
+        elif r["phase"] == "label_final":
+            # 16 per vertex, plus 4 per gather along the exit chains (fewer than
+            # two per vertex on a smooth field)
+            assert 16 * n <= r["bytes"] < 24 * n, r
         else:
             assert r["bytes"] > 0, r
     assert seen == set(WHOLE_FIELD)
@@ -84,5 +88,5 @@ def test_batch_records(msz):
     # every field is validated, its deltas written and its directions of f
     # and g computed at least once: a lower bound on the bytes
     nv = sum(f.numel() for f, _, _ in fields)
-    assert sum(r["bytes"] for r in recs) >= (16 + 5 + 9 + 24 + 16) * nv
+    assert sum(r["bytes"] for r in recs) >= (16 + 5 + 9 + 16 + 16) * nv
     assert sum(r["us"] for r in recs) > 0

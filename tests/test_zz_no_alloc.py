@@ -86,8 +86,8 @@ def test_noalloc_limits_and_arguments(msz):
     or the timing flag: EINVAL."""
     import ctypes
     limit = msz.NOALLOC_SCRATCH_BYTES
-    assert msz.workspace_bytes((144, 144, 144)) > limit
-    f = torch.zeros((144, 144, 144), dtype=torch.float32, device="cuda")
+    assert msz.workspace_bytes((150, 150, 150)) < limit < msz.workspace_bytes((160, 160, 160))
+    f = torch.zeros((160, 160, 160), dtype=torch.float32, device="cuda")
     rc, _, _, st = msz.fix_noalloc(f, f, 0.1)
     assert rc == msz.ETOOBIG and st["status"] == msz.ETOOBIG
     assert "static scratch" in msz.strerror(rc)
