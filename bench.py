@@ -4,13 +4,19 @@ A step corrects the 96-field batch to zero segmentation error in one
 device-scheduled run (msz_fix_batch): 64 2D k^-3 Gaussian random fields with
 sides drawn from 64..2048 and 32 3D cubes of 32^3..192^3, each with its own
 bound xi in {1e-4, 1e-3, 1e-2} x range, about 1.35e8 vertices in all, the
-tile of each field from the autotuner's table.  The fields are resident in
-HBM before the clock starts.  The roofline comes from one instrumented run of
-the same step: every step-kernel launch reports its duration (GPU clock
-stamps) and the algorithmic bytes of the units its blocks visited.
+tile of each field from the autotuner's table, with merged C rounds (all four
+false-critical-point types fixed in one round: the parallel C-loop of
+Sec. 6.1; the result is bit-identical to the oracle's merged schedule).  The
+fields are resident in HBM before the clock starts.  The roofline comes from
+one instrumented run of the same step: every step-kernel launch reports its
+duration (GPU clock stamps) and the algorithmic bytes of the units its blocks
+visited.
 
 The same run times the other forms and configurations (reported under
 "forms"), each result checked for zero segmentation error outside the clock:
+  batch       the headline's instrumented run (kernels, bytes)
+  batch_default  the batch with the default schedule, C sub-loops FPmax..FNmin
+              in turn (opt-in)
   plain       the 3600x2400 k^-3 pair (xi = 1e-4 and 1e-3 x range), per-step
               operation times and bytes, and the oracle on one pinned core
   merged      the same pair with merged C rounds (Sec. 6.1 parallel C-loop)
@@ -19,7 +25,7 @@ The same run times the other forms and configurations (reported under
   turb256     the 256^3 k^-11/3 field with 64 blobs
   learned     the 512^3 k^-11/3 field: the warm-started loop against the plain one
   edits       the plain loop's edits on the pair, encoded and decoded on the GPU
-  batch_modes the batch with merged C rounds and preemptive (opt-in)
+  batch_modes the batch in the preemptive mode (opt-in)
 Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--forms plain,merged,...]
@@ -162,12 +168,12 @@ def bench_batch(msz, torch, dev, args):
         return res
 
     log(f"bench: batch warmup {args.warmup}, timing {args.steps} steps")
-    ms, res = timed(run, args.steps, args.warmup, torch)
+    ms, res = timed(lambda: run(merged=True), args.steps, args.warmup, torch)
     log(f"bench: batch {ms:.3f} ms/step, {verts / ms / 1e6:.3f} Gvertices/s")
     for (f, fh, xi), (_, _, g, _) in zip(fields, res):
         checked(msz, f, g, xi)
     # one instrumented run of the same step: every step-kernel launch
-    run(timing=True)
+    run(timing=True, merged=True)
     torch.cuda.synchronize()
     kern = by_kernel(msz.last_launches())
     dominant = max(kern, key=lambda k: kern[k]["us"])
@@ -198,8 +204,13 @@ def bench_batch(msz, torch, dev, args):
     info = {"kernels": kernels, "max_rounds": max(rounds), "total_rounds": sum(rounds),
             "tiles": {v: tiles.count(v) for v in sorted(set(tiles))}}
     extra = {}
-    if "batch_modes" in args.forms:
-        for name, kw in (("merged", {"merged": True}), ("preemptive", {"preemptive": True})):
+    # opt-in (they launch the same step kernels, which would mix into a kernel
+    # trace of the default command): the default schedule (C sub-loops of one
+    # type at a time) and the preemptive mode
+    modes = (("default_schedule", {}),) if "batch_default" in args.forms else ()
+    modes += (("preemptive", {"preemptive": True}),) if "batch_modes" in args.forms else ()
+    if modes:
+        for name, kw in modes:
             ms_m, res_m = timed(lambda: run(**kw), args.form_steps, 1, torch)
             for (f, fh, xi), (_, _, g, _) in zip(fields, res_m):
                 checked(msz, f, g, xi)
@@ -211,8 +222,9 @@ def bench_batch(msz, torch, dev, args):
 
 
 def oracle_batch_all_cores(host_fields):
-    """The serial C oracle over the whole batch, one field per task on a pool
-    of host threads (ctypes releases the GIL), largest fields first."""
+    """The serial C oracle (merged C rounds, as the headline) over the whole
+    batch, one field per task on a pool of host threads (ctypes releases the
+    GIL), largest fields first."""
     import concurrent.futures
 
     import oracle
@@ -223,14 +235,14 @@ def oracle_batch_all_cores(host_fields):
     log(f"bench: oracle over the batch on {workers} host threads")
     t0 = time.perf_counter()
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
-        rcs = list(ex.map(lambda t: oracle.fix(*t)[0], order))
+        rcs = list(ex.map(lambda t: oracle.fix(*t, merged_c=True)[0], order))
     dt = time.perf_counter() - t0
     if not all(rc == 0 for rc in rcs):
         raise RuntimeError("oracle failed on a batch field")
     log(f"bench: oracle batch {dt:.1f} s")
     return {"value": round(verts / dt / 1e9, 6), "unit": "Gvertices/s", "cores": workers, "kind": "oracle",
-            "sample": "the whole 96-field batch (the headline workload), the serial C oracle once per field, "
-                      f"fields spread over {workers} host threads, largest first",
+            "sample": "the whole 96-field batch (the headline workload), the serial C oracle with merged C rounds "
+                      f"once per field, fields spread over {workers} host threads, largest first",
             "seconds": round(dt, 2), "host_cpus": host_cpus(), "os_cpu_count": os.cpu_count(),
             "cpu_model": cpu_model()}
 
@@ -482,7 +494,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batch96: 96 uneven k^-3 Gaussian random fields (64 2D, sides U{64..2048}; "
                                "32 3D cubes, U{32..192}^3), xi in {1e-4,1e-3,1e-2} x range, corrected together "
-                               "by msz_fix_batch",
+                               "by msz_fix_batch with merged C rounds (parallel C-loop)",
                    "vertices_per_step": verts, "form": "batched"},
         "roofline": roofline,
         "cpu_baseline": cpu,

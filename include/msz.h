@@ -227,7 +227,9 @@ enum {
 typedef struct {
     int32_t kernel;  /* MSZ_KERNEL_* */
     int32_t phase;   /* MSZ_PHASE_* of a one-field step; -1 for a batch step (mixed) or an idle step */
-    double us;       /* first block's start to last block's end, microseconds (0 if no block ran) */
+    double us;       /* first block's start to last block's end, microseconds (0 if no block ran); a
+                        batch step's two kernels both start at the earlier of their first blocks'
+                        starts (they are released together; the second waits for compute units) */
     int64_t bytes;   /* algorithmic bytes of the units the launch visited */
 } msz_launch;
 /* Writes at most max records (out may be NULL); returns the number recorded. */

@@ -505,12 +505,23 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
             const int ph = single ? phase_of_op(E.host[1 + k]) : -1;
             if (single) last_schedule().push_back(ph);
             for (int j = 0; !single && j < nf; ++j) last_schedule().push_back(phase_of_op(batch_log[k * nf + j]));
+            // A batch step's two kernels are released together (both follow
+            // the last scan) and the second one's blocks wait for compute
+            // units the first one holds: each kernel's duration runs from the
+            // earlier of the two first-block starts, as a kernel trace counts
+            // it from the dispatch.
+            unsigned long long t_rel = ~0ull;
+            for (int d = 0; d < 2; ++d) {
+                const unsigned long long s0 = E.host_stamps()[(2 * k + d) * kEngStampWords];
+                if (!single && (d == 0 ? has2 : has3) && s0) t_rel = std::min(t_rel, s0);
+            }
             for (int d = 0; d < 2; ++d) {
                 if (single ? d != 0 : !(d == 0 ? has2 : has3)) continue;
                 const unsigned long long* t = E.host_stamps() + (2 * k + d) * kEngStampWords;
                 unsigned long long end = 0;
                 for (int w = 1; w <= kEngEndSlots; ++w) end = std::max(end, t[w]);
-                const double dms = end >= t[0] ? static_cast<double>(end - t[0]) / wall_khz : 0.0;
+                const unsigned long long t0 = single ? t[0] : std::min(t[0], t_rel);
+                const double dms = end >= t0 && t0 ? static_cast<double>(end - t0) / wall_khz : 0.0;
                 msz_launch rec{};
                 rec.kernel = single ? (has3 ? MSZ_KERNEL_STEP1_3D : MSZ_KERNEL_STEP1_2D)
                                     : (d == 0 ? MSZ_KERNEL_BATCH_2D : MSZ_KERNEL_BATCH_3D);
