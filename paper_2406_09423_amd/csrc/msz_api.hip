@@ -410,8 +410,9 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         const bool three = hf[j].gr.ndim == 3;
         has2 = has2 || !three;
         has3 = has3 || three;
-        p2[j + 1] = p2[j] + (three ? 0 : items);
-        p3[j + 1] = p3[j] + (three ? items : 0);
+        const int units = single ? items : items * eng_weight_host(hf[j], kOpPreA);
+        p2[j + 1] = p2[j] + (three ? 0 : units);
+        p3[j + 1] = p3[j] + (three ? units : 0);
     }
     if (!single) {
         // batch step kernels: twice as many blocks as fit on the device at

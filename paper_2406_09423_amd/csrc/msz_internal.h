@@ -192,6 +192,7 @@ struct EngStats {
 
 // Number of work items of operation op for one field (device and host).
 int eng_items_host(const EngField& F, int op);
+int eng_weight_host(const EngField& F, int op);  // cost units of one item (batch splits)
 int label_tile_count(const Grid& gr);   // label tiles of the grid
 const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, pre2, pre3, ctl, oplog, step, cnt_all)

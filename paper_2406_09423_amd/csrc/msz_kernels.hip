@@ -1394,6 +1394,30 @@ __host__ __device__ inline int eng_items(const EngField& F, int op) {
 
 int eng_items_host(const EngField& F, int op) { return eng_items(F, op); }
 
+// Cost of one work item of op, in units of about 3 us of one block (measured
+// per item on a 256^3 field): a batch step splits the weighted index space,
+// not the item count, evenly over its blocks, so a block that draws
+// troublemaker tiles draws fewer of them than one that draws sparse apply
+// chunks.  Direction items scale with their tile's vertex count.
+__host__ __device__ inline int eng_weight(const EngField& F, int op) {
+    const DirsVariant v = variant_of(F.gr.ndim, F.variant);
+    const int dv = kTileX * v.ty * (F.gr.ndim == 3 ? v.zc : 1);  // vertices of a direction item
+    switch (op) {
+        case kOpPreA: return F.warm ? 6 : 5;
+        case kOpPreA2: return (5 * dv + kEngChunk - 1) / kEngChunk;
+        case kOpPreE: case kOpFullC: case kOpFullR: return (6 * dv + kEngChunk - 1) / kEngChunk;
+        case kOpPreB: case kOpRTile: return 5;
+        case kOpPreD: return 9;
+        case kOpRDetect: return 10;
+        case kOpApplyC: return 2;
+        case kOpRefreshC: case kOpRefreshR: return 3;
+        case kOpDelta: return 4;
+        default: return 1;
+    }
+}
+
+int eng_weight_host(const EngField& F, int op) { return eng_weight(F, op); }
+
 // Direction work items [a, b) of field F with its variant's tile shape.
 template <int NDIM, int MODE>
 __device__ __forceinline__ void eng_dirs(const EngField& F, const float* h, uint8_t* out, int a, int b, float* sm,
@@ -1791,7 +1815,10 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
 }
 
 // One step of every field of dimension NDIM.  pre[0..nf] are the prefix sums
-// of the fields' items in this step (fields of the other dimension count 0).
+// of the fields' weighted items in this step, items times eng_weight (fields
+// of the other dimension count 0; one field: its plain item count).  Item i
+// of field f starts at unit pre[f] + i w and is run by the block whose range
+// of units holds that start.
 template <int NDIM>
 __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
                                               int nf, char* smem, unsigned long long& acct) {
@@ -1823,7 +1850,9 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         const int base = pre[a];
         const int end = min(hi, pre[a + 1]);
         const EngState st = cur[a];
-        eng_run_range<NDIM>(fields[a], st, lo - base, end - base, smem, fields[a].cnt, acct);
+        const int w = eng_weight(fields[a], st.op);
+        const int i0 = (lo - base + w - 1) / w, i1 = (end - base + w - 1) / w;
+        if (i0 < i1) eng_run_range<NDIM>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
         lo = end;
     }
 }
@@ -2158,7 +2187,7 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
     const int f = threadIdx.x;
     int a2 = 0, a3 = 0;
     if (f < nf) {
-        const int it = nxt[f].items;
+        const int it = nxt[f].items * eng_weight(fields[f], nxt[f].op);
         if (fields[f].gr.ndim == 3) a3 = it;
         else a2 = it;
     }
