@@ -212,7 +212,8 @@ int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, flo
 
 /* Profiling aid: every step-kernel launch of the calling host thread's last
  * msz_fix or msz_fix_batch call that ran with MSZ_FLAG_TIMING, in launch
- * order.  A step kernel records, from the GPU's constant-rate clock, its first
+ * order (a batch: per step index, the 2D chain's launch, then the 3D
+ * chain's).  A step kernel records, from the GPU's constant-rate clock, its first
  * block's start and its last block's end, and the algorithmic bytes of the
  * units its blocks visited: per operation, the compulsory reads and writes of
  * each vertex of a visited direction or label tile, each scanned flag byte,
@@ -227,9 +228,7 @@ enum {
 typedef struct {
     int32_t kernel;  /* MSZ_KERNEL_* */
     int32_t phase;   /* MSZ_PHASE_* of a one-field step; -1 for a batch step (mixed) or an idle step */
-    double us;       /* first block's start to last block's end, microseconds (0 if no block ran); a
-                        batch step's two kernels both start at the earlier of their first blocks'
-                        starts (they are released together; the second waits for compute units) */
+    double us;       /* first block's start to last block's end, microseconds (0 if no block ran) */
     int64_t bytes;   /* algorithmic bytes of the units the launch visited */
 } msz_launch;
 /* Writes at most max records (out may be NULL); returns the number recorded. */
@@ -241,8 +240,8 @@ int32_t msz_last_launches(msz_launch* out, int32_t max);
  * phases_out[k] (an MSZ_PHASE_* index, or -1 for the idle steps that end the
  * last graph launch), and the entries line up one to one with the step-kernel
  * dispatches of that call in a kernel trace; for a batch of n_jobs fields,
- * phases_out[k * n_jobs + j] is field j's operation in step k (-1 once it is
- * done).  Writes at most max entries (phases_out may be NULL) and returns the
+ * phases_out[k * n_jobs + j] is field j's operation in step k of its
+ * dimension's chain of steps (-1 once it is done).  Writes at most max entries (phases_out may be NULL) and returns the
  * number of entries recorded. */
 int32_t msz_last_schedule(int32_t* phases_out, int32_t max);
 
@@ -279,10 +278,13 @@ typedef struct {
 /*
  * msz_fix_batch -- corrects n_jobs (<= 1024) independent fields of uneven
  * sizes together: every device step advances each unfinished field by one
- * operation of the schedule msz_fix follows (one step kernel per dimension
- * runs the work items of all its fields as one index space, the 2D and 3D
- * kernels side by side; a decide kernel picks each field's next operation),
- * so each field's result is bit-identical to its own msz_fix.  The steps run from a HIP graph relaunched until no field
+ * operation of the schedule msz_fix follows, so each field's result is
+ * bit-identical to its own msz_fix.  The 2D fields and the 3D fields form two
+ * chains of steps that run side by side without waiting for each other; per
+ * step of a chain, one step kernel runs the work items of all its fields as
+ * one index space split over the blocks by each operation's cost, a decide
+ * kernel picks each field's next operation and a scan kernel sums the next
+ * step's items.  The steps run from a HIP graph relaunched until no field
  * is active.  opt->workspace (if given) must hold
  * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
  * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);

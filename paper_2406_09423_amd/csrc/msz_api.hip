@@ -178,8 +178,8 @@ struct EngineCtx {
     int* hflag_dev = nullptr;  // its device address
     hipEvent_t ev[1] = {nullptr};  // end of the last graph launch
     // cached graph
-    int g_nf = -1, g_grid2 = 0, g_grid3 = 0;
-    bool g_has2 = false, g_has3 = false, g_timing = false;
+    int g_nf = -1, g_n2 = -1, g_grid2 = 0, g_grid3 = 0;
+    bool g_timing = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 
@@ -253,10 +253,11 @@ struct EngineCtx {
         return MSZ_OK;
     }
 
-    // (Re)builds the graph when the topology changed.
-    int graph_for(int nf, bool has2, bool has3, bool timing, int grid2, int grid3) {
-        if (exec && g_nf == nf && g_has2 == has2 && g_has3 == has3 && g_timing == timing && g_grid2 == grid2 &&
-            g_grid3 == grid3)
+    // (Re)builds the graph when the topology changed.  A batch's table holds
+    // its n2 2D fields first, then its 3D fields.
+    int graph_for(int nf, int n2, bool timing, int grid2, int grid3) {
+        const bool has3 = nf > n2;
+        if (exec && g_nf == nf && g_n2 == n2 && g_timing == timing && g_grid2 == grid2 && g_grid3 == grid3)
             return MSZ_OK;
         drop_graph();
         if (hipGraphCreate(&graph, 0) != hipSuccess) return MSZ_EDEVICE;
@@ -291,42 +292,39 @@ struct EngineCtx {
                 if (!add_kernel(fn, dim3(grid), dim3(256), a)) return MSZ_EDEVICE;
             }
         }
-        for (int st = 0; nf > 1 && st < kGraphSteps; ++st) {
-            const int par = st & 1;
-            EngState* cur = states + par * nf;
-            EngState* nxt = states + (par ^ 1) * nf;
-            unsigned long long* ts2 = timing ? tstamp + 2 * st * kEngStampWords : nullptr;
-            unsigned long long* ts3 = timing ? tstamp + (2 * st + 1) * kEngStampWords : nullptr;
-            // the 2D and the 3D step kernels work on disjoint fields: both
-            // follow the last step's scan and may run side by side; the
-            // decision follows both
-            hipGraphNode_t prev = last, dep[2];
-            int nd = 0;
-            if (has2) {
-                last = prev;
-                void* a[] = {&fields, &cur, &pre2, &nf, &ts2};
-                if (!add_kernel(eng_step_kernel(2), dim3(grid2), dim3(256), a)) return MSZ_EDEVICE;
-                dep[nd++] = last;
-            }
-            if (has3) {
-                last = prev;
-                void* a[] = {&fields, &cur, &pre3, &nf, &ts3};
-                if (!add_kernel(eng_step_kernel(3), dim3(grid3), dim3(256), a)) return MSZ_EDEVICE;
-                dep[nd++] = last;
-            }
-            int* log = timing ? oplog : nullptr;
-            int stp = st;
-            void* d[] = {&fields, &cur, &nxt, &stats, &nf, &pre2, &pre3, &ctl, &log, &stp, &counters};
-            if (!add_kernel_after(eng_decide_kernel(), dim3(nf), dim3(256), d, dep, nd)) return MSZ_EDEVICE;
-            if (nf > 1) {
-                void* c[] = {&fields, &nxt, &nf, &pre2, &pre3, &ctl, &hflag_dev};
+        // A batch: two chains of steps, one per dimension, with no edges
+        // between them, so that each runs at its own pace and fills the
+        // other's idle compute units (a chain's step waits only for its own
+        // last scan).  Per step: the step kernel, the decisions, the scan.
+        for (int d = 0; nf > 1 && d < 2; ++d) {
+            int cnt = d == 0 ? n2 : nf - n2;
+            if (cnt == 0) continue;
+            const int off = d == 0 ? 0 : n2;
+            last = nullptr;  // the chain starts at the graph's root
+            for (int st = 0; st < kGraphSteps; ++st) {
+                const int par = st & 1;
+                EngField* fp = fields + off;
+                EngState* cur = states + par * nf + off;
+                EngState* nxt = states + (par ^ 1) * nf + off;
+                EngStats* sp = stats + off;
+                int* pre = d == 0 ? pre2 : pre3;
+                unsigned long long* ts = timing ? tstamp + (2 * st + d) * kEngStampWords : nullptr;
+                int* log = timing ? oplog + (d == 0 ? 0 : kGraphSteps * n2) : nullptr;
+                int stp = st;
+                int* cs = ctl + d;
+                int* co = ctl + (1 - d);
+                void* a[] = {&fp, &cur, &pre, &cnt, &ts};
+                if (!add_kernel(eng_step_kernel(d == 0 ? 2 : 3), dim3(d == 0 ? grid2 : grid3), dim3(256), a))
+                    return MSZ_EDEVICE;
+                void* dd[] = {&fp, &cur, &nxt, &sp, &cnt, &log, &stp};
+                if (!add_kernel(eng_decide_kernel(), dim3(cnt), dim3(256), dd)) return MSZ_EDEVICE;
+                void* c[] = {&fp, &nxt, &cnt, &pre, &cs, &co, &hflag_dev};
                 if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
             }
         }
         if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
         g_nf = nf;
-        g_has2 = has2;
-        g_has3 = has3;
+        g_n2 = n2;
         g_timing = timing;
         g_grid2 = grid2;
         g_grid3 = grid3;
@@ -400,27 +398,36 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     const bool single = nf == 1;
     int grid2 = step_grid(dev, 2, single), grid3 = step_grid(dev, 3, single);
     if (grid2 < 1 || grid3 < 1) return MSZ_EDEVICE;
-    bool has2 = false, has3 = false;
+    // The device table holds the 2D fields first, then the 3D fields (each
+    // dimension is one chain of steps); order[p] is the caller's index of
+    // table entry p.
+    std::vector<int> order(nf);
+    for (int j = 0; j < nf; ++j) order[j] = j;
+    std::stable_partition(order.begin(), order.end(), [&](int j) { return hf[j].gr.ndim == 2; });
+    std::vector<EngField> tab(nf);
+    for (int p = 0; p < nf; ++p) tab[p] = hf[order[p]];
+    int n2 = 0;
     std::vector<EngState> hs(2 * nf);
-    std::vector<int> p2(nf + 1, 0), p3(nf + 1, 0);
+    std::vector<int> p2(1, 0), p3(1, 0);
     for (int j = 0; j < nf; ++j) {
-        const int items = eng_items_host(hf[j], kOpPreA);
+        const int items = eng_items_host(tab[j], kOpPreA);
         hs[j] = EngState{kOpPreA, 0, items, 0};
         hs[nf + j] = EngState{kOpDone, 0, 0, 0};
-        const bool three = hf[j].gr.ndim == 3;
-        has2 = has2 || !three;
-        has3 = has3 || three;
-        const int units = single ? items : items * eng_weight_host(hf[j], kOpPreA);
-        p2[j + 1] = p2[j] + (three ? 0 : units);
-        p3[j + 1] = p3[j] + (three ? units : 0);
+        const bool three = tab[j].gr.ndim == 3;
+        n2 += !three;
+        std::vector<int>& p = three ? p3 : p2;
+        p.push_back(p.back() + (single ? items : items * eng_weight_host(tab[j], kOpPreA)));
     }
+    const int n3 = nf - n2;
+    const bool has2 = n2 > 0, has3 = n3 > 0;
     if (!single) {
         // batch step kernels: twice as many blocks as fit on the device at
-        // once, so the 2D and 3D kernels running side by side keep each
+        // once, so the 2D and 3D chains running side by side keep each
         // other's idle slots filled (the 96-field batch: 61.9 ms against 68.1
-        // with one resident grid each, 89.7 with half).  The single-field
-        // kernel stays at one resident grid: each of its blocks takes the
-        // schedule decision itself, and twice as many cost 38% more.
+        // with one resident grid each, 89.7 with half, 43.6 against 45.7
+        // after the items were weighted by cost).  The single-field kernel
+        // stays at one resident grid: each of its blocks takes the schedule
+        // decision itself, and twice as many cost 38% more.
         grid2 *= 2;
         grid3 *= 2;
     }
@@ -428,8 +435,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         last_schedule().clear();
         last_launches().clear();
     }
-    for (int j = 0; j < nf; ++j) hf[j].cnt = E.counters + static_cast<size_t>(j) * kCntBlockWords;
-    if (int rc = E.graph_for(nf, has2, has3, timing, grid2, grid3)) {
+    for (int j = 0; j < nf; ++j) tab[j].cnt = E.counters + static_cast<size_t>(j) * kCntBlockWords;
+    if (int rc = E.graph_for(nf, n2, timing, grid2, grid3)) {
         E.drop_graph();
         return rc;
     }
@@ -438,7 +445,7 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     if (single) {
         // one setup kernel: field entry, start states, counters, statistics,
         // marks, case bytes and dirty flags (no uploads, no memsets)
-        EngField F = hf[0];
+        EngField F = tab[0];
         EngField* fp = E.fields;
         EngState* sp = E.states;
         EngStats* tp = E.stats;
@@ -450,15 +457,16 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         MSZ_HIP(hipLaunchKernel(eng_setup1_kernel(), dim3(std::max(1, std::min(2048, (nw + 255) / 256))), dim3(256),
                                 a, 0, s));
     } else {
-        const int one = 1;
-        MSZ_HIP(hipMemcpyAsync(E.fields, hf.data(), sizeof(EngField) * nf, hipMemcpyHostToDevice, s));
+        // the chains' active words (a chain without fields is inactive from the start)
+        const int active[2] = {has2 ? 1 : 0, has3 ? 1 : 0};
+        MSZ_HIP(hipMemcpyAsync(E.fields, tab.data(), sizeof(EngField) * nf, hipMemcpyHostToDevice, s));
         MSZ_HIP(hipMemcpyAsync(E.states, hs.data(), sizeof(EngState) * 2 * nf, hipMemcpyHostToDevice, s));
-        MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
-        MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * (nf + 1), hipMemcpyHostToDevice, s));
-        MSZ_HIP(hipMemcpyAsync(E.ctl, &one, sizeof(int), hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * p2.size(), hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * p3.size(), hipMemcpyHostToDevice, s));
+        MSZ_HIP(hipMemcpyAsync(E.ctl, active, sizeof(active), hipMemcpyHostToDevice, s));
         MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * nf, s));
         int total = 0;
-        for (const EngField& F : hf) total = std::max(total, (F.gr.n + 15) >> 4);
+        for (const EngField& F : tab) total = std::max(total, (F.gr.n + 15) >> 4);
         EngField* fp = E.fields;
         int nfv = nf;
         void* a[] = {&fp, &nfv};
@@ -485,6 +493,8 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         }
     }
     std::vector<int> batch_log;  // timed batch: the operation of every field in every step of a launch
+    std::vector<int> pos(nf);    // table position of the caller's field j
+    for (int p = 0; p < nf; ++p) pos[order[p]] = p;
     if (timing && !single) batch_log.resize(static_cast<size_t>(kGraphSteps) * nf);
     while (timing) {  // one launch at a time, with the schedule and clock stamps of each step read back
         if (hipMemsetAsync(E.tstamp, 0, EngineCtx::stamp_bytes(), s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
@@ -505,23 +515,18 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         for (int k = 0; k < kGraphSteps; ++k) {
             const int ph = single ? phase_of_op(E.host[1 + k]) : -1;
             if (single) last_schedule().push_back(ph);
-            for (int j = 0; !single && j < nf; ++j) last_schedule().push_back(phase_of_op(batch_log[k * nf + j]));
-            // A batch step's two kernels are released together (both follow
-            // the last scan) and the second one's blocks wait for compute
-            // units the first one holds: each kernel's duration runs from the
-            // earlier of the two first-block starts, as a kernel trace counts
-            // it from the dispatch.
-            unsigned long long t_rel = ~0ull;
-            for (int d = 0; d < 2; ++d) {
-                const unsigned long long s0 = E.host_stamps()[(2 * k + d) * kEngStampWords];
-                if (!single && (d == 0 ? has2 : has3) && s0) t_rel = std::min(t_rel, s0);
+            // a batch logs each chain's steps apart: [step][field of the chain]
+            for (int j = 0; !single && j < nf; ++j) {
+                const int p = pos[j];
+                const int op = p < n2 ? batch_log[k * n2 + p] : batch_log[kGraphSteps * n2 + k * n3 + (p - n2)];
+                last_schedule().push_back(phase_of_op(op));
             }
             for (int d = 0; d < 2; ++d) {
                 if (single ? d != 0 : !(d == 0 ? has2 : has3)) continue;
                 const unsigned long long* t = E.host_stamps() + (2 * k + d) * kEngStampWords;
                 unsigned long long end = 0;
                 for (int w = 1; w <= kEngEndSlots; ++w) end = std::max(end, t[w]);
-                const unsigned long long t0 = single ? t[0] : std::min(t[0], t_rel);
+                const unsigned long long t0 = t[0];
                 const double dms = end >= t0 && t0 ? static_cast<double>(end - t0) / wall_khz : 0.0;
                 msz_launch rec{};
                 rec.kernel = single ? (has3 ? MSZ_KERNEL_STEP1_3D : MSZ_KERNEL_STEP1_2D)
@@ -537,7 +542,7 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
             }
         }
         steps += kGraphSteps;
-        if (E.host[0] == 0) break;
+        if ((single ? E.host[0] : *flag) == 0) break;
         if (steps > max_steps) { rc = MSZ_EDEVICE; break; }
     }
     if (rc != MSZ_OK) {
@@ -552,8 +557,10 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         std::memcpy(st.data(), const_cast<const int*>(E.hflag) + kHostStatsWord, sizeof(EngStats));
         return MSZ_OK;
     }
-    MSZ_HIP(hipMemcpyAsync(st.data(), E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
+    std::vector<EngStats> by_pos(nf);
+    MSZ_HIP(hipMemcpyAsync(by_pos.data(), E.stats, sizeof(EngStats) * nf, hipMemcpyDeviceToHost, s));
     MSZ_HIP(hipStreamSynchronize(s));
+    for (int p = 0; p < nf; ++p) st[order[p]] = by_pos[p];
     return MSZ_OK;
 }
 

@@ -1394,24 +1394,26 @@ __host__ __device__ inline int eng_items(const EngField& F, int op) {
 
 int eng_items_host(const EngField& F, int op) { return eng_items(F, op); }
 
-// Cost of one work item of op, in units of about 3 us of one block (measured
-// per item on a 256^3 field): a batch step splits the weighted index space,
-// not the item count, evenly over its blocks, so a block that draws
-// troublemaker tiles draws fewer of them than one that draws sparse apply
-// chunks.  Direction items scale with their tile's vertex count.
+// Cost of one work item of op, in units of about 1 us of one block (per-item
+// block times measured inside the 96-field batch): a batch step splits the
+// weighted index space, not the item count, evenly over its blocks, so a
+// block that draws troublemaker tiles draws fewer of them than one that
+// draws sparse apply chunks.  Direction items scale with their tile's vertex
+// count (per 4096 vertices: 5.6 for the directions of f, 8.5 with the cases).
 __host__ __device__ inline int eng_weight(const EngField& F, int op) {
     const DirsVariant v = variant_of(F.gr.ndim, F.variant);
     const int dv = kTileX * v.ty * (F.gr.ndim == 3 ? v.zc : 1);  // vertices of a direction item
     switch (op) {
-        case kOpPreA: return F.warm ? 6 : 5;
-        case kOpPreA2: return (5 * dv + kEngChunk - 1) / kEngChunk;
-        case kOpPreE: case kOpFullC: case kOpFullR: return (6 * dv + kEngChunk - 1) / kEngChunk;
-        case kOpPreB: case kOpRTile: return 5;
-        case kOpPreD: return 9;
-        case kOpRDetect: return 10;
-        case kOpApplyC: return 2;
-        case kOpRefreshC: case kOpRefreshR: return 3;
-        case kOpDelta: return 4;
+        case kOpPreA: return F.warm ? 12 : 10;
+        case kOpPreA2: return (56 * dv + 10 * kEngChunk - 1) / (10 * kEngChunk);
+        case kOpPreE: case kOpFullC: case kOpFullR: return (85 * dv + 10 * kEngChunk - 1) / (10 * kEngChunk);
+        case kOpPreB: return 21;
+        case kOpPreD: return 22;
+        case kOpRTile: return 13;  // the clean tiles of g are skipped
+        case kOpRDetect: return 22;
+        case kOpApplyC: case kOpRefreshC: return 2;
+        case kOpRefreshR: return 3;
+        case kOpDelta: return 5;
         default: return 1;
     }
 }
@@ -1814,26 +1816,15 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
     __syncthreads();  // the next range reuses the LDS
 }
 
-// One step of every field of dimension NDIM.  pre[0..nf] are the prefix sums
-// of the fields' weighted items in this step, items times eng_weight (fields
-// of the other dimension count 0; one field: its plain item count).  Item i
-// of field f starts at unit pre[f] + i w and is run by the block whose range
-// of units holds that start.
+// One step of the fields of one chain (all of dimension NDIM).  pre[0..nf]
+// are the prefix sums of the fields' weighted items in this step, items times
+// eng_weight.  Item i of field f starts at unit pre[f] + i w and is run by the
+// block whose range of units holds that start.
 template <int NDIM>
 __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
                                               int nf, char* smem, unsigned long long& acct) {
-    // The tables were written by the previous kernel of the stream, so plain
-    // loads see them; one field needs no search.
-    if (nf == 1) {
-        const int total = pre[1];
-        const EngState st = cur[0];
-        if (total == 0) return;
-        const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
-        const int per = (total + nb - 1) / nb;
-        const int lo = b * per, hi = min(total, lo + per);
-        if (lo < hi) eng_run_range<NDIM>(fields[0], st, lo, hi, smem, fields[0].cnt, acct);
-        return;
-    }
+    // The tables were written by the previous kernels of the chain, so plain
+    // loads see them.
     const int total = pre[nf];
     if (total == 0) return;
     const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
@@ -2025,12 +2016,11 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
 // active count; if oplog is set, oplog[step * nf + f] receives the operation
 // field f ran in this step.
 __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__ fields, const EngState* cur,
-                                                    EngState* nxt, EngStats* stats, int nf, int* pre2, int* pre3,
-                                                    int* ctl, int* oplog, int step, unsigned* cnt_all) {
+                                                    EngState* nxt, EngStats* stats, int nf, int* oplog, int step) {
     __shared__ unsigned part[256];
     __shared__ unsigned red[kCntSlots];
     const int f = blockIdx.x;
-    unsigned* cnt = cnt_all + static_cast<long>(f) * kCntBlockWords;
+    unsigned* cnt = fields[f].cnt;
     // thread t sums counter (t % 16) over the slots t / 16, t / 16 + 16, ...
     const int k = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
     constexpr int PER = kSlots / (256 / kCntSlots);
@@ -2064,17 +2054,7 @@ __global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__
             stats[f] = S;
         }
     }
-    if (threadIdx.x == 0) {
-        nxt[f] = ns;
-        if (nf == 1) {
-            const bool three = fields[0].gr.ndim == 3;
-            pre2[0] = 0;
-            pre3[0] = 0;
-            pre2[1] = three ? 0 : ns.items;
-            pre3[1] = three ? ns.items : 0;
-            ctl[0] = ns.items > 0 ? 1 : 0;
-        }
-    }
+    if (threadIdx.x == 0) nxt[f] = ns;
 }
 
 // One field, one kernel per step: every block takes the schedule decision
@@ -2179,38 +2159,35 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
     if (ts) stamp_end(ts, acct);
 }
 
-// Prefix sums of the next step's items per dimension, and the active count
-// (one block of kEngMaxFields threads, one field each).
+// Prefix sums of the next step's weighted items of one chain, and its active
+// word (one block of kEngMaxFields threads, one field each).  A batch runs
+// its 2D and its 3D fields as two chains of steps that do not wait for each
+// other; the done word is cleared by the chain that finds both inactive (each
+// stores its own word, then loads the other's, both sequentially consistent:
+// of two chains ending together at least one sees the other's store).
 __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
-                                                           int nf, int* pre2, int* pre3, int* ctl, int* hflag) {
-    __shared__ int s2[kEngMaxFields], s3[kEngMaxFields];
+                                                           int nf, int* pre, int* ctl_self, const int* ctl_other,
+                                                           int* hflag) {
+    __shared__ int sm[kEngMaxFields];
     const int f = threadIdx.x;
-    int a2 = 0, a3 = 0;
-    if (f < nf) {
-        const int it = nxt[f].items * eng_weight(fields[f], nxt[f].op);
-        if (fields[f].gr.ndim == 3) a3 = it;
-        else a2 = it;
-    }
-    s2[f] = a2;
-    s3[f] = a3;
+    sm[f] = f < nf ? nxt[f].items * eng_weight(fields[f], nxt[f].op) : 0;
     __syncthreads();
     for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive Hillis-Steele scan
-        const int v2 = f >= o ? s2[f - o] : 0, v3 = f >= o ? s3[f - o] : 0;
+        const int v = f >= o ? sm[f - o] : 0;
         __syncthreads();
-        s2[f] += v2;
-        s3[f] += v3;
+        sm[f] += v;
         __syncthreads();
     }
-    if (f < nf) {
-        pre2[f + 1] = s2[f];
-        pre3[f + 1] = s3[f];
-    }
+    if (f < nf) pre[f + 1] = sm[f];
     if (f == 0) {
-        pre2[0] = 0;
-        pre3[0] = 0;
-        const bool active = (s2[nf - 1] + s3[nf - 1]) > 0;
-        ctl[0] = active ? 1 : 0;
-        if (!active && hflag) __hip_atomic_store(hflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        pre[0] = 0;
+        if (sm[nf - 1] > 0) {
+            __hip_atomic_store(ctl_self, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(ctl_self, 0, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+            const int other = __hip_atomic_load(ctl_other, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+            if (other == 0 && hflag) __hip_atomic_store(hflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
     }
 }
 
