@@ -284,8 +284,10 @@ typedef struct {
  * step of a chain, one step kernel runs the work items of all its fields as
  * one index space split over the blocks by each operation's cost, a decide
  * kernel picks each field's next operation and a scan kernel sums the next
- * step's items.  The steps run from a HIP graph relaunched until no field
- * is active.  opt->workspace (if given) must hold
+ * step's items.  Each chain's steps run from a HIP graph on a stream of the
+ * library's own, relaunched until its fields are done; the chains start
+ * after the work already queued on `stream` and the work queued on it
+ * afterwards waits for them.  opt->workspace (if given) must hold
  * msz_batch_workspace_bytes(jobs, n_jobs) bytes; opt->warm_start, opt->g_out
  * and opt->tile_override must be unset (use msz_job.g_out / msz_job.tile);
  * opt->max_rounds, MSZ_FLAG_MERGED_C and MSZ_FLAG_PREEMPTIVE apply to every field

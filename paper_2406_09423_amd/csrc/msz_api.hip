@@ -11,8 +11,9 @@
 //            troublemakers' targets; back to the C phase whenever those edits
 //            created a false critical point.
 // The host captures kGraphSteps steps in a HIP graph and relaunches it until
-// the device clears a done word in pinned host memory.
-// msz_fix runs the same schedule for one field.
+// the device clears a done word in pinned host memory; a batch has one graph
+// and one stream per chain (its 2D fields, its 3D fields), each relaunched
+// on its own.  msz_fix runs the same schedule for one field.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -174,20 +175,28 @@ struct EngineCtx {
     unsigned long long* tstamp = nullptr;  // profiling: kEngStampWords words per step
     unsigned* counters = nullptr;          // kCntBlockWords per field
     int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog, then 2 * kGraphSteps stamps
-    int* hflag = nullptr;      // pinned, device-mapped: [0] 1 while active (the device clears it), final stats from word kHostStatsWord
+    // pinned, device-mapped: [0] 1 while a single field is active, [1], [2] 1
+    // while a batch's 2D / 3D chain is active (the device clears them), final
+    // statistics of a single field from word kHostStatsWord
+    int* hflag = nullptr;
     int* hflag_dev = nullptr;  // its device address
-    hipEvent_t ev[1] = {nullptr};  // end of the last graph launch
-    // cached graph
+    // ev[0]: end of the last graph launch of a single field; ev[1], ev[2]: of
+    // each batch chain; ev[3]: the caller's stream reached the batch's start
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t cs[2] = {nullptr, nullptr};  // the batch chains' streams (default priority)
+    // cached graphs: a single field's, or one per batch chain
     int g_nf = -1, g_n2 = -1, g_grid2 = 0, g_grid3 = 0;
     bool g_timing = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
 
     void drop_graph() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
+        for (int d = 0; d < 2; ++d) {
+            if (exec[d]) (void)hipGraphExecDestroy(exec[d]);
+            if (graph[d]) (void)hipGraphDestroy(graph[d]);
+            exec[d] = nullptr;
+            graph[d] = nullptr;
+        }
         g_nf = -1;
     }
     // No destructor work: at process exit the HIP runtime may already be torn
@@ -249,23 +258,22 @@ struct EngineCtx {
         }
         for (hipEvent_t& e : ev)
             if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MSZ_EDEVICE;
+        for (hipStream_t& c : cs)
+            if (!c && hipStreamCreateWithFlags(&c, hipStreamNonBlocking) != hipSuccess) return MSZ_EDEVICE;
         device = dev;
         return MSZ_OK;
     }
 
-    // (Re)builds the graph when the topology changed.  A batch's table holds
+    // (Re)builds the graphs when the topology changed.  A batch's table holds
     // its n2 2D fields first, then its 3D fields.
     int graph_for(int nf, int n2, bool timing, int grid2, int grid3) {
-        const bool has3 = nf > n2;
-        if (exec && g_nf == nf && g_n2 == n2 && g_timing == timing && g_grid2 == grid2 && g_grid3 == grid3)
+        if (g_nf == nf && g_n2 == n2 && g_timing == timing && g_grid2 == grid2 && g_grid3 == grid3)
             return MSZ_OK;
         drop_graph();
-        if (hipGraphCreate(&graph, 0) != hipSuccess) return MSZ_EDEVICE;
+        hipGraph_t gcur = nullptr;
         hipGraphNode_t last = nullptr;
-        auto chain = [&](hipGraphNode_t n) { last = n; };
-        // a kernel node after the nodes deps[0 .. nd)
-        auto add_kernel_after = [&](const void* fn, dim3 g, dim3 b, void** args, const hipGraphNode_t* deps,
-                                    int nd) -> bool {
+        // a kernel node after the last one added to the current graph
+        auto add_kernel = [&](const void* fn, dim3 g, dim3 b, void** args) -> bool {
             hipKernelNodeParams p{};
             p.func = const_cast<void*>(fn);
             p.gridDim = g;
@@ -273,15 +281,15 @@ struct EngineCtx {
             p.sharedMemBytes = 0;
             p.kernelParams = args;
             hipGraphNode_t n = nullptr;
-            if (hipGraphAddKernelNode(&n, graph, nd ? deps : nullptr, nd, &p) != hipSuccess) return false;
-            chain(n);
+            if (hipGraphAddKernelNode(&n, gcur, last ? &last : nullptr, last ? 1 : 0, &p) != hipSuccess)
+                return false;
+            last = n;
             return true;
         };
-        // a kernel node after the last one added
-        auto add_kernel = [&](const void* fn, dim3 g, dim3 b, void** args) -> bool {
-            return add_kernel_after(fn, g, b, args, last ? &last : nullptr, last ? 1 : 0);
-        };
         if (nf == 1) {  // one field: one step kernel per step, deciding for itself
+            const bool has3 = n2 == 0;
+            if (hipGraphCreate(&graph[0], 0) != hipSuccess) return MSZ_EDEVICE;
+            gcur = graph[0];
             const void* fn = eng_step1_kernel(has3 ? 3 : 2);
             const int grid = has3 ? grid3 : grid2;
             for (int st = 0; st < kGraphSteps; ++st) {
@@ -291,16 +299,20 @@ struct EngineCtx {
                 void* a[] = {&fields, &states, &states, &stats, &counters, &ctl, &hflag_dev, &log, &stp, &ts};
                 if (!add_kernel(fn, dim3(grid), dim3(256), a)) return MSZ_EDEVICE;
             }
+            if (hipGraphInstantiate(&exec[0], graph[0], nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
         }
-        // A batch: two chains of steps, one per dimension, with no edges
-        // between them, so that each runs at its own pace and fills the
-        // other's idle compute units (a chain's step waits only for its own
-        // last scan).  Per step: the step kernel, the decisions, the scan.
+        // A batch: one graph per dimension's chain of steps, each launched on
+        // its own stream, so that the chains never wait for each other (not
+        // even where a launch ends).  Per step: the step kernel, the
+        // decisions, the scan.
         for (int d = 0; nf > 1 && d < 2; ++d) {
             int cnt = d == 0 ? n2 : nf - n2;
             if (cnt == 0) continue;
             const int off = d == 0 ? 0 : n2;
-            last = nullptr;  // the chain starts at the graph's root
+            if (hipGraphCreate(&graph[d], 0) != hipSuccess) return MSZ_EDEVICE;
+            gcur = graph[d];
+            last = nullptr;
+            int* word = hflag_dev + 1 + d;
             for (int st = 0; st < kGraphSteps; ++st) {
                 const int par = st & 1;
                 EngField* fp = fields + off;
@@ -311,18 +323,16 @@ struct EngineCtx {
                 unsigned long long* ts = timing ? tstamp + (2 * st + d) * kEngStampWords : nullptr;
                 int* log = timing ? oplog + (d == 0 ? 0 : kGraphSteps * n2) : nullptr;
                 int stp = st;
-                int* cs = ctl + d;
-                int* co = ctl + (1 - d);
                 void* a[] = {&fp, &cur, &pre, &cnt, &ts};
                 if (!add_kernel(eng_step_kernel(d == 0 ? 2 : 3), dim3(d == 0 ? grid2 : grid3), dim3(256), a))
                     return MSZ_EDEVICE;
                 void* dd[] = {&fp, &cur, &nxt, &sp, &cnt, &log, &stp};
                 if (!add_kernel(eng_decide_kernel(), dim3(cnt), dim3(256), dd)) return MSZ_EDEVICE;
-                void* c[] = {&fp, &nxt, &cnt, &pre, &cs, &co, &hflag_dev};
+                void* c[] = {&fp, &nxt, &cnt, &pre, &word};
                 if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
             }
+            if (hipGraphInstantiate(&exec[d], graph[d], nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
         }
-        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
         g_nf = nf;
         g_n2 = n2;
         g_timing = timing;
@@ -442,6 +452,9 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     }
     volatile int* flag = E.hflag;
     *flag = 1;  // cleared by the device when the work is done
+    volatile int* chain_word = E.hflag + 1;  // a batch: each chain's done word
+    chain_word[0] = has2 ? 1 : 0;
+    chain_word[1] = has3 ? 1 : 0;
     if (single) {
         // one setup kernel: field entry, start states, counters, statistics,
         // marks, case bytes and dirty flags (no uploads, no memsets)
@@ -478,11 +491,30 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         return MSZ_EDEVICE;
     int64_t steps = 0;
     int rc = MSZ_OK;
-    if (!timing) {
+    // a batch: the chains start once the caller's stream reaches this point,
+    // and the caller's stream waits for them at the end
+    bool live[2] = {!single && has2, !single && has3};
+    int64_t chain_steps[2] = {0, 0};
+    auto chains_after_caller = [&]() {
+        if (hipEventRecord(E.ev[3], s) != hipSuccess) return false;
+        for (int d = 0; d < 2; ++d)
+            if (live[d] && hipStreamWaitEvent(E.cs[d], E.ev[3], 0) != hipSuccess) return false;
+        return true;
+    };
+    auto launch_chain = [&](int d) {
+        chain_steps[d] += kGraphSteps;
+        return hipGraphLaunch(E.exec[d], E.cs[d]) == hipSuccess && hipEventRecord(E.ev[1 + d], E.cs[d]) == hipSuccess;
+    };
+    auto caller_after_chains = [&]() {
+        for (int d = 0; d < 2; ++d)
+            if ((d == 0 ? has2 : has3) && hipStreamWaitEvent(s, E.ev[1 + d], 0) != hipSuccess) return false;
+        return true;
+    };
+    if (!timing && single) {
         // Relaunch until the device clears the done word (pinned host memory):
         // no read-back copy per launch.
         for (;;) {
-            if (hipGraphLaunch(E.exec, s) != hipSuccess || hipEventRecord(E.ev[0], s) != hipSuccess ||
+            if (hipGraphLaunch(E.exec[0], s) != hipSuccess || hipEventRecord(E.ev[0], s) != hipSuccess ||
                 hipEventSynchronize(E.ev[0]) != hipSuccess) {
                 rc = MSZ_EDEVICE;
                 break;
@@ -492,13 +524,44 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
             if (steps > max_steps) { rc = MSZ_EDEVICE; break; }
         }
     }
+    if (!timing && !single) {
+        // Each chain is relaunched as soon as its last launch has ended and
+        // its done word is still raised, independently of the other chain.
+        bool ok = chains_after_caller();
+        for (int d = 0; ok && d < 2; ++d)
+            if (live[d]) ok = launch_chain(d);
+        while (ok && (live[0] || live[1])) {
+            for (int d = 0; ok && d < 2; ++d) {
+                if (!live[d]) continue;
+                const hipError_t q = hipEventQuery(E.ev[1 + d]);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) { ok = false; break; }
+                if (chain_word[d] == 0) { live[d] = false; continue; }
+                if (chain_steps[d] > max_steps) { ok = false; break; }
+                ok = launch_chain(d);
+            }
+        }
+        if (!ok) {
+            rc = MSZ_EDEVICE;
+            for (int d = 0; d < 2; ++d) (void)hipStreamSynchronize(E.cs[d]);
+        }
+        if (!caller_after_chains()) rc = MSZ_EDEVICE;
+    }
     std::vector<int> batch_log;  // timed batch: the operation of every field in every step of a launch
     std::vector<int> pos(nf);    // table position of the caller's field j
     for (int p = 0; p < nf; ++p) pos[order[p]] = p;
     if (timing && !single) batch_log.resize(static_cast<size_t>(kGraphSteps) * nf);
     while (timing) {  // one launch at a time, with the schedule and clock stamps of each step read back
         if (hipMemsetAsync(E.tstamp, 0, EngineCtx::stamp_bytes(), s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
-        if (hipGraphLaunch(E.exec, s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        bool launched[2] = {live[0], live[1]};
+        if (single) {
+            if (hipGraphLaunch(E.exec[0], s) != hipSuccess) { rc = MSZ_EDEVICE; break; }
+        } else {
+            bool ok = chains_after_caller();
+            for (int d = 0; ok && d < 2; ++d)
+                if (live[d]) ok = launch_chain(d);
+            if (!ok || !caller_after_chains()) { rc = MSZ_EDEVICE; break; }
+        }
         if (hipMemcpyAsync(E.host, E.ctl, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(E.host + 1, E.oplog, sizeof(int) * kGraphSteps, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(E.host_stamps(), E.tstamp, EngineCtx::stamp_bytes(), hipMemcpyDeviceToHost, s) !=
@@ -515,14 +578,18 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         for (int k = 0; k < kGraphSteps; ++k) {
             const int ph = single ? phase_of_op(E.host[1 + k]) : -1;
             if (single) last_schedule().push_back(ph);
-            // a batch logs each chain's steps apart: [step][field of the chain]
+            // a batch logs each chain's steps apart: [step][field of the
+            // chain]; a chain that was not launched (done) logs nothing
             for (int j = 0; !single && j < nf; ++j) {
                 const int p = pos[j];
-                const int op = p < n2 ? batch_log[k * n2 + p] : batch_log[kGraphSteps * n2 + k * n3 + (p - n2)];
+                const bool two = p < n2;
+                int op = kOpDone;
+                if (launched[two ? 0 : 1])
+                    op = two ? batch_log[k * n2 + p] : batch_log[kGraphSteps * n2 + k * n3 + (p - n2)];
                 last_schedule().push_back(phase_of_op(op));
             }
             for (int d = 0; d < 2; ++d) {
-                if (single ? d != 0 : !(d == 0 ? has2 : has3)) continue;
+                if (single ? d != 0 : !launched[d]) continue;
                 const unsigned long long* t = E.host_stamps() + (2 * k + d) * kEngStampWords;
                 unsigned long long end = 0;
                 for (int w = 1; w <= kEngEndSlots; ++w) end = std::max(end, t[w]);
@@ -542,7 +609,13 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
             }
         }
         steps += kGraphSteps;
-        if ((single ? E.host[0] : *flag) == 0) break;
+        if (single) {
+            if (E.host[0] == 0) break;
+        } else {
+            for (int d = 0; d < 2; ++d)
+                if (live[d] && chain_word[d] == 0) live[d] = false;
+            if (!live[0] && !live[1]) break;
+        }
         if (steps > max_steps) { rc = MSZ_EDEVICE; break; }
     }
     if (rc != MSZ_OK) {

@@ -1367,7 +1367,8 @@ void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s) {
 // neighbouring items share an L2); k_eng_decide reduces each field's counters
 // and writes its next operation; k_eng_scan forms the prefix sums of the next
 // step's items.  The host captures a fixed number of steps in a HIP graph and
-// relaunches it until no field is active.  Kernel boundaries order the steps:
+// relaunches it until no field is active; a batch's 2D fields and 3D fields
+// form two chains of steps, each with its own graph.  Kernel boundaries order the steps:
 // every write of a step is visible to the next one without device-scope
 // fences inside a kernel (which on MI355X write back and invalidate the L2 of
 // each XCD).
@@ -2159,15 +2160,11 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
     if (ts) stamp_end(ts, acct);
 }
 
-// Prefix sums of the next step's weighted items of one chain, and its active
-// word (one block of kEngMaxFields threads, one field each).  A batch runs
-// its 2D and its 3D fields as two chains of steps that do not wait for each
-// other; the done word is cleared by the chain that finds both inactive (each
-// stores its own word, then loads the other's, both sequentially consistent:
-// of two chains ending together at least one sees the other's store).
+// Prefix sums of the next step's weighted items of one chain of a batch (its
+// 2D or its 3D fields; the host relaunches each chain until it is done), and
+// its done word (one block of kEngMaxFields threads, one field each).
 __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
-                                                           int nf, int* pre, int* ctl_self, const int* ctl_other,
-                                                           int* hflag) {
+                                                           int nf, int* pre, int* word) {
     __shared__ int sm[kEngMaxFields];
     const int f = threadIdx.x;
     sm[f] = f < nf ? nxt[f].items * eng_weight(fields[f], nxt[f].op) : 0;
@@ -2181,13 +2178,8 @@ __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __re
     if (f < nf) pre[f + 1] = sm[f];
     if (f == 0) {
         pre[0] = 0;
-        if (sm[nf - 1] > 0) {
-            __hip_atomic_store(ctl_self, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(ctl_self, 0, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-            const int other = __hip_atomic_load(ctl_other, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-            if (other == 0 && hflag) __hip_atomic_store(hflag, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
+        // the done word lives in pinned host memory, which the host polls
+        if (sm[nf - 1] == 0) __hip_atomic_store(word, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
