@@ -1115,79 +1115,113 @@ struct TargetList {
     }
 };
 
-// Troublemaker detection, tile by tile (see k_label_final for the order).
-// The tile's G groups are loaded GB at a time (the step kernel uses one: on
-// ocean2d more groups in flight measured slower).
-template <int NDIM, int GB = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024>
+// Troublemakers of one tile (Sec. 5.2).  Only a vertex whose direction in g
+// differs from f's (each family apart) can be one, so only such vertices
+// have their labels resolved -- their pointers and f's labels loaded and
+// their exit chains followed; the rest of the tile costs its two direction
+// bytes per vertex.  Mislabelled vertices need not be counted for the loop:
+// one exists exactly when a troublemaker of its family does (on the steepest
+// path in g of a mislabelled vertex, the first vertex whose direction
+// differs from f's carries the same labels in g and in f), so the
+// troublemaker count ends the R loop alike.  With full set, every vertex's
+// labels are resolved and the mislabelled ones counted in wrong (the start
+// field's count).  bytes receives the algorithmic bytes of the loads.
+template <int NDIM>
 __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
                                               const int* __restrict__ Mf, const int* __restrict__ mf, const Grid& gr,
-                                              int tile, const TargetList& tl, unsigned& wrong, unsigned& cases,
-                                              unsigned& changed, unsigned& bad, unsigned& hops) {
+                                              int tile, bool full, const TargetList& tl, unsigned& wrong,
+                                              unsigned& cases, unsigned& changed, unsigned& bad, unsigned& hops,
+                                              unsigned long long& bytes) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
-    static_assert(G % GB == 0, "whole batches of groups");
+    static_assert(G == 4, "four row groups per thread");
+    // every direction word of the tile first, all in flight together (kept
+    // in named registers: the group loop below is not unrolled, and an array
+    // indexed by its counter would go to private memory)
+    unsigned w[2 * G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const TileGroup<NDIM> t = tile_group<NDIM>(gr, tile, k);
+        unsigned a = 0u, b = 0u;
+        if (t.vec) {
+            a = *reinterpret_cast<const unsigned*>(dirs_f + t.i0);
+            b = *reinterpret_cast<const unsigned*>(dirs_g + t.i0);
+        } else {
+            for (int j = 0; j < t.count; ++j) {
+                a |= static_cast<unsigned>(dirs_f[t.i0 + j]) << (8 * j);
+                b |= static_cast<unsigned>(dirs_g[t.i0 + j]) << (8 * j);
+            }
+        }
+        w[2 * k] = a;
+        w[2 * k + 1] = b;
+    }
+    const unsigned f0 = w[0], g0 = w[1], f1 = w[2], g1 = w[3], f2 = w[4], g2 = w[5], f3 = w[6], g3 = w[7];
 #pragma unroll 1
-    for (int k0 = 0; k0 < G; k0 += GB) {
-        int qu[GB][4], qd[GB][4], Mv[GB][4], mv[GB][4];
-        unsigned df4[GB], dg4[GB];
-        TileGroup<NDIM> tg[GB];
+    for (int k = 0; k < G; ++k) {
+        const unsigned dfw = k == 0 ? f0 : k == 1 ? f1 : k == 2 ? f2 : f3;
+        const unsigned dgw = k == 0 ? g0 : k == 1 ? g1 : k == 2 ? g2 : g3;
+        // bit j: vertex j's ascent (dup) / descent (ddn) differs (bytes past
+        // the group's count are equal zeros); up, dn: the labels to resolve
+        const unsigned x = dfw ^ dgw;
+        unsigned dup = 0, ddn = 0;
 #pragma unroll
-        for (int k = 0; k < GB; ++k) {
-            tg[k] = tile_group<NDIM>(gr, tile, k0 + k);
-            const int i0 = tg[k].i0;
-            df4[k] = dg4[k] = 0xFFFFFFFFu;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) qu[k][j] = qd[k][j] = Mv[k][j] = mv[k][j] = 0;
-            if (tg[k].vec) {
-                df4[k] = *reinterpret_cast<const unsigned*>(dirs_f + i0);
-                dg4[k] = *reinterpret_cast<const unsigned*>(dirs_g + i0);
-                const int4 u = *reinterpret_cast<const int4*>(q_up + i0);
-                const int4 d = *reinterpret_cast<const int4*>(q_dn + i0);
-                const int4 U = *reinterpret_cast<const int4*>(Mf + i0);
-                const int4 D = *reinterpret_cast<const int4*>(mf + i0);
-                qu[k][0] = u.x, qu[k][1] = u.y, qu[k][2] = u.z, qu[k][3] = u.w;
-                qd[k][0] = d.x, qd[k][1] = d.y, qd[k][2] = d.z, qd[k][3] = d.w;
-                Mv[k][0] = U.x, Mv[k][1] = U.y, Mv[k][2] = U.z, Mv[k][3] = U.w;
-                mv[k][0] = D.x, mv[k][1] = D.y, mv[k][2] = D.z, mv[k][3] = D.w;
-            } else {
-                for (int j = 0; j < tg[k].count; ++j) {
-                    const int i = i0 + j;
-                    df4[k] = (df4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_f[i]) << (8 * j));
-                    dg4[k] = (dg4[k] & ~(0xFFu << (8 * j))) | (static_cast<unsigned>(dirs_g[i]) << (8 * j));
-                    qu[k][j] = q_up[i], qd[k][j] = q_dn[i], Mv[k][j] = Mf[i], mv[k][j] = mf[i];
-                }
-            }
+        for (int j = 0; j < 4; ++j) {
+            dup |= ((x >> (8 * j + 4)) & 15u) ? 1u << j : 0u;
+            ddn |= ((x >> (8 * j)) & 15u) ? 1u << j : 0u;
         }
-        int y[8 * GB];  // the labels of the batch's vertices: their chains walked together
-#pragma unroll
-        for (int k = 0; k < GB; ++k)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                y[8 * k + 2 * j] = j < tg[k].count ? qu[k][j] : 0;
-                y[8 * k + 2 * j + 1] = j < tg[k].count ? qd[k][j] : 0;
+        const TileGroup<NDIM> t = tile_group<NDIM>(gr, tile, k);
+        const unsigned all = (1u << t.count) - 1u;
+        const unsigned up = full ? all : dup, dn = full ? all : ddn;
+        if (!__any(up | dn)) continue;
+        const int i0 = t.i0;
+        // pointers and f's labels of the differing vertices (int4 lanes x..w
+        // are the group's vertices 0..3; no arrays, which would be indexed
+        // at run time in the scalar path and go to private memory)
+        int4 u = make_int4(0, 0, 0, 0), U = u, d = u, D = u;
+        if (t.vec) {
+            if (up) {
+                u = *reinterpret_cast<const int4*>(q_up + i0);
+                U = *reinterpret_cast<const int4*>(Mf + i0);
+                bytes += 32;
             }
-        follow_roots<8 * GB>(q_up, q_dn, y, bad, hops);
-#pragma unroll
-        for (int k = 0; k < GB; ++k) {
-            int tn[4], tx[4], nloc = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                tn[j] = tx[j] = -1;
-                if (j >= tg[k].count) continue;
-                const int i = tg[k].i0 + j;
-                const unsigned df = (df4[k] >> (8 * j)) & 0xFFu, dg = (dg4[k] >> (8 * j)) & 0xFFu;
-                const bool wM = y[8 * k + 2 * j] != Mv[k][j];
-                const bool wm = y[8 * k + 2 * j + 1] != mv[k][j];
-                wrong += wM || wm;
-                const bool rmin = wm && ((dg & 15u) != (df & 15u));
-                const bool rmax = wM && ((dg >> 4) != (df >> 4));
-                cases += rmin + rmax;
-                nloc += rmin + rmax;
-                if (rmin) tn[j] = i + gr.off[df & 15u];
-                if (rmax) tx[j] = i + gr.off[dg >> 4];
+            if (dn) {
+                d = *reinterpret_cast<const int4*>(q_dn + i0);
+                D = *reinterpret_cast<const int4*>(mf + i0);
+                bytes += 32;
             }
-            if (tl.list) tl.add_wave<NDIM>(gr, tn, tx, nloc, changed);
+        } else {  // bits past the count are clear
+            if (up & 1u) u.x = q_up[i0], U.x = Mf[i0];
+            if (up & 2u) u.y = q_up[i0 + 1], U.y = Mf[i0 + 1];
+            if (up & 4u) u.z = q_up[i0 + 2], U.z = Mf[i0 + 2];
+            if (up & 8u) u.w = q_up[i0 + 3], U.w = Mf[i0 + 3];
+            if (dn & 1u) d.x = q_dn[i0], D.x = mf[i0];
+            if (dn & 2u) d.y = q_dn[i0 + 1], D.y = mf[i0 + 1];
+            if (dn & 4u) d.z = q_dn[i0 + 2], D.z = mf[i0 + 2];
+            if (dn & 8u) d.w = q_dn[i0 + 3], D.w = mf[i0 + 3];
+            bytes += 8 * (__popc(up) + __popc(dn));
         }
+        // chains of the differing directions only (0: nothing to follow)
+        int y[8] = {(up & 1u) ? u.x : 0, (dn & 1u) ? d.x : 0, (up & 2u) ? u.y : 0, (dn & 2u) ? d.y : 0,
+                    (up & 4u) ? u.z : 0, (dn & 4u) ? d.z : 0, (up & 8u) ? u.w : 0, (dn & 8u) ? d.w : 0};
+        follow_roots<8>(q_up, q_dn, y, bad, hops);
+        const int Ms[4] = {U.x, U.y, U.z, U.w}, ms[4] = {D.x, D.y, D.z, D.w};
+        int tn[4], tx[4], nloc = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            tn[j] = tx[j] = -1;
+            const int i = i0 + j;
+            const unsigned df = (dfw >> (8 * j)) & 0xFFu, dg = (dgw >> (8 * j)) & 0xFFu;
+            const bool wM = ((up >> j) & 1u) && y[2 * j] != Ms[j];
+            const bool wm = ((dn >> j) & 1u) && y[2 * j + 1] != ms[j];
+            wrong += wM || wm;  // all resolved only when full
+            const bool rmax = wM && ((dup >> j) & 1u);
+            const bool rmin = wm && ((ddn >> j) & 1u);
+            cases += rmin + rmax;
+            nloc += rmin + rmax;
+            if (rmin) tn[j] = i + gr.off[df & 15u];
+            if (rmax) tx[j] = i + gr.off[dg >> 4];
+        }
+        if (tl.list) tl.add_wave<NDIM>(gr, tn, tx, nloc, changed);
     }
 }
 
@@ -1564,8 +1598,10 @@ __device__ __forceinline__ void refresh_vertex(const EngField& F, int j, unsigne
 //   validate 16 B per vertex (20 with a warm start), directions of f 5,
 //   full direction and case pass over g 9, label tile 9 per vertex of a
 //   relabelled tile plus 10 per saved face vertex (16 per restored one of an
-//   unchanged tile), labels of f 16 and troublemakers 18 per vertex of a
-//   visited tile, both plus 4 per gather along an exit chain, deltas 16; an
+//   unchanged tile), labels of f 16 per vertex of a visited tile,
+//   troublemakers 2 per vertex of a visited tile plus 16 per direction of a
+//   4-vertex group whose labels are resolved, both plus 4 per gather along
+//   an exit chain, deltas 16; an
 //   apply or refresh 1 per scanned flag byte, plus 16 per
 //   edit attempt and 1 per neighbour flagged after a change (apply) or 9 per
 //   recomputed vertex and 32 per cleared flag word (refresh); the compression
@@ -1602,10 +1638,7 @@ __device__ __forceinline__ long long chunk_vertices(const Grid& gr, int lo, int 
 }
 
 // acct: this thread's share of the algorithmic bytes of the range (see above).
-// RGB: 4-vertex groups per thread whose label chains the troublemaker pass
-// walks together (more overlap their gathers; the one-field kernel has the
-// registers for two, the batch kernel for one).
-template <int NDIM, int RGB = 1>
+template <int NDIM>
 __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem,
                                               unsigned* cnt, unsigned long long& acct) {
     constexpr int NS = NDIM == 3 ? 14 : 6;
@@ -1775,9 +1808,11 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             __syncthreads();
             unsigned bad = 0, hops = 0;
             for (int item = lo; item < hi; ++item) {
-                detect_r_tile<NDIM, RGB>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, tl, wrong, cases,
-                                         changed, bad, hops);
-                if (lead) acct += 18 * tile_vertices<NDIM>(gr, item);
+                // the start field's count needs every mislabelled vertex;
+                // the loop's rounds need only the troublemakers
+                detect_r_tile<NDIM>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, st.init != 0, tl, wrong,
+                                    cases, changed, bad, hops, acct);
+                if (lead) acct += 2 * tile_vertices<NDIM>(gr, item);
                 __syncthreads();  // every wave's additions to the list are in s_targets
                 // past half the list: edit what it holds and empty it
                 if (tl.list && s_targets > TargetList::kCap / 2) {
@@ -1985,7 +2020,9 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
                 st.type = 0;
                 return c_decide();
             }
-            if (c[kCntWrong] == 0) return finish(MSZ_OK);
+            // no troublemaker exactly when no vertex is mislabelled (the
+            // detection of the rounds counts only the former)
+            if (c[kCntRCases] == 0) return finish(MSZ_OK);
             if (st.type != 0) return finish(MSZ_ENOCONV);
             if (c[kCntChanged] == 0) return finish(MSZ_ESTALL);
             S->rounds_total += 1;
@@ -2155,7 +2192,7 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
         const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
         const int per = (st.items + nb - 1) / nb;
         const int lo = b * per, hi = min(st.items, lo + per);
-        if (lo < hi) eng_run_range<NDIM, 2>(F, st, lo, hi, smem, c_cur, acct);
+        if (lo < hi) eng_run_range<NDIM>(F, st, lo, hi, smem, c_cur, acct);
     }
     if (ts) stamp_end(ts, acct);
 }
