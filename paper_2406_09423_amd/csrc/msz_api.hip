@@ -67,7 +67,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Workspace of one field.
 struct Layout {
-    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, tile_dirty, Mf, mf, qu, qd, total;
+    size_t L, g, dirs_f, dirs_g, marks, cases, dirty, chunk_dirty, chunk_cnt, chunk_unk, tile_dirty, Mf, mf, qu, qd, total;
 };
 
 Layout layout_for(const Grid& gr) {
@@ -86,6 +86,9 @@ Layout layout_for(const Grid& gr) {
     l.marks = take((n + 15) & ~int64_t(15));
     l.cases = take((n + 15) & ~int64_t(15));
     l.dirty = take((n + 15) & ~int64_t(15));
+    l.chunk_dirty = take(((n + kEngChunk - 1) / kEngChunk) * 4);
+    l.chunk_cnt = take(((n + kEngChunk - 1) / kEngChunk) * 8);
+    l.chunk_unk = take(((n + kEngChunk - 1) / kEngChunk) * 4);
     l.tile_dirty = take(label_tile_count(gr));
     l.Mf = take(n * 4);
     l.mf = take(n * 4);
@@ -446,6 +449,12 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         last_launches().clear();
     }
     for (int j = 0; j < nf; ++j) tab[j].cnt = E.counters + static_cast<size_t>(j) * kCntBlockWords;
+    // a single field keeps chunk summaries of its flag arrays when each block
+    // of the step kernel scans at least kSelectChunks chunks
+    if (single) {
+        const int64_t chunks = (static_cast<int64_t>(tab[0].gr.n) + kEngChunk - 1) / kEngChunk;
+        tab[0].sum = chunks >= static_cast<int64_t>(kSelectChunks) * (has3 ? grid3 : grid2) ? 1 : 0;
+    }
     if (int rc = E.graph_for(nf, n2, timing, grid2, grid3)) {
         E.drop_graph();
         return rc;
@@ -646,6 +655,9 @@ void bind_field(EngField& F, char* w) {
     F.marks = reinterpret_cast<uint8_t*>(w + l.marks);
     F.cases = reinterpret_cast<uint8_t*>(w + l.cases);
     F.dirty = reinterpret_cast<uint8_t*>(w + l.dirty);
+    F.chunk_dirty = reinterpret_cast<unsigned*>(w + l.chunk_dirty);
+    F.chunk_cnt = reinterpret_cast<unsigned*>(w + l.chunk_cnt);
+    F.chunk_unk = reinterpret_cast<unsigned*>(w + l.chunk_unk);
     F.tile_dirty = reinterpret_cast<uint8_t*>(w + l.tile_dirty);
     F.Mf = reinterpret_cast<int*>(w + l.Mf);
     F.mf = reinterpret_cast<int*>(w + l.mf);

@@ -135,7 +135,9 @@ constexpr int kEngTimeSlots = 48;                   // steps per graph launch (a
 constexpr int kEngEndSlots = 64;                    // per timed step: start, 64 slots of block ends,
 constexpr int kEngBytesWord = 1 + kEngEndSlots;     // then the algorithmic bytes the step's blocks visited
 constexpr int kEngStampWords = 2 + kEngEndSlots;
-constexpr int kEngChunk = 4096;                     // vertices per flat work item
+constexpr int kEngChunkShift = 12;
+constexpr int kEngChunk = 1 << kEngChunkShift;      // vertices per flat work item
+constexpr int kSelectChunks = 8;                    // a block's range of chunks from which flag scans select
 constexpr int kHostStatsWord = 32;                  // final statistics in the host word block, from word 32
 
 enum EngOp : int {
@@ -166,6 +168,7 @@ struct EngField {
     int merged;      // 1: merged C rounds
     int preempt;     // 1: shared targets edited without claims (preemptive mode; implies merged)
     int count_init;  // 1: label the start field once and count its mislabelled vertices
+    int sum;         // 1: keep chunk summaries of the flag arrays and skip empty chunks (large single fields)
     float xi;
     long long cap;
     const float *f, *fhat, *warm;
@@ -174,6 +177,10 @@ struct EngField {
     uint8_t *dirs_f, *dirs_g, *marks;
     uint8_t *cases;  // per vertex: bit t set when it is a case of type t (FPmax, FPmin, FNmax, FNmin)
     uint8_t *dirty;  // per vertex: its directions in g must be recomputed (it or a neighbour was edited)
+    unsigned* chunk_dirty;  // per kEngChunk vertices: 1 when some dirty flag of the chunk may be set
+    unsigned* chunk_cnt;    // per kEngChunk vertices, 2 words: the number of cases of types 0, 1 (16-bit
+                            // halves of word 0) and 2, 3 (word 1) in the chunk -- exact unless chunk_unk
+    unsigned* chunk_unk;    // per kEngChunk vertices: 1 when the counts are not known (after a full pass)
     uint8_t *tile_dirty;  // per label tile: a direction of g in it changed since its last tile pass
     int *Mf, *mf, *qu, *qd;
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block

@@ -561,14 +561,27 @@ __device__ __forceinline__ bool slot_in_grid(const Grid& gr, int x, int y, int z
     return NDIM == 2 ? in2 : in2 && z + dz >= 0 && z + dz < gr.nz;
 }
 
+// The refresh flags: one byte per vertex, and per kEngChunk vertices a word
+// that is set when some flag of the chunk may be (chunk: NULL where the
+// summaries are not kept), so that a refresh reads only the chunks an edit
+// touched.
+struct Dirty {
+    uint8_t* v;
+    unsigned* chunk;
+    __device__ __forceinline__ void mark(int i) const {
+        v[i] = 1;
+        if (chunk) chunk[i >> kEngChunkShift] = 1u;
+    }
+};
+
 // Halves g[t] once, from its value old and floor lt as read by the caller;
 // flags t (so the refresh clears its mark) and, if the value changed, its
 // neighbours.
 template <int NDIM>
-__device__ __forceinline__ void edit_value(float* __restrict__ g, uint8_t* __restrict__ dirty, const Grid& gr,
+__device__ __forceinline__ void edit_value(float* __restrict__ g, const Dirty& dirty, const Grid& gr,
                                            int t, float old, float lt, unsigned& changed) {
     const float nv = halve(old, lt);
-    dirty[t] = 1;
+    dirty.mark(t);
     if (nv == old) return;
     g[t] = nv;
     ++changed;
@@ -576,12 +589,12 @@ __device__ __forceinline__ void edit_value(float* __restrict__ g, uint8_t* __res
     constexpr int NS = NDIM == 3 ? 14 : 6;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-        if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
+        if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty.mark(t + gr.off[s]);
 }
 
 template <int NDIM>
 __device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* __restrict__ L,
-                                            uint8_t* __restrict__ dirty, const Grid& gr, int t, unsigned& changed) {
+                                            const Dirty& dirty, const Grid& gr, int t, unsigned& changed) {
     edit_value<NDIM>(g, dirty, gr, t, g[t], L[t], changed);
 }
 
@@ -592,7 +605,7 @@ __device__ __forceinline__ void edit_vertex(float* __restrict__ g, const float* 
 // the winner writes g[t], so the value read is the round's.
 template <int NDIM>
 __device__ __forceinline__ void claim_edit(uint8_t* __restrict__ marks, float* __restrict__ g,
-                                           const float* __restrict__ L, uint8_t* __restrict__ dirty,
+                                           const float* __restrict__ L, const Dirty& dirty,
                                            const Grid& gr, int t, unsigned& changed) {
     const unsigned bit = 1u << (8 * (t & 3));
     // relaxed workgroup-scope atomic loads: plain cached loads that the
@@ -613,10 +626,10 @@ __device__ __forceinline__ void claim_edit(uint8_t* __restrict__ marks, float* _
 // lowers each target it changes and the loop ends as the synchronous one does.
 template <int NDIM>
 __device__ __forceinline__ void preempt_edit(float* __restrict__ g, const float* __restrict__ L,
-                                             uint8_t* __restrict__ dirty, const Grid& gr, int t, unsigned& changed) {
+                                             const Dirty& dirty, const Grid& gr, int t, unsigned& changed) {
     const float old = __hip_atomic_load(g + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const float nv = halve(old, L[t]);
-    dirty[t] = 1;
+    dirty.mark(t);
     if (nv == old) return;
     __hip_atomic_store(g + t, nv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ++changed;
@@ -624,13 +637,13 @@ __device__ __forceinline__ void preempt_edit(float* __restrict__ g, const float*
     constexpr int NS = NDIM == 3 ? 14 : 6;
 #pragma unroll
     for (int s = 0; s < NS; ++s)
-        if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty[t + gr.off[s]] = 1;
+        if (slot_in_grid<NDIM>(gr, x, y, z, s)) dirty.mark(t + gr.off[s]);
 }
 
 // A shared target's edit: claimed (synchronous rounds) or preemptive.
 template <int NDIM>
 __device__ __forceinline__ void target_edit(bool preempt, uint8_t* __restrict__ marks, float* __restrict__ g,
-                                            const float* __restrict__ L, uint8_t* __restrict__ dirty,
+                                            const float* __restrict__ L, const Dirty& dirty,
                                             const Grid& gr, int t, unsigned& changed) {
     if (preempt) preempt_edit<NDIM>(g, L, dirty, gr, t, changed);
     else claim_edit<NDIM>(marks, g, L, dirty, gr, t, changed);
@@ -1084,7 +1097,7 @@ struct TargetList {
     uint8_t* marks;
     float* g;
     const float* L;
-    uint8_t* dirty;
+    Dirty dirty;
     bool preempt;  // edits without claims (preemptive mode)
     template <int NDIM>
     __device__ __forceinline__ void put(const Grid& gr, unsigned k, int t, unsigned& changed) const {
@@ -1498,37 +1511,71 @@ __device__ __forceinline__ unsigned steepest_at(const float* __restrict__ g, con
 // Runs fn(v) for every flagged vertex v of the chunks [lo, hi) (kEngChunk
 // vertices each; thread t loads the 16 flag bytes t of a chunk, and a byte
 // flags its vertex when it has a bit of `mask` set; bytes past the grid are
-// never set).  The flagged vertices are first gathered into an LDS list so
-// that all threads of the block work on them at once: one memory round trip
-// for the whole range instead of one per vertex and thread.  after_load(w)
-// runs once per loaded word w that flagged something, after it was read.
-// list: LDS of kEngChunk ints; wsum: 4 ints.
-template <typename Fn, typename AfterLoad>
-__device__ __forceinline__ void for_flagged(const uint8_t* flags, int n, int lo, int hi, unsigned mask, int* list,
-                                            int* wsum, Fn&& fn, AfterLoad&& after_load) {
+// never set).  With use_sel, a range of at least kSelectChunks chunks reads only the
+// chunks c with sel(c): the block evaluates sel for 256 chunks at once (one
+// per thread) and takes the selected ones from its ballots, so a range with
+// none costs one summary load per thread; after chunk c was read, thread 0
+// calls done(c, w0, w1), where with COUNT w0 and w1 hold the numbers of its
+// bytes with bit 0 and 1 (low and high 16 bits of w0) and bit 2 and 3 (w1)
+// set.  A shorter range reads every chunk and calls neither (its summaries
+// are left as they were).  The flagged vertices are gathered into an LDS
+// list so that all threads of the block work on them at once: one memory
+// round trip for the whole range instead of one per vertex and thread.
+// after_load(w) runs once per loaded word w that flagged something, after
+// it was read.  list: LDS of kEngChunk ints; wsum: 4 ints.  Returns the
+// number of chunks read.
+template <bool COUNT, typename Sel, typename Done, typename Fn, typename AfterLoad>
+__device__ __forceinline__ int for_flagged(const uint8_t* flags, int n, int lo, int hi, unsigned mask, bool use_sel,
+                                           int* list, int* wsum, Sel&& sel, Done&& done, Fn&& fn,
+                                           AfterLoad&& after_load) {
     constexpr int MAXW = 4;  // chunks gathered together
     const int nw = (n + 15) >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c0 = lo; c0 < hi; c0 += MAXW) {
+    const bool select = use_sel && hi - lo >= kSelectChunks;  // block-uniform
+    __shared__ unsigned long long s_sel[4];
+    __shared__ unsigned s_cnt[MAXW][2];
+    if (COUNT && select && threadIdx.x < 2 * MAXW) s_cnt[threadIdx.x >> 1][threadIdx.x & 1] = 0u;  // read after a barrier
+    int read = 0;
+    // one group of up to MAXW chunks (-1: none)
+    auto group = [&](const int (&ch)[MAXW]) {
         unsigned m[MAXW][4];
         int cnt = 0;
 #pragma unroll
         for (int k = 0; k < MAXW; ++k) {
-            const int w = (c0 + k) * (kEngChunk / 16) + threadIdx.x;
-            const uint4 u = (c0 + k < hi && w < nw) ? reinterpret_cast<const uint4*>(flags)[w]
-                                                    : make_uint4(0u, 0u, 0u, 0u);
+            read += ch[k] >= 0;
+            const int w = ch[k] * (kEngChunk / 16) + threadIdx.x;
+            const uint4 u = (ch[k] >= 0 && w < nw) ? reinterpret_cast<const uint4*>(flags)[w]
+                                                   : make_uint4(0u, 0u, 0u, 0u);
+            if (COUNT && select) {  // bytes with bit t set, over the block (16-bit lanes: at most 4096)
+                unsigned c01 = 0u, c23 = 0u;
+                const unsigned q4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    c01 += __popc(q4[q] & 0x01010101u) + 65536u * __popc(q4[q] & 0x02020202u);
+                    c23 += __popc(q4[q] & 0x04040404u) + 65536u * __popc(q4[q] & 0x08080808u);
+                }
+#pragma unroll
+                for (int sh = 32; sh > 0; sh >>= 1) {
+                    c01 += __shfl_xor(c01, sh);
+                    c23 += __shfl_xor(c23, sh);
+                }
+                if (lane == 0 && ch[k] >= 0) {
+                    atomicAdd(&s_cnt[k][0], c01);
+                    atomicAdd(&s_cnt[k][1], c23);
+                }
+            }
             m[k][0] = u.x & mask, m[k][1] = u.y & mask, m[k][2] = u.z & mask, m[k][3] = u.w & mask;
         }
 #pragma unroll
         for (int k = 0; k < MAXW; ++k) {
             const unsigned any = m[k][0] | m[k][1] | m[k][2] | m[k][3];
-            if (any) after_load((c0 + k) * (kEngChunk / 16) + threadIdx.x);
+            if (any) after_load(ch[k] * (kEngChunk / 16) + threadIdx.x);
             // one flagged vertex per byte: count the bytes with a bit set
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const unsigned b = m[k][q];
-                const unsigned nz = (b | (b >> 1) | (b >> 2) | (b >> 3) | (b >> 4) | (b >> 5) | (b >> 6) | (b >> 7)) &
-                                    0x01010101u;
+                const unsigned nz =
+                    (b | (b >> 1) | (b >> 2) | (b >> 3) | (b >> 4) | (b >> 5) | (b >> 6) | (b >> 7)) & 0x01010101u;
                 m[k][q] = nz;
                 cnt += __popc(nz);
             }
@@ -1541,30 +1588,38 @@ __device__ __forceinline__ void for_flagged(const uint8_t* flags, int n, int lo,
             if (lane >= o) incl += v;
         }
         if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        int base = 0, total = 0;
+        __syncthreads();  // wsum and s_cnt are complete
+        int base_pos = 0, total = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int t = wsum[k];
-            base += k < wave ? t : 0;
+            base_pos += k < wave ? t : 0;
             total += t;
         }
-        __syncthreads();  // wsum is rewritten by the next range
+        if (select && threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k)
+                if (ch[k] >= 0) {
+                    done(ch[k], COUNT ? s_cnt[k][0] : 0u, COUNT ? s_cnt[k][1] : 0u);
+                    if (COUNT) s_cnt[k][0] = s_cnt[k][1] = 0u;
+                }
+        }
+        __syncthreads();  // wsum and s_cnt are rewritten by the next group
         // the list holds kEngChunk entries; more are done in several passes
         for (int pass = 0; pass * kEngChunk < total; ++pass) {
             const int p0 = pass * kEngChunk;
-            int pos = base + incl - cnt;
+            int pos = base_pos + incl - cnt;
             if (pos < p0 + kEngChunk && pos + cnt > p0) {
 #pragma unroll
                 for (int k = 0; k < MAXW; ++k)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        unsigned bits = m[k][q];
-                        while (bits) {
-                            const int b = (__ffs(bits) - 1) >> 3;
-                            bits &= bits - 1u;
+                        unsigned bb = m[k][q];
+                        while (bb) {
+                            const int b = (__ffs(bb) - 1) >> 3;
+                            bb &= bb - 1u;
                             if (pos >= p0 && pos < p0 + kEngChunk)
-                                list[pos - p0] = (c0 + k) * kEngChunk + 16 * threadIdx.x + 4 * q + b;
+                                list[pos - p0] = ch[k] * kEngChunk + 16 * threadIdx.x + 4 * q + b;
                             ++pos;
                         }
                     }
@@ -1574,19 +1629,71 @@ __device__ __forceinline__ void for_flagged(const uint8_t* flags, int n, int lo,
             for (int e = threadIdx.x; e < np; e += blockDim.x) fn(list[e]);
             __syncthreads();  // the list is rewritten next
         }
+    };
+    if (!select) {
+        for (int c0 = lo; c0 < hi; c0 += MAXW) {
+            int ch[MAXW];
+#pragma unroll
+            for (int k = 0; k < MAXW; ++k) ch[k] = c0 + k < hi ? c0 + k : -1;
+            group(ch);
+        }
+        return read;
     }
+    for (int base = lo; base < hi; base += 256) {
+        const int mine = base + static_cast<int>(threadIdx.x);
+        const unsigned long long bw = __ballot(mine < hi && sel(mine));
+        if (lane == 0) s_sel[wave] = bw;
+        __syncthreads();
+        unsigned long long sel4[4];  // block-uniform
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sel4[w] = s_sel[w];
+        __syncthreads();  // s_sel is rewritten by the next window
+        for (int sw = 0; sw < 4; ++sw) {
+            unsigned long long bits = sel4[sw];
+            while (bits) {
+                int ch[MAXW];
+#pragma unroll
+                for (int k = 0; k < MAXW; ++k) {
+                    ch[k] = bits ? base + 64 * sw + __ffsll(static_cast<long long>(bits)) - 1 : -1;
+                    bits &= bits - 1;
+                }
+                group(ch);
+            }
+        }
+    }
+    return read;
+}
+
+__device__ __forceinline__ Dirty dirty_of(const EngField& F, bool sum) { return Dirty{F.dirty, sum ? F.chunk_dirty : nullptr}; }
+
+// An apply's record of a chunk it read in full: its exact case counts.
+__device__ __forceinline__ auto chunk_counted(const EngField& F) {
+    return [&F](int c, unsigned w0, unsigned w1) {
+        F.chunk_cnt[2 * c] = w0;
+        F.chunk_cnt[2 * c + 1] = w1;
+        F.chunk_unk[c] = 0u;
+    };
 }
 
 // Directions and case byte of vertex j recomputed from g; c receives the
 // change of each case count (modulo 2^32), and j's label tile is flagged if
 // its direction changed.
 template <int NDIM>
-__device__ __forceinline__ void refresh_vertex(const EngField& F, int j, unsigned (&c)[4]) {
+__device__ __forceinline__ void refresh_vertex(const EngField& F, int j, bool sum, unsigned (&c)[4]) {
     const unsigned dg = steepest_at<NDIM>(F.g, F.gr, j);
     const unsigned now = case_bits(F.dirs_f[j], dg), was = F.cases[j];
     if (dg != F.dirs_g[j]) F.tile_dirty[tile_of_vertex<NDIM>(F.gr, j)] = 1;
     F.dirs_g[j] = static_cast<uint8_t>(dg);
     F.cases[j] = static_cast<uint8_t>(now);
+    if (sum && now != was) {  // the chunk's case counts: types 0, 1 in word 0, types 2, 3 in word 1 (16 bits each)
+        const int d0 = static_cast<int>(now & 1u) - static_cast<int>(was & 1u);
+        const int d1 = static_cast<int>((now >> 1) & 1u) - static_cast<int>((was >> 1) & 1u);
+        const int d2 = static_cast<int>((now >> 2) & 1u) - static_cast<int>((was >> 2) & 1u);
+        const int d3 = static_cast<int>((now >> 3) & 1u) - static_cast<int>((was >> 3) & 1u);
+        unsigned* w = F.chunk_cnt + 2 * (j >> kEngChunkShift);
+        if (d0 | d1) atomicAdd(w, static_cast<unsigned>(d0 + d1 * 65536));
+        if (d2 | d3) atomicAdd(w + 1, static_cast<unsigned>(d2 + d3 * 65536));
+    }
 #pragma unroll
     for (int t = 0; t < 4; ++t) c[t] += ((now >> t) & 1u) - ((was >> t) & 1u);
 }
@@ -1602,7 +1709,9 @@ __device__ __forceinline__ void refresh_vertex(const EngField& F, int j, unsigne
 //   troublemakers 2 per vertex of a visited tile plus 16 per direction of a
 //   4-vertex group whose labels are resolved, both plus 4 per gather along
 //   an exit chain, deltas 16; an
-//   apply or refresh 1 per scanned flag byte, plus 16 per
+//   apply or refresh 1 per flag byte of a chunk it reads (an apply reads only
+//   chunks that may hold a case of its type, a refresh only chunks an edit
+//   touched) and 12 (apply) or 4 (refresh) per chunk summary, plus 16 per
 //   edit attempt and 1 per neighbour flagged after a change (apply) or 9 per
 //   recomputed vertex and 32 per cleared flag word (refresh); the compression
 //   4 per pointer load or store of its walks and root records.
@@ -1638,11 +1747,16 @@ __device__ __forceinline__ long long chunk_vertices(const Grid& gr, int lo, int 
 }
 
 // acct: this thread's share of the algorithmic bytes of the range (see above).
-template <int NDIM>
+// SUM: keep and use the chunk summaries of the flag arrays where the field
+// asks for them (F.sum: the one-field kernel on a field whose blocks scan
+// long ranges of chunks; a batch step sizes its blocks' shares for a full
+// scan and waits for the slowest, so skipping chunks gains it nothing).
+template <int NDIM, bool SUM>
 __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState& st, int lo, int hi, char* smem,
                                               unsigned* cnt, unsigned long long& acct) {
     constexpr int NS = NDIM == 3 ? 14 : 6;
     const bool lead = threadIdx.x == 0;  // adds the bytes that are fixed per range
+    const bool sum = SUM && F.sum != 0;  // this field keeps chunk summaries
     const Grid& gr = F.gr;
     int* su = reinterpret_cast<int*>(smem);
     int* sd = su + 4096;
@@ -1703,45 +1817,55 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             unsigned changed = 0, tries = 0;
             int* list = reinterpret_cast<int*>(smem);
             const int type = st.type;
-            if (lead) acct += chunk_vertices(gr, lo, hi);  // the case bytes scanned
+            int scanned = 0;  // chunks whose case bytes were read
             if (type == kTypeMerged) {
                 // every case of every type; all targets claimed, so a vertex
                 // proposed by several cases is edited once (or, preemptive,
                 // edited by each case that gets there, racing)
                 const bool pre = F.preempt != 0;
-                for_flagged(
-                    F.cases, gr.n, lo, hi, 0x0F0F0F0Fu, list, list + kEngChunk,
+                const Dirty dirty = dirty_of(F, sum);
+                scanned = for_flagged<true>(
+                    F.cases, gr.n, lo, hi, 0x0F0F0F0Fu, sum, list, list + kEngChunk,
+                    [&](int c) { return F.chunk_unk[c] != 0u || (F.chunk_cnt[2 * c] | F.chunk_cnt[2 * c + 1]) != 0u; },
+                    chunk_counted(F),
                     [&](int i) {
                         const unsigned b = F.cases[i];
                         tries += __popc(b & 0xFu);
-                        if (b & 9u) target_edit<NDIM>(pre, F.marks, F.g, F.L, F.dirty, gr, i, changed);
+                        if (b & 9u) target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i, changed);
                         if (b & 2u)
-                            target_edit<NDIM>(pre, F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_f[i] & 15u],
+                            target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i + gr.off[F.dirs_f[i] & 15u],
                                               changed);
                         if (b & 4u)
-                            target_edit<NDIM>(pre, F.marks, F.g, F.L, F.dirty, gr, i + gr.off[F.dirs_g[i] >> 4],
+                            target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i + gr.off[F.dirs_g[i] >> 4],
                                               changed);
                     },
                     [](int) {});
+                if (lead) acct += 12ull * (hi - lo) + static_cast<unsigned long long>(scanned) * kEngChunk;
                 acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed;
                 unsigned v[1] = {changed};
                 const int idx[1] = {kCntChanged};
                 block_add<1>(v, cnt, idx);
                 break;
             }
-            for_flagged(
-                F.cases, gr.n, lo, hi, 0x01010101u << type, list, list + kEngChunk,
+            const Dirty dirty = dirty_of(F, sum);
+            scanned = for_flagged<true>(
+                F.cases, gr.n, lo, hi, 0x01010101u << type, sum, list, list + kEngChunk,
+                [&](int c) {
+                    return F.chunk_unk[c] != 0u || ((F.chunk_cnt[2 * c + (type >> 1)] >> (16 * (type & 1))) & 0xFFFFu);
+                },
+                chunk_counted(F),
                 [&](int i) {
                     ++tries;
                     if (type == 0 || type == 3) {
-                        edit_vertex<NDIM>(F.g, F.L, F.dirty, gr, i, changed);
+                        edit_vertex<NDIM>(F.g, F.L, dirty, gr, i, changed);
                         return;
                     }
                     // FPmin and FNmax targets may be shared
                     const int t = i + gr.off[type == 1 ? (F.dirs_f[i] & 15u) : (F.dirs_g[i] >> 4)];
-                    claim_edit<NDIM>(F.marks, F.g, F.L, F.dirty, gr, t, changed);
+                    claim_edit<NDIM>(F.marks, F.g, F.L, dirty, gr, t, changed);
                 },
                 [](int) {});
+            if (lead) acct += 12ull * (hi - lo) + static_cast<unsigned long long>(scanned) * kEngChunk;
             acct += 16ull * tries + static_cast<unsigned long long>(NS) * changed;
             unsigned v[1] = {changed};
             const int idx[1] = {kCntChanged};
@@ -1758,6 +1882,14 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             // every label tile is redone next time: this range's share of the flags
             const long long nt = label_tiles_of(gr), items = eng_items(F, st.op);
             for (long long t = lo * nt / items + threadIdx.x; t < hi * nt / items; t += blockDim.x) F.tile_dirty[t] = 1;
+            // and every refresh flag is cleared, every case byte rewritten:
+            // this range's share of the chunk summaries (counts unknown until
+            // the next apply reads the chunk)
+            const long long nc = (gr.n + kEngChunk - 1) / kEngChunk;
+            for (long long t = lo * nc / items + threadIdx.x; sum && t < hi * nc / items; t += blockDim.x) {
+                F.chunk_dirty[t] = 0u;
+                F.chunk_unk[t] = 1u;
+            }
             break;
         }
         case kOpRefreshC:
@@ -1767,10 +1899,12 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             unsigned c[4] = {0u, 0u, 0u, 0u};
             unsigned nv = 0, nw = 0;
             int* list = reinterpret_cast<int*>(smem);
-            for_flagged(
-                F.dirty, gr.n, lo, hi, 0xFFFFFFFFu, list, list + kEngChunk,
+            const int scanned = for_flagged<false>(
+                F.dirty, gr.n, lo, hi, 0xFFFFFFFFu, sum, list, list + kEngChunk,
+                [&](int c) { return F.chunk_dirty[c] != 0u; },
+                [&](int c, unsigned, unsigned) { F.chunk_dirty[c] = 0u; },
                 [&](int j) {
-                    refresh_vertex<NDIM>(F, j, c);
+                    refresh_vertex<NDIM>(F, j, sum, c);
                     ++nv;
                 },
                 [&](int w) {
@@ -1780,7 +1914,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 });
             block_add<4>(c, cnt, cidx);
             acct += 9ull * nv + 32ull * nw;
-            if (lead) acct += chunk_vertices(gr, lo, hi);
+            if (lead) acct += 4ull * (hi - lo) + static_cast<unsigned long long>(scanned) * kEngChunk;
             break;
         }
         case kOpRDetect: {
@@ -1793,13 +1927,13 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             __shared__ unsigned s_targets;
             unsigned wrong = 0, cases = 0, changed = 0;
             const TargetList tl{st.type == 0 ? reinterpret_cast<int*>(smem) : nullptr, &s_targets, F.marks, F.g,
-                                F.L, F.dirty, F.preempt != 0};
+                                F.L, dirty_of(F, sum), F.preempt != 0};
             // the listed targets, edited by all threads; ends with a barrier
             unsigned tries = 0;
             auto edit_targets = [&]() {
                 const int nt = min(static_cast<int>(s_targets), TargetList::kCap);
                 for (int e = threadIdx.x; e < nt; e += blockDim.x) {
-                    target_edit<NDIM>(tl.preempt, F.marks, F.g, F.L, F.dirty, gr, tl.list[e], changed);
+                    target_edit<NDIM>(tl.preempt, F.marks, F.g, F.L, tl.dirty, gr, tl.list[e], changed);
                     ++tries;
                 }
                 __syncthreads();
@@ -1879,7 +2013,7 @@ __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ field
         const EngState st = cur[a];
         const int w = eng_weight(fields[a], st.op);
         const int i0 = (lo - base + w - 1) / w, i1 = (end - base + w - 1) / w;
-        if (i0 < i1) eng_run_range<NDIM>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
+        if (i0 < i1) eng_run_range<NDIM, false>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
         lo = end;
     }
 }
@@ -2192,7 +2326,7 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
         const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
         const int per = (st.items + nb - 1) / nb;
         const int lo = b * per, hi = min(st.items, lo + per);
-        if (lo < hi) eng_run_range<NDIM>(F, st, lo, hi, smem, c_cur, acct);
+        if (lo < hi) eng_run_range<NDIM, true>(F, st, lo, hi, smem, c_cur, acct);
     }
     if (ts) stamp_end(ts, acct);
 }
@@ -2245,9 +2379,15 @@ __global__ void __launch_bounds__(256) k_eng_setup1(const EngField F, EngField* 
         reinterpret_cast<uint4*>(F.cases)[w] = make_uint4(0u, 0u, 0u, 0u);
         reinterpret_cast<uint4*>(F.dirty)[w] = make_uint4(0u, 0u, 0u, 0u);
     }
+    const int nc = (F.gr.n + kEngChunk - 1) / kEngChunk;
+    for (int c = tid; c < nc; c += nthr) {
+        F.chunk_dirty[c] = F.chunk_cnt[2 * c] = F.chunk_cnt[2 * c + 1] = 0u;
+        F.chunk_unk[c] = 1u;
+    }
 }
 
-// Clears every field's marks, case bytes, dirty flags and counter block.
+// Clears every field's marks, case bytes, dirty flags, their chunk summaries
+// and counter block.
 __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ fields, int nf) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nthr = gridDim.x * blockDim.x;
     for (int f = 0; f < nf; ++f) {
@@ -2260,6 +2400,11 @@ __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ f
             m[w] = make_uint4(0u, 0u, 0u, 0u);
             cs[w] = make_uint4(0u, 0u, 0u, 0u);
             dt[w] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        const int nc = (F.gr.n + kEngChunk - 1) / kEngChunk;
+        for (int c = tid; c < nc; c += nthr) {
+            F.chunk_dirty[c] = F.chunk_cnt[2 * c] = F.chunk_cnt[2 * c + 1] = 0u;
+            F.chunk_unk[c] = 1u;
         }
         for (int w = tid; w < kCntBlockWords; w += nthr) F.cnt[w] = 0u;
     }

@@ -427,6 +427,30 @@ def test_full_turb512_learned_properties(msz):
     assert rounds(st_l) < rounds(st_p), (rounds(st_l), rounds(st_p))
 
 
+@pytest.mark.parametrize("merged", [False, True])
+def test_turb512_chunk_summaries_bit_exact(msz, merged):
+    """At 512^3 the one-field kernel keeps chunk summaries of its flag arrays
+    and skips chunks with nothing flagged; the batch kernel never does.  The
+    field corrected alone and corrected in a batch (beside a tiny field, so
+    that the batch kernels run) must agree bit for bit, with equal stats."""
+    f, fh, xi = synth.turb512()[0]
+    _say(f"512^3 summaries vs batch, merged={merged}")
+    fd, fhd = dev(f), dev(fh)
+    del f, fh
+    rc, d1, g1, st1 = msz.fix(fd, fhd, xi, merged=merged)
+    assert rc == msz.OK
+    b1, b2 = _bits(host(g1)), _bits(host(d1))
+    del d1, g1
+    rng = np.random.default_rng(5)
+    tf = rng.uniform(0, 1, size=(9, 10, 11)).astype(np.float32)
+    rc_b, res = msz.fix_batch([(fd, fhd, xi), (dev(tf), dev(synth.quantize(tf, np.float32(0.05))), 0.05)],
+                              merged=merged)
+    assert rc_b == msz.OK
+    st_b, d2, g2, st2 = res[0]
+    assert st_b == msz.OK and st1 == st2
+    assert (_bits(host(g2)) == b1).all() and (_bits(host(d2)) == b2).all()
+
+
 # ------------------------------------------------------- merged C rounds ---
 
 def _merged_case(name):
