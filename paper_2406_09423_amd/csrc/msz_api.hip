@@ -331,7 +331,8 @@ struct EngineCtx {
                     return MSZ_EDEVICE;
                 void* dd[] = {&fp, &cur, &nxt, &sp, &cnt, &log, &stp};
                 if (!add_kernel(eng_decide_kernel(), dim3(cnt), dim3(256), dd)) return MSZ_EDEVICE;
-                void* c[] = {&fp, &nxt, &cnt, &pre, &word};
+                int gridv = d == 0 ? grid2 : grid3;
+                void* c[] = {&fp, &nxt, &cnt, &pre, &word, &gridv};
                 if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
             }
             if (hipGraphInstantiate(&exec[d], graph[d], nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
@@ -421,15 +422,14 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
     for (int p = 0; p < nf; ++p) tab[p] = hf[order[p]];
     int n2 = 0;
     std::vector<EngState> hs(2 * nf);
-    std::vector<int> p2(1, 0), p3(1, 0);
+    std::vector<int64_t> u2, u3;  // a batch: each chain's fields' units (items x weight) of the first step
     for (int j = 0; j < nf; ++j) {
         const int items = eng_items_host(tab[j], kOpPreA);
         hs[j] = EngState{kOpPreA, 0, items, 0};
         hs[nf + j] = EngState{kOpDone, 0, 0, 0};
         const bool three = tab[j].gr.ndim == 3;
         n2 += !three;
-        std::vector<int>& p = three ? p3 : p2;
-        p.push_back(p.back() + (single ? items : items * eng_weight_host(tab[j], kOpPreA)));
+        (three ? u3 : u2).push_back(static_cast<int64_t>(items) * eng_weight_host(tab[j], kOpPreA));
     }
     const int n3 = nf - n2;
     const bool has2 = n2 > 0, has3 = n3 > 0;
@@ -443,7 +443,23 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         // decision itself, and twice as many cost 38% more.
         grid2 *= 2;
         grid3 *= 2;
+        // every field of a chain needs a block of its own in a step
+        grid2 = std::max(grid2, n2 + 1);
+        grid3 = std::max(grid3, n3 + 1);
     }
+    // the first step's blocks per field, as k_eng_scan assigns them for the
+    // steps after it
+    auto block_prefix = [](const std::vector<int64_t>& u, int grid) {
+        const int m = static_cast<int>(u.size());
+        int64_t total = 0;
+        for (int64_t x : u) total += x;
+        const int64_t slots = grid > m ? grid - m : 1;
+        const int64_t per = total > 0 ? (total + slots - 1) / slots : 1;
+        std::vector<int> p(m + 1, 0);
+        for (int i = 0; i < m; ++i) p[i + 1] = p[i] + static_cast<int>((u[i] + per - 1) / per);
+        return p;
+    };
+    const std::vector<int> p2 = block_prefix(u2, grid2), p3 = block_prefix(u3, grid3);
     if (timing) {
         last_schedule().clear();
         last_launches().clear();

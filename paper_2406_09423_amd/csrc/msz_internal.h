@@ -203,7 +203,7 @@ int eng_weight_host(const EngField& F, int op);  // cost units of one item (batc
 int label_tile_count(const Grid& gr);   // label tiles of the grid
 const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
 const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, oplog, step)
-const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre, word)
+const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre, word, grid)
 const void* eng_init_kernel();          // k_eng_init(fields, nf)
 const void* eng_setup1_kernel();        // k_eng_setup1(F, fields, states, stats, cnt3, ctl, done_word)
 const void* eng_step1_kernel(int ndim); // k_eng_step1<ndim>(fields, states, states, stats, cnt3, ctl, hflag, oplog, k, ts)

@@ -1987,35 +1987,30 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
 }
 
 // One step of the fields of one chain (all of dimension NDIM).  pre[0..nf]
-// are the prefix sums of the fields' weighted items in this step, items times
-// eng_weight.  Item i of field f starts at unit pre[f] + i w and is run by the
-// block whose range of units holds that start.
+// are the prefix sums of the blocks given to each field in this step (the
+// scan gives a field blocks in proportion to its items times eng_weight, at
+// least one if it has items, and no more than the grid holds in all): block
+// b runs one contiguous share of the items of the field whose blocks contain
+// b.  A block never spans two fields -- a loop over fields around the
+// operations cost the kernel a third of its occupancy in registers.
 template <int NDIM>
 __device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
                                               int nf, char* smem, unsigned long long& acct) {
     // The tables were written by the previous kernels of the chain, so plain
     // loads see them.
-    const int total = pre[nf];
-    if (total == 0) return;
-    const int nb = gridDim.x, b = xcd_logical_block(blockIdx.x, nb);
-    const int per = (total + nb - 1) / nb;
-    int lo = b * per;
-    const int hi = min(total, lo + per);
-    while (lo < hi) {
-        int a = 0, z = nf - 1;  // the field whose items contain lo: largest f with pre[f] <= lo
-        while (a < z) {
-            const int mid = (a + z + 1) >> 1;
-            if (pre[mid] <= lo) a = mid;
-            else z = mid - 1;
-        }
-        const int base = pre[a];
-        const int end = min(hi, pre[a + 1]);
-        const EngState st = cur[a];
-        const int w = eng_weight(fields[a], st.op);
-        const int i0 = (lo - base + w - 1) / w, i1 = (end - base + w - 1) / w;
-        if (i0 < i1) eng_run_range<NDIM, false>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
-        lo = end;
+    const int used = pre[nf];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    if (b >= used) return;
+    int a = 0, z = nf - 1;  // the field whose blocks contain b: largest f with pre[f] <= b
+    while (a < z) {
+        const int mid = (a + z + 1) >> 1;
+        if (pre[mid] <= b) a = mid;
+        else z = mid - 1;
     }
+    const EngState st = cur[a];
+    const long long nbf = pre[a + 1] - pre[a], j = b - pre[a];
+    const int i0 = static_cast<int>(j * st.items / nbf), i1 = static_cast<int>((j + 1) * st.items / nbf);
+    if (i0 < i1) eng_run_range<NDIM, false>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
 }
 
 // Profiling record of a step (ts: kEngStampWords zeroed words, or NULL): block
@@ -2331,26 +2326,42 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
     if (ts) stamp_end(ts, acct);
 }
 
-// Prefix sums of the next step's weighted items of one chain of a batch (its
-// 2D or its 3D fields; the host relaunches each chain until it is done), and
-// its done word (one block of kEngMaxFields threads, one field each).
+// The blocks of the next step of one chain of a batch (its 2D or its 3D
+// fields; the host relaunches each chain until it is done), and its done word
+// (one block of kEngMaxFields threads, one field each).  A field with items
+// gets ceil(units / per) blocks, units = items * eng_weight and per = the
+// chain's units over (grid - nf) blocks, rounded up: at most the grid in all.
+// pre[f] = the first block of field f, pre[nf] = the blocks used.
 __global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
-                                                           int nf, int* pre, int* word) {
-    __shared__ int sm[kEngMaxFields];
+                                                           int nf, int* pre, int* word, int grid) {
+    __shared__ long long sl[kEngMaxFields];
+    __shared__ int si[kEngMaxFields];
     const int f = threadIdx.x;
-    sm[f] = f < nf ? nxt[f].items * eng_weight(fields[f], nxt[f].op) : 0;
+    const long long units = f < nf ? static_cast<long long>(nxt[f].items) * eng_weight(fields[f], nxt[f].op) : 0;
+    sl[f] = units;
     __syncthreads();
-    for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive Hillis-Steele scan
-        const int v = f >= o ? sm[f - o] : 0;
+    for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive Hillis-Steele scan of the units
+        const long long v = f >= o ? sl[f - o] : 0;
         __syncthreads();
-        sm[f] += v;
+        sl[f] += v;
         __syncthreads();
     }
-    if (f < nf) pre[f + 1] = sm[f];
+    const long long total = sl[kEngMaxFields - 1];
+    const long long slots = grid > nf ? grid - nf : 1;
+    const long long per = total > 0 ? (total + slots - 1) / slots : 1;
+    si[f] = static_cast<int>((units + per - 1) / per);
+    __syncthreads();
+    for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive scan of the blocks
+        const int v = f >= o ? si[f - o] : 0;
+        __syncthreads();
+        si[f] += v;
+        __syncthreads();
+    }
+    if (f < nf) pre[f + 1] = si[f];
     if (f == 0) {
         pre[0] = 0;
         // the done word lives in pinned host memory, which the host polls
-        if (sm[nf - 1] == 0) __hip_atomic_store(word, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (total == 0) __hip_atomic_store(word, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
