@@ -860,6 +860,7 @@ int msz_fix(const float* f, const float* fhat, msz_dims d, float xi, float* edit
     F.preempt = (o.flags & MSZ_FLAG_PREEMPTIVE) != 0;
     F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0 || F.preempt;
     F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
+    F.flabels = 1;
     F.xi = xi;
     F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
     F.f = f;
@@ -912,6 +913,7 @@ int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, flo
     F.preempt = (o.flags & MSZ_FLAG_PREEMPTIVE) != 0;
     F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0 || F.preempt;
     F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
+    F.flabels = 1;
     F.xi = xi;
     F.cap = o.max_rounds > 0 ? o.max_rounds : (int64_t(1) << 30);
     F.f = f;
@@ -990,6 +992,11 @@ int msz_fix_batch(const msz_job* jobs, int32_t n_jobs, const msz_options* opt, v
         F.preempt = (o.flags & MSZ_FLAG_PREEMPTIVE) != 0;
         F.merged = (o.flags & MSZ_FLAG_MERGED_C) != 0 || F.preempt;
         F.count_init = (o.flags & MSZ_FLAG_COUNT_INIT) != 0;
+        // a batch's troublemaker passes follow f's chains where they need f's
+        // labels: cheaper than one more full step for every field (a field
+        // corrected alone, whose R rounds resolve many labels, resolves them
+        // once instead)
+        F.flabels = 0;
         F.xi = J.xi;
         F.cap = cap;
         F.f = J.f;

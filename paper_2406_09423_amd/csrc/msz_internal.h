@@ -143,8 +143,8 @@ constexpr int kHostStatsWord = 32;                  // final statistics in the h
 enum EngOp : int {
     kOpPreA = 0,   // validation, floors, start field
     kOpPreA2,      // directions of f
-    kOpPreB,       // label tiles of f
-    kOpPreD,       // labels of f (following the exit chains)
+    kOpPreB,       // label tiles of f (the pointers of f's forests)
+    kOpPreD,       // labels of f, in place (fields with flabels)
     kOpPreE,       // directions of g and the case bytes of every vertex
     kOpApplyC,     // C-loop apply: the targets of every case of the current type
     kOpRefreshC,   // directions and cases of the vertices around the last C edits
@@ -169,6 +169,7 @@ struct EngField {
     int preempt;     // 1: shared targets edited without claims (preemptive mode; implies merged)
     int count_init;  // 1: label the start field once and count its mislabelled vertices
     int sum;         // 1: keep chunk summaries of the flag arrays and skip empty chunks (large single fields)
+    int flabels;     // 1: resolve f's labels once before the loop (else the troublemaker passes follow f's chains)
     float xi;
     long long cap;
     const float *f, *fhat, *warm;
@@ -182,7 +183,7 @@ struct EngField {
                             // halves of word 0) and 2, 3 (word 1) in the chunk -- exact unless chunk_unk
     unsigned* chunk_unk;    // per kEngChunk vertices: 1 when the counts are not known (after a full pass)
     uint8_t *tile_dirty;  // per label tile: a direction of g in it changed since its last tile pass
-    int *Mf, *mf, *qu, *qd;
+    int *Mf, *mf, *qu, *qd;  // pointers of f's (Mf, mf) and g's (qu, qd) ascending / descending forests
     unsigned* cnt;  // kCntBlockWords words (kSlots slots), in the engine's control block
 };
 

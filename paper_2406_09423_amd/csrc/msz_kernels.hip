@@ -7,10 +7,12 @@
 //   marks          uint8[n]   claims of the targets edited in the current round (an
 //                             edit shared by several cases is made once; padded to 16 B)
 //   dirty          uint8[n]   directions to recompute after an apply (padded to 16 B)
-//   M_f, m_f       int32[n]   labels of f (max, min)
-//   q_up, q_dn     int32[n]   pointer arrays of the ascending / descending forests: a
-//                             root (extremum) id as itself (>= 0), an exit of the vertex's
-//                             label tile, a vertex e of the next tile on its line, as -e-1
+//   M_f, m_f       int32[n]   pointer arrays of f's ascending / descending forests
+//   q_up, q_dn     int32[n]   pointer arrays of g's ascending / descending forests; in
+//                             both pairs a root (extremum) id as itself (>= 0), an exit
+//                             of the vertex's label tile, a vertex e of the next tile on
+//                             its line, as -e-1 (a label is the root at the end of the
+//                             vertex's chain of exits)
 //   tile_dirty     uint8      per label tile: a direction of g in it changed since its
 //                             last tile pass
 //   cnt            uint32[kSlots][kSlotStride] round counters; block b adds into slot
@@ -1130,9 +1132,9 @@ struct TargetList {
 
 // Troublemakers of one tile (Sec. 5.2).  Only a vertex whose direction in g
 // differs from f's (each family apart) can be one, so only such vertices
-// have their labels resolved -- their pointers and f's labels loaded and
-// their exit chains followed; the rest of the tile costs its two direction
-// bytes per vertex.  Mislabelled vertices need not be counted for the loop:
+// have their labels resolved -- their pointers in g's and f's forests (Mf,
+// mf hold f's tile pointers) loaded and both exit chains followed; the rest
+// of the tile costs its two direction bytes per vertex.  Mislabelled vertices need not be counted for the loop:
 // one exists exactly when a troublemaker of its family does (on the steepest
 // path in g of a mislabelled vertex, the first vertex whose direction
 // differs from f's carries the same labels in g and in f), so the
@@ -1217,7 +1219,12 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
         int y[8] = {(up & 1u) ? u.x : 0, (dn & 1u) ? d.x : 0, (up & 2u) ? u.y : 0, (dn & 2u) ? d.y : 0,
                     (up & 4u) ? u.z : 0, (dn & 4u) ? d.z : 0, (up & 8u) ? u.w : 0, (dn & 8u) ? d.w : 0};
         follow_roots<8>(q_up, q_dn, y, bad, hops);
-        const int Ms[4] = {U.x, U.y, U.z, U.w}, ms[4] = {D.x, D.y, D.z, D.w};
+        // and f's labels along f's chains (most are roots already: a tile
+        // pass leaves every in-tile path at its extremum or exit)
+        int yf[8] = {(up & 1u) ? U.x : 0, (dn & 1u) ? D.x : 0, (up & 2u) ? U.y : 0, (dn & 2u) ? D.y : 0,
+                     (up & 4u) ? U.z : 0, (dn & 4u) ? D.z : 0, (up & 8u) ? U.w : 0, (dn & 8u) ? D.w : 0};
+        follow_roots<8>(Mf, mf, yf, bad, hops);
+        const int Ms[4] = {yf[0], yf[2], yf[4], yf[6]}, ms[4] = {yf[1], yf[3], yf[5], yf[7]};
         int tn[4], tx[4], nloc = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1781,9 +1788,9 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             if (lead) acct += 5 * dirs_vertices<NDIM>(F, lo, hi);
             break;
         }
-        case kOpPreB:
+        case kOpPreB:  // the pointers of f's forests, kept for the troublemaker passes
             for (int item = lo; item < hi; ++item) {
-                label_tile_body<NDIM>(F.dirs_f, gr, item, F.qu, F.qd, su, sd);
+                label_tile_body<NDIM>(F.dirs_f, gr, item, F.Mf, F.mf, su, sd);
                 __syncthreads();
                 if (lead) acct += 9 * tile_vertices<NDIM>(gr, item);
             }
@@ -1801,11 +1808,10 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 }
             }
             break;
-        case kOpPreD:
-        {
+        case kOpPreD: {  // f's labels, in place: each pointer becomes the root at the end of its chain
             unsigned bad = 0, hops = 0;
             for (int item = lo; item < hi; ++item) {
-                bad |= label_final_tile<NDIM>(F.qu, F.qd, gr, item, F.Mf, F.mf, hops);
+                bad |= label_final_tile<NDIM>(F.Mf, F.mf, gr, item, F.Mf, F.mf, hops);
                 if (lead) acct += 16 * tile_vertices<NDIM>(gr, item);
             }
             acct += 4ull * hops;
@@ -2107,11 +2113,11 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
             return go(kOpPreA2);
         case kOpPreA2:
             return go(kOpPreB);
-        case kOpPreB:  // the labels of f follow the exit chains: no compression
-            return go(kOpPreD);
+        case kOpPreB:  // f's labels: resolved once, or followed where the troublemaker passes need them
+            st.type = 0;
+            return go(F.flabels ? kOpPreD : kOpPreE);
         case kOpPreD:
             if (c[kCntErr] & kErrWalk) return stop(MSZ_EDEVICE);
-            st.type = 0;
             return go(kOpPreE);
         case kOpPreE:
             set_cases(true);
