@@ -544,14 +544,32 @@ __global__ void __launch_bounds__(256) k_dirs(const float* __restrict__ h, Grid 
 // refresh step recomputes exactly those (the synchronous round is unchanged,
 // so results are identical to a full recomputation).
 
-// Slot deltas in the order of the neighbour table at the top of this file.
+// Slot deltas in the order of the neighbour table at the top of this file,
+// as (d + 1) in two bits per slot (slot 0 lowest; slots 14 and 15, the self
+// slot, are 0, 0, 0): decoded in registers, where a table indexed by a
+// per-lane slot would be a memory load per lookup.
+constexpr int kSlotDX[14] = {1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1};
+constexpr int kSlotDY[14] = {0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int kSlotDZ[14] = {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr unsigned pack_slots(const int (&d)[14]) {
+    unsigned p = 0;
+    for (int s = 0; s < 16; ++s) p |= static_cast<unsigned>((s < 14 ? d[s] : 0) + 1) << (2 * s);
+    return p;
+}
+constexpr unsigned kPackDX = pack_slots(kSlotDX), kPackDY = pack_slots(kSlotDY), kPackDZ = pack_slots(kSlotDZ);
+
 __device__ __forceinline__ void slot_delta(unsigned s, int& dx, int& dy, int& dz) {
-    constexpr int DX[14] = {1, -1, 0, 0, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1};
-    constexpr int DY[14] = {0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
-    constexpr int DZ[14] = {0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
-    dx = DX[s];
-    dy = DY[s];
-    dz = DZ[s];
+    dx = static_cast<int>((kPackDX >> (2 * s)) & 3u) - 1;
+    dy = static_cast<int>((kPackDY >> (2 * s)) & 3u) - 1;
+    dz = static_cast<int>((kPackDZ >> (2 * s)) & 3u) - 1;
+}
+
+// Linear id offset of neighbour slot s (0 for the self slot); the same as
+// gr.off[s], computed in registers for a per-lane slot.
+__device__ __forceinline__ int slot_offset(const Grid& gr, unsigned s) {
+    int dx, dy, dz;
+    slot_delta(s, dx, dy, dz);
+    return dx + gr.nx * dy + gr.nxy * dz;
 }
 
 // Whether neighbour slot s of the vertex at (x, y, z) lies in the grid.
@@ -804,7 +822,7 @@ __device__ __forceinline__ void label_tile_body(const uint8_t* __restrict__ dirs
                         if (ax >= 0 && ax < T::X && ay >= 0 && ay < T::Y && az >= 0 && az < T::Z)
                             p[w] = ax + T::X * (ay + T::Y * az);
                         else
-                            p[w] = -(i + gr.off[s]) - 1;
+                            p[w] = -(i + slot_offset(gr, s)) - 1;
                     }
                 }
             }
@@ -1238,8 +1256,8 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
             const bool rmin = wm && ((ddn >> j) & 1u);
             cases += rmin + rmax;
             nloc += rmin + rmax;
-            if (rmin) tn[j] = i + gr.off[df & 15u];
-            if (rmax) tx[j] = i + gr.off[dg >> 4];
+            if (rmin) tn[j] = i + slot_offset(gr, df & 15u);
+            if (rmax) tx[j] = i + slot_offset(gr, dg >> 4);
         }
         if (tl.list) tl.add_wave<NDIM>(gr, tn, tx, nloc, changed);
     }
@@ -1839,10 +1857,10 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                         tries += __popc(b & 0xFu);
                         if (b & 9u) target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i, changed);
                         if (b & 2u)
-                            target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i + gr.off[F.dirs_f[i] & 15u],
+                            target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i + slot_offset(gr, F.dirs_f[i] & 15u),
                                               changed);
                         if (b & 4u)
-                            target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i + gr.off[F.dirs_g[i] >> 4],
+                            target_edit<NDIM>(pre, F.marks, F.g, F.L, dirty, gr, i + slot_offset(gr, F.dirs_g[i] >> 4),
                                               changed);
                     },
                     [](int) {});
@@ -1867,7 +1885,7 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                         return;
                     }
                     // FPmin and FNmax targets may be shared
-                    const int t = i + gr.off[type == 1 ? (F.dirs_f[i] & 15u) : (F.dirs_g[i] >> 4)];
+                    const int t = i + slot_offset(gr, type == 1 ? (F.dirs_f[i] & 15u) : (F.dirs_g[i] >> 4));
                     claim_edit<NDIM>(F.marks, F.g, F.L, dirty, gr, t, changed);
                 },
                 [](int) {});
