@@ -282,9 +282,9 @@ typedef struct {
  * bit-identical to its own msz_fix.  The 2D fields and the 3D fields form two
  * chains of steps that run side by side without waiting for each other; per
  * step of a chain, one step kernel runs the work items of all its fields as
- * one index space split over the blocks by each operation's cost, a decide
- * kernel picks each field's next operation and a scan kernel sums the next
- * step's items.  Each chain's steps run from a HIP graph on a stream of the
+ * one index space split over the blocks by each operation's cost; in the
+ * same kernel the last block of each field picks the field's next operation
+ * and the last field decided splits the next step's items over the blocks.  Each chain's steps run from a HIP graph on a stream of the
  * library's own, relaunched until its fields are done; the chains start
  * after the work already queued on `stream` and the work queued on it
  * afterwards waits for them.  opt->workspace (if given) must hold

@@ -165,16 +165,20 @@ int check_xi(float xi) {
 
 constexpr int kGraphSteps = kEngTimeSlots;  // steps per graph launch (even: parities line up)
 static_assert(kGraphSteps % 2 == 0, "states alternate between two buffers");
+// a batch chain's block prefix of one step: nf + 1 prefix sums, then the
+// number of fields given blocks; two of them, by step parity
+constexpr int kPreWords = kEngMaxFields + 2;
 
 // Per host thread and device: the engine's control block (device), a pinned
 // read-back word, and the graph of kGraphSteps steps for the last topology.
 struct EngineCtx {
     int device = -1;
-    char* ctl_mem = nullptr;  // fields, states, stats, pre2, pre3, ctl, oplog
+    char* ctl_mem = nullptr;  // fields, states, stats, pre2, pre3, tick2, tick3, ctl, oplog
     EngField* fields = nullptr;
     EngState* states = nullptr;
     EngStats* stats = nullptr;
     int *pre2 = nullptr, *pre3 = nullptr, *ctl = nullptr, *oplog = nullptr;
+    int *tick2 = nullptr, *tick3 = nullptr;  // a chain's tickets: kEngMaxFields + 1 words
     unsigned long long* tstamp = nullptr;  // profiling: kEngStampWords words per step
     unsigned* counters = nullptr;          // kCntBlockWords per field
     int* host = nullptr;  // pinned: [0] ctl, [1 .. kGraphSteps] oplog, then 2 * kGraphSteps stamps
@@ -226,8 +230,10 @@ struct EngineCtx {
         const size_t of = take(sizeof(EngField) * kEngMaxFields);
         const size_t os = take(sizeof(EngState) * 2 * kEngMaxFields);
         const size_t ost = take(sizeof(EngStats) * kEngMaxFields);
-        const size_t op2 = take(sizeof(int) * (kEngMaxFields + 1));
-        const size_t op3 = take(sizeof(int) * (kEngMaxFields + 1));
+        const size_t op2 = take(sizeof(int) * 2 * kPreWords);
+        const size_t op3 = take(sizeof(int) * 2 * kPreWords);
+        const size_t ot2 = take(sizeof(int) * (kEngMaxFields + 1));
+        const size_t ot3 = take(sizeof(int) * (kEngMaxFields + 1));
         const size_t oc = take(sizeof(int) * 4);
         const size_t ol = take(sizeof(int) * kGraphSteps * kEngMaxFields);
         const size_t ot = take(stamp_bytes());
@@ -240,6 +246,8 @@ struct EngineCtx {
         stats = reinterpret_cast<EngStats*>(ctl_mem + ost);
         pre2 = reinterpret_cast<int*>(ctl_mem + op2);
         pre3 = reinterpret_cast<int*>(ctl_mem + op3);
+        tick2 = reinterpret_cast<int*>(ctl_mem + ot2);
+        tick3 = reinterpret_cast<int*>(ctl_mem + ot3);
         ctl = reinterpret_cast<int*>(ctl_mem + oc);
         oplog = reinterpret_cast<int*>(ctl_mem + ol);
         tstamp = reinterpret_cast<unsigned long long*>(ctl_mem + ot);
@@ -306,8 +314,8 @@ struct EngineCtx {
         }
         // A batch: one graph per dimension's chain of steps, each launched on
         // its own stream, so that the chains never wait for each other (not
-        // even where a launch ends).  Per step: the step kernel, the
-        // decisions, the scan.
+        // even where a launch ends).  Per step: one kernel, which also takes
+        // the decisions and forms the next step's block prefix.
         for (int d = 0; nf > 1 && d < 2; ++d) {
             int cnt = d == 0 ? n2 : nf - n2;
             if (cnt == 0) continue;
@@ -322,18 +330,15 @@ struct EngineCtx {
                 EngState* cur = states + par * nf + off;
                 EngState* nxt = states + (par ^ 1) * nf + off;
                 EngStats* sp = stats + off;
-                int* pre = d == 0 ? pre2 : pre3;
+                int* pre = (d == 0 ? pre2 : pre3) + par * kPreWords;
+                int* pre_next = (d == 0 ? pre2 : pre3) + (par ^ 1) * kPreWords;
+                int* tick = d == 0 ? tick2 : tick3;
                 unsigned long long* ts = timing ? tstamp + (2 * st + d) * kEngStampWords : nullptr;
                 int* log = timing ? oplog + (d == 0 ? 0 : kGraphSteps * n2) : nullptr;
                 int stp = st;
-                void* a[] = {&fp, &cur, &pre, &cnt, &ts};
+                void* a[] = {&fp, &cur, &nxt, &sp, &pre, &pre_next, &cnt, &tick, &word, &log, &stp, &ts};
                 if (!add_kernel(eng_step_kernel(d == 0 ? 2 : 3), dim3(d == 0 ? grid2 : grid3), dim3(256), a))
                     return MSZ_EDEVICE;
-                void* dd[] = {&fp, &cur, &nxt, &sp, &cnt, &log, &stp};
-                if (!add_kernel(eng_decide_kernel(), dim3(cnt), dim3(256), dd)) return MSZ_EDEVICE;
-                int gridv = d == 0 ? grid2 : grid3;
-                void* c[] = {&fp, &nxt, &cnt, &pre, &word, &gridv};
-                if (!add_kernel(eng_scan_kernel(), dim3(1), dim3(kEngMaxFields), c)) return MSZ_EDEVICE;
             }
             if (hipGraphInstantiate(&exec[d], graph[d], nullptr, nullptr, 0) != hipSuccess) return MSZ_EDEVICE;
         }
@@ -447,16 +452,20 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         grid2 = std::max(grid2, n2 + 1);
         grid3 = std::max(grid3, n3 + 1);
     }
-    // the first step's blocks per field, as k_eng_scan assigns them for the
-    // steps after it
+    // the first step's blocks per field, as the step kernel assigns them for
+    // the steps after it, and the number of fields given blocks
     auto block_prefix = [](const std::vector<int64_t>& u, int grid) {
         const int m = static_cast<int>(u.size());
         int64_t total = 0;
         for (int64_t x : u) total += x;
         const int64_t slots = grid > m ? grid - m : 1;
         const int64_t per = total > 0 ? (total + slots - 1) / slots : 1;
-        std::vector<int> p(m + 1, 0);
-        for (int i = 0; i < m; ++i) p[i + 1] = p[i] + static_cast<int>((u[i] + per - 1) / per);
+        std::vector<int> p(m + 2, 0);
+        for (int i = 0; i < m; ++i) {
+            const int nb = static_cast<int>((u[i] + per - 1) / per);
+            p[i + 1] = p[i] + nb;
+            p[m + 1] += nb > 0;
+        }
         return p;
     };
     const std::vector<int> p2 = block_prefix(u2, grid2), p3 = block_prefix(u3, grid3);
@@ -501,6 +510,9 @@ int run_engine(std::vector<EngField>& hf, std::vector<EngStats>& st, bool timing
         MSZ_HIP(hipMemcpyAsync(E.states, hs.data(), sizeof(EngState) * 2 * nf, hipMemcpyHostToDevice, s));
         MSZ_HIP(hipMemcpyAsync(E.pre2, p2.data(), sizeof(int) * p2.size(), hipMemcpyHostToDevice, s));
         MSZ_HIP(hipMemcpyAsync(E.pre3, p3.data(), sizeof(int) * p3.size(), hipMemcpyHostToDevice, s));
+        // the tickets (every step resets the ones it draws; cleared here as well)
+        MSZ_HIP(hipMemsetAsync(E.tick2, 0, sizeof(int) * (kEngMaxFields + 1), s));
+        MSZ_HIP(hipMemsetAsync(E.tick3, 0, sizeof(int) * (kEngMaxFields + 1), s));
         MSZ_HIP(hipMemcpyAsync(E.ctl, active, sizeof(active), hipMemcpyHostToDevice, s));
         MSZ_HIP(hipMemsetAsync(E.stats, 0, sizeof(EngStats) * nf, s));
         int total = 0;

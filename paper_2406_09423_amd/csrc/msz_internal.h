@@ -128,8 +128,8 @@ namespace msz {
 
 // ------------------------------------------------------------ batch engine ---
 // The correction schedule on the device: per step, k_eng_step<2>/<3> run the
-// current operation of every field, k_eng_decide picks each field's next one,
-// k_eng_scan sums the next step's items (see the engine in msz_kernels.hip).
+// current operation of every field of a chain, pick each field's next one and
+// split the next step's items over the blocks (see the engine in msz_kernels.hip).
 constexpr int kEngMaxFields = 1024;
 constexpr int kEngTimeSlots = 48;                   // steps per graph launch (a multiple of 2 and 3)
 constexpr int kEngEndSlots = 64;                    // per timed step: start, 64 slots of block ends,
@@ -202,9 +202,8 @@ struct EngStats {
 int eng_items_host(const EngField& F, int op);
 int eng_weight_host(const EngField& F, int op);  // cost units of one item (batch splits)
 int label_tile_count(const Grid& gr);   // label tiles of the grid
-const void* eng_step_kernel(int ndim);  // k_eng_step<ndim>(fields, cur, pre, nf, ts)
-const void* eng_decide_kernel();        // k_eng_decide(fields, cur, nxt, stats, nf, oplog, step)
-const void* eng_scan_kernel();          // k_eng_scan(fields, nxt, nf, pre, word, grid)
+// k_eng_step<ndim>(fields, cur, nxt, stats, pre, pre_next, nf, tick, word, oplog, step, ts)
+const void* eng_step_kernel(int ndim);
 const void* eng_init_kernel();          // k_eng_init(fields, nf)
 const void* eng_setup1_kernel();        // k_eng_setup1(F, fields, states, stats, cnt3, ctl, done_word)
 const void* eng_step1_kernel(int ndim); // k_eng_step1<ndim>(fields, states, states, stats, cnt3, ctl, hflag, oplog, k, ts)

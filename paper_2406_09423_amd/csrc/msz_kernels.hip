@@ -1435,15 +1435,15 @@ void launch_check_finite(const float* h, int n, unsigned* cnt, hipStream_t s) {
 // corrected alone, so results are identical.  One field: k_eng_step1 decides
 // in every block and runs the chosen operation, one kernel per step.  A
 // batch: k_eng_step<NDIM> runs the work items of all fields of one dimension
-// as one index space, cut into one contiguous range per block (XCD-aware, so
-// neighbouring items share an L2); k_eng_decide reduces each field's counters
-// and writes its next operation; k_eng_scan forms the prefix sums of the next
-// step's items.  The host captures a fixed number of steps in a HIP graph and
+// as one index space, cut into contiguous ranges per block (XCD-aware, so
+// neighbouring items share an L2), and its last blocks reduce each field's
+// counters, write its next operation and split the next step's items over
+// the blocks.  The host captures a fixed number of steps in a HIP graph and
 // relaunches it until no field is active; a batch's 2D fields and 3D fields
-// form two chains of steps, each with its own graph.  Kernel boundaries order the steps:
-// every write of a step is visible to the next one without device-scope
-// fences inside a kernel (which on MI355X write back and invalidate the L2 of
-// each XCD).
+// form two chains of steps, each with its own graph.  Kernel boundaries order
+// the steps: every write of a step is visible to the next one without
+// device-scope fences inside a kernel (which on MI355X write back and
+// invalidate the L2 of each XCD).
 
 __host__ __device__ inline int dirs_items_of(const Grid& gr, int variant) {
     const DirsVariant v = variant_of(gr.ndim, variant);
@@ -2010,33 +2010,6 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
     __syncthreads();  // the next range reuses the LDS
 }
 
-// One step of the fields of one chain (all of dimension NDIM).  pre[0..nf]
-// are the prefix sums of the blocks given to each field in this step (the
-// scan gives a field blocks in proportion to its items times eng_weight, at
-// least one if it has items, and no more than the grid holds in all): block
-// b runs one contiguous share of the items of the field whose blocks contain
-// b.  A block never spans two fields -- a loop over fields around the
-// operations cost the kernel a third of its occupancy in registers.
-template <int NDIM>
-__device__ __forceinline__ void eng_step_body(const EngField* __restrict__ fields, const EngState* cur, const int* pre,
-                                              int nf, char* smem, unsigned long long& acct) {
-    // The tables were written by the previous kernels of the chain, so plain
-    // loads see them.
-    const int used = pre[nf];
-    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
-    if (b >= used) return;
-    int a = 0, z = nf - 1;  // the field whose blocks contain b: largest f with pre[f] <= b
-    while (a < z) {
-        const int mid = (a + z + 1) >> 1;
-        if (pre[mid] <= b) a = mid;
-        else z = mid - 1;
-    }
-    const EngState st = cur[a];
-    const long long nbf = pre[a + 1] - pre[a], j = b - pre[a];
-    const int i0 = static_cast<int>(j * st.items / nbf), i1 = static_cast<int>((j + 1) * st.items / nbf);
-    if (i0 < i1) eng_run_range<NDIM, false>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
-}
-
 // Profiling record of a step (ts: kEngStampWords zeroed words, or NULL): block
 // 0 stores its start in ts[0]; every block raises ts[1 + blockIdx % 64] to its
 // end (64 slots keep the atomics from queueing on one address) and adds the
@@ -2050,17 +2023,6 @@ __device__ __forceinline__ void stamp_end(unsigned long long* ts, unsigned long 
     __syncthreads();
     if (threadIdx.x == 0)
         atomicMax(ts + 1 + blockIdx.x % kEngEndSlots, static_cast<unsigned long long>(wall_clock64()));
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
-                                                  const int* pre, int nf, unsigned long long* ts) {
-    __shared__ __align__(16) char smem[kEngSmemBytes];
-    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
-    if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = static_cast<unsigned long long>(wall_clock64());
-    unsigned long long acct = 0;
-    eng_step_body<NDIM>(fields, cur, pre, nf, smem, acct);
-    if (ts) stamp_end(ts, acct);
 }
 
 // The schedule (the host loop of a single correction, step by step): the next
@@ -2199,53 +2161,183 @@ __device__ __forceinline__ EngState eng_decide(const EngField& F, EngState st, E
     }
 }
 
-// Block f decides field f: the 256 threads reduce the field's counter block
-// (kSlots slots of kCntSlots counters, at cnt_all + f * kCntBlockWords), clear
-// it, and thread 0 writes the next state.  Every load (state, counters,
-// statistics) is issued before any is used, so a decision costs one memory
-// round trip.  With one field it also writes the next prefix sums and the
-// active count; if oplog is set, oplog[step * nf + f] receives the operation
-// field f ran in this step.
-__global__ void __launch_bounds__(256) k_eng_decide(const EngField* __restrict__ fields, const EngState* cur,
-                                                    EngState* nxt, EngStats* stats, int nf, int* oplog, int step) {
-    __shared__ unsigned part[256];
-    __shared__ unsigned red[kCntSlots];
-    const int f = blockIdx.x;
-    unsigned* cnt = fields[f].cnt;
-    // thread t sums counter (t % 16) over the slots t / 16, t / 16 + 16, ...
+// One step of one chain of a batch (its 2D or its 3D fields, all of
+// dimension NDIM), schedule included, in one kernel.  pre[0..nf] are the
+// prefix sums of the blocks given to each field in this step and pre[nf + 1]
+// the number of fields given blocks; block b runs one contiguous share of the
+// items of the field whose blocks contain b (a block never spans two fields:
+// a loop over fields around the operations cost the kernel a third of its
+// occupancy in registers).  The last block of a field to finish takes the
+// field's decision (its next state, from the counters its blocks left), and
+// the last field to be decided forms the next step's prefix sums in pre_next
+// (cost-weighted: a field gets ceil(units / per) blocks, units = items *
+// eng_weight and per = the chain's units over (grid - nf) blocks, rounded up;
+// at most the grid in all) and clears the chain's done word once no field has
+// items.  tick[f] counts the finished blocks of field f and tick[nf] the
+// decided fields; the block that draws the last ticket resets it.
+//
+// Blocks hand counters, tickets and decided states to each other inside the
+// kernel through device-scope atomics only (every XCD sees one value of each),
+// and a block draws its ticket after its own memory operations have
+// completed: a device-scope fence, which on MI355X writes back the L2 of the
+// XCD, is never needed.  Everything else a step writes is read by later
+// steps, after the kernel boundary.
+__device__ __forceinline__ int ld_dev(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// True in every thread of the block that draws ticket n - 1 of *ticket.
+__device__ __forceinline__ bool draw_last(int* ticket, int n, int* s_flag) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores and atomics have completed
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *s_flag = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == n - 1;
+    __syncthreads();
+    return *s_flag != 0;
+}
+
+// The decision of field F after its step (all its blocks have finished): the
+// 256 threads reduce and clear its counter block, thread 0 runs the schedule.
+__device__ __forceinline__ void decide_field(const EngField& F, const EngState& st, EngStats* stats_f,
+                                             EngState* nxt_f, int* oplog_f, unsigned* part, unsigned* red) {
+    unsigned* cnt = F.cnt;
     const int k = threadIdx.x % kCntSlots, s0 = threadIdx.x / kCntSlots;
     constexpr int PER = kSlots / (256 / kCntSlots);
     unsigned v[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) v[q] = cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k];
-    const EngState st = cur[f];
-    EngStats S;
-    if (threadIdx.x == 0) S = stats[f];
-    if (oplog && threadIdx.x == 0) oplog[step * nf + f] = st.items > 0 ? st.op : kOpDone;
-    EngState ns = st;
-    if (st.items > 0) {
-        unsigned acc = 0;
+    for (int q = 0; q < PER; ++q) v[q] = ld_dev(cnt + (s0 + q * (256 / kCntSlots)) * kSlotStride + k);
+    unsigned acc = 0;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            acc = k == kCntErr ? (acc | v[q]) : acc + v[q];
-            cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k] = 0u;
+    for (int q = 0; q < PER; ++q) {
+        acc = k == kCntErr ? (acc | v[q]) : acc + v[q];
+        cnt[(s0 + q * (256 / kCntSlots)) * kSlotStride + k] = 0u;  // read next by the step after the next
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < kCntSlots) {
+        unsigned a = 0;
+        for (int j = threadIdx.x; j < 256; j += kCntSlots) a = threadIdx.x == kCntErr ? (a | part[j]) : a + part[j];
+        red[threadIdx.x] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        EngStats S = *stats_f;
+        unsigned c[kCntSlots];
+        for (int j = 0; j < kCntSlots; ++j) c[j] = red[j];
+        const EngState ns = eng_decide(F, st, &S, c);
+        *stats_f = S;
+        st_dev(&nxt_f->op, ns.op);
+        st_dev(&nxt_f->type, ns.type);
+        st_dev(&nxt_f->items, ns.items);
+        st_dev(&nxt_f->init, ns.init);
+        if (oplog_f) *oplog_f = st.op;
+    }
+}
+
+// The next step's blocks per field (the first wave of the block that decided
+// the chain's last field; su: kEngMaxFields words of LDS).  Lane l takes the
+// fields l, l + 64, ...; a field no block ran (done) carries its state over.
+__device__ __forceinline__ void scan_chain(const EngField* __restrict__ fields, const EngState* cur, EngState* nxt,
+                                           const int* pre, int* pre_next, int nf, int* word, int* oplog, int step,
+                                           long long* su) {
+    const int lane = threadIdx.x;
+    long long total = 0;
+#pragma unroll 1
+    for (int f = lane; f < nf; f += 64) {
+        int op, items;
+        if (pre[f + 1] == pre[f]) {
+            const EngState s = cur[f];
+            nxt[f] = s;
+            if (oplog) oplog[step * nf + f] = kOpDone;
+            op = s.op;
+            items = s.items;
+        } else {
+            op = ld_dev(&nxt[f].op);
+            items = ld_dev(&nxt[f].items);
         }
-        part[threadIdx.x] = acc;
-        __syncthreads();
-        if (threadIdx.x < kCntSlots) {
-            unsigned a = 0;
-            for (int j = threadIdx.x; j < 256; j += kCntSlots) a = threadIdx.x == kCntErr ? (a | part[j]) : a + part[j];
-            red[threadIdx.x] = a;
+        su[f] = static_cast<long long>(items) * eng_weight(fields[f], op);
+        total += su[f];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, 64);
+    const long long slots = static_cast<int>(gridDim.x) > nf ? static_cast<int>(gridDim.x) - nf : 1;
+    const long long per = total > 0 ? (total + slots - 1) / slots : 1;
+    int carry = 0, act = 0;
+#pragma unroll 1
+    for (int base = 0; base < nf; base += 64) {
+        const int f = base + lane;  // the lane that stored su[f]
+        const int nb = f < nf ? static_cast<int>((su[f] + per - 1) / per) : 0;
+        int incl = nb;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned c[kCntSlots];
-            for (int j = 0; j < kCntSlots; ++j) c[j] = red[j];
-            ns = eng_decide(fields[f], st, &S, c);
-            stats[f] = S;
+        if (f < nf) pre_next[f + 1] = carry + incl;
+        carry += __shfl(incl, 63, 64);
+        act += __popcll(__ballot(nb > 0));
+    }
+    if (lane == 0) {
+        pre_next[0] = 0;
+        pre_next[nf + 1] = act;
+        // the done word lives in pinned host memory, which the host polls
+        if (total == 0) __hip_atomic_store(word, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_eng_step(const EngField* __restrict__ fields, const EngState* cur,
+                                                  EngState* nxt, EngStats* stats, const int* pre, int* pre_next,
+                                                  int nf, int* tick, int* word, int* oplog, int step,
+                                                  unsigned long long* ts) {
+    __shared__ __align__(16) char smem[kEngSmemBytes];
+    __shared__ int s_flag;
+    static_assert(3 * DirsGeom<3, 32, 16>::P * sizeof(float) <= sizeof(smem), "stencil planes fit the LDS");
+    static_assert(kEngMaxFields * sizeof(long long) <= sizeof(smem), "the chain's units fit the LDS");
+    if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = static_cast<unsigned long long>(wall_clock64());
+    unsigned long long acct = 0;
+    // the tables were written by the previous steps, so plain loads see them
+    const int used = pre[nf];
+    const int b = xcd_logical_block(blockIdx.x, gridDim.x);
+    if (used == 0) {
+        // the chain is done (the rest of this graph launch): carry the states over
+        if (b == 0) {
+            for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+                nxt[f] = cur[f];
+                if (oplog) oplog[step * nf + f] = kOpDone;
+            }
+            if (threadIdx.x == 0) pre_next[nf] = 0, pre_next[nf + 1] = 0;
+        }
+    } else if (b < used) {
+        int a = 0, z = nf - 1;  // the field whose blocks contain b: largest f with pre[f] <= b
+        while (a < z) {
+            const int mid = (a + z + 1) >> 1;
+            if (pre[mid] <= b) a = mid;
+            else z = mid - 1;
+        }
+        const EngState st = cur[a];
+        const int nbf = pre[a + 1] - pre[a];
+        const long long j = b - pre[a];
+        const int i0 = static_cast<int>(j * st.items / nbf), i1 = static_cast<int>((j + 1) * st.items / nbf);
+        if (i0 < i1) eng_run_range<NDIM, false>(fields[a], st, i0, i1, smem, fields[a].cnt, acct);
+        if (draw_last(tick + a, nbf, &s_flag)) {
+            unsigned* part = reinterpret_cast<unsigned*>(smem);
+            decide_field(fields[a], st, stats + a, nxt + a, oplog ? oplog + step * nf + a : nullptr, part,
+                         part + 256);
+            if (threadIdx.x == 0) st_dev(tick + a, 0);
+            if (draw_last(tick + nf, pre[nf + 1], &s_flag)) {
+                if (threadIdx.x < 64)
+                    scan_chain(fields, cur, nxt, pre, pre_next, nf, word, oplog, step,
+                               reinterpret_cast<long long*>(smem));
+                if (threadIdx.x == 0) st_dev(tick + nf, 0);
+            }
         }
     }
-    if (threadIdx.x == 0) nxt[f] = ns;
+    if (ts) stamp_end(ts, acct);
 }
 
 // One field, one kernel per step: every block takes the schedule decision
@@ -2350,45 +2442,6 @@ __global__ void __launch_bounds__(256) k_eng_step1(const EngField* __restrict__ 
     if (ts) stamp_end(ts, acct);
 }
 
-// The blocks of the next step of one chain of a batch (its 2D or its 3D
-// fields; the host relaunches each chain until it is done), and its done word
-// (one block of kEngMaxFields threads, one field each).  A field with items
-// gets ceil(units / per) blocks, units = items * eng_weight and per = the
-// chain's units over (grid - nf) blocks, rounded up: at most the grid in all.
-// pre[f] = the first block of field f, pre[nf] = the blocks used.
-__global__ void __launch_bounds__(kEngMaxFields) k_eng_scan(const EngField* __restrict__ fields, const EngState* nxt,
-                                                           int nf, int* pre, int* word, int grid) {
-    __shared__ long long sl[kEngMaxFields];
-    __shared__ int si[kEngMaxFields];
-    const int f = threadIdx.x;
-    const long long units = f < nf ? static_cast<long long>(nxt[f].items) * eng_weight(fields[f], nxt[f].op) : 0;
-    sl[f] = units;
-    __syncthreads();
-    for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive Hillis-Steele scan of the units
-        const long long v = f >= o ? sl[f - o] : 0;
-        __syncthreads();
-        sl[f] += v;
-        __syncthreads();
-    }
-    const long long total = sl[kEngMaxFields - 1];
-    const long long slots = grid > nf ? grid - nf : 1;
-    const long long per = total > 0 ? (total + slots - 1) / slots : 1;
-    si[f] = static_cast<int>((units + per - 1) / per);
-    __syncthreads();
-    for (int o = 1; o < kEngMaxFields; o <<= 1) {  // inclusive scan of the blocks
-        const int v = f >= o ? si[f - o] : 0;
-        __syncthreads();
-        si[f] += v;
-        __syncthreads();
-    }
-    if (f < nf) pre[f + 1] = si[f];
-    if (f == 0) {
-        pre[0] = 0;
-        // the done word lives in pinned host memory, which the host polls
-        if (total == 0) __hip_atomic_store(word, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-}
-
 // Start of a one-field run: the field table entry (passed by value), the
 // states of "step -1" (done) and step 0 (start), the three counter sets, the
 // statistics, the active word, the done word (when it lives in device memory,
@@ -2448,11 +2501,9 @@ __global__ void __launch_bounds__(256) k_eng_init(const EngField* __restrict__ f
 const void* eng_step_kernel(int ndim) {
     return ndim == 3 ? reinterpret_cast<const void*>(&k_eng_step<3>) : reinterpret_cast<const void*>(&k_eng_step<2>);
 }
-const void* eng_decide_kernel() { return reinterpret_cast<const void*>(&k_eng_decide); }
 const void* eng_step1_kernel(int ndim) {
     return ndim == 3 ? reinterpret_cast<const void*>(&k_eng_step1<3>) : reinterpret_cast<const void*>(&k_eng_step1<2>);
 }
-const void* eng_scan_kernel() { return reinterpret_cast<const void*>(&k_eng_scan); }
 const void* eng_init_kernel() { return reinterpret_cast<const void*>(&k_eng_init); }
 const void* eng_setup1_kernel() { return reinterpret_cast<const void*>(&k_eng_setup1); }
 
