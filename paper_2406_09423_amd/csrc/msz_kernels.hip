@@ -723,15 +723,16 @@ __device__ __forceinline__ int tile_term_global(const Grid& gr, int X0, int Y0, 
 
 // Follows K chains of exits from stored pointers y[k] to their roots, one
 // level per pass, so that the gathers of a pass are in flight together (y[k]
-// in q_up when k is even, in q_dn when odd; entries already >= 0 stay).
-// Every chain of the forest ends at an extremum within finitely many tiles.
-// hops counts the gathers; the pass cap only guards against corrupted input
-// and sets bad.
+// in q_up when k is even, in q_dn when odd; entries already >= 0 stay).  With
+// S < K, the entries from S on belong to a second forest, r_up / r_dn, whose
+// chains are followed in the same passes.  Every chain of the forest ends at
+// an extremum within finitely many tiles.  hops counts the gathers; the pass
+// cap only guards against corrupted input and sets bad.
 constexpr int kMaxChain = 1 << 20;
 
-template <int K>
+template <int K, int S = K>
 __device__ __forceinline__ void follow_roots(const int* q_up, const int* q_dn, int (&y)[K], unsigned& bad,
-                                             unsigned& hops) {
+                                             unsigned& hops, const int* r_up = nullptr, const int* r_dn = nullptr) {
     for (int pass = 0;; ++pass) {
         bool any = false;
 #pragma unroll
@@ -747,7 +748,8 @@ __device__ __forceinline__ void follow_roots(const int* q_up, const int* q_dn, i
         // the whole wave), so that all K are issued before the first wait
         int z[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) z[k] = ((k & 1) ? q_dn : q_up)[y[k] < 0 ? -y[k] - 1 : 0];
+        for (int k = 0; k < K; ++k)
+            z[k] = (k < S ? ((k & 1) ? q_dn : q_up) : ((k & 1) ? r_dn : r_up))[y[k] < 0 ? -y[k] - 1 : 0];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             hops += y[k] < 0;
@@ -1163,7 +1165,7 @@ template <int NDIM>
 __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
                                               const int* __restrict__ Mf, const int* __restrict__ mf, const Grid& gr,
-                                              int tile, bool full, const TargetList& tl, unsigned& wrong,
+                                              int tile, bool full, bool flabels, const TargetList& tl, unsigned& wrong,
                                               unsigned& cases, unsigned& changed, unsigned& bad, unsigned& hops,
                                               unsigned long long& bytes) {
     constexpr int G = LabelTile<NDIM>::X * LabelTile<NDIM>::Y * LabelTile<NDIM>::Z / 1024;
@@ -1233,16 +1235,25 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
             if (dn & 8u) d.w = q_dn[i0 + 3], D.w = mf[i0 + 3];
             bytes += 8 * (__popc(up) + __popc(dn));
         }
-        // chains of the differing directions only (0: nothing to follow)
-        int y[8] = {(up & 1u) ? u.x : 0, (dn & 1u) ? d.x : 0, (up & 2u) ? u.y : 0, (dn & 2u) ? d.y : 0,
-                    (up & 4u) ? u.z : 0, (dn & 4u) ? d.z : 0, (up & 8u) ? u.w : 0, (dn & 8u) ? d.w : 0};
-        follow_roots<8>(q_up, q_dn, y, bad, hops);
-        // and f's labels along f's chains (most are roots already: a tile
-        // pass leaves every in-tile path at its extremum or exit)
-        int yf[8] = {(up & 1u) ? U.x : 0, (dn & 1u) ? D.x : 0, (up & 2u) ? U.y : 0, (dn & 2u) ? D.y : 0,
+        // chains of the differing directions only (0: nothing to follow) in
+        // g's forest, then f's labels along f's chains (entries 8..15): with
+        // f's labels resolved (flabels) they are roots already; else both
+        // forests' chains are followed in the same passes
+        int y[16] = {(up & 1u) ? u.x : 0, (dn & 1u) ? d.x : 0, (up & 2u) ? u.y : 0, (dn & 2u) ? d.y : 0,
+                     (up & 4u) ? u.z : 0, (dn & 4u) ? d.z : 0, (up & 8u) ? u.w : 0, (dn & 8u) ? d.w : 0,
+                     (up & 1u) ? U.x : 0, (dn & 1u) ? D.x : 0, (up & 2u) ? U.y : 0, (dn & 2u) ? D.y : 0,
                      (up & 4u) ? U.z : 0, (dn & 4u) ? D.z : 0, (up & 8u) ? U.w : 0, (dn & 8u) ? D.w : 0};
-        follow_roots<8>(Mf, mf, yf, bad, hops);
-        const int Ms[4] = {yf[0], yf[2], yf[4], yf[6]}, ms[4] = {yf[1], yf[3], yf[5], yf[7]};
+        if (flabels) {
+            int yg[8] = {y[0], y[1], y[2], y[3], y[4], y[5], y[6], y[7]};
+            int yf[8] = {y[8], y[9], y[10], y[11], y[12], y[13], y[14], y[15]};
+            follow_roots<8>(q_up, q_dn, yg, bad, hops);
+            follow_roots<8>(Mf, mf, yf, bad, hops);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) y[k] = yg[k], y[8 + k] = yf[k];
+        } else {
+            follow_roots<16, 8>(q_up, q_dn, y, bad, hops, Mf, mf);
+        }
+        const int Ms[4] = {y[8], y[10], y[12], y[14]}, ms[4] = {y[9], y[11], y[13], y[15]};
         int tn[4], tx[4], nloc = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1968,7 +1979,8 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
             for (int item = lo; item < hi; ++item) {
                 // the start field's count needs every mislabelled vertex;
                 // the loop's rounds need only the troublemakers
-                detect_r_tile<NDIM>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, st.init != 0, tl, wrong,
+                detect_r_tile<NDIM>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, st.init != 0,
+                                    F.flabels != 0, tl, wrong,
                                     cases, changed, bad, hops, acct);
                 if (lead) acct += 2 * tile_vertices<NDIM>(gr, item);
                 __syncthreads();  // every wave's additions to the list are in s_targets
