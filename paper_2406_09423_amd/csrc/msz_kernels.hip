@@ -1113,7 +1113,7 @@ constexpr int kEngSmemBytes = 2 * kEngChunk * sizeof(int);
 // The troublemakers' targets found by one block, kept in LDS until its tiles
 // are done; a target beyond the list's capacity is edited at once.
 struct TargetList {
-    static constexpr int kCap = kEngSmemBytes / sizeof(int);
+    static constexpr int kCap = kEngSmemBytes / 2 / sizeof(int);  // the other half: the candidate lists
     int* list;  // nullptr: count only
     unsigned* count;
     uint8_t* marks;
@@ -1160,7 +1160,8 @@ struct TargetList {
 // differs from f's carries the same labels in g and in f), so the
 // troublemaker count ends the R loop alike.  With full set, every vertex's
 // labels are resolved and the mislabelled ones counted in wrong (the start
-// field's count).  bytes receives the algorithmic bytes of the loads.
+// field's count; the loop's rounds use detect_r_tile_sparse, below).  bytes
+// receives the algorithmic bytes of the loads.
 template <int NDIM>
 __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f, const uint8_t* __restrict__ dirs_g,
                                               const int* __restrict__ q_up, const int* __restrict__ q_dn,
@@ -1272,6 +1273,151 @@ __device__ __forceinline__ void detect_r_tile(const uint8_t* __restrict__ dirs_f
         }
         if (tl.list) tl.add_wave<NDIM>(gr, tn, tx, nloc, changed);
     }
+}
+
+// Global id of the vertex with tile-local index l (l = x + X (y + Y z) in the
+// tile's box).
+template <int NDIM>
+__device__ __forceinline__ int tile_vertex(const Grid& gr, int tile, int l) {
+    using T = LabelTile<NDIM>;
+    const int tx_n = (gr.nx + T::X - 1) / T::X, ty_n = (gr.ny + T::Y - 1) / T::Y;
+    const int bx = tile % tx_n, by = (tile / tx_n) % ty_n, bz = tile / (tx_n * ty_n);
+    const int x = bx * T::X + l % T::X, y = by * T::Y + (l / T::X) % T::Y, z = bz * T::Z + l / (T::X * T::Y);
+    return x + gr.nx * y + gr.nxy * z;
+}
+
+// The troublemakers of one tile as detect_r_tile finds them without full, in
+// two phases: the vertices whose ascent (descent) differs are listed in LDS
+// first (cand_up / cand_dn, 4096 entries each: the tile-local index in bits
+// 0..11 and the slot of the target's direction -- g's ascent, f's descent --
+// in bits 12..15; *s_n counts them, ascents in its low and descents in its
+// high 16 bits, and is 0 on entry and on return), then resolved four per
+// thread, every walk of a round in flight together.  A wave then waits for
+// one round of pointer loads and walks per 1024 listed vertices of the tile
+// instead of one per row group it holds.
+template <int NDIM>
+__device__ __forceinline__ void detect_r_tile_sparse(const uint8_t* __restrict__ dirs_f,
+                                                     const uint8_t* __restrict__ dirs_g,
+                                                     const int* __restrict__ q_up, const int* __restrict__ q_dn,
+                                                     const int* __restrict__ Mf, const int* __restrict__ mf,
+                                                     const Grid& gr, int tile, const TargetList& tl,
+                                                     unsigned short* cand_up, unsigned short* cand_dn, unsigned* s_n,
+                                                     unsigned& cases, unsigned& changed, unsigned& bad,
+                                                     unsigned& hops, unsigned long long& bytes) {
+    using T = LabelTile<NDIM>;
+    constexpr int G = T::X * T::Y * T::Z / 1024;
+    static_assert(G == 4 && T::X * T::Y * T::Z == 4096, "4096 vertices, four row groups per thread");
+    unsigned w[2 * G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const TileGroup<NDIM> t = tile_group<NDIM>(gr, tile, k);
+        unsigned a = 0u, b = 0u;
+        if (t.vec) {
+            a = *reinterpret_cast<const unsigned*>(dirs_f + t.i0);
+            b = *reinterpret_cast<const unsigned*>(dirs_g + t.i0);
+        } else {  // bytes past the count stay equal zeros
+            for (int j = 0; j < t.count; ++j) {
+                a |= static_cast<unsigned>(dirs_f[t.i0 + j]) << (8 * j);
+                b |= static_cast<unsigned>(dirs_g[t.i0 + j]) << (8 * j);
+            }
+        }
+        w[2 * k] = a;
+        w[2 * k + 1] = b;
+    }
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        const unsigned dfw = w[2 * k], dgw = w[2 * k + 1], x = dfw ^ dgw;
+        unsigned dup = 0, ddn = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            dup |= ((x >> (8 * j + 4)) & 15u) ? 1u << j : 0u;
+            ddn |= ((x >> (8 * j)) & 15u) ? 1u << j : 0u;
+        }
+        if (!__any(dup | ddn)) continue;
+        const unsigned mine = static_cast<unsigned>(__popc(dup)) | (static_cast<unsigned>(__popc(ddn)) << 16);
+        unsigned incl = mine;  // each half stays below 2^13: no carry between them
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned v = __shfl_up(incl, o);
+            if (lane >= o) incl += v;
+        }
+        unsigned base = 0;
+        if (lane == 63) base = atomicAdd(s_n, incl);
+        base = __shfl(base, 63);
+        const unsigned before = incl - mine;
+        unsigned pu = (base & 0xFFFFu) + (before & 0xFFFFu), pd = (base >> 16) + (before >> 16);
+        const unsigned l0 = 4u * threadIdx.x + 1024u * k;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if ((dup >> j) & 1u) cand_up[pu++] = static_cast<unsigned short>((l0 + j) | (((dgw >> (8 * j + 4)) & 15u) << 12));
+            if ((ddn >> j) & 1u) cand_dn[pd++] = static_cast<unsigned short>((l0 + j) | (((dfw >> (8 * j)) & 15u) << 12));
+        }
+    }
+    __syncthreads();
+    const unsigned nn = *s_n;
+    const int nu = static_cast<int>(nn & 0xFFFFu), n = nu + static_cast<int>(nn >> 16);
+    for (int b0 = 0; b0 < n; b0 += 4 * static_cast<int>(blockDim.x)) {  // block-uniform rounds
+        int vi[4], yg[4], yf[4];
+        unsigned code[4];
+        bool dn[4], ok[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = b0 + e * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+            ok[e] = idx < n;
+            dn[e] = idx >= nu;
+            code[e] = ok[e] ? (dn[e] ? cand_dn[idx - nu] : cand_up[idx]) : 0u;
+            vi[e] = ok[e] ? tile_vertex<NDIM>(gr, tile, static_cast<int>(code[e] & 4095u)) : 0;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {  // g's tile pointer and f's (a label when f's are resolved)
+            yg[e] = ok[e] ? (dn[e] ? q_dn : q_up)[vi[e]] : 0;
+            yf[e] = ok[e] ? (dn[e] ? mf : Mf)[vi[e]] : 0;
+        }
+        // both walks of every entry, one gather level per pass
+        for (int pass = 0;; ++pass) {
+            bool any = false;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) any |= (yg[e] < 0) | (yf[e] < 0);
+            if (!any) break;
+            if (pass == kMaxChain) {
+                bad = kErrWalk;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) yg[e] = max(yg[e], 0), yf[e] = max(yf[e], 0);
+                break;
+            }
+            int zg[4], zf[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                zg[e] = (dn[e] ? q_dn : q_up)[yg[e] < 0 ? -yg[e] - 1 : 0];
+                zf[e] = (dn[e] ? mf : Mf)[yf[e] < 0 ? -yf[e] - 1 : 0];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                hops += (yg[e] < 0) + (yf[e] < 0);
+                yg[e] = yg[e] < 0 ? zg[e] : yg[e];
+                yf[e] = yf[e] < 0 ? zf[e] : yf[e];
+            }
+        }
+        // a listed vertex with different labels is a troublemaker; its target
+        // is the neighbour along g's ascent (max) or f's descent (min)
+        int tn[4], tx[4], nloc = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            tn[e] = tx[e] = -1;
+            bytes += ok[e] ? 8u : 0u;
+            if (ok[e] && yg[e] != yf[e]) {
+                const int t = vi[e] + slot_offset(gr, code[e] >> 12);
+                if (dn[e]) tn[e] = t;
+                else tx[e] = t;
+                ++cases;
+                ++nloc;
+            }
+        }
+        if (tl.list) tl.add_wave<NDIM>(gr, tn, tx, nloc, changed);
+    }
+    __syncthreads();  // every entry read before the next tile lists its own
+    if (threadIdx.x == 0) *s_n = 0u;
 }
 
 // ------------------------------------------------ count_false comparison ---
@@ -1973,15 +2119,23 @@ __device__ __forceinline__ void eng_run_range(const EngField& F, const EngState&
                 }
                 __syncthreads();
             };
-            if (threadIdx.x == 0) s_targets = 0;
+            // the troublemaker candidates of a tile: the upper half of the LDS
+            __shared__ unsigned s_cand;
+            unsigned short* cand_up = reinterpret_cast<unsigned short*>(smem + kEngSmemBytes / 2);
+            unsigned short* cand_dn = cand_up + 4096;
+            static_assert(kEngSmemBytes / 2 >= 2 * 4096 * sizeof(unsigned short), "candidate lists fit");
+            if (threadIdx.x == 0) s_targets = 0, s_cand = 0;
             __syncthreads();
             unsigned bad = 0, hops = 0;
             for (int item = lo; item < hi; ++item) {
                 // the start field's count needs every mislabelled vertex;
                 // the loop's rounds need only the troublemakers
-                detect_r_tile<NDIM>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, st.init != 0,
-                                    F.flabels != 0, tl, wrong,
-                                    cases, changed, bad, hops, acct);
+                if (st.init)
+                    detect_r_tile<NDIM>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, true,
+                                        F.flabels != 0, tl, wrong, cases, changed, bad, hops, acct);
+                else
+                    detect_r_tile_sparse<NDIM>(F.dirs_f, F.dirs_g, F.qu, F.qd, F.Mf, F.mf, gr, item, tl, cand_up,
+                                               cand_dn, &s_cand, cases, changed, bad, hops, acct);
                 if (lead) acct += 2 * tile_vertices<NDIM>(gr, item);
                 __syncthreads();  // every wave's additions to the list are in s_targets
                 // past half the list: edit what it holds and empty it
