@@ -1888,9 +1888,11 @@ __device__ __forceinline__ void refresh_vertex(const EngField& F, int j, bool su
 //   full direction and case pass over g 9, label tile 9 per vertex of a
 //   relabelled tile plus 10 per saved face vertex (16 per restored one of an
 //   unchanged tile), labels of f 16 per vertex of a visited tile,
-//   troublemakers 2 per vertex of a visited tile plus 16 per direction of a
-//   4-vertex group whose labels are resolved, both plus 4 per gather along
-//   an exit chain, deltas 16; an
+//   troublemakers 2 per vertex of a visited tile plus 8 per vertex whose
+//   labels are resolved in a direction that differs (16 per direction of a
+//   4-vertex group in the start field's count), both plus 4 per gather
+//   along an exit chain, 16 per edit attempt and 1 per neighbour flagged
+//   after a change; deltas 16; an
 //   apply or refresh 1 per flag byte of a chunk it reads (an apply reads only
 //   chunks that may hold a case of its type, a refresh only chunks an edit
 //   touched) and 12 (apply) or 4 (refresh) per chunk summary, plus 16 per

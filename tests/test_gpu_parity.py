@@ -382,25 +382,41 @@ def test_batch_error_and_cap(msz):
     assert rc != msz.OK
 
 
-def test_full_batch96_properties(msz):
-    """The 96-field batch of the batched form (about 1.35e8 vertices) in one run:
-    every field reaches zero segmentation error within its bound, and the
-    smallest fields (which the oracle corrects in moments) match it bit for bit."""
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("merged", [False, True])
+def test_full_batch96_bit_exact(msz, merged):
+    """The 96-field batch of the batched form (about 1.35e8 vertices) in one
+    run, under the default and the merged C schedule: every field's edited
+    values, deltas and statistics (the start field's mislabel count included)
+    bit for bit against the oracle's run of the same schedule on that field
+    alone, and every field reaches zero segmentation error within its bound.
+    The oracle runs on a pool of host threads, started before the GPU run,
+    largest fields first."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     fields = synth.batch_fields(0)
-    _say("full 96-field batch")
-    rc, res = msz.fix_batch([(dev(f), dev(fh), xi) for f, fh, xi in fields])
-    assert rc == msz.OK
-    for j, (f, fh, xi) in enumerate(fields):
-        st_b, d_b, g_b, s_b = res[j]
-        assert st_b == msz.OK, j
-        _full_invariants(msz, f, fh, xi, host(g_b), host(d_b), s_b)
-    smallest = sorted(range(len(fields)), key=lambda j: fields[j][0].size)[:3]
-    for j in smallest:
-        f, fh, xi = fields[j]
-        rc_o, d_o, g_o, st_o = oracle.fix(f, fh, xi)
-        assert rc_o == msz.OK
-        assert (_bits(host(res[j][2])) == _bits(g_o)).all(), j
-        assert (_bits(host(res[j][1])) == _bits(d_o)).all(), j
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count() or 1
+    order = sorted(range(len(fields)), key=lambda j: -fields[j][0].size)
+    _say(f"full 96-field batch, {'merged' if merged else 'default'} schedule, oracle on {min(16, cpus)} threads")
+    with ThreadPoolExecutor(max_workers=max(1, min(16, cpus))) as pool:
+        fut = {j: pool.submit(oracle.fix, *fields[j], merged_c=merged) for j in order}
+        rc, res = msz.fix_batch([(dev(f), dev(fh), xi) for f, fh, xi in fields], merged=merged, count_init=True)
+        torch.cuda.synchronize()
+        assert rc == msz.OK
+        for j, (f, fh, xi) in enumerate(fields):
+            st_b, d_b, g_b, s_b = res[j]
+            assert st_b == msz.OK, j
+            _full_invariants(msz, f, fh, xi, host(g_b), host(d_b), s_b)
+        for j in order:
+            rc_o, d_o, g_o, st_o = fut[j].result()
+            st_b, d_b, g_b, s_b = res[j]
+            assert rc_o == st_b == msz.OK, (j, rc_o, st_b)
+            assert (_bits(host(g_b)) == _bits(g_o)).all(), ("edited values differ", j, fields[j][0].shape)
+            assert (_bits(host(d_b)) == _bits(d_o)).all(), ("deltas differ", j)
+            assert s_b == st_o, (j, s_b, st_o)
 
 
 def test_full_turb512_learned_properties(msz):
