@@ -130,6 +130,23 @@ def test_fix_random_small(msz, shape):
         assert_fix_parity(msz, f, fh, xi)
 
 
+@pytest.mark.parametrize("merged", [False, True])
+@pytest.mark.parametrize("shape", [(256, 128), (64, 16, 16), (32, 32, 16)])
+def test_fix_dense_troublemakers(msz, shape, merged):
+    """Random fields under a bound of a tenth of their range: more than a
+    quarter of the vertices start mislabelled and most directions differ, so
+    each label tile lists thousands of vertices in a troublemaker pass and the
+    blocks' LDS target lists take many targets per pass (edited when half
+    full; any beyond their capacity at once).  Bit for bit with the oracle
+    under both schedules."""
+    rng = np.random.default_rng(41)
+    for levels in (0, 4):
+        f, fh, xi = synth.random_small(rng, shape, xi=0.1, levels=levels)
+        _say("dense troublemakers", shape, "levels", levels, "merged" if merged else "default")
+        rc, st = assert_fix_parity(msz, f, fh, xi, merged=merged)
+        assert rc == msz.OK and st["mislabel_init"] * 4 > f.size and st["rounds_r"] > 0
+
+
 def test_fix_ragged_multi_tile_2d_and_3d(msz):
     rng = np.random.default_rng(16)
     f = synth.gaussian_random_field((301, 517), 3.0, rng).astype(np.float32)
