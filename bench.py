@@ -343,6 +343,7 @@ def bench_learned(msz, torch, dev, steps):
     n = fd.numel()
     out = {"workload": "512^3 k^-11/3 Gaussian random field, xi = 1e-3 x range", "vertices": n,
            "p_min": p_min, "steps": steps}
+    ebuf = torch.empty(msz.edits_bound(n), dtype=torch.uint8, device=dev)
     for name, fn in (("plain", lambda t: msz.fix(fd, fhd, xi, workspace=ws, edits_out=e, g_out=g, timing=t)),
                      ("learned", lambda t: msz.fix_learned(fd, fhd, xi, params, p_min=p_min, workspace=ws,
                                                            edits_out=e, g_out=g, timing=t))):
@@ -351,12 +352,19 @@ def bench_learned(msz, torch, dev, steps):
             raise RuntimeError(f"{name} failed: {msz.strerror(rc)}")
         checked(msz, fd, g, xi)
         _, _, _, stt = fn(True)
+        phases = by_phase(msz.last_launches())
+        # what the edits cost to store: the lossless stream of this result's edits
+        rc, _, est = msz.encode_edits(e, out=ebuf)
+        if rc != msz.OK:
+            raise RuntimeError(f"msz_encode_edits: {msz.strerror(rc)}")
         out[name] = {"ms": round(ms, 3), "value": round(n / ms / 1e6, 4),
                      "rounds": sum(st["rounds"]) + st["rounds_r"], "outer_iters": st["outer_iters"],
                      "n_edited": st["n_edited"], "net_ms": round(stt["timing"]["net"]["ms"], 3),
-                     "phases": by_phase(msz.last_launches())}
+                     "edit_bytes": est["bytes"], "edit_bits_per_vertex": round(8 * est["bytes"] / n, 5),
+                     "phases": phases}
         log(f"bench: {name} 512^3 {ms:.2f} ms, rounds {out[name]['rounds']}")
     out["speedup"] = round(out["plain"]["ms"] / out["learned"]["ms"], 4)
+    out["edit_bytes_ratio"] = round(out["learned"]["edit_bytes"] / max(out["plain"]["edit_bytes"], 1), 4)
     out["unit"] = "Gvertices/s"
     for name, fn in (("plain_merged", lambda: msz.fix(fd, fhd, xi, workspace=ws, edits_out=e, g_out=g, merged=True)),
                      ("learned_merged", lambda: msz.fix_learned(fd, fhd, xi, params, p_min=p_min, workspace=ws,
