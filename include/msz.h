@@ -217,8 +217,10 @@ int msz_fix_noalloc(const float* f, const float* fhat, msz_dims d, float xi, flo
  * block's start and its last block's end, and the algorithmic bytes of the
  * units its blocks visited: per operation, the compulsory reads and writes of
  * each vertex of a visited direction or label tile, each scanned flag byte,
- * edit attempt, recomputed vertex, face-layer pointer, and each pointer load
- * or store of the compression walks (halo and cache re-reads not counted). */
+ * edit attempt, recomputed vertex, face-layer pointer, the two forests'
+ * pointers of each vertex whose labels the troublemaker search resolves, and
+ * each pointer load of an exit-chain walk or load or store of a compression
+ * walk (halo and cache re-reads not counted). */
 enum {
     MSZ_KERNEL_STEP1_2D = 0, /* one field: the step kernel of a 2D field (decides and runs) */
     MSZ_KERNEL_STEP1_3D = 1,
